@@ -1,0 +1,178 @@
+/*
+ * tucker.h - C ABI of the MI355X (gfx950) ST-HOSVD Tucker compression library.
+ *
+ * Method: sequentially truncated higher-order SVD (ST-HOSVD) as stated in
+ * Ballard, Klinvex & Kolda, "TuckerMPI" (ACM TOMS), Algorithm 1: for each mode
+ * n in a caller-chosen order, form the Gram matrix S = Y_(n) Y_(n)^T of the
+ * current working tensor (Algorithm 2), take its eigendecomposition, keep the
+ * smallest number R_n of leading eigenvectors whose discarded eigenvalues sum
+ * to at most eps^2 ||X||^2 / N (eq. Un), and shrink the working tensor with
+ * Y <- Y x_n U_n^T (Algorithm 3).  The result satisfies
+ * ||X - X^|| <= eps ||X|| (Corollary 1).  Reconstruction of a sub-tensor is a
+ * chain of mode products in a flop-minimising order (Sec. 8).
+ *
+ * Layout (Sec. 4.1, eq. idxtolin): every tensor is a flat array in the
+ * "natural descending" order: element (i_0,...,i_{N-1}) sits at
+ * sum_n i_n * prod_{k<n} I_k  (mode 0 fastest).  A C-ordered array of shape
+ * (I_{N-1},...,I_0) has identical bytes.  Factor matrices U_n are I_n x R_n,
+ * column-major (element (i,r) at i + r*I_n), FP64.
+ *
+ * Pointers: "device" pointers are HIP device memory of the current device;
+ * "host" pointers are ordinary host memory.  Sizes are element counts unless
+ * stated.  Every call returns a tucker_status; on error no output is produced,
+ * nothing leaks, and tucker_last_error() returns a message (thread-local).
+ *
+ * Streams: work is enqueued on the caller's stream.  Calls that must learn a
+ * data-dependent size (the truncation ranks) synchronise that stream.
+ */
+#ifndef TUCKER_H
+#define TUCKER_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  TUCKER_OK = 0,
+  TUCKER_EINVAL = 1,       /* invalid argument (shape, eps, order, null pointer, non-finite data) */
+  TUCKER_ENOMEM = 2,       /* device memory could not be allocated */
+  TUCKER_EHIP = 3,         /* a HIP runtime call failed; message holds its error string */
+  TUCKER_ENOCONV = 4,      /* an eigenvalue iteration exceeded its iteration cap */
+  TUCKER_EUNSUPPORTED = 5  /* combination not supported (e.g. no gfx950 device) */
+} tucker_status;
+
+typedef enum { TUCKER_F32 = 0, TUCKER_F64 = 1 } tucker_dtype;
+
+/* Arithmetic of the Gram step.  FP64 is the reference path.  The two mixed
+ * forms keep the eigensolve, ||X||^2 and the truncation decision in FP64 and
+ * carry the working tensor in FP32; they are not part of the paper (which is
+ * FP64 only) and each result's error is reported against the FP64 path.
+ *   FP32   : FP32 MFMA products, FP32 accumulation within chunks of the
+ *            unfolding's columns, chunk sums accumulated in FP64.
+ *   BF16X3 : each FP32 value split as b0 + b1 (+ b2) in bfloat16; products
+ *            b0*b0' + b0*b1' + b1*b0' on BF16 MFMA, FP32 accumulation per chunk,
+ *            FP64 across chunks (Henry, Tang & Heinecke, ARITH 2019). */
+typedef enum { TUCKER_GRAM_FP64 = 0, TUCKER_GRAM_FP32 = 1, TUCKER_GRAM_BF16X3 = 2 } tucker_gram_prec;
+
+typedef struct tucker_t tucker_t; /* opaque result handle */
+
+#define TUCKER_MAX_MODES 16
+
+/* ------------------------------------------------------------------------
+ * Compression
+ * ------------------------------------------------------------------------ */
+
+/* ST-HOSVD of one tensor (Algorithm 1).
+ *   data       device, prod(dims) values of `dtype`, natural descending; read only.
+ *   dims       host, N sizes, each >= 1; 1 <= N <= TUCKER_MAX_MODES.
+ *   eps        relative error target, finite and >= 0.
+ *   mode_order host, N ints: a permutation of 0..N-1 giving the order in which
+ *              modes are processed (Sec. 7 discusses the choice); NULL = 0..N-1.
+ *   prec       Gram arithmetic (see tucker_gram_prec).  TUCKER_GRAM_FP64 keeps
+ *              the working tensor in FP64; the mixed forms keep it in FP32.
+ *   stream     HIP stream for all work (0 = default stream).
+ *   out        receives a new handle owning core, factors, eigenvalues and
+ *              ranks; release it with tucker_free.
+ * Errors: EINVAL for bad arguments or non-finite ||X||^2; ENOMEM; EHIP;
+ *         ENOCONV if the eigensolver exceeded its iteration cap.
+ * Synchronises `stream` once per mode to read back the rank R_n. */
+tucker_status tucker_sthosvd(const void* data, tucker_dtype dtype, const int64_t* dims, int N,
+                             double eps, const int* mode_order, tucker_gram_prec prec,
+                             hipStream_t stream, tucker_t** out);
+
+/* Handle accessors.  Pointers returned are owned by the handle and valid until
+ * tucker_free.  All of them are cheap and do not synchronise. */
+int tucker_ndims(const tucker_t* t);
+/* host out[N]: the original sizes I_n / the ranks R_n. */
+tucker_status tucker_dims(const tucker_t* t, int64_t* dims_out);
+tucker_status tucker_ranks(const tucker_t* t, int64_t* ranks_out);
+/* host out[N]: mode_order used. */
+tucker_status tucker_mode_order(const tucker_t* t, int* order_out);
+/* Core G (device, prod(R) values of *dtype, natural descending). */
+const void* tucker_core(const tucker_t* t, tucker_dtype* dtype);
+/* Factor U_n (device, I_n x R_n column-major FP64, orthonormal columns; in
+ * each column the entry of largest magnitude is positive, lowest row on ties). */
+const double* tucker_factor(const tucker_t* t, int n);
+/* Eigenvalues of mode n's Gram matrix (device, FP64, descending); count in
+ * *count = J_n, the size of mode n of the working tensor when it was processed. */
+const double* tucker_eigenvalues(const tucker_t* t, int n, int64_t* count);
+/* ||X||^2 in FP64. */
+double tucker_norm2(const tucker_t* t);
+/* host out[N]: per mode, the sum of the discarded (clamped) eigenvalues;
+ * by Corollary 1 their total is ||X - X^||^2 (up to rounding). */
+tucker_status tucker_discarded(const tucker_t* t, double* disc_out);
+/* host out[4*N]: per mode (in mode index order) milliseconds, measured with HIP
+ * events on the call's stream: [4n+0] Gram step (main kernel, split-K
+ * reduction, norm), [4n+1] eigensolve + truncation, [4n+2] TTM, [4n+3] the
+ * main Gram kernel alone. */
+tucker_status tucker_timings(const tucker_t* t, double* ms_out);
+void tucker_free(tucker_t* t);
+
+/* ------------------------------------------------------------------------
+ * Reconstruction (Sec. 8): X^[begin:end) = G x_0 U_0[b_0:e_0,:] ... x_{N-1} U_{N-1}[b:e,:]
+ * ------------------------------------------------------------------------ */
+
+/* begin/end  host, N each; half-open index ranges 0 <= begin_n < end_n <= I_n;
+ *            NULL means the full range.
+ * order      host, N ints, permutation giving the order of the mode products;
+ *            NULL = the flop-minimising order of tucker_reconstruct_order.
+ * out        device, caller-allocated, prod(end-begin) values of out_dtype,
+ *            natural descending.
+ * Scratch for intermediate results is taken from the device's stream-ordered
+ * pool and released before return (stream order). */
+tucker_status tucker_reconstruct(const tucker_t* t, const int64_t* begin, const int64_t* end,
+                                 const int* order, void* out, tucker_dtype out_dtype,
+                                 hipStream_t stream);
+
+/* Flop-minimising order of a Multi-TTM G (sizes R) -> Z (sizes K), Sec. 8:
+ * mode i precedes mode j when K_i R_i R_j + K_i R_j K_j < R_i R_j K_j + R_i K_i K_j,
+ * i.e. sorting by 1/R_i - 1/K_i ascending (ties: lower mode first).
+ * ranks, out_sizes: host, N each, >= 1.  order_out: host, N ints.  Host only. */
+tucker_status tucker_reconstruct_order(int N, const int64_t* ranks, const int64_t* out_sizes,
+                                       int* order_out);
+
+/* ------------------------------------------------------------------------
+ * Single steps of the path, for testing and for callers composing their own
+ * loop.  All pointers are device pointers except dims (host).
+ * ------------------------------------------------------------------------ */
+
+/* S = Y_(n) Y_(n)^T (Algorithm 2) for Y of sizes dims (natural descending) in
+ * `dtype`; S is J_n x J_n FP64, full symmetric.  If norm2 is non-NULL, the
+ * FP64 sum of squares of Y is written to it (device, one double).
+ * prec selects the arithmetic; FP32/BF16X3 need dtype == TUCKER_F32. */
+tucker_status tucker_gram(const void* Y, tucker_dtype dtype, const int64_t* dims, int N, int n,
+                          tucker_gram_prec prec, double* S, double* norm2, hipStream_t stream);
+
+/* Eigendecomposition of a J x J symmetric FP64 matrix S (device, read only)
+ * followed by the truncation rule eq. Un with threshold thr:
+ *   lam  device, J values, eigenvalues in descending order;
+ *   U    device, J x J column-major: columns 0..R-1 receive the leading
+ *        eigenvectors (sign convention as for tucker_factor); the rest is scratch;
+ *   R    device, one int64: the chosen rank (1 <= R <= J);
+ *   disc device, one double: sum of the discarded (clamped) eigenvalues.
+ * Does not synchronise. */
+tucker_status tucker_eig_truncate(const double* S, int64_t J, double thr, double* lam, double* U,
+                                  int64_t* R, double* disc, hipStream_t stream);
+
+/* Mode product Z = Y x_n M (Sec. 2.2.3, Algorithm 3), M a K x J_n FP64
+ * matrix with element (k,j) at M[k*msk + j*msj]; Z has the sizes of Y with
+ * mode n replaced by K, in `zdtype`.  Y in `ydtype`. */
+tucker_status tucker_ttm(const void* Y, tucker_dtype ydtype, const int64_t* dims, int N, int n,
+                         const double* M, int64_t K, int64_t msk, int64_t msj, void* Z,
+                         tucker_dtype zdtype, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Diagnostics
+ * ------------------------------------------------------------------------ */
+const char* tucker_last_error(void);
+const char* tucker_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TUCKER_H */

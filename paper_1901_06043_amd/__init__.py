@@ -1,0 +1,303 @@
+"""MI355X (gfx950) ST-HOSVD Tucker compression: thin Python binding.
+
+Every computation runs in the HIP library ``libtuckerhip.so`` (built from
+``csrc/`` by ``build.py``) through its C ABI (``include/tucker.h``).  This
+module only marshals arguments: torch tensors provide device memory and the
+current HIP stream.  There is no CPU fallback: if the library is missing or no
+gfx950 device is present, calls raise.
+
+Tensor convention: the paper's natural-descending layout (mode 0 fastest).  A
+C-contiguous torch tensor of shape (I_{N-1}, ..., I_0) holds a tensor with
+dims (I_0, ..., I_{N-1}); ``dims`` below are always in the paper's order.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtuckerhip.so")
+
+F32, F64 = 0, 1
+GRAM_FP64, GRAM_FP32, GRAM_BF16X3 = 0, 1, 2
+_PREC = {"fp64": GRAM_FP64, "fp32": GRAM_FP32, "bf16x3": GRAM_BF16X3}
+STATUS = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EHIP", 4: "ENOCONV", 5: "EUNSUPPORTED"}
+MAX_MODES = 16
+
+EXPORTS = [
+    "tucker_sthosvd", "tucker_ndims", "tucker_dims", "tucker_ranks", "tucker_mode_order", "tucker_core",
+    "tucker_factor", "tucker_eigenvalues", "tucker_norm2", "tucker_discarded", "tucker_timings",
+    "tucker_free", "tucker_reconstruct", "tucker_reconstruct_order", "tucker_gram",
+    "tucker_eig_truncate", "tucker_ttm", "tucker_last_error", "tucker_version",
+]
+
+_lib = None
+
+
+class TuckerError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+        self.name = STATUS.get(status, str(status))
+
+
+def lib():
+    """Load libtuckerhip.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run `python -m paper_1901_06043_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        P, i32, i64, d = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_double
+        PP = ctypes.POINTER(ctypes.c_void_p)
+        sig = {
+            "tucker_sthosvd": (i32, [P, i32, P, i32, d, P, i32, P, PP]),
+            "tucker_ndims": (i32, [P]),
+            "tucker_dims": (i32, [P, P]),
+            "tucker_ranks": (i32, [P, P]),
+            "tucker_mode_order": (i32, [P, P]),
+            "tucker_core": (P, [P, P]),
+            "tucker_factor": (P, [P, i32]),
+            "tucker_eigenvalues": (P, [P, i32, P]),
+            "tucker_norm2": (d, [P]),
+            "tucker_discarded": (i32, [P, P]),
+            "tucker_timings": (i32, [P, P]),
+            "tucker_free": (None, [P]),
+            "tucker_reconstruct": (i32, [P, P, P, P, P, i32, P]),
+            "tucker_reconstruct_order": (i32, [i32, P, P, P]),
+            "tucker_gram": (i32, [P, i32, P, i32, i32, i32, P, P, P]),
+            "tucker_eig_truncate": (i32, [P, i64, d, P, P, P, P, P]),
+            "tucker_ttm": (i32, [P, i32, P, i32, i32, P, i64, i64, i64, P, i32, P]),
+            "tucker_last_error": (ctypes.c_char_p, []),
+            "tucker_version": (ctypes.c_char_p, []),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(status: int):
+    if status != 0:
+        raise TuckerError(status, lib().tucker_last_error().decode(errors="replace"))
+
+
+def _i64(vals):
+    arr = (ctypes.c_int64 * len(vals))(*[int(v) for v in vals])
+    return arr
+
+
+def _i32(vals):
+    return (ctypes.c_int * len(vals))(*[int(v) for v in vals])
+
+
+def _stream(stream=None) -> int:
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def _dtype_code(t) -> int:
+    import torch
+    if t.dtype == torch.float64:
+        return F64
+    if t.dtype == torch.float32:
+        return F32
+    raise TypeError(f"unsupported dtype {t.dtype} (float32 or float64)")
+
+
+def _dims_of(x, dims):
+    if dims is None:
+        dims = list(reversed(x.shape))
+    dims = [int(v) for v in dims]
+    n = 1
+    for v in dims:
+        n *= v
+    if x.numel() != n:
+        raise ValueError(f"tensor has {x.numel()} elements, dims {dims} need {n}")
+    if not x.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    if not x.is_cuda:
+        raise ValueError("tensor must live on the GPU")
+    return dims
+
+
+class _DevArray:
+    """Exposes handle-owned device memory to torch via __cuda_array_interface__."""
+
+    def __init__(self, ptr: int, shape, typestr: str, owner):
+        self.__cuda_array_interface__ = {"shape": tuple(shape), "typestr": typestr, "data": (ptr, False),
+                                         "version": 2, "strides": None}
+        self._owner = owner
+
+
+def _view(ptr, shape, typestr, owner):
+    import torch
+    return torch.as_tensor(_DevArray(ptr, shape, typestr, owner), device="cuda")
+
+
+@dataclass
+class Timing:
+    gram_ms: float         # Gram step: main kernel + split-K reduction + norm
+    eig_ms: float          # eigensolve + truncation
+    ttm_ms: float
+    gram_kernel_ms: float  # main Gram kernel alone
+
+
+class Tucker:
+    """Result of tucker_sthosvd: core, factors, ranks, eigenvalues (device memory
+    owned by the C handle; tensors returned here are views kept alive by this
+    object)."""
+
+    def __init__(self, handle: int, stream: int):
+        self._h = handle
+        self._stream = stream
+        L = lib()
+        self.N = L.tucker_ndims(handle)
+        d = (ctypes.c_int64 * self.N)()
+        _check(L.tucker_dims(handle, d))
+        self.dims = list(d)
+        r = (ctypes.c_int64 * self.N)()
+        _check(L.tucker_ranks(handle, r))
+        self.ranks = list(r)
+        o = (ctypes.c_int * self.N)()
+        _check(L.tucker_mode_order(handle, o))
+        self.mode_order = list(o)
+        self.norm2 = float(L.tucker_norm2(handle))
+        disc = (ctypes.c_double * self.N)()
+        _check(L.tucker_discarded(handle, disc))
+        self.discarded = list(disc)
+        ms = (ctypes.c_double * (4 * self.N))()
+        _check(L.tucker_timings(handle, ms))
+        self.timings = [Timing(ms[4 * n], ms[4 * n + 1], ms[4 * n + 2], ms[4 * n + 3]) for n in range(self.N)]
+
+    def _alive(self):
+        if not self._h:
+            raise RuntimeError("Tucker handle already freed")
+
+    @property
+    def core(self):
+        """Core tensor G as a torch view of shape ranks[::-1] (natural descending)."""
+        self._alive()
+        dt = ctypes.c_int(0)
+        p = lib().tucker_core(self._h, ctypes.byref(dt))
+        return _view(p, list(reversed(self.ranks)), "<f8" if dt.value == F64 else "<f4", self)
+
+    @property
+    def core_dtype(self) -> int:
+        dt = ctypes.c_int(0)
+        lib().tucker_core(self._h, ctypes.byref(dt))
+        return dt.value
+
+    def factor(self, n: int):
+        """U_n, I_n x R_n with orthonormal columns (a torch view)."""
+        self._alive()
+        p = lib().tucker_factor(self._h, n)
+        # column-major I x R == C-ordered (R, I); return its transpose view
+        return _view(p, (self.ranks[n], self.dims[n]), "<f8", self).t()
+
+    @property
+    def factors(self):
+        return [self.factor(n) for n in range(self.N)]
+
+    def eigenvalues(self, n: int):
+        self._alive()
+        cnt = ctypes.c_int64(0)
+        p = lib().tucker_eigenvalues(self._h, n, ctypes.byref(cnt))
+        return _view(p, (cnt.value,), "<f8", self)
+
+    def reconstruct(self, begin=None, end=None, order=None, out_dtype=None, out=None, stream=None):
+        """Sub-tensor X^[begin:end) by Multi-TTM (paper Sec. 8); returns a torch
+        tensor of shape (end-begin)[::-1]."""
+        import torch
+        self._alive()
+        b = list(begin) if begin is not None else [0] * self.N
+        e = list(end) if end is not None else list(self.dims)
+        shape = [int(e[k]) - int(b[k]) for k in range(self.N)]
+        if out is None:
+            if out_dtype is None:
+                out_dtype = torch.float64 if self.core_dtype == F64 else torch.float32
+            out = torch.empty(list(reversed(shape)), dtype=out_dtype, device="cuda")
+        code = _dtype_code(out)
+        _check(lib().tucker_reconstruct(self._h, _i64(b), _i64(e), _i32(order) if order is not None else None,
+                                        out.data_ptr(), code, _stream(stream)))
+        return out
+
+    def free(self):
+        if self._h:
+            lib().tucker_free(self._h)
+            self._h = 0
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def sthosvd(x, eps: float, mode_order=None, prec: str = "fp64", dims=None, stream=None) -> Tucker:
+    """ST-HOSVD of a GPU tensor (paper Alg. 1) -> Tucker handle."""
+    dims = _dims_of(x, dims)
+    h = ctypes.c_void_p(0)
+    s = _stream(stream)
+    _check(lib().tucker_sthosvd(x.data_ptr(), _dtype_code(x), _i64(dims), len(dims), float(eps),
+                                _i32(mode_order) if mode_order is not None else None, _PREC[prec], s,
+                                ctypes.byref(h)))
+    return Tucker(h.value, s)
+
+
+def reconstruct_order(ranks, out_sizes):
+    """Flop-minimising Multi-TTM order (host rule of Sec. 8)."""
+    N = len(ranks)
+    o = (ctypes.c_int * N)()
+    _check(lib().tucker_reconstruct_order(N, _i64(ranks), _i64(out_sizes), o))
+    return list(o)
+
+
+def gram(y, n: int, prec: str = "fp64", dims=None, with_norm: bool = False, stream=None):
+    """S = Y_(n) Y_(n)^T (paper Alg. 2) as a J_n x J_n float64 tensor."""
+    import torch
+    dims = _dims_of(y, dims)
+    J = dims[n]
+    S = torch.empty((J, J), dtype=torch.float64, device=y.device)
+    nrm = torch.empty((1,), dtype=torch.float64, device=y.device) if with_norm else None
+    _check(lib().tucker_gram(y.data_ptr(), _dtype_code(y), _i64(dims), len(dims), n, _PREC[prec], S.data_ptr(),
+                             nrm.data_ptr() if with_norm else None, _stream(stream)))
+    return (S, nrm) if with_norm else S
+
+
+def eig_truncate(S, thr: float, stream=None):
+    """(lam descending, U leading columns, R, disc) of a symmetric J x J float64 matrix."""
+    import torch
+    J = S.shape[0]
+    if S.dtype != torch.float64 or not S.is_contiguous() or tuple(S.shape) != (J, J):
+        raise ValueError("S must be a contiguous J x J float64 tensor")
+    lam = torch.empty((J,), dtype=torch.float64, device=S.device)
+    Ubuf = torch.empty((J, J), dtype=torch.float64, device=S.device)
+    R = torch.empty((1,), dtype=torch.int64, device=S.device)
+    disc = torch.empty((1,), dtype=torch.float64, device=S.device)
+    _check(lib().tucker_eig_truncate(S.data_ptr(), J, float(thr), lam.data_ptr(), Ubuf.data_ptr(), R.data_ptr(),
+                                     disc.data_ptr(), _stream(stream)))
+    r = int(R.item())
+    # column-major J x J buffer: row k of Ubuf is column k of U
+    return lam, Ubuf[:r].t(), r, float(disc.item())
+
+
+def ttm(y, n: int, M, dims=None, out_dtype=None, stream=None):
+    """Z = Y x_n M (paper Sec. 2.2.3), M a K x J_n float64 tensor (any strides)."""
+    import torch
+    dims = _dims_of(y, dims)
+    if M.dtype != torch.float64 or M.dim() != 2 or M.shape[1] != dims[n]:
+        raise ValueError("M must be a K x J_n float64 matrix")
+    K = M.shape[0]
+    zd = list(dims)
+    zd[n] = K
+    if out_dtype is None:
+        out_dtype = y.dtype
+    Z = torch.empty(list(reversed(zd)), dtype=out_dtype, device=y.device)
+    _check(lib().tucker_ttm(y.data_ptr(), _dtype_code(y), _i64(dims), len(dims), n, M.data_ptr(), K,
+                            M.stride(0), M.stride(1), Z.data_ptr(), _dtype_code(Z), _stream(stream)))
+    return Z

@@ -1,0 +1,565 @@
+// C ABI of the library (include/tucker.h): argument validation, the ST-HOSVD
+// mode loop of paper Alg. 1, Multi-TTM reconstruction of Sec. 8, and the
+// single-step entry points.  All device work is enqueued on the caller's
+// stream; device memory comes from the device's stream-ordered pool
+// (hipMallocAsync), whose release threshold is raised so that repeated calls
+// reuse memory instead of returning it to the driver.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "../../include/tucker.h"
+#include "common.hpp"
+#include "kernels.hpp"
+
+using tk::ceil_div;
+
+namespace {
+
+thread_local std::string g_err;
+
+tucker_status fail(tucker_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+#define HIP_TRY(expr)                                                                        \
+  do {                                                                                       \
+    hipError_t _e = (expr);                                                                  \
+    if (_e != hipSuccess)                                                                    \
+      return fail(_e == hipErrorOutOfMemory ? TUCKER_ENOMEM : TUCKER_EHIP, "%s: %s (%s:%d)", \
+                  #expr, hipGetErrorString(_e), __FILE__, __LINE__);                         \
+  } while (0)
+
+size_t dtype_size(tucker_dtype t) { return t == TUCKER_F64 ? 8 : 4; }
+
+// Device checks and pool set-up, once per device.
+std::mutex g_dev_mu;
+bool g_dev_ok[64];
+bool g_dev_checked[64];
+
+tucker_status ensure_device() {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail(TUCKER_EUNSUPPORTED, "no HIP device: %s", hipGetErrorString(e));
+  if (dev < 0 || dev >= 64) return fail(TUCKER_EUNSUPPORTED, "device index %d out of range", dev);
+  std::lock_guard<std::mutex> lk(g_dev_mu);
+  if (!g_dev_checked[dev]) {
+    g_dev_checked[dev] = true;
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDeviceProperties(&prop, dev));
+    g_dev_ok[dev] = std::strncmp(prop.gcnArchName, "gfx950", 6) == 0;
+    if (g_dev_ok[dev]) {
+      hipMemPool_t pool;
+      if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+        uint64_t thr = UINT64_MAX;
+        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+      }
+    }
+  }
+  if (!g_dev_ok[dev]) return fail(TUCKER_EUNSUPPORTED, "device %d is not gfx950 (MI355X)", dev);
+  return TUCKER_OK;
+}
+
+// Stream-ordered temporary device buffer.
+struct TmpBuf {
+  void* p = nullptr;
+  hipStream_t s = nullptr;
+  TmpBuf() = default;
+  TmpBuf(const TmpBuf&) = delete;
+  TmpBuf& operator=(const TmpBuf&) = delete;
+  ~TmpBuf() { release(); }
+  void release() {
+    if (p) (void)hipFreeAsync(p, s);
+    p = nullptr;
+  }
+  hipError_t alloc(size_t bytes, hipStream_t st) {
+    release();
+    s = st;
+    return hipMallocAsync(&p, std::max<size_t>(bytes, 256), st);
+  }
+  template <typename T>
+  T* as() const {
+    return static_cast<T*>(p);
+  }
+};
+
+// Small pinned host staging area for rank read-back (one per thread).
+struct Pinned {
+  void* p = nullptr;
+  ~Pinned() {
+    if (p) (void)hipHostFree(p);
+  }
+};
+thread_local Pinned g_pinned;
+
+tucker_status pinned(void** out) {
+  if (!g_pinned.p) HIP_TRY(hipHostMalloc(&g_pinned.p, 4096, hipHostMallocDefault));
+  *out = g_pinned.p;
+  return TUCKER_OK;
+}
+
+tucker_status validate_dims(const int64_t* dims, int N) {
+  if (!dims) return fail(TUCKER_EINVAL, "dims is NULL");
+  if (N < 1 || N > TUCKER_MAX_MODES) return fail(TUCKER_EINVAL, "N=%d outside 1..%d", N, TUCKER_MAX_MODES);
+  for (int k = 0; k < N; ++k)
+    if (dims[k] < 1) return fail(TUCKER_EINVAL, "dims[%d]=%lld < 1", k, (long long)dims[k]);
+  return TUCKER_OK;
+}
+
+tucker_status validate_order(const int* order, int N, int* out) {
+  if (!order) {
+    for (int k = 0; k < N; ++k) out[k] = k;
+    return TUCKER_OK;
+  }
+  bool seen[TUCKER_MAX_MODES] = {false};
+  for (int k = 0; k < N; ++k) {
+    if (order[k] < 0 || order[k] >= N || seen[order[k]])
+      return fail(TUCKER_EINVAL, "mode order is not a permutation of 0..%d", N - 1);
+    seen[order[k]] = true;
+    out[k] = order[k];
+  }
+  return TUCKER_OK;
+}
+
+void left_right(const int64_t* dims, int N, int n, int64_t& L, int64_t& Rt) {
+  L = 1;
+  Rt = 1;
+  for (int k = 0; k < n; ++k) L *= dims[k];
+  for (int k = n + 1; k < N; ++k) Rt *= dims[k];
+}
+
+constexpr int64_t kMaxEigJ = 1024;
+
+// Gram of mode n of a tensor in (ptr, dtype) -> S (J x J FP64), optional norm.
+tucker_status run_gram(const void* Y, tucker_dtype dt, const int64_t* dims, int N, int n, tucker_gram_prec prec,
+                       double* S, double* norm2, hipStream_t s, hipEvent_t after_main = nullptr) {
+  int64_t L, Rt;
+  left_right(dims, N, n, L, Rt);
+  const int64_t J = dims[n];
+  const int64_t K = L * Rt;
+  if (K >= (int64_t(1) << 32) || J >= (int64_t(1) << 31))
+    return fail(TUCKER_EUNSUPPORTED, "unfolding of mode %d has %lld columns (limit 2^32)", n, (long long)K);
+  if (prec == TUCKER_GRAM_FP64) {
+    tk::GramPlan p = tk::plan_gram_f64((int)J, (uint64_t)L, (uint64_t)K);
+    TmpBuf part, sq;
+    HIP_TRY(part.alloc(sizeof(double) * p.part_elems, s));
+    HIP_TRY(sq.alloc(sizeof(double) * p.sq_elems, s));
+    if (dt == TUCKER_F64)
+      HIP_TRY(tk::launch_gram_f64(static_cast<const double*>(Y), (int)J, L, K, p, part.as<double>(),
+                                  sq.as<double>(), S, norm2, s, after_main));
+    else
+      HIP_TRY(tk::launch_gram_f64(static_cast<const float*>(Y), (int)J, L, K, p, part.as<double>(),
+                                  sq.as<double>(), S, norm2, s, after_main));
+    return TUCKER_OK;
+  }
+  if (dt != TUCKER_F32) return fail(TUCKER_EINVAL, "mixed-precision Gram needs FP32 data");
+  tk::GramPlan p = tk::plan_gram_mixed((int)J, (uint64_t)L, (uint64_t)K);
+  TmpBuf part, sq;
+  HIP_TRY(part.alloc(sizeof(double) * p.part_elems, s));
+  HIP_TRY(sq.alloc(sizeof(double) * p.sq_elems, s));
+  HIP_TRY(tk::launch_gram_mixed(static_cast<const float*>(Y), (int)J, L, K, (int)prec, p, part.as<double>(),
+                                sq.as<double>(), S, norm2, s, after_main));
+  return TUCKER_OK;
+}
+
+tucker_status run_ttm(const void* Y, tucker_dtype yd, const int64_t* dims, int N, int n, const double* M,
+                      int64_t K, int64_t msk, int64_t msj, void* Z, tucker_dtype zd, hipStream_t s) {
+  int64_t L, Rt;
+  left_right(dims, N, n, L, Rt);
+  const int64_t J = dims[n];
+  const int64_t cols = L * Rt;
+  if (cols >= (int64_t(1) << 32) || K >= (int64_t(1) << 31) || J >= (int64_t(1) << 31))
+    return fail(TUCKER_EUNSUPPORTED, "TTM of mode %d too large for 32-bit column indexing", n);
+  if (yd == TUCKER_F64 && zd == TUCKER_F64)
+    HIP_TRY(tk::launch_ttm(static_cast<const double*>(Y), (int)J, L, cols, M, msk, msj, (int)K,
+                           static_cast<double*>(Z), s));
+  else if (yd == TUCKER_F32 && zd == TUCKER_F64)
+    HIP_TRY(tk::launch_ttm(static_cast<const float*>(Y), (int)J, L, cols, M, msk, msj, (int)K,
+                           static_cast<double*>(Z), s));
+  else if (yd == TUCKER_F64 && zd == TUCKER_F32)
+    HIP_TRY(tk::launch_ttm(static_cast<const double*>(Y), (int)J, L, cols, M, msk, msj, (int)K,
+                           static_cast<float*>(Z), s));
+  else
+    HIP_TRY(tk::launch_ttm(static_cast<const float*>(Y), (int)J, L, cols, M, msk, msj, (int)K,
+                           static_cast<float*>(Z), s));
+  return TUCKER_OK;
+}
+
+}  // namespace
+
+struct tucker_t {
+  int N = 0;
+  int64_t dims[TUCKER_MAX_MODES] = {0};
+  int64_t ranks[TUCKER_MAX_MODES] = {0};
+  int64_t eigcount[TUCKER_MAX_MODES] = {0};
+  int order[TUCKER_MAX_MODES] = {0};
+  double disc[TUCKER_MAX_MODES] = {0};
+  double ms[4 * TUCKER_MAX_MODES] = {0};
+  double norm2 = 0.0;
+  tucker_dtype core_dtype = TUCKER_F64;
+  void* core = nullptr;
+  double* U[TUCKER_MAX_MODES] = {nullptr};
+  double* lam[TUCKER_MAX_MODES] = {nullptr};
+  double* scalars = nullptr;  // [0] = ||X||^2, [1..N] = disc, then ranks (int64) in a separate buffer
+  int64_t* dranks = nullptr;
+  hipStream_t stream = nullptr;
+  std::vector<void*> owned;
+
+  hipError_t alloc(void** p, size_t bytes) {
+    hipError_t e = hipMallocAsync(p, std::max<size_t>(bytes, 256), stream);
+    if (e == hipSuccess) owned.push_back(*p);
+    return e;
+  }
+  void release() {
+    for (void* p : owned) (void)hipFreeAsync(p, stream);
+    owned.clear();
+  }
+};
+
+namespace {
+
+struct HandleGuard {
+  tucker_t* t;
+  explicit HandleGuard(tucker_t* h) : t(h) {}
+  ~HandleGuard() {
+    if (t) {
+      t->release();
+      delete t;
+    }
+  }
+  tucker_t* take() {
+    tucker_t* h = t;
+    t = nullptr;
+    return h;
+  }
+};
+
+struct Events {
+  hipEvent_t ev[5 * TUCKER_MAX_MODES] = {nullptr};
+  int n = 0;
+  ~Events() {
+    for (int i = 0; i < n; ++i) (void)hipEventDestroy(ev[i]);
+  }
+  hipError_t create(int count) {
+    for (; n < count; ++n) {
+      hipError_t e = hipEventCreate(&ev[n]);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
+};
+
+}  // namespace
+
+extern "C" {
+
+const char* tucker_last_error(void) { return g_err.c_str(); }
+const char* tucker_version(void) { return "tuckerhip 0.1 (gfx950)"; }
+
+tucker_status tucker_reconstruct_order(int N, const int64_t* ranks, const int64_t* out_sizes, int* order_out) {
+  if (!ranks || !out_sizes || !order_out) return fail(TUCKER_EINVAL, "NULL argument");
+  if (N < 1 || N > TUCKER_MAX_MODES) return fail(TUCKER_EINVAL, "N=%d outside 1..%d", N, TUCKER_MAX_MODES);
+  for (int k = 0; k < N; ++k)
+    if (ranks[k] < 1 || out_sizes[k] < 1) return fail(TUCKER_EINVAL, "sizes must be >= 1");
+  std::vector<int> ord(N);
+  std::iota(ord.begin(), ord.end(), 0);
+  // i before j iff K_i R_i R_j + K_i R_j K_j < R_i R_j K_j + R_i K_i K_j  (exact, 128-bit)
+  std::stable_sort(ord.begin(), ord.end(), [&](int i, int j) {
+    const __int128 Ri = ranks[i], Rj = ranks[j], Ki = out_sizes[i], Kj = out_sizes[j];
+    return Ki * Ri * Rj + Ki * Rj * Kj < Ri * Rj * Kj + Ri * Ki * Kj;
+  });
+  for (int k = 0; k < N; ++k) order_out[k] = ord[k];
+  return TUCKER_OK;
+}
+
+tucker_status tucker_sthosvd(const void* data, tucker_dtype dtype, const int64_t* dims, int N, double eps,
+                             const int* mode_order, tucker_gram_prec prec, hipStream_t stream, tucker_t** out) {
+  if (!out) return fail(TUCKER_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!data) return fail(TUCKER_EINVAL, "data is NULL");
+  if (dtype != TUCKER_F32 && dtype != TUCKER_F64) return fail(TUCKER_EINVAL, "bad dtype");
+  if (prec != TUCKER_GRAM_FP64 && prec != TUCKER_GRAM_FP32 && prec != TUCKER_GRAM_BF16X3)
+    return fail(TUCKER_EINVAL, "bad Gram precision");
+  if (prec != TUCKER_GRAM_FP64 && dtype != TUCKER_F32)
+    return fail(TUCKER_EINVAL, "mixed-precision Gram needs FP32 data");
+  if (!(eps >= 0.0) || !std::isfinite(eps)) return fail(TUCKER_EINVAL, "eps must be finite and >= 0");
+  tucker_status st = validate_dims(dims, N);
+  if (st) return st;
+  int order[TUCKER_MAX_MODES];
+  if ((st = validate_order(mode_order, N, order))) return st;
+  for (int k = 0; k < N; ++k)
+    if (dims[k] > kMaxEigJ)
+      return fail(TUCKER_EUNSUPPORTED, "mode %d has size %lld; the eigensolver supports up to %lld", k,
+                  (long long)dims[k], (long long)kMaxEigJ);
+  if ((st = ensure_device())) return st;
+
+  HandleGuard g(new tucker_t);
+  tucker_t* t = g.t;
+  t->N = N;
+  t->stream = stream;
+  std::memcpy(t->dims, dims, sizeof(int64_t) * N);
+  std::memcpy(t->order, order, sizeof(int) * N);
+  const tucker_dtype wdt = (prec == TUCKER_GRAM_FP64) ? TUCKER_F64 : TUCKER_F32;
+  t->core_dtype = wdt;
+  HIP_TRY(t->alloc((void**)&t->scalars, sizeof(double) * (2 + 2 * TUCKER_MAX_MODES)));
+  HIP_TRY(t->alloc((void**)&t->dranks, sizeof(int64_t) * TUCKER_MAX_MODES));
+  double* d_nx2 = t->scalars;
+  double* d_disc = t->scalars + 2;
+
+  void* hp = nullptr;
+  if ((st = pinned(&hp))) return st;
+  int64_t* h_R = static_cast<int64_t*>(hp);
+
+  Events evs;
+  HIP_TRY(evs.create(5 * N));
+
+  int64_t cur[TUCKER_MAX_MODES];
+  std::memcpy(cur, dims, sizeof(int64_t) * N);
+  const void* Y = data;
+  tucker_dtype ydt = dtype;
+  TmpBuf ybuf;  // owns Y after the first TTM (unless it became the core)
+  int64_t maxJ = 0;
+  for (int k = 0; k < N; ++k) maxJ = std::max(maxJ, dims[k]);
+  TmpBuf Sbuf, ewbuf;
+  HIP_TRY(Sbuf.alloc(sizeof(double) * maxJ * maxJ, stream));
+  HIP_TRY(ewbuf.alloc(sizeof(double) * tk::eig_work_doubles(maxJ), stream));
+  const double thr_mul = eps * eps / N;
+
+  for (int step = 0; step < N; ++step) {
+    const int n = order[step];
+    const int64_t J = cur[n];
+    hipEvent_t* ev = evs.ev + 5 * step;
+    HIP_TRY(hipEventRecord(ev[0], stream));
+    if ((st = run_gram(Y, ydt, cur, N, n, prec, Sbuf.as<double>(), step == 0 ? d_nx2 : nullptr, stream, ev[4])))
+      return st;
+    HIP_TRY(hipEventRecord(ev[1], stream));
+    HIP_TRY(t->alloc((void**)&t->U[n], sizeof(double) * J * J));
+    HIP_TRY(t->alloc((void**)&t->lam[n], sizeof(double) * J));
+    t->eigcount[n] = J;
+    tk::EigWork w;
+    tk::eig_work_carve(ewbuf.as<double>(), J, w);
+    HIP_TRY(tk::launch_eig_truncate(Sbuf.as<double>(), (int)J, thr_mul, d_nx2, w, t->lam[n], t->U[n],
+                                    t->dranks + n, d_disc + n, stream));
+    HIP_TRY(hipEventRecord(ev[2], stream));
+    HIP_TRY(hipMemcpyAsync(h_R, t->dranks + n, sizeof(int64_t), hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    const int64_t R = h_R[0];
+    if (R < 1 || R > J) return fail(TUCKER_ENOCONV, "eigensolver returned rank %lld for J=%lld", (long long)R, (long long)J);
+    if (step == 0) {
+      // non-finite data shows up as a non-finite norm
+      double nx2 = 0.0;
+      HIP_TRY(hipMemcpy(&nx2, d_nx2, sizeof(double), hipMemcpyDeviceToHost));
+      if (!std::isfinite(nx2)) return fail(TUCKER_EINVAL, "data contains non-finite values (||X||^2 = %g)", nx2);
+      t->norm2 = nx2;
+    }
+    t->ranks[n] = R;
+    // Y <- Y x_n U_n^T: M(k, j) = U[j + k*J]
+    int64_t total = 1;
+    for (int k = 0; k < N; ++k) total *= cur[k];
+    const int64_t next_elems = total / J * R;
+    TmpBuf nbuf;
+    HIP_TRY(nbuf.alloc(dtype_size(wdt) * next_elems, stream));
+    if ((st = run_ttm(Y, ydt, cur, N, n, t->U[n], R, J, 1, nbuf.p, wdt, stream))) return st;
+    HIP_TRY(hipEventRecord(ev[3], stream));
+    ybuf.release();  // stream-ordered: after the TTM that read it
+    ybuf.p = nbuf.p;
+    ybuf.s = stream;
+    nbuf.p = nullptr;
+    Y = ybuf.p;
+    ydt = wdt;
+    cur[n] = R;
+  }
+  // the last Y is the core; hand ownership to the handle
+  t->core = ybuf.p;
+  t->owned.push_back(ybuf.p);
+  ybuf.p = nullptr;
+  HIP_TRY(hipMemcpyAsync(t->disc, d_disc, sizeof(double) * N, hipMemcpyDeviceToHost, stream));
+  HIP_TRY(hipStreamSynchronize(stream));
+  for (int step = 0; step < N; ++step) {
+    const int n = order[step];
+    float a = 0, b = 0, c = 0, k = 0;
+    hipEvent_t* ev = evs.ev + 5 * step;
+    HIP_TRY(hipEventElapsedTime(&a, ev[0], ev[1]));
+    HIP_TRY(hipEventElapsedTime(&b, ev[1], ev[2]));
+    HIP_TRY(hipEventElapsedTime(&c, ev[2], ev[3]));
+    HIP_TRY(hipEventElapsedTime(&k, ev[0], ev[4]));
+    t->ms[4 * n + 0] = a;
+    t->ms[4 * n + 1] = b;
+    t->ms[4 * n + 2] = c;
+    t->ms[4 * n + 3] = k;
+  }
+  *out = g.take();
+  return TUCKER_OK;
+}
+
+int tucker_ndims(const tucker_t* t) { return t ? t->N : 0; }
+
+tucker_status tucker_dims(const tucker_t* t, int64_t* o) {
+  if (!t || !o) return fail(TUCKER_EINVAL, "NULL argument");
+  std::memcpy(o, t->dims, sizeof(int64_t) * t->N);
+  return TUCKER_OK;
+}
+
+tucker_status tucker_ranks(const tucker_t* t, int64_t* o) {
+  if (!t || !o) return fail(TUCKER_EINVAL, "NULL argument");
+  std::memcpy(o, t->ranks, sizeof(int64_t) * t->N);
+  return TUCKER_OK;
+}
+
+tucker_status tucker_mode_order(const tucker_t* t, int* o) {
+  if (!t || !o) return fail(TUCKER_EINVAL, "NULL argument");
+  std::memcpy(o, t->order, sizeof(int) * t->N);
+  return TUCKER_OK;
+}
+
+const void* tucker_core(const tucker_t* t, tucker_dtype* dt) {
+  if (!t) return nullptr;
+  if (dt) *dt = t->core_dtype;
+  return t->core;
+}
+
+const double* tucker_factor(const tucker_t* t, int n) {
+  if (!t || n < 0 || n >= t->N) return nullptr;
+  return t->U[n];
+}
+
+const double* tucker_eigenvalues(const tucker_t* t, int n, int64_t* count) {
+  if (!t || n < 0 || n >= t->N) return nullptr;
+  if (count) *count = t->eigcount[n];
+  return t->lam[n];
+}
+
+double tucker_norm2(const tucker_t* t) { return t ? t->norm2 : 0.0; }
+
+tucker_status tucker_discarded(const tucker_t* t, double* o) {
+  if (!t || !o) return fail(TUCKER_EINVAL, "NULL argument");
+  std::memcpy(o, t->disc, sizeof(double) * t->N);
+  return TUCKER_OK;
+}
+
+tucker_status tucker_timings(const tucker_t* t, double* o) {
+  if (!t || !o) return fail(TUCKER_EINVAL, "NULL argument");
+  std::memcpy(o, t->ms, sizeof(double) * 4 * t->N);
+  return TUCKER_OK;
+}
+
+void tucker_free(tucker_t* t) {
+  if (!t) return;
+  t->release();
+  delete t;
+}
+
+tucker_status tucker_reconstruct(const tucker_t* t, const int64_t* begin, const int64_t* end, const int* order,
+                                 void* out, tucker_dtype out_dtype, hipStream_t stream) {
+  if (!t) return fail(TUCKER_EINVAL, "handle is NULL");
+  if (!out) return fail(TUCKER_EINVAL, "out is NULL");
+  if (out_dtype != TUCKER_F32 && out_dtype != TUCKER_F64) return fail(TUCKER_EINVAL, "bad dtype");
+  const int N = t->N;
+  int64_t b[TUCKER_MAX_MODES], e[TUCKER_MAX_MODES], K[TUCKER_MAX_MODES];
+  for (int k = 0; k < N; ++k) {
+    b[k] = begin ? begin[k] : 0;
+    e[k] = end ? end[k] : t->dims[k];
+    if (b[k] < 0 || e[k] > t->dims[k] || b[k] >= e[k])
+      return fail(TUCKER_EINVAL, "mode %d range [%lld, %lld) invalid for size %lld", k, (long long)b[k],
+                  (long long)e[k], (long long)t->dims[k]);
+    K[k] = e[k] - b[k];
+  }
+  int ord[TUCKER_MAX_MODES];
+  tucker_status st;
+  if (order) {
+    if ((st = validate_order(order, N, ord))) return st;
+  } else if ((st = tucker_reconstruct_order(N, t->ranks, K, ord))) {
+    return st;
+  }
+  if ((st = ensure_device())) return st;
+  int64_t cur[TUCKER_MAX_MODES];
+  std::memcpy(cur, t->ranks, sizeof(int64_t) * N);
+  const void* Y = t->core;
+  tucker_dtype ydt = t->core_dtype;
+  TmpBuf a;
+  for (int step = 0; step < N; ++step) {
+    const int n = ord[step];
+    int64_t total = 1;
+    for (int k = 0; k < N; ++k) total *= cur[k];
+    const int64_t next = total / cur[n] * K[n];
+    const bool last = (step == N - 1);
+    void* Z = out;
+    tucker_dtype zdt = out_dtype;
+    TmpBuf nb;
+    if (!last) {
+      zdt = ydt;
+      HIP_TRY(nb.alloc(dtype_size(zdt) * next, stream));
+      Z = nb.p;
+    }
+    // M(k, j) = U_n[b_n + k, j]  (U_n is I_n x R_n column-major)
+    const double* M = t->U[n] + b[n];
+    if ((st = run_ttm(Y, ydt, cur, N, n, M, K[n], 1, t->dims[n], Z, zdt, stream))) return st;
+    a.release();
+    if (!last) {
+      a.p = nb.p;
+      a.s = stream;
+      nb.p = nullptr;
+      Y = a.p;
+      ydt = zdt;
+    }
+    cur[n] = K[n];
+  }
+  return TUCKER_OK;
+}
+
+tucker_status tucker_gram(const void* Y, tucker_dtype dtype, const int64_t* dims, int N, int n,
+                          tucker_gram_prec prec, double* S, double* norm2, hipStream_t stream) {
+  if (!Y || !S) return fail(TUCKER_EINVAL, "NULL pointer");
+  if (dtype != TUCKER_F32 && dtype != TUCKER_F64) return fail(TUCKER_EINVAL, "bad dtype");
+  tucker_status st = validate_dims(dims, N);
+  if (st) return st;
+  if (n < 0 || n >= N) return fail(TUCKER_EINVAL, "mode %d outside 0..%d", n, N - 1);
+  if (prec != TUCKER_GRAM_FP64 && prec != TUCKER_GRAM_FP32 && prec != TUCKER_GRAM_BF16X3)
+    return fail(TUCKER_EINVAL, "bad Gram precision");
+  if (prec != TUCKER_GRAM_FP64 && dtype != TUCKER_F32)
+    return fail(TUCKER_EINVAL, "mixed-precision Gram needs FP32 data");
+  if ((st = ensure_device())) return st;
+  return run_gram(Y, dtype, dims, N, n, prec, S, norm2, stream);
+}
+
+tucker_status tucker_eig_truncate(const double* S, int64_t J, double thr, double* lam, double* U, int64_t* R,
+                                  double* disc, hipStream_t stream) {
+  if (!S || !lam || !U || !R || !disc) return fail(TUCKER_EINVAL, "NULL pointer");
+  if (J < 1 || J > kMaxEigJ) return fail(TUCKER_EINVAL, "J=%lld outside 1..%lld", (long long)J, (long long)kMaxEigJ);
+  if (!(thr >= 0.0) || !std::isfinite(thr)) return fail(TUCKER_EINVAL, "thr must be finite and >= 0");
+  tucker_status st;
+  if ((st = ensure_device())) return st;
+  TmpBuf wb;
+  HIP_TRY(wb.alloc(sizeof(double) * tk::eig_work_doubles(J), stream));
+  tk::EigWork w;
+  tk::eig_work_carve(wb.as<double>(), J, w);
+  HIP_TRY(tk::launch_eig_truncate(S, (int)J, thr, nullptr, w, lam, U, R, disc, stream));
+  return TUCKER_OK;
+}
+
+tucker_status tucker_ttm(const void* Y, tucker_dtype ydtype, const int64_t* dims, int N, int n, const double* M,
+                         int64_t K, int64_t msk, int64_t msj, void* Z, tucker_dtype zdtype, hipStream_t stream) {
+  if (!Y || !M || !Z) return fail(TUCKER_EINVAL, "NULL pointer");
+  if ((ydtype != TUCKER_F32 && ydtype != TUCKER_F64) || (zdtype != TUCKER_F32 && zdtype != TUCKER_F64))
+    return fail(TUCKER_EINVAL, "bad dtype");
+  tucker_status st = validate_dims(dims, N);
+  if (st) return st;
+  if (n < 0 || n >= N) return fail(TUCKER_EINVAL, "mode %d outside 0..%d", n, N - 1);
+  if (K < 1) return fail(TUCKER_EINVAL, "K=%lld < 1", (long long)K);
+  if ((st = ensure_device())) return st;
+  return run_ttm(Y, ydtype, dims, N, n, M, K, msk, msj, Z, zdtype, stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,47 @@
+// Internal helpers shared by the HIP translation units of the library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace tk {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+// Number of XCDs on MI355X.  Workgroups are dispatched to XCDs round-robin by
+// linear workgroup id, so id w runs on XCD (w % 8).
+constexpr int kXcds = 8;
+
+// Remap a linear workgroup id so that work items with consecutive indices land
+// on the same XCD (and therefore share its L2).  `total` work items are spread
+// over `grid` >= total workgroups, grid a multiple of kXcds; returns -1 for
+// workgroups with no work.
+__device__ __forceinline__ int64_t xcd_remap(int64_t w, int64_t grid, int64_t total) {
+  const int64_t per = grid / kXcds;
+  const int64_t item = (w % kXcds) * per + (w / kXcds);
+  return item < total ? item : -1;
+}
+
+__host__ __device__ __forceinline__ int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+template <typename T>
+__device__ __forceinline__ double to_f64(T v) {
+  return static_cast<double>(v);
+}
+
+// Wave-wide (64 lanes) sum with butterfly shuffles; every lane gets the sum.
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+}  // namespace tk

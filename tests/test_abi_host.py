@@ -1,0 +1,143 @@
+"""Host-side checks of the C ABI: the library loads without a GPU, exports every
+function declared in include/tucker.h, rejects bad arguments before touching
+the device, and implements the flop-minimising Multi-TTM order rule of Sec. 8."""
+import ctypes
+import itertools
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+GOLDEN = os.path.join(ROOT, "tests", "golden")
+
+
+@pytest.fixture(scope="module")
+def tk():
+    import paper_1901_06043_amd as tk
+    if not os.path.exists(tk.LIB_PATH):
+        pytest.fail("libtuckerhip.so is not built (run __graft_entry__.build())")
+    tk.lib()
+    return tk
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "tucker.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(tucker_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_symbols_exported(tk):
+    names = declared_functions()
+    assert len(names) >= 15
+    L = tk.lib()
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(tk.EXPORTS)
+    assert b"gfx950" in L.tucker_version()
+
+
+def _read_recon():
+    vals = {}
+    for line in open(os.path.join(GOLDEN, "reconstruction_sp.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        tok = line.split()
+        vals[tok[0]] = [float(v) for v in tok[1:]]
+    return vals
+
+
+def _flops(order, R, K):
+    cur, f = list(R), 0
+    for n in order:
+        other = int(np.prod(cur)) // cur[n]
+        f += other * cur[n] * K[n]
+        cur[n] = K[n]
+    return f
+
+
+def test_reconstruct_order_reproduces_paper(tk):
+    """Sec. 9 partial reconstruction: the flop-minimising order is 43120 for the
+    SP High and Low cores; it also minimises over all 5! orders by brute force."""
+    g = _read_recon()
+    K = [int(v) for v in g["out"]]
+    for core in ("core_high", "core_low"):
+        R = [int(v) for v in g[core]]
+        order = tk.reconstruct_order(R, K)
+        assert order == [int(v) for v in g["best_order"]]
+        best = min(itertools.permutations(range(5)), key=lambda o: _flops(o, R, K))
+        assert _flops(order, R, K) == _flops(best, R, K)
+
+
+def test_reconstruction_intermediate_sizes_match_table(tk):
+    """Intermediate sizes (GB at 8 bytes/value) printed for orders 01234 and 43120."""
+    g = _read_recon()
+    R = [int(v) for v in g["core_high"]]
+    K = [int(v) for v in g["out"]]
+    for key, order in (("sizes_01234", [0, 1, 2, 3, 4]), ("sizes_43120", [4, 3, 1, 2, 0])):
+        cur = list(R)
+        sizes = [np.prod(cur) * 8 / 1e9]
+        for n in order:
+            cur[n] = K[n]
+            sizes.append(np.prod(cur) * 8 / 1e9)
+        for got, want in zip(sizes, g[key]):
+            if want == 0.01:
+                assert got < 0.01
+            else:
+                assert round(got, 2) == pytest.approx(want, abs=0.006)
+
+
+@pytest.mark.parametrize("seed", range(20))
+def test_reconstruct_order_is_flop_optimal_random(tk, seed):
+    rng = np.random.default_rng(seed)
+    N = int(rng.integers(1, 6))
+    R = [int(v) for v in rng.integers(1, 40, N)]
+    K = [int(v) for v in rng.integers(1, 60, N)]
+    order = tk.reconstruct_order(R, K)
+    assert sorted(order) == list(range(N))
+    best = min(_flops(o, R, K) for o in itertools.permutations(range(N)))
+    assert _flops(order, R, K) == best
+
+
+def test_sthosvd_rejects_bad_arguments_without_gpu(tk):
+    L = tk.lib()
+    h = ctypes.c_void_p(0)
+    dummy = ctypes.c_void_p(16)  # never dereferenced: validation precedes device work
+    dims = tk._i64([4, 5, 6])
+    E = 1
+    assert L.tucker_sthosvd(dummy, 1, dims, 0, 0.1, None, 0, None, ctypes.byref(h)) == E
+    assert L.tucker_sthosvd(dummy, 1, dims, 17, 0.1, None, 0, None, ctypes.byref(h)) == E
+    assert L.tucker_sthosvd(dummy, 1, tk._i64([4, 0, 6]), 3, 0.1, None, 0, None, ctypes.byref(h)) == E
+    assert L.tucker_sthosvd(dummy, 1, dims, 3, -1.0, None, 0, None, ctypes.byref(h)) == E
+    assert L.tucker_sthosvd(dummy, 1, dims, 3, float("nan"), None, 0, None, ctypes.byref(h)) == E
+    assert L.tucker_sthosvd(dummy, 1, dims, 3, float("inf"), None, 0, None, ctypes.byref(h)) == E
+    assert L.tucker_sthosvd(dummy, 1, dims, 3, 0.1, tk._i32([0, 0, 2]), 0, None, ctypes.byref(h)) == E
+    assert L.tucker_sthosvd(dummy, 1, dims, 3, 0.1, tk._i32([0, 1, 3]), 0, None, ctypes.byref(h)) == E
+    assert L.tucker_sthosvd(None, 1, dims, 3, 0.1, None, 0, None, ctypes.byref(h)) == E
+    assert L.tucker_sthosvd(dummy, 7, dims, 3, 0.1, None, 0, None, ctypes.byref(h)) == E
+    assert L.tucker_sthosvd(dummy, 1, dims, 3, 0.1, None, 9, None, ctypes.byref(h)) == E
+    # mixed-precision Gram needs FP32 data
+    assert L.tucker_sthosvd(dummy, 1, dims, 3, 0.1, None, 1, None, ctypes.byref(h)) == E
+    assert h.value is None
+    assert L.tucker_sthosvd(dummy, 1, dims, 3, -1.0, None, 0, None, ctypes.byref(h)) == E
+    assert b"eps" in L.tucker_last_error()
+
+
+def test_other_entry_points_reject_bad_arguments(tk):
+    L = tk.lib()
+    dummy = ctypes.c_void_p(16)
+    assert L.tucker_reconstruct(None, None, None, None, dummy, 1, None) == 1
+    assert L.tucker_gram(dummy, 1, tk._i64([3, 3]), 2, 2, 0, dummy, None, None) == 1
+    assert L.tucker_gram(dummy, 1, tk._i64([3, 3]), 2, 0, 2, dummy, None, None) == 1  # bf16x3 on f64 data
+    assert L.tucker_eig_truncate(dummy, 0, 0.0, dummy, dummy, dummy, dummy, None) == 1
+    assert L.tucker_eig_truncate(dummy, 2000, 0.0, dummy, dummy, dummy, dummy, None) == 1
+    assert L.tucker_eig_truncate(dummy, 4, -1.0, dummy, dummy, dummy, dummy, None) == 1
+    assert L.tucker_ttm(dummy, 1, tk._i64([3, 3]), 2, 0, dummy, 0, 1, 1, dummy, 1, None) == 1
+    assert L.tucker_reconstruct_order(0, None, None, None) == 1
+    o = (ctypes.c_int * 2)()
+    assert L.tucker_reconstruct_order(2, tk._i64([1, 0]), tk._i64([1, 1]), o) == 1
+    assert L.tucker_ndims(None) == 0
+    assert L.tucker_core(None, None) is None
+    assert L.tucker_factor(None, 0) is None
+    L.tucker_free(None)
