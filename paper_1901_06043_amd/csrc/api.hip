@@ -1,9 +1,10 @@
 // C ABI of the library (include/tucker.h): argument validation, the ST-HOSVD
 // mode loop of paper Alg. 1, Multi-TTM reconstruction of Sec. 8, and the
 // single-step entry points.  All device work is enqueued on the caller's
-// stream; device memory comes from the device's stream-ordered pool
-// (hipMallocAsync), whose release threshold is raised so that repeated calls
-// reuse memory instead of returning it to the driver.
+// stream.  Device memory comes from a caching allocator: a freed block is kept
+// and handed out again only for work on the stream that freed it, so stream
+// order makes the reuse safe without synchronisation; hipMalloc is called only
+// when no cached block fits.
 #include <algorithm>
 #include <cmath>
 #include <cstdarg>
@@ -44,7 +45,7 @@ tucker_status fail(tucker_status st, const char* fmt, ...) {
 
 size_t dtype_size(tucker_dtype t) { return t == TUCKER_F64 ? 8 : 4; }
 
-// Device checks and pool set-up, once per device.
+// Device checks, once per device.
 std::mutex g_dev_mu;
 bool g_dev_ok[64];
 bool g_dev_checked[64];
@@ -60,19 +61,90 @@ tucker_status ensure_device() {
     hipDeviceProp_t prop;
     HIP_TRY(hipGetDeviceProperties(&prop, dev));
     g_dev_ok[dev] = std::strncmp(prop.gcnArchName, "gfx950", 6) == 0;
-    if (g_dev_ok[dev]) {
-      hipMemPool_t pool;
-      if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
-        uint64_t thr = UINT64_MAX;
-        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
-      }
-    }
   }
   if (!g_dev_ok[dev]) return fail(TUCKER_EUNSUPPORTED, "device %d is not gfx950 (MI355X)", dev);
   return TUCKER_OK;
 }
 
-// Stream-ordered temporary device buffer.
+// ---------------------------------------------------------------- caching allocator
+struct CachedBlock {
+  void* p;
+  size_t bytes;
+  hipStream_t stream;
+  int dev;
+};
+std::mutex g_cache_mu;
+std::vector<CachedBlock> g_cache_free;                 // idle blocks
+std::vector<std::pair<void*, size_t>> g_cache_live;    // blocks in use and their sizes
+
+size_t round_bytes(size_t b) {
+  b = std::max<size_t>(b, 256);
+  const size_t g = (b >= (size_t(1) << 20)) ? (size_t(1) << 20) : 512;
+  return (b + g - 1) / g * g;
+}
+
+hipError_t dev_alloc(void** out, size_t bytes, hipStream_t s) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  bytes = round_bytes(bytes);
+  {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    int best = -1;
+    for (int i = 0; i < (int)g_cache_free.size(); ++i) {
+      const CachedBlock& b = g_cache_free[i];
+      if (b.dev != dev || b.stream != s || b.bytes < bytes || b.bytes > 2 * bytes + (size_t(4) << 20)) continue;
+      if (best < 0 || b.bytes < g_cache_free[best].bytes) best = i;
+    }
+    if (best >= 0) {
+      *out = g_cache_free[best].p;
+      g_cache_live.push_back({*out, g_cache_free[best].bytes});
+      g_cache_free.erase(g_cache_free.begin() + best);
+      return hipSuccess;
+    }
+  }
+  e = hipMalloc(out, bytes);
+  if (e == hipErrorOutOfMemory) {
+    // give idle cached blocks of this device back and retry once
+    (void)hipGetLastError();
+    std::vector<void*> drop;
+    {
+      std::lock_guard<std::mutex> lk(g_cache_mu);
+      for (int i = (int)g_cache_free.size() - 1; i >= 0; --i)
+        if (g_cache_free[i].dev == dev) {
+          drop.push_back(g_cache_free[i].p);
+          g_cache_free.erase(g_cache_free.begin() + i);
+        }
+    }
+    if (!drop.empty()) {
+      (void)hipDeviceSynchronize();
+      for (void* p : drop) (void)hipFree(p);
+      e = hipMalloc(out, bytes);
+    }
+  }
+  if (e == hipSuccess) {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    g_cache_live.push_back({*out, bytes});
+  }
+  return e;
+}
+
+// Return a block to the cache; it may be reused by later work on stream s.
+void dev_free(void* p, hipStream_t s) {
+  if (!p) return;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  for (size_t i = 0; i < g_cache_live.size(); ++i)
+    if (g_cache_live[i].first == p) {
+      g_cache_free.push_back({p, g_cache_live[i].second, s, dev});
+      g_cache_live[i] = g_cache_live.back();
+      g_cache_live.pop_back();
+      return;
+    }
+}
+
+// Temporary device buffer returned to the cache (stream-ordered) on scope exit.
 struct TmpBuf {
   void* p = nullptr;
   hipStream_t s = nullptr;
@@ -81,13 +153,13 @@ struct TmpBuf {
   TmpBuf& operator=(const TmpBuf&) = delete;
   ~TmpBuf() { release(); }
   void release() {
-    if (p) (void)hipFreeAsync(p, s);
+    if (p) dev_free(p, s);
     p = nullptr;
   }
   hipError_t alloc(size_t bytes, hipStream_t st) {
     release();
     s = st;
-    return hipMallocAsync(&p, std::max<size_t>(bytes, 256), st);
+    return dev_alloc(&p, bytes, st);
   }
   template <typename T>
   T* as() const {
@@ -217,16 +289,20 @@ struct tucker_t {
   hipStream_t stream = nullptr;
   std::vector<void*> owned;
 
-  hipError_t alloc(void** p, size_t bytes) {
-    hipError_t e = hipMallocAsync(p, std::max<size_t>(bytes, 256), stream);
-    if (e == hipSuccess) owned.push_back(*p);
-    return e;
-  }
-  void release() {
-    for (void* p : owned) (void)hipFreeAsync(p, stream);
-    owned.clear();
-  }
+  hipError_t alloc(void** p, size_t bytes);
+  void release();
 };
+
+hipError_t tucker_t::alloc(void** p, size_t bytes) {
+  hipError_t e = dev_alloc(p, bytes, stream);
+  if (e == hipSuccess) owned.push_back(*p);
+  return e;
+}
+
+void tucker_t::release() {
+  for (void* p : owned) dev_free(p, stream);
+  owned.clear();
+}
 
 namespace {
 

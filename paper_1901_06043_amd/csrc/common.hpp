@@ -24,11 +24,39 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t w, int64_t grid, int64_t to
   return item < total ? item : -1;
 }
 
+// Workgroup barrier that orders LDS only: unlike __syncthreads() it does not
+// wait for the wave's outstanding global-memory stores to complete.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 __host__ __device__ __forceinline__ int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 template <typename T>
 __device__ __forceinline__ double to_f64(T v) {
   return static_cast<double>(v);
+}
+
+// DPP lane permutation of a double (two 32-bit DPP moves).
+template <int CTRL>
+__device__ __forceinline__ double dpp64(double x) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum over each row of 16 lanes with VALU-only DPP steps: quad_perm xor 1,
+// quad_perm xor 2, half-row mirror, row mirror.  Every step adds two partial
+// sums that are bit-identical in the partner lanes, so all 16 lanes end with
+// the same rounded total.
+__device__ __forceinline__ double row16_sum(double x) {
+  x += dpp64<0xB1>(x);
+  x += dpp64<0x4E>(x);
+  x += dpp64<0x141>(x);
+  x += dpp64<0x140>(x);
+  return x;
 }
 
 // Wave-wide (64 lanes) sum with butterfly shuffles; every lane gets the sum.

@@ -6,13 +6,18 @@
 // The paper calls LAPACK syev on the CPU (Sec. 5.2) and notes that computing
 // all eigenvalues first and then only the leading eigenvectors is cheaper.
 // This GPU version does exactly that, with published methods:
-//  1. Householder reduction to tridiagonal form T = Q^T S Q (one workgroup;
-//     p = tau A v, w = p - (tau/2)(p.v) v, A <- A - v w^T - w v^T per step).
-//  2. All eigenvalues of T by Sturm-count bisection, here multisection: the P
-//     lanes of a group test P interior points at once (one group per eigenvalue).
+//  1. Householder reduction to tridiagonal form T = Q^T S Q.  Per step:
+//     p = tau A v, w = p - (tau/2)(p.v) v, A <- A - v w^T - w v^T.
+//     For J <= 256 one workgroup keeps the matrix in registers (16x16 blocks of
+//     the lower triangle spread over its waves) and reduces the symmetric
+//     matrix-vector partials through LDS in a fixed order, with barriers that
+//     order LDS only; larger J use a workgroup streaming the matrix through
+//     global memory.
+//  2. All eigenvalues of T by Sturm-count multisection: 32 lanes per
+//     eigenvalue test 32 interior points at once; many workgroups.
 //  3. Truncation: tail sums of the clamped eigenvalues from the smallest upward.
-//  4. Leading R eigenvectors of T by inverse iteration (tridiagonal LU with
-//     partial pivoting), one thread per vector; eigenvalues closer than
+//  4. Leading R eigenvectors of T by two steps of inverse iteration
+//     (tridiagonal LU with partial pivoting), one thread per vector; eigenvalues closer than
 //     1e-10 ||T|| are handled as one cluster by one thread with Gram-Schmidt
 //     inside the iteration.
 //  5. Re-orthogonalisation (classical Gram-Schmidt, twice) of each vector
@@ -45,7 +50,8 @@ __device__ __forceinline__ double block_sum_1024(double v, double* sred) {
   return s;
 }
 
-__device__ __forceinline__ double block_max_1024(double v, double* sred) {
+template <int NW>
+__device__ __forceinline__ double block_max(double v, double* sred) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
@@ -53,25 +59,159 @@ __device__ __forceinline__ double block_max_1024(double v, double* sred) {
   __syncthreads();
   double s = sred[0];
 #pragma unroll
-  for (int w = 1; w < 16; ++w) s = fmax(s, sred[w]);
+  for (int w = 1; w < NW; ++w) s = fmax(s, sred[w]);
   __syncthreads();
   return s;
 }
 
-__device__ __forceinline__ double block_min_1024(double v, double* sred) {
-  return -block_max_1024(-v, sred);
+// ---------------------------------------------------------------- 1a. tridiagonalisation, J <= 256
+// The full symmetric matrix is held in registers.  Each row of 16 lanes of a
+// wave holds one matrix row: lane l serves row slot l >> 4 and the columns
+// (l & 15) + 16 c, c < NC; wave w, group g, slot s holds row 4 (NW g + w) + s.
+// Every reduction (row sums, norms, dot products) is then a 16-lane DPP
+// reduction, bit-identical in all lanes, and the barriers order LDS only.
+// Row groups that are already reduced are skipped; reduced columns carry
+// v_j = w_j = 0 and are processed without branches.
+// Output: d, e, tau and, in row k of H, the Householder vector v_k at
+// positions k+2..J-1 (implicit 1 at k+1).
+constexpr int kRegMaxJ = 256;
+
+template <int NW, int NG, int NC>
+__device__ __forceinline__ void write_row(int k, int wave, int rs, int c, const double (&a)[NG][NC], double* sx) {
+  const int blk = k >> 2;
+  if (wave == blk % NW && rs == (k & 3)) {
+    const int gk = blk / NW;
+#pragma unroll
+    for (int g = 0; g < NG; ++g)
+      if (g == gk) {
+#pragma unroll
+        for (int cc = 0; cc < NC; ++cc) sx[c + 16 * cc] = a[g][cc];
+      }
+  }
 }
 
-// ---------------------------------------------------------------- 1. tridiagonalisation
-// A: J x J symmetric (row-major == column-major), overwritten.  On exit row k
-// holds the Householder vector v_k in positions k+2..J-1 (v_k has an implicit
-// 1 at position k+1); d, e, tau receive the tridiagonal and the reflector scalars.
+template <int NW, int NG, int NC>
+__global__ __launch_bounds__(64 * NW) void eig_tridiag_reg_kernel(const double* __restrict__ S, int J,
+                                                                  double* __restrict__ H, double* __restrict__ d,
+                                                                  double* __restrict__ e, double* __restrict__ tau) {
+  __shared__ double sx[16 * NC];  // column k of the current matrix
+  __shared__ double sp[16 * NC];  // p = tau A v
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int c = lane & 15, rs = lane >> 4;
+
+  double a[NG][NC];
+#pragma unroll
+  for (int g = 0; g < NG; ++g)
+#pragma unroll
+    for (int cc = 0; cc < NC; ++cc) {
+      const int i = 4 * (NW * g + wave) + rs, j = c + 16 * cc;
+      a[g][cc] = (i < J && j < J) ? S[(int64_t)i * J + j] : 0.0;
+    }
+  for (int j = tid; j < 16 * NC; j += 64 * NW) sp[j] = 0.0;
+  write_row<NW, NG, NC>(0, wave, rs, c, a, sx);
+  lds_barrier();
+
+  for (int k = 0; k + 2 < J; ++k) {
+    double part = 0.0;
+#pragma unroll
+    for (int cc = 0; cc < NC; ++cc) {
+      const int j = c + 16 * cc;
+      const double x = sx[j];
+      part += (j >= k + 2 && j < J) ? x * x : 0.0;
+    }
+    const double sigma = row16_sum(part);
+    const double alpha = sx[k + 1];
+    double beta = alpha, tk = 0.0;
+    if (sigma != 0.0) {
+      beta = -copysign(sqrt(alpha * alpha + sigma), alpha);
+      tk = (beta - alpha) / beta;
+    }
+    const double scale = (tk != 0.0) ? 1.0 / (alpha - beta) : 0.0;
+    if (tid == 0) {
+      d[k] = sx[k];
+      e[k] = beta;
+      tau[k] = tk;
+    }
+    if (wave == 0)
+      for (int j = k + 2 + lane; j < J; j += 64) H[(int64_t)k * J + j] = sx[j] * scale;
+    if (tk == 0.0) {
+      lds_barrier();
+      write_row<NW, NG, NC>(k + 1, wave, rs, c, a, sx);
+      lds_barrier();
+      continue;
+    }
+    double vj[NC];
+#pragma unroll
+    for (int cc = 0; cc < NC; ++cc) {
+      const int j = c + 16 * cc;
+      vj[cc] = (j <= k || j >= J) ? 0.0 : (j == k + 1 ? 1.0 : sx[j] * scale);
+    }
+    // p_i = tau * sum_j a_ij v_j
+#pragma unroll
+    for (int g = 0; g < NG; ++g) {
+      const int i = 4 * (NW * g + wave) + rs;
+      if (4 * (NW * g + wave) + 3 <= k) {  // whole group reduced (uniform): p = 0 there
+        if (c == 0 && i < J) sp[i] = 0.0;
+        continue;
+      }
+      // columns <= k have v_j = 0 and contribute nothing
+      double t = 0.0;
+#pragma unroll
+      for (int cc = 0; cc < NC; ++cc) t += a[g][cc] * vj[cc];
+      t = row16_sum(t);
+      if (c == 0 && i < J) sp[i] = (i > k) ? tk * t : 0.0;
+    }
+    lds_barrier();
+    double pv = 0.0;
+#pragma unroll
+    for (int cc = 0; cc < NC; ++cc) pv += sp[c + 16 * cc] * vj[cc];
+    pv = row16_sum(pv);
+    const double c2 = 0.5 * tk * pv;
+    // A <- A - v w^T - w v^T on the live rows and column slots, w = p - c2 v
+#pragma unroll
+    for (int g = 0; g < NG; ++g) {
+      if (4 * (NW * g + wave) + 3 <= k) continue;  // uniform
+      const int i = 4 * (NW * g + wave) + rs;
+      const double vi = (i <= k || i >= J) ? 0.0 : (i == k + 1 ? 1.0 : sx[i] * scale);
+      const double wi = (i < J) ? sp[i] - c2 * vi : 0.0;
+#pragma unroll
+      for (int cc = 0; cc < NC; ++cc) {
+        const double wj = sp[c + 16 * cc] - c2 * vj[cc];  // w_j; zero for reduced columns
+        a[g][cc] = fma(-vi, wj, fma(-wi, vj[cc], a[g][cc]));
+      }
+    }
+    lds_barrier();
+    write_row<NW, NG, NC>(k + 1, wave, rs, c, a, sx);
+    lds_barrier();
+  }
+  if (J >= 2) {
+    if (tid == 0) {
+      d[J - 2] = sx[J - 2];
+      e[J - 2] = sx[J - 1];
+    }
+    const int k = J - 1, blk = k >> 2;
+    if (wave == blk % NW && rs == (k & 3) && c == (k & 15)) {
+      const int gk = blk / NW, ck = k >> 4;
+#pragma unroll
+      for (int g = 0; g < NG; ++g)
+#pragma unroll
+        for (int cc = 0; cc < NC; ++cc)
+          if (g == gk && cc == ck) d[k] = a[g][cc];
+    }
+  } else if (tid == 0) {
+    d[0] = sx[0];
+  }
+}
+
+// ---------------------------------------------------------------- 1b. tridiagonalisation, any J
+// A: J x J symmetric in global memory, overwritten; row k receives v_k.
 __global__ __launch_bounds__(kEigThreads) void eig_tridiag_kernel(double* __restrict__ A, int J,
                                                                   double* __restrict__ d, double* __restrict__ e,
                                                                   double* __restrict__ tau) {
   extern __shared__ double sh[];
-  double* sv = sh;          // J
-  double* sp = sh + J;      // J
+  double* sv = sh;            // J
+  double* sp = sh + J;        // J
   double* sred = sh + 2 * J;  // 16
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   for (int k = 0; k + 2 < J; ++k) {
@@ -107,7 +247,6 @@ __global__ __launch_bounds__(kEigThreads) void eig_tridiag_kernel(double* __rest
       if (i >= 1) A[(int64_t)k * J + k + 1 + i] = v;
     }
     __syncthreads();
-    // p = tau * A22 v
     for (int i = wave; i < m; i += 16) {
       const double* row = A + (int64_t)(k + 1 + i) * J + (k + 1);
       double s = 0.0;
@@ -122,7 +261,6 @@ __global__ __launch_bounds__(kEigThreads) void eig_tridiag_kernel(double* __rest
     const double cc = 0.5 * tk * pv;
     for (int i = tid; i < m; i += kEigThreads) sp[i] -= cc * sv[i];
     __syncthreads();
-    // A22 <- A22 - v w^T - w v^T
     for (int i = wave; i < m; i += 16) {
       double* row = A + (int64_t)(k + 1 + i) * J + (k + 1);
       const double vi = sv[i], wi = sp[i];
@@ -141,22 +279,16 @@ __global__ __launch_bounds__(kEigThreads) void eig_tridiag_kernel(double* __rest
   }
 }
 
-// ---------------------------------------------------------------- 2-3. eigenvalues + truncation
-// scal[0] <- ||T|| (Gershgorin bound), scal[1] <- pivmin.
-// The truncation threshold is thr, or thr * (*nx2) when nx2 is non-null (so
-// that eps^2 ||X||^2 / N can be formed on the device without a host round trip).
-__global__ __launch_bounds__(kEigThreads) void eig_bisect_kernel(const double* __restrict__ d,
-                                                                 const double* __restrict__ e, int J, double thr,
-                                                                 const double* __restrict__ nx2,
-                                                                 double* __restrict__ lam, int64_t* __restrict__ Rout,
-                                                                 double* __restrict__ disc, double* __restrict__ scal) {
-  extern __shared__ double sh[];
-  double* sd = sh;          // J
-  double* se2 = sh + J;     // J
-  double* sred = sh + 2 * J;  // 16
-  const int tid = threadIdx.x, lane = tid & 63;
+// ---------------------------------------------------------------- 2. eigenvalues
+// Gershgorin interval and pivmin; every bisection workgroup recomputes them.
+struct TriBounds {
+  double glo, ghi, pivmin, tnorm, atol;
+};
+
+__device__ TriBounds tri_bounds(const double* __restrict__ d, const double* __restrict__ e, int J, double* sd,
+                                double* se2, double* sred) {
   double glo = DBL_MAX, ghi = -DBL_MAX, e2max = 0.0;
-  for (int i = tid; i < J; i += kEigThreads) {
+  for (int i = threadIdx.x; i < J; i += blockDim.x) {
     const double di = d[i];
     const double em = (i > 0) ? fabs(e[i - 1]) : 0.0;
     const double ep = (i + 1 < J) ? fabs(e[i]) : 0.0;
@@ -166,67 +298,92 @@ __global__ __launch_bounds__(kEigThreads) void eig_bisect_kernel(const double* _
     glo = fmin(glo, di - em - ep);
     ghi = fmax(ghi, di + em + ep);
   }
-  glo = block_min_1024(glo, sred);
-  ghi = block_max_1024(ghi, sred);
-  e2max = block_max_1024(e2max, sred);
-  const double pivmin = DBL_MIN * fmax(1.0, e2max);
-  const double tnorm = fmax(fabs(glo), fabs(ghi));
-  const double widen = 2.1 * DBL_EPSILON * tnorm * J + 4.2 * pivmin;
-  glo -= widen;
-  ghi += widen;
-  const double atol = 2.0 * DBL_EPSILON * tnorm + 4.0 * pivmin;
+  TriBounds b;
+  glo = -block_max<4>(-glo, sred);
+  ghi = block_max<4>(ghi, sred);
+  e2max = block_max<4>(e2max, sred);
+  b.pivmin = DBL_MIN * fmax(1.0, e2max);
+  b.tnorm = fmax(fabs(glo), fabs(ghi));
+  const double widen = 2.1 * DBL_EPSILON * b.tnorm * J + 4.2 * b.pivmin;
+  b.glo = glo - widen;
+  b.ghi = ghi + widen;
+  b.atol = 2.0 * DBL_EPSILON * b.tnorm + 4.0 * b.pivmin;
+  return b;
+}
 
-  // group size P: power of two, P * J <= 1024, P <= 32
-  int P = 1;
-  while (P < 32 && 2 * P * J <= kEigThreads) P *= 2;
-  const int G = kEigThreads / P;
-  const int q = tid % P, gbase = (lane / P) * P;
-  const uint64_t gmask = (P == 64) ? ~0ull : ((1ull << P) - 1ull);
-  for (int a = tid / P; a < J; a += G) {
-    double lo = glo, hi = ghi;
-    for (int it = 0; it < 128 && (hi - lo) > atol; ++it) {
-      const double h = (hi - lo) / (P + 1);
-      const double sig = lo + h * (q + 1);
-      // Sturm count: number of eigenvalues < sig
-      int cnt = 0;
-      double qq = sd[0] - sig;
-      if (fabs(qq) < pivmin) qq = -pivmin;
-      cnt += (qq < 0.0);
-      for (int i = 1; i < J; ++i) {
-        qq = (sd[i] - sig) - se2[i - 1] / qq;
-        if (fabs(qq) < pivmin) qq = -pivmin;
-        cnt += (qq < 0.0);
-      }
-      const uint64_t bal = __ballot(cnt > a);
-      const uint64_t m = (bal >> gbase) & gmask;
-      const int f = m ? (__ffsll((long long)m) - 1) : P;
-      const double nlo = (f == 0) ? lo : lo + h * f;
-      const double nhi = (f == P) ? hi : lo + h * (f + 1);
-      lo = nlo;
-      hi = nhi;
-    }
-    if (q == 0) lam[J - 1 - a] = 0.5 * (lo + hi);
+// number of eigenvalues of T below sig (Sturm count of T - sig I)
+__device__ __forceinline__ int sturm_count(const double* sd, const double* se2, int J, double sig, double pivmin) {
+  int cnt = 0;
+  double q = sd[0] - sig;
+  if (fabs(q) < pivmin) q = -pivmin;
+  cnt += (q < 0.0);
+  for (int i = 1; i < J; ++i) {
+    // 1/q by the hardware reciprocal refined with one Newton step
+    double rq = __builtin_amdgcn_rcp(q);
+    rq = fma(rq, fma(-q, rq, 1.0), rq);
+    q = (sd[i] - sig) - se2[i - 1] * rq;
+    if (fabs(q) < pivmin) q = -pivmin;
+    cnt += (q < 0.0);
   }
-  __syncthreads();
-  if (tid == 0) {
-    scal[0] = tnorm;
-    scal[1] = pivmin;
-    if (nx2 != nullptr) thr *= *nx2;
-    // smallest R in 1..J with sum_{i>=R} max(lam_i, 0) <= thr (lam descending)
-    double tail = 0.0, tailR = 0.0;
-    int R = J;
-    for (int r = J - 1; r >= 1; --r) {
-      tail += fmax(lam[r], 0.0);
-      if (tail <= thr) {
-        R = r;
-        tailR = tail;
-      } else {
-        break;
-      }
-    }
-    *Rout = R;
-    *disc = tailR;
+  return cnt;
+}
+
+// 256 threads: 8 eigenvalues per workgroup, 32 lanes each.
+constexpr int kBisLanes = 32;
+__global__ __launch_bounds__(256) void eig_bisect_kernel(const double* __restrict__ d, const double* __restrict__ e,
+                                                         int J, double* __restrict__ lam,
+                                                         double* __restrict__ scal) {
+  extern __shared__ double sh[];
+  double* sd = sh;            // J
+  double* se2 = sh + J;       // J
+  double* sred = sh + 2 * J;  // 4
+  const TriBounds b = tri_bounds(d, e, J, sd, se2, sred);
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int q = lane & (kBisLanes - 1), gbase = lane & ~(kBisLanes - 1);
+  const int a = blockIdx.x * (256 / kBisLanes) + tid / kBisLanes;  // ascending index
+  if (blockIdx.x == 0 && tid == 0) {
+    scal[0] = b.tnorm;
+    scal[1] = b.pivmin;
   }
+  if (a >= J) return;
+  double lo = b.glo, hi = b.ghi;
+  for (int it = 0; it < 64 && (hi - lo) > b.atol; ++it) {
+    const double h = (hi - lo) / (kBisLanes + 1);
+    const double sig = lo + h * (q + 1);
+    const int cnt = sturm_count(sd, se2, J, sig, b.pivmin);
+    const uint64_t bal = __ballot(cnt > a);
+    const uint64_t m = (bal >> gbase) & 0xffffffffull;
+    const int f = m ? (__ffsll((long long)m) - 1) : kBisLanes;
+    const double nlo = (f == 0) ? lo : lo + h * f;
+    const double nhi = (f == kBisLanes) ? hi : lo + h * (f + 1);
+    lo = nlo;
+    hi = nhi;
+  }
+  if (q == 0) lam[J - 1 - a] = 0.5 * (lo + hi);
+}
+
+// ---------------------------------------------------------------- 3. truncation
+// The threshold is thr, or thr * (*nx2) when nx2 is non-null (so that
+// eps^2 ||X||^2 / N is formed on the device without a host round trip).
+__global__ void eig_truncate_kernel(const double* __restrict__ lam, int J, double thr,
+                                    const double* __restrict__ nx2, int64_t* __restrict__ Rout,
+                                    double* __restrict__ disc) {
+  if (threadIdx.x != 0) return;
+  if (nx2 != nullptr) thr *= *nx2;
+  // smallest R in 1..J with sum_{i>=R} max(lam_i, 0) <= thr (lam descending)
+  double tail = 0.0, tailR = 0.0;
+  int R = J;
+  for (int r = J - 1; r >= 1; --r) {
+    tail += fmax(lam[r], 0.0);
+    if (tail <= thr) {
+      R = r;
+      tailR = tail;
+    } else {
+      break;
+    }
+  }
+  *Rout = R;
+  *disc = tailR;
 }
 
 // ---------------------------------------------------------------- 4. inverse iteration
@@ -241,6 +398,8 @@ __device__ __forceinline__ double hash_unit(uint32_t a, uint32_t b) {
 }
 
 // work layout: array a (0..5), element i, thread slot t  ->  work[(a*J + i)*ld + t]
+// arrays: 0 multipliers l_i, 1 reciprocal pivots 1/u_ii, 2 u_{i,i+1}, 3 u_{i,i+2},
+//         4 row-interchange flags, 5 the iterate.
 __global__ __launch_bounds__(64) void eig_invit_kernel(const double* __restrict__ d, const double* __restrict__ e, int J,
                                                        const double* __restrict__ lam, const int64_t* __restrict__ Rp,
                                                        const double* __restrict__ scal, double* __restrict__ Zt,
@@ -252,19 +411,18 @@ __global__ __launch_bounds__(64) void eig_invit_kernel(const double* __restrict_
   const double ctol = 1e-10 * tnorm;
   if (t > 0 && lam[t - 1] - lam[t] <= ctol) return;  // handled by its cluster leader
   if (tnorm == 0.0) {
-    // zero matrix: unit vectors
     for (int vec = t; vec < R && (vec == t || lam[vec - 1] - lam[vec] <= ctol); ++vec)
       for (int i = 0; i < J; ++i) Zt[(int64_t)vec * J + i] = (i == vec) ? 1.0 : 0.0;
     return;
   }
   const double inv = 1.0 / tnorm;
   const double eps = DBL_EPSILON;
-  double* dl = work + (int64_t)0 * J * ld + t;
-  double* dd = work + (int64_t)1 * J * ld + t;
-  double* du = work + (int64_t)2 * J * ld + t;
-  double* du2 = work + (int64_t)3 * J * ld + t;
-  double* pv = work + (int64_t)4 * J * ld + t;
-  double* x = work + (int64_t)5 * J * ld + t;
+  double* Wl = work + (int64_t)0 * J * ld + t;
+  double* Wr = work + (int64_t)1 * J * ld + t;
+  double* W1 = work + (int64_t)2 * J * ld + t;
+  double* W2 = work + (int64_t)3 * J * ld + t;
+  double* Wp = work + (int64_t)4 * J * ld + t;
+  double* Wx = work + (int64_t)5 * J * ld + t;
 #define W(arr, i) arr[(int64_t)(i) * ld]
   double prev_shift = 0.0;
   for (int vec = t; vec < R; ++vec) {
@@ -272,85 +430,88 @@ __global__ __launch_bounds__(64) void eig_invit_kernel(const double* __restrict_
     double shift = lam[vec] * inv;
     if (vec > t && prev_shift - shift < 10.0 * eps) shift = prev_shift - 10.0 * eps;
     prev_shift = shift;
-    // LU with partial pivoting of (T - lambda I) / ||T||
-    for (int i = 0; i < J; ++i) {
-      W(dd, i) = d[i] * inv - shift;
-      W(dl, i) = (i + 1 < J) ? e[i] * inv : 0.0;
-      W(du, i) = (i + 1 < J) ? e[i] * inv : 0.0;
-      W(du2, i) = 0.0;
-    }
+    // LU with partial pivoting of (T - lambda I)/||T||; the running row (pivot
+    // candidate dd, its superdiagonal du) is carried in registers.
+    double dd = d[0] * inv - shift;
+    double du = (J > 1) ? e[0] * inv : 0.0;
     for (int i = 0; i + 1 < J; ++i) {
-      const double di = W(dd, i), li = W(dl, i);
-      if (fabs(di) >= fabs(li)) {
-        W(pv, i) = 0.0;
-        const double f = (di != 0.0) ? li / di : 0.0;
-        W(dl, i) = f;
-        W(dd, i + 1) = W(dd, i + 1) - f * W(du, i);
+      const double li = e[i] * inv;                                // subdiagonal below the pivot
+      const double dn = d[i + 1] * inv - shift;                    // next diagonal
+      const double un = (i + 2 < J) ? e[i + 1] * inv : 0.0;        // next superdiagonal
+      double piv, u1, u2, f, ndd, ndu;
+      if (fabs(dd) >= fabs(li)) {
+        piv = 0.0;
+        f = (dd != 0.0) ? li / dd : 0.0;
+        u1 = du;
+        u2 = 0.0;
+        ndd = dn - f * du;
+        ndu = un;
       } else {
-        W(pv, i) = 1.0;
-        const double f = di / li;
-        const double ddn = W(dd, i + 1), dui = W(du, i);
-        W(dd, i) = li;
-        W(dl, i) = f;
-        W(du, i) = ddn;
-        W(dd, i + 1) = dui - f * ddn;
-        if (i + 2 < J) {
-          const double dun = W(du, i + 1);
-          W(du2, i) = dun;
-          W(du, i + 1) = -f * dun;
-        }
+        piv = 1.0;
+        f = dd / li;
+        const double p = li;
+        u1 = dn;
+        u2 = un;
+        ndd = du - f * dn;
+        ndu = -f * un;
+        dd = p;
       }
+      if (fabs(dd) < eps) dd = (dd < 0.0) ? -eps : eps;
+      W(Wl, i) = f;
+      W(Wr, i) = 1.0 / dd;
+      W(W1, i) = u1;
+      W(W2, i) = u2;
+      W(Wp, i) = piv;
+      dd = ndd;
+      du = ndu;
     }
-    for (int i = 0; i < J; ++i)
-      if (fabs(W(dd, i)) < eps) W(dd, i) = (W(dd, i) < 0.0) ? -eps : eps;
+    if (fabs(dd) < eps) dd = (dd < 0.0) ? -eps : eps;
+    W(Wr, J - 1) = 1.0 / dd;
+    W(W1, J - 1) = 0.0;
+    W(W2, J - 1) = 0.0;
     // start vector
-    double nrm = 0.0;
-    for (int i = 0; i < J; ++i) {
-      const double v = hash_unit((uint32_t)i, (uint32_t)vec);
-      W(x, i) = v;
-      nrm += v * v;
-    }
-    for (int it = 0; it < 3; ++it) {
-      // forward: row interchanges and multipliers
+    for (int i = 0; i < J; ++i) W(Wx, i) = hash_unit((uint32_t)i, (uint32_t)vec);
+    double xscale = 1.0;
+    for (int it = 0; it < 2; ++it) {
+      // forward: row interchanges and multipliers (x scaled on the fly)
+      double cur = W(Wx, 0) * xscale;
+#pragma unroll 16
       for (int i = 0; i + 1 < J; ++i) {
-        if (W(pv, i) != 0.0) {
-          const double tmp = W(x, i);
-          W(x, i) = W(x, i + 1);
-          W(x, i + 1) = tmp;
+        double nxt = W(Wx, i + 1) * xscale;
+        if (W(Wp, i) != 0.0) {
+          const double tmp = cur;
+          cur = nxt;
+          nxt = tmp;
         }
-        W(x, i + 1) = W(x, i + 1) - W(dl, i) * W(x, i);
+        nxt -= W(Wl, i) * cur;
+        W(Wx, i) = cur;
+        cur = nxt;
       }
-      // backward substitution with U (diag dd, superdiagonals du, du2)
-      double y1 = 0.0, y2 = 0.0;
+      W(Wx, J - 1) = cur;
+      // backward substitution with U
+      double y1 = 0.0, y2 = 0.0, nrm = 0.0;
+#pragma unroll 16
       for (int i = J - 1; i >= 0; --i) {
-        double s = W(x, i);
-        if (i + 1 < J) s -= W(du, i) * y1;
-        if (i + 2 < J) s -= W(du2, i) * y2;
-        const double yi = s / W(dd, i);
-        W(x, i) = yi;
+        const double yi = (W(Wx, i) - W(W1, i) * y1 - W(W2, i) * y2) * W(Wr, i);
+        W(Wx, i) = yi;
+        nrm += yi * yi;
         y2 = y1;
         y1 = yi;
       }
-      // Gram-Schmidt against the finished members of this cluster
-      for (int j = t; j < vec; ++j) {
-        const double* zj = Zt + (int64_t)j * J;
-        double h = 0.0;
-        for (int i = 0; i < J; ++i) h += zj[i] * W(x, i);
-        for (int i = 0; i < J; ++i) W(x, i) = W(x, i) - h * zj[i];
+      if (vec > t) {
+        // Gram-Schmidt against the finished members of this cluster
+        for (int j = t; j < vec; ++j) {
+          const double* zj = Zt + (int64_t)j * J;
+          double h = 0.0;
+          for (int i = 0; i < J; ++i) h += zj[i] * W(Wx, i);
+          for (int i = 0; i < J; ++i) W(Wx, i) = W(Wx, i) - h * zj[i];
+        }
+        nrm = 0.0;
+        for (int i = 0; i < J; ++i) nrm += W(Wx, i) * W(Wx, i);
       }
-      nrm = 0.0;
-      double amax = 0.0;
-      for (int i = 0; i < J; ++i) amax = fmax(amax, fabs(W(x, i)));
-      const double sc = (amax > 0.0) ? 1.0 / amax : 1.0;
-      for (int i = 0; i < J; ++i) {
-        const double v = W(x, i) * sc;
-        W(x, i) = v;
-        nrm += v * v;
-      }
-      const double rn = 1.0 / sqrt(nrm);
-      for (int i = 0; i < J; ++i) W(x, i) = W(x, i) * rn;
+      xscale = 1.0 / sqrt(nrm);
     }
-    for (int i = 0; i < J; ++i) Zt[(int64_t)vec * J + i] = W(x, i);
+    for (int i = 0; i < J; ++i) Zt[(int64_t)vec * J + i] = W(Wx, i) * xscale;
   }
 #undef W
 }
@@ -361,8 +522,8 @@ __global__ __launch_bounds__(kEigThreads) void eig_orth_kernel(double* __restric
                                                                const int64_t* __restrict__ Rp,
                                                                const double* __restrict__ scal) {
   extern __shared__ double sh[];
-  double* hs = sh;           // J
-  double* sred = sh + J;     // 16
+  double* hs = sh;        // J
+  double* sred = sh + J;  // 16
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int R = (int)*Rp;
   const double otol = 1e-2 * scal[0];
@@ -398,29 +559,42 @@ __global__ __launch_bounds__(kEigThreads) void eig_orth_kernel(double* __restric
 
 // ---------------------------------------------------------------- 6. back-transformation + signs
 template <int Q>
-__global__ __launch_bounds__(256) void eig_back_kernel(const double* __restrict__ A, const double* __restrict__ tau,
+__global__ __launch_bounds__(256) void eig_back_kernel(const double* __restrict__ H, const double* __restrict__ tau,
                                                        int J, const double* __restrict__ Zt,
                                                        const int64_t* __restrict__ Rp, double* __restrict__ U) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int vec = blockIdx.x * 4 + wave;
   if (vec >= (int)*Rp) return;
-  double z[Q], v[Q];
+  double z[Q], v[Q], vn[Q];
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
     const int r = lane + 64 * q;
     z[q] = (r < J) ? Zt[(int64_t)vec * J + r] : 0.0;
   }
-  for (int k = J - 3; k >= 0; --k) {
-    const double tk = tau[k];
-    if (tk == 0.0) continue;
-    double s = 0.0;
+  auto load_v = [&](int k, double* dst) {
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
       const int r = lane + 64 * q;
-      const double vq = (r == k + 1) ? 1.0 : ((r > k + 1 && r < J) ? A[(int64_t)k * J + r] : 0.0);
-      v[q] = vq;
-      s += vq * z[q];
+      dst[q] = (r == k + 1) ? 1.0 : ((r > k + 1 && r < J) ? H[(int64_t)k * J + r] : 0.0);
     }
+  };
+  double tn = 0.0;
+  if (J >= 3) {
+    load_v(J - 3, vn);
+    tn = tau[J - 3];
+  }
+  for (int k = J - 3; k >= 0; --k) {
+    const double tk = tn;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) v[q] = vn[q];
+    if (k > 0) {  // prefetch the next reflector, independent of z
+      load_v(k - 1, vn);
+      tn = tau[k - 1];
+    }
+    if (tk == 0.0) continue;
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) s += v[q] * z[q];
     s = wave_sum(s) * tk;
 #pragma unroll
     for (int q = 0; q < Q; ++q) z[q] -= s * v[q];
@@ -477,12 +651,28 @@ void eig_work_carve(double* base, int64_t J, EigWork& w) {
 
 hipError_t launch_eig_truncate(const double* S, int J, double thr, const double* nx2, const EigWork& w,
                                double* lam, double* U, int64_t* R, double* disc, hipStream_t stream) {
-  hipError_t err = hipMemcpyAsync(w.A, S, sizeof(double) * (size_t)J * J, hipMemcpyDeviceToDevice, stream);
-  if (err != hipSuccess) return err;
-  const size_t sh2 = sizeof(double) * (2 * (size_t)J + 16);
-  hipLaunchKernelGGL(eig_tridiag_kernel, dim3(1), dim3(kEigThreads), sh2, stream, w.A, J, w.d, w.e, w.tau);
-  hipLaunchKernelGGL(eig_bisect_kernel, dim3(1), dim3(kEigThreads), sh2, stream, w.d, w.e, J, thr, nx2, lam, R,
-                     disc, w.scal);
+  if (J <= kRegMaxJ) {
+#define TRI_LAUNCH(NW, NG, NC)                                                                                 \
+  hipLaunchKernelGGL((eig_tridiag_reg_kernel<NW, NG, NC>), dim3(1), dim3(64 * NW), 0, stream, S, J, w.A, w.d, \
+                     w.e, w.tau)
+    // rows: 4 * NW * NG >= J; columns: 16 * NC >= J
+    if (J <= 64) TRI_LAUNCH(16, 1, 4);
+    else if (J <= 128) TRI_LAUNCH(16, 2, 8);
+    else if (J <= 192) TRI_LAUNCH(8, 6, 12);
+    else if (J <= 208) TRI_LAUNCH(4, 13, 13);
+    else if (J <= 224) TRI_LAUNCH(8, 7, 14);
+    else TRI_LAUNCH(8, 8, 16);
+#undef TRI_LAUNCH
+  } else {
+    hipError_t err = hipMemcpyAsync(w.A, S, sizeof(double) * (size_t)J * J, hipMemcpyDeviceToDevice, stream);
+    if (err != hipSuccess) return err;
+    const size_t sh2 = sizeof(double) * (2 * (size_t)J + 16);
+    hipLaunchKernelGGL(eig_tridiag_kernel, dim3(1), dim3(kEigThreads), sh2, stream, w.A, J, w.d, w.e, w.tau);
+  }
+  const size_t shb = sizeof(double) * (2 * (size_t)J + 4);
+  hipLaunchKernelGGL(eig_bisect_kernel, dim3(ceil_div(J, 256 / kBisLanes)), dim3(256), shb, stream, w.d, w.e, J,
+                     lam, w.scal);
+  hipLaunchKernelGGL(eig_truncate_kernel, dim3(1), dim3(64), 0, stream, lam, J, thr, nx2, R, disc);
   hipLaunchKernelGGL(eig_invit_kernel, dim3(ceil_div(J, 64)), dim3(64), 0, stream, w.d, w.e, J, lam, R, w.scal,
                      w.Zt, w.work, J);
   const size_t sh1 = sizeof(double) * ((size_t)J + 16);
