@@ -211,6 +211,176 @@ __global__ __launch_bounds__(256) void gram_reduce_kernel(const double* __restri
   S[(int64_t)b * J + a] = s;
 }
 
+// ---------------------------------------------------------------- J <= 256: whole triangle per workgroup
+// One workgroup of 8 waves computes every upper-triangle 16x16 block of S for
+// a contiguous range of column chunks, so each value of Y is read from HBM
+// once.  The flattened block list (row-major over bi <= bj) is cut into 8
+// contiguous ranges of equal size (+-1), one per wave.  LDS holds all J rows
+// of a 16-column chunk, double-buffered: one barrier per chunk.
+constexpr int kTriWaves = 8;
+constexpr int kTriRows = 256;  // J_pad limit
+
+template <typename T, int NBW, bool UNIT_L>
+__global__ __launch_bounds__(64 * kTriWaves) void gram_tri_kernel(GramParams g) {
+  constexpr int NT = 64 * kTriWaves;
+  __shared__ double sY[2][kTriRows * kLds];
+  __shared__ double sred[kTriWaves];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int64_t split = blockIdx.x;
+  const int J = g.J;
+  const int Jp = (J + 15) & ~15;
+  const uint32_t L = g.L, K = g.K;
+  const int64_t JL = (int64_t)J * L;
+  const int64_t ch_begin = split * g.cps;
+  const int64_t ch_end = min(ch_begin + g.cps, g.nchunks);
+  const T* __restrict__ Y = static_cast<const T*>(g.Y);
+  const int nb = Jp / 16, nblk = nb * (nb + 1) / 2;
+
+  // this wave's blocks [q0, q0 + nq)
+  const int q0 = (int)(((int64_t)nblk * wave) / kTriWaves);
+  const int nq = (int)(((int64_t)nblk * (wave + 1)) / kTriWaves) - q0;
+  int bI[NBW], bJ[NBW];
+  {
+    int bi = 0, bj = 0, q = 0;
+    while (q < q0) {  // advance to block q0 (row-major over bi <= bj)
+      ++q;
+      if (++bj == nb) {
+        ++bi;
+        bj = bi;
+      }
+    }
+    // slots past nq repeat the wave's last block: computed, never stored, so
+    // that the MFMA loop below has no per-slot branch
+#pragma unroll
+    for (int t = 0; t < NBW; ++t) {
+      bI[t] = bi;
+      bJ[t] = bj;
+      if (t + 1 < nq && ++bj == nb) {
+        ++bi;
+        bj = bi;
+      }
+    }
+  }
+  d4 acc[NBW];
+#pragma unroll
+  for (int t = 0; t < NBW; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
+
+  constexpr int E = (kTriRows * kKC + NT - 1) / NT;  // loads per thread per chunk (upper bound)
+  const int nel = Jp * kKC;
+  double rv[E];
+  double sq = 0.0;
+  // (row, column-in-chunk) of each element this thread moves (L = 1 layout)
+  int erow[E], ek[E];
+#pragma unroll
+  for (int p = 0; p < E; ++p) {
+    const int e = tid + NT * p;
+    erow[p] = (e < nel) ? e % Jp : Jp;
+    ek[p] = (e < nel) ? e / Jp : 0;
+  }
+  auto load = [&](int64_t ch) {
+    if constexpr (UNIT_L) {
+#pragma unroll
+      for (int p = 0; p < E; ++p) {
+        const int row = erow[p];
+        const int64_t c = ch * kKC + ek[p];
+        rv[p] = (row < J && c < (int64_t)K) ? to_f64(Y[(int64_t)row + (int64_t)J * c]) : 0.0;
+      }
+    } else {
+      const int k = tid % kKC;
+      const int64_t c = ch * kKC + k;
+      const bool cv = c < (int64_t)K;
+      int64_t base = 0;
+      if (cv) {
+        const uint32_t cc = (uint32_t)c;
+        const uint32_t r = cc / L, l = cc - r * L;
+        base = (int64_t)l + JL * r;
+      }
+#pragma unroll
+      for (int p = 0; p < E; ++p) {
+        const int row = tid / kKC + (NT / kKC) * p;
+        rv[p] = (cv && row < J) ? to_f64(Y[base + (int64_t)L * row]) : 0.0;
+      }
+    }
+  };
+  auto store = [&](double* buf) {
+    if constexpr (UNIT_L) {
+#pragma unroll
+      for (int p = 0; p < E; ++p) {
+        if (erow[p] < Jp) buf[erow[p] * kLds + ek[p]] = rv[p];
+        sq += rv[p] * rv[p];
+      }
+    } else {
+      const int k = tid % kKC;
+#pragma unroll
+      for (int p = 0; p < E; ++p) {
+        const int row = tid / kKC + (NT / kKC) * p;
+        if (row < Jp) buf[row * kLds + k] = rv[p];
+        sq += rv[p] * rv[p];
+      }
+    }
+  };
+
+  if (ch_begin < ch_end) load(ch_begin);
+  for (int64_t ch = ch_begin; ch < ch_end; ++ch) {
+    double* buf = sY[ch & 1];
+    store(buf);
+    lds_barrier();
+    if (ch + 1 < ch_end) load(ch + 1);
+#pragma unroll
+    for (int s = 0; s < kKC / 4; ++s) {
+#pragma unroll
+      for (int t = 0; t < NBW; ++t) {
+        const double av = buf[(16 * bI[t] + (lane & 15)) * kLds + 4 * s + (lane >> 4)];
+        const double bv = buf[(16 * bJ[t] + (lane & 15)) * kLds + 4 * s + (lane >> 4)];
+        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[t], 0, 0, 0);
+      }
+      __builtin_amdgcn_sched_barrier(0);  // bound the operand reads in flight (registers)
+    }
+  }
+  // partial blocks out: part[split][q][16 x 16]; f64 MFMA layout D[(l>>4)+4v][l&15]
+  double* __restrict__ P = g.part + split * (int64_t)nblk * 256;
+#pragma unroll
+  for (int t = 0; t < NBW; ++t) {
+    if (t < nq) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) P[(int64_t)(q0 + t) * 256 + ((lane >> 4) + 4 * v) * 16 + (lane & 15)] = acc[t][v];
+    }
+  }
+  if (g.sq != nullptr) {
+    const double w = wave_sum(sq);
+    if (lane == 0) sred[wave] = w;
+    __syncthreads();
+    if (tid == 0) {
+      double tot = 0.0;
+      for (int w2 = 0; w2 < kTriWaves; ++w2) tot += sred[w2];
+      g.sq[split] = tot;
+    }
+  }
+}
+
+// Sum the per-split partial blocks in split order; write both triangles of S.
+__global__ __launch_bounds__(256) void gram_tri_reduce_kernel(const double* __restrict__ part, int nb,
+                                                              int64_t nsplit, int J, double* __restrict__ S) {
+  const int nblk = nb * (nb + 1) / 2;
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= (int64_t)nblk * 256) return;
+  const int q = (int)(idx >> 8), rem = (int)(idx & 255);
+  int bi = 0, qq = q;
+  while (qq >= nb - bi) {
+    qq -= nb - bi;
+    ++bi;
+  }
+  const int bj = bi + qq;
+  const int r = rem >> 4, c = rem & 15;
+  const int a = 16 * bi + r, b = 16 * bj + c;
+  if (a >= J || b >= J || (bi == bj && r > c)) return;
+  double s = 0.0;
+  for (int64_t sp = 0; sp < nsplit; ++sp) s += part[(sp * nblk + q) * 256 + rem];
+  S[(int64_t)a * J + b] = s;
+  S[(int64_t)b * J + a] = s;
+}
+
 }  // namespace
 
 // Fixed-order sum of n doubles by one workgroup (deterministic).
@@ -230,10 +400,23 @@ __global__ __launch_bounds__(256) void sum_fixed_kernel(const double* __restrict
 
 GramPlan plan_gram_f64(int J, uint64_t L, uint64_t K) {
   GramPlan p{};
-  p.tile = (J <= 64) ? 64 : 128;
+  p.nchunks = ceil_div((int64_t)K, kKC);
+  if (J <= kTriRows) {
+    // whole triangle per workgroup: split K over ~2 workgroups per CU
+    p.tile = 0;
+    p.ntiles = (J + 15) / 16;  // 16-row blocks
+    p.npairs = p.ntiles * (p.ntiles + 1) / 2;
+    int64_t nsplit = std::min<int64_t>(256, std::max<int64_t>(1, p.nchunks / 8));
+    p.cps = ceil_div(p.nchunks, nsplit);
+    p.nsplit = ceil_div(p.nchunks, p.cps);
+    p.part_elems = p.nsplit * p.npairs * 256;
+    p.sq_elems = p.nsplit;
+    (void)L;
+    return p;
+  }
+  p.tile = 128;
   p.ntiles = (int)ceil_div(J, p.tile);
   p.npairs = p.ntiles * (p.ntiles + 1) / 2;
-  p.nchunks = ceil_div((int64_t)K, kKC);
   // enough workgroups to cover 256 CUs a few times, at least 4 chunks each
   const int64_t target = 1024;
   int64_t nsplit = ceil_div(target, p.npairs);
@@ -264,7 +447,24 @@ hipError_t launch_gram_f64(const T* Y, int J, uint64_t L, uint64_t K, const Gram
   g.sq = norm2 ? sq : nullptr;
   const int64_t grid = ceil_div(g.total, kXcds) * kXcds;
   const bool unit = (L == 1);
-  if (p.tile == 64) {
+  if (p.tile == 0) {
+    const int nblk = p.npairs;
+    const int nbw = (int)ceil_div(nblk, kTriWaves);
+#define TRI_GRAM(NBW)                                                                                        \
+  do {                                                                                                       \
+    if (unit) hipLaunchKernelGGL((gram_tri_kernel<T, NBW, true>), dim3(p.nsplit), dim3(64 * kTriWaves), 0, stream, g); \
+    else hipLaunchKernelGGL((gram_tri_kernel<T, NBW, false>), dim3(p.nsplit), dim3(64 * kTriWaves), 0, stream, g);    \
+  } while (0)
+    if (nbw <= 2) TRI_GRAM(2);
+    else if (nbw <= 5) TRI_GRAM(5);
+    else if (nbw <= 9) TRI_GRAM(9);
+    else if (nbw <= 12) TRI_GRAM(12);
+    else TRI_GRAM(17);
+#undef TRI_GRAM
+    if (after_main) (void)hipEventRecord(after_main, stream);
+    hipLaunchKernelGGL(gram_tri_reduce_kernel, dim3(ceil_div((int64_t)nblk * 256, 256)), dim3(256), 0, stream, part,
+                       p.ntiles, p.nsplit, J, S);
+  } else if (p.tile == 64) {
     if (unit) hipLaunchKernelGGL((gram_f64_kernel<T, 64, true>), dim3(grid), dim3(256), 0, stream, g);
     else hipLaunchKernelGGL((gram_f64_kernel<T, 64, false>), dim3(grid), dim3(256), 0, stream, g);
     if (after_main) (void)hipEventRecord(after_main, stream);

@@ -4,13 +4,20 @@
 // ST-HOSVD uses M = U_n^T (shrinking, K = R_n <= J); reconstruction uses
 // M = rows of U_n (expanding, K >= R_n).
 //
-// Kernel design (gfx950): each workgroup owns a 64 (k) x 64 (c) output tile;
-// J is consumed in chunks of 16 staged through LDS ([c][j] and [k][j] with row
-// stride 17 doubles: conflict-free stores and MFMA reads); four waves each own
-// 16 columns and up to 4 row blocks of v_mfma_f64_16x16x4f64.  Global loads
-// walk the contiguous axis (j for L = 1, c otherwise).  For L = 1 the output
-// is staged through LDS so that stores run along k, the contiguous axis of Z.
-// Row blocks beyond K are skipped, so small ranks cost proportionally less.
+// Kernel design (gfx950): the shrinking TTM is bound by reading Y once from
+// HBM, so Y is not staged through LDS.  Each wave owns 16 output columns and
+// up to 4 blocks of 16 output rows (v_mfma_f64_16x16x4f64) and loads its MFMA
+// B operands straight from global memory.  Since the reduction index of an
+// MFMA may be assigned to (step, lane group) in any order, it is chosen so
+// that loads run along the contiguous axis:
+//   L = 1 (columns contiguous along j): lane group q of step s reads row
+//         16 t + 4 q + s, so each lane reads 4 consecutive values of its column;
+//   L > 1 (rows contiguous along c):    lane group q of step s reads row
+//         16 t + 4 s + q, so the 16 lanes of a group read 16 consecutive columns.
+// The A operand (M, small) is staged through LDS in 64 x 64 blocks shared by
+// the workgroup's four waves and follows the same assignment.  Four 16-row
+// chunks of Y are loaded before they are consumed, keeping enough bytes in
+// flight per CU.
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -18,149 +25,102 @@ namespace tk {
 
 namespace {
 
-constexpr int kTC = 64;   // output columns per workgroup
-constexpr int kTK = 64;   // output rows per workgroup
-constexpr int kJC = 16;   // input rows (j) per chunk
-constexpr int kS = kJC + 1;
+constexpr int kTK = 64;     // output rows per wave (4 MFMA blocks)
+constexpr int kWaves = 4;   // waves per workgroup; each owns 16 columns
+constexpr int kJB = 64;     // reduction rows per LDS block of M (4 chunks of 16)
+constexpr int kMS = kJB + 1;
 
 template <typename T>
 __device__ __forceinline__ void store_as(T* p, double v) {
   *p = static_cast<T>(v);
 }
 
-template <typename TI, typename TO, bool UNIT_L>
-__global__ __launch_bounds__(256, 2) void ttm_kernel(const TI* __restrict__ Y, int J, uint32_t L, uint32_t cols,
-                                                     const double* __restrict__ M, int64_t msk, int64_t msj, int K,
-                                                     TO* __restrict__ Z, int nrt, int64_t total) {
-  __shared__ double sY[kTC * kS];
-  __shared__ double sM[kTK * kS];
-  __shared__ double sZ[UNIT_L ? kTC * (kTK + 1) : 1];
-
+// RB: 16-row output blocks per wave (1..4), chosen from K at launch.
+template <typename TI, typename TO, bool UNIT_L, int RB>
+__global__ __launch_bounds__(256) void ttm_kernel(const TI* __restrict__ Y, int J, uint32_t L, uint32_t cols,
+                                                  const double* __restrict__ M, int64_t msk, int64_t msj, int K,
+                                                  TO* __restrict__ Z, int nrt, int64_t total) {
+  __shared__ double sM[kTK * kMS];  // M block: 64 output rows x 64 reduction rows
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t item = xcd_remap(blockIdx.x, gridDim.x, total);
   if (item < 0) return;
   const int rt = (int)(item % nrt);
   const int64_t ct = item / nrt;
-  const int64_t c0 = ct * kTC;
+  const int64_t c0 = (ct * kWaves + wave) * 16;  // this wave's first column
   const int k0 = rt * kTK;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int q = lane >> 4, i = lane & 15;
   const int64_t JL = (int64_t)J * L;
 
-  d4 acc[4];
-#pragma unroll
-  for (int b = 0; b < 4; ++b) acc[b] = d4{0.0, 0.0, 0.0, 0.0};
-  bool rneed[4];
-#pragma unroll
-  for (int b = 0; b < 4; ++b) rneed[b] = (k0 + 16 * b) < K;
-
-  // per-thread fixed column for the general (L > 1) loader
-  int64_t colbase = 0;
-  bool colok = false;
-  if constexpr (!UNIT_L) {
-    const int64_t c = c0 + (tid % kTC);
-    colok = c < (int64_t)cols;
-    if (colok) {
+  // the column this lane reads (B operand: column c0 + i)
+  const int64_t c = c0 + i;
+  const bool cok = c < (int64_t)cols;
+  int64_t cbase = 0;
+  if (cok) {
+    if constexpr (UNIT_L) {
+      cbase = (int64_t)J * c;
+    } else {
       const uint32_t cc = (uint32_t)c;
       const uint32_t r = cc / L, l = cc - r * L;
-      colbase = (int64_t)l + JL * r;
+      cbase = (int64_t)l + JL * r;
     }
   }
+  d4 acc[RB];
+#pragma unroll
+  for (int b = 0; b < RB; ++b) acc[b] = d4{0.0, 0.0, 0.0, 0.0};
 
-  double ry[4], rm[4];
-  auto load = [&](int j0) {
-    if constexpr (UNIT_L) {
-      const int j = tid % kJC, cb = tid / kJC;
+  for (int jb = 0; jb < J; jb += kJB) {
+    // Y operands of the four 16-row chunks of this block (row of (chunk t, step s)
+    // is jb + 16 t + 4 q + s for L = 1 and jb + 16 t + 4 s + q otherwise)
+    double yv[4][4];
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int64_t c = c0 + cb + 16 * e;
-        ry[e] = (j0 + j < J && c < (int64_t)cols) ? to_f64(Y[(int64_t)(j0 + j) + (int64_t)J * c]) : 0.0;
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int j = jb + 16 * t + (UNIT_L ? 4 * q + s : 4 * s + q);
+        yv[t][s] = (cok && j < J) ? to_f64(Y[cbase + (UNIT_L ? (int64_t)j : (int64_t)L * j)]) : 0.0;
       }
-    } else {
-      const int jb = tid / kTC;
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int j = j0 + jb + 4 * e;
-        ry[e] = (colok && j < J) ? to_f64(Y[colbase + (int64_t)L * j]) : 0.0;
-      }
-    }
-    {
-      const int j = tid % kJC, kb = tid / kJC;
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int k = k0 + kb + 16 * e;
-        rm[e] = (k < K && j0 + j < J) ? M[(int64_t)k * msk + (int64_t)(j0 + j) * msj] : 0.0;
-      }
-    }
-  };
-  auto store = [&]() {
-    if constexpr (UNIT_L) {
-      const int j = tid % kJC, cb = tid / kJC;
-#pragma unroll
-      for (int e = 0; e < 4; ++e) sY[(cb + 16 * e) * kS + j] = ry[e];
-    } else {
-      const int c = tid % kTC, jb = tid / kTC;
-#pragma unroll
-      for (int e = 0; e < 4; ++e) sY[c * kS + jb + 4 * e] = ry[e];
-    }
-    const int j = tid % kJC, kb = tid / kJC;
-#pragma unroll
-    for (int e = 0; e < 4; ++e) sM[(kb + 16 * e) * kS + j] = rm[e];
-  };
-
-  load(0);
-  for (int j0 = 0; j0 < J; j0 += kJC) {
-    store();
+    // M block into LDS: sM[k][j] = M(k0 + k, jb + j)
     __syncthreads();
-    if (j0 + kJC < J) load(j0 + kJC);
+    for (int e = tid; e < 16 * RB * kJB; e += 256) {
+      const int kk = e / kJB, jj = e - kk * kJB;
+      const int k = k0 + kk, j = jb + jj;
+      sM[kk * kMS + jj] = (k < K && j < J) ? M[(int64_t)k * msk + (int64_t)j * msj] : 0.0;
+    }
+    __syncthreads();
 #pragma unroll
-    for (int s = 0; s < kJC / 4; ++s) {
-      // B[j][c] = Y: lane (c = l & 15, j = l >> 4); A[k][j] = M: lane (k = l & 15, j = l >> 4)
-      const double bv = sY[(16 * wave + (lane & 15)) * kS + 4 * s + (lane >> 4)];
+    for (int t = 0; t < 4; ++t)
 #pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        if (rneed[b]) {
-          const double av = sM[(16 * b + (lane & 15)) * kS + 4 * s + (lane >> 4)];
-          acc[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[b], 0, 0, 0);
+      for (int s = 0; s < 4; ++s) {
+        const int jj = 16 * t + (UNIT_L ? 4 * q + s : 4 * s + q);
+#pragma unroll
+        for (int b = 0; b < RB; ++b) {
+          const double av = sM[(16 * b + i) * kMS + jj];
+          acc[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, yv[t][s], acc[b], 0, 0, 0);
         }
       }
-    }
-    __syncthreads();
   }
 
   // f64 MFMA result: lane l, register v holds D[(l >> 4) + 4 v][l & 15]
+  // (output row k0 + 16 b + (l >> 4) + 4 v, output column c0 + (l & 15))
+  if (!cok) return;
+  int64_t zb;
+  int64_t kstride;
   if constexpr (UNIT_L) {
-#pragma unroll
-    for (int b = 0; b < 4; ++b)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int kk = 16 * b + (lane >> 4) + 4 * v;
-        const int cc = 16 * wave + (lane & 15);
-        sZ[cc * (kTK + 1) + kk] = acc[b][v];
-      }
-    __syncthreads();
-    const int kk = tid % kTK, cb = tid / kTK;
-    if (k0 + kk < K) {
-#pragma unroll 4
-      for (int e = 0; e < kTC / 4; ++e) {
-        const int cc = cb + 4 * e;
-        const int64_t c = c0 + cc;
-        if (c < (int64_t)cols) store_as(&Z[(int64_t)(k0 + kk) + (int64_t)K * c], sZ[cc * (kTK + 1) + kk]);
-      }
-    }
+    zb = (int64_t)K * c;
+    kstride = 1;
   } else {
-    const int64_t c = c0 + 16 * wave + (lane & 15);
-    if (c < (int64_t)cols) {
-      const uint32_t cc = (uint32_t)c;
-      const uint32_t r = cc / L, l = cc - r * L;
-      const int64_t zb = (int64_t)l + (int64_t)L * K * r;
-#pragma unroll
-      for (int b = 0; b < 4; ++b)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int k = k0 + 16 * b + (lane >> 4) + 4 * v;
-          if (k < K) store_as(&Z[zb + (int64_t)L * k], acc[b][v]);
-        }
-    }
+    const uint32_t cc = (uint32_t)c;
+    const uint32_t r = cc / L, l = cc - r * L;
+    zb = (int64_t)l + (int64_t)L * K * r;
+    kstride = L;
   }
+#pragma unroll
+  for (int b = 0; b < RB; ++b)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int k = k0 + 16 * b + q + 4 * v;
+      if (k < K) store_as(&Z[zb + kstride * k], acc[b][v]);
+    }
 }
 
 }  // namespace
@@ -169,15 +129,25 @@ template <typename TI, typename TO>
 hipError_t launch_ttm(const TI* Y, int J, uint64_t L, uint64_t cols, const double* M, int64_t msk, int64_t msj,
                       int K, TO* Z, hipStream_t stream) {
   const int nrt = (int)ceil_div(K, kTK);
-  const int64_t nct = ceil_div((int64_t)cols, kTC);
+  const int64_t nct = ceil_div((int64_t)cols, 16 * kWaves);
   const int64_t total = nct * nrt;
   const int64_t grid = ceil_div(total, kXcds) * kXcds;
-  if (L == 1)
-    hipLaunchKernelGGL((ttm_kernel<TI, TO, true>), dim3(grid), dim3(256), 0, stream, Y, J, (uint32_t)L,
-                       (uint32_t)cols, M, msk, msj, K, Z, nrt, total);
-  else
-    hipLaunchKernelGGL((ttm_kernel<TI, TO, false>), dim3(grid), dim3(256), 0, stream, Y, J, (uint32_t)L,
-                       (uint32_t)cols, M, msk, msj, K, Z, nrt, total);
+  const int rb = (K >= kTK) ? 4 : (int)ceil_div(K, 16);
+#define TTM_LAUNCH(U, RBV)                                                                                     \
+  hipLaunchKernelGGL((ttm_kernel<TI, TO, U, RBV>), dim3(grid), dim3(64 * kWaves), 0, stream, Y, J, (uint32_t)L, \
+                     (uint32_t)cols, M, msk, msj, K, Z, nrt, total)
+  if (L == 1) {
+    if (rb == 1) TTM_LAUNCH(true, 1);
+    else if (rb == 2) TTM_LAUNCH(true, 2);
+    else if (rb == 3) TTM_LAUNCH(true, 3);
+    else TTM_LAUNCH(true, 4);
+  } else {
+    if (rb == 1) TTM_LAUNCH(false, 1);
+    else if (rb == 2) TTM_LAUNCH(false, 2);
+    else if (rb == 3) TTM_LAUNCH(false, 3);
+    else TTM_LAUNCH(false, 4);
+  }
+#undef TTM_LAUNCH
   return hipGetLastError();
 }
 
