@@ -66,6 +66,15 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// Wave-wide sum: 16-lane DPP reduction, then two cross-row exchanges; all
+// lanes get the same (bit-identical) total.
+__device__ __forceinline__ double wave_sum_fast(double v) {
+  v = row16_sum(v);
+  v += __shfl_xor(v, 16, 64);
+  v += __shfl_xor(v, 32, 64);
+  return v;
+}
+
 __device__ __forceinline__ float wave_sum(float v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);

@@ -17,7 +17,7 @@
 //     eigenvalue test 32 interior points at once; many workgroups.
 //  3. Truncation: tail sums of the clamped eigenvalues from the smallest upward.
 //  4. Leading R eigenvectors of T by two steps of inverse iteration
-//     (tridiagonal LU with partial pivoting), one thread per vector; eigenvalues closer than
+//     (tridiagonal LU with partial pivoting, factors in LDS), one thread per vector; eigenvalues closer than
 //     1e-10 ||T|| are handled as one cluster by one thread with Gram-Schmidt
 //     inside the iteration.
 //  5. Re-orthogonalisation (classical Gram-Schmidt, twice) of each vector
@@ -90,8 +90,13 @@ __device__ __forceinline__ void write_row(int k, int wave, int rs, int c, const 
   }
 }
 
+// Phase of the reduction: the matrix block S[k0.., k0..] (leading dimension
+// ld) of size J is reduced for at most `nsteps` steps; if rows remain, the
+// trailing block is written to A (leading dimension ld, same global indices)
+// for the next, smaller, phase.  d, e, tau and H use global indices.
 template <int NW, int NG, int NC>
-__global__ __launch_bounds__(64 * NW) void eig_tridiag_reg_kernel(const double* __restrict__ S, int J,
+__global__ __launch_bounds__(64 * NW) void eig_tridiag_reg_kernel(const double* __restrict__ S, int ld, int k0,
+                                                                  int J, int nsteps, double* __restrict__ A,
                                                                   double* __restrict__ H, double* __restrict__ d,
                                                                   double* __restrict__ e, double* __restrict__ tau) {
   __shared__ double sx[16 * NC];  // column k of the current matrix
@@ -106,13 +111,18 @@ __global__ __launch_bounds__(64 * NW) void eig_tridiag_reg_kernel(const double* 
 #pragma unroll
     for (int cc = 0; cc < NC; ++cc) {
       const int i = 4 * (NW * g + wave) + rs, j = c + 16 * cc;
-      a[g][cc] = (i < J && j < J) ? S[(int64_t)i * J + j] : 0.0;
+      a[g][cc] = (i < J && j < J) ? S[(int64_t)(k0 + i) * ld + (k0 + j)] : 0.0;
     }
   for (int j = tid; j < 16 * NC; j += 64 * NW) sp[j] = 0.0;
+  d += k0;
+  e += k0;
+  tau += k0;
+  H += (int64_t)k0 * ld + k0;
   write_row<NW, NG, NC>(0, wave, rs, c, a, sx);
   lds_barrier();
 
-  for (int k = 0; k + 2 < J; ++k) {
+  int k = 0;
+  for (; k + 2 < J && k < nsteps; ++k) {
     double part = 0.0;
 #pragma unroll
     for (int cc = 0; cc < NC; ++cc) {
@@ -134,7 +144,7 @@ __global__ __launch_bounds__(64 * NW) void eig_tridiag_reg_kernel(const double* 
       tau[k] = tk;
     }
     if (wave == 0)
-      for (int j = k + 2 + lane; j < J; j += 64) H[(int64_t)k * J + j] = sx[j] * scale;
+      for (int j = k + 2 + lane; j < J; j += 64) H[(int64_t)k * ld + j] = sx[j] * scale;
     if (tk == 0.0) {
       lds_barrier();
       write_row<NW, NG, NC>(k + 1, wave, rs, c, a, sx);
@@ -185,19 +195,33 @@ __global__ __launch_bounds__(64 * NW) void eig_tridiag_reg_kernel(const double* 
     write_row<NW, NG, NC>(k + 1, wave, rs, c, a, sx);
     lds_barrier();
   }
+  if (k + 2 < J) {
+    // stopped early: hand the trailing block (rows and columns >= k) to the next phase
+#pragma unroll
+    for (int g = 0; g < NG; ++g) {
+      const int i = 4 * (NW * g + wave) + rs;
+      if (i < k || i >= J) continue;
+#pragma unroll
+      for (int cc = 0; cc < NC; ++cc) {
+        const int j = c + 16 * cc;
+        if (j >= k && j < J) A[(int64_t)(k0 + i) * ld + (k0 + j)] = a[g][cc];
+      }
+    }
+    return;
+  }
   if (J >= 2) {
     if (tid == 0) {
       d[J - 2] = sx[J - 2];
       e[J - 2] = sx[J - 1];
     }
-    const int k = J - 1, blk = k >> 2;
-    if (wave == blk % NW && rs == (k & 3) && c == (k & 15)) {
-      const int gk = blk / NW, ck = k >> 4;
+    const int kl = J - 1, blk = kl >> 2;
+    if (wave == blk % NW && rs == (kl & 3) && c == (kl & 15)) {
+      const int gk = blk / NW, ck = kl >> 4;
 #pragma unroll
       for (int g = 0; g < NG; ++g)
 #pragma unroll
         for (int cc = 0; cc < NC; ++cc)
-          if (g == gk && cc == ck) d[k] = a[g][cc];
+          if (g == gk && cc == ck) d[kl] = a[g][cc];
     }
   } else if (tid == 0) {
     d[0] = sx[0];
@@ -397,16 +421,28 @@ __device__ __forceinline__ double hash_unit(uint32_t a, uint32_t b) {
   return (double)x * (2.0 / 4294967296.0) - 1.0;
 }
 
-// work layout: array a (0..5), element i, thread slot t  ->  work[(a*J + i)*ld + t]
-// arrays: 0 multipliers l_i, 1 reciprocal pivots 1/u_ii, 2 u_{i,i+1}, 3 u_{i,i+2},
-//         4 row-interchange flags, 5 the iterate.
+// 1/x from the hardware reciprocal refined by one Newton step.
+__device__ __forceinline__ double rcp_refined(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  return fma(r, fma(-x, r, 1.0), r);
+}
+
+// One thread per vector; a workgroup of 64 threads serves `nvw` vectors and
+// keeps, per vector, the upper factor of the pivoted LU of (T - lambda I)/||T||
+// (reciprocal pivots, first and second superdiagonal) and the iterate in LDS,
+// interleaved by thread so that accesses are bank-conflict free.  Each
+// iteration factors and forward-substitutes in one pass (the multipliers and
+// interchanges are applied to the right-hand side as they are produced) and
+// back-substitutes in a second pass.
 __global__ __launch_bounds__(64) void eig_invit_kernel(const double* __restrict__ d, const double* __restrict__ e, int J,
                                                        const double* __restrict__ lam, const int64_t* __restrict__ Rp,
                                                        const double* __restrict__ scal, double* __restrict__ Zt,
-                                                       double* __restrict__ work, int ld) {
-  const int t = blockIdx.x * 64 + threadIdx.x;
+                                                       int nvw) {
+  extern __shared__ double sh[];
+  const int tid = threadIdx.x;
+  const int t = blockIdx.x * nvw + tid;
   const int R = (int)*Rp;
-  if (t >= R) return;
+  if (tid >= nvw || t >= R) return;
   const double tnorm = scal[0];
   const double ctol = 1e-10 * tnorm;
   if (t > 0 && lam[t - 1] - lam[t] <= ctol) return;  // handled by its cluster leader
@@ -417,80 +453,66 @@ __global__ __launch_bounds__(64) void eig_invit_kernel(const double* __restrict_
   }
   const double inv = 1.0 / tnorm;
   const double eps = DBL_EPSILON;
-  double* Wl = work + (int64_t)0 * J * ld + t;
-  double* Wr = work + (int64_t)1 * J * ld + t;
-  double* W1 = work + (int64_t)2 * J * ld + t;
-  double* W2 = work + (int64_t)3 * J * ld + t;
-  double* Wp = work + (int64_t)4 * J * ld + t;
-  double* Wx = work + (int64_t)5 * J * ld + t;
-#define W(arr, i) arr[(int64_t)(i) * ld]
+  double* Wr = sh + 0 * (size_t)J * nvw + tid;  // 1 / u_ii
+  double* W1 = sh + 1 * (size_t)J * nvw + tid;  // u_{i,i+1}
+  double* W2 = sh + 2 * (size_t)J * nvw + tid;  // u_{i,i+2}
+  double* Wx = sh + 3 * (size_t)J * nvw + tid;  // iterate
+#define W(arr, i) arr[(size_t)(i) * nvw]
   double prev_shift = 0.0;
   for (int vec = t; vec < R; ++vec) {
     if (vec > t && !(lam[vec - 1] - lam[vec] <= ctol)) break;
     double shift = lam[vec] * inv;
     if (vec > t && prev_shift - shift < 10.0 * eps) shift = prev_shift - 10.0 * eps;
     prev_shift = shift;
-    // LU with partial pivoting of (T - lambda I)/||T||; the running row (pivot
-    // candidate dd, its superdiagonal du) is carried in registers.
-    double dd = d[0] * inv - shift;
-    double du = (J > 1) ? e[0] * inv : 0.0;
-    for (int i = 0; i + 1 < J; ++i) {
-      const double li = e[i] * inv;                                // subdiagonal below the pivot
-      const double dn = d[i + 1] * inv - shift;                    // next diagonal
-      const double un = (i + 2 < J) ? e[i + 1] * inv : 0.0;        // next superdiagonal
-      double piv, u1, u2, f, ndd, ndu;
-      if (fabs(dd) >= fabs(li)) {
-        piv = 0.0;
-        f = (dd != 0.0) ? li / dd : 0.0;
-        u1 = du;
-        u2 = 0.0;
-        ndd = dn - f * du;
-        ndu = un;
-      } else {
-        piv = 1.0;
-        f = dd / li;
-        const double p = li;
-        u1 = dn;
-        u2 = un;
-        ndd = du - f * dn;
-        ndu = -f * un;
-        dd = p;
-      }
-      if (fabs(dd) < eps) dd = (dd < 0.0) ? -eps : eps;
-      W(Wl, i) = f;
-      W(Wr, i) = 1.0 / dd;
-      W(W1, i) = u1;
-      W(W2, i) = u2;
-      W(Wp, i) = piv;
-      dd = ndd;
-      du = ndu;
-    }
-    if (fabs(dd) < eps) dd = (dd < 0.0) ? -eps : eps;
-    W(Wr, J - 1) = 1.0 / dd;
-    W(W1, J - 1) = 0.0;
-    W(W2, J - 1) = 0.0;
-    // start vector
     for (int i = 0; i < J; ++i) W(Wx, i) = hash_unit((uint32_t)i, (uint32_t)vec);
     double xscale = 1.0;
     for (int it = 0; it < 2; ++it) {
-      // forward: row interchanges and multipliers (x scaled on the fly)
-      double cur = W(Wx, 0) * xscale;
-#pragma unroll 16
+      // factor + forward substitution; the running row (dd, du) and its
+      // right-hand side xc are carried in registers
+      double dd = d[0] * inv - shift;
+      double du = (J > 1) ? e[0] * inv : 0.0;
+      double xc = W(Wx, 0) * xscale;
       for (int i = 0; i + 1 < J; ++i) {
-        double nxt = W(Wx, i + 1) * xscale;
-        if (W(Wp, i) != 0.0) {
-          const double tmp = cur;
-          cur = nxt;
-          nxt = tmp;
+        const double li = e[i] * inv;
+        const double dn = d[i + 1] * inv - shift;
+        const double un = (i + 2 < J) ? e[i + 1] * inv : 0.0;
+        double xn = W(Wx, i + 1) * xscale;
+        double u1, u2, ndd, ndu, rp;
+        if (fabs(dd) >= fabs(li)) {
+          if (fabs(dd) < eps) dd = (dd < 0.0) ? -eps : eps;
+          rp = rcp_refined(dd);
+          const double f = li * rp;
+          u1 = du;
+          u2 = 0.0;
+          ndd = dn - f * du;
+          ndu = un;
+          xn -= f * xc;
+        } else {  // interchange rows i and i+1
+          rp = rcp_refined(li);
+          const double f = dd * rp;
+          u1 = dn;
+          u2 = un;
+          ndd = du - f * dn;
+          ndu = -f * un;
+          const double tmp = xc;
+          xc = xn;
+          xn = tmp - f * xn;
         }
-        nxt -= W(Wl, i) * cur;
-        W(Wx, i) = cur;
-        cur = nxt;
+        W(Wr, i) = rp;
+        W(W1, i) = u1;
+        W(W2, i) = u2;
+        W(Wx, i) = xc;
+        dd = ndd;
+        du = ndu;
+        xc = xn;
       }
-      W(Wx, J - 1) = cur;
-      // backward substitution with U
+      if (fabs(dd) < eps) dd = (dd < 0.0) ? -eps : eps;
+      W(Wr, J - 1) = rcp_refined(dd);
+      W(W1, J - 1) = 0.0;
+      W(W2, J - 1) = 0.0;
+      W(Wx, J - 1) = xc;
+      // back substitution
       double y1 = 0.0, y2 = 0.0, nrm = 0.0;
-#pragma unroll 16
       for (int i = J - 1; i >= 0; --i) {
         const double yi = (W(Wx, i) - W(W1, i) * y1 - W(W2, i) * y2) * W(Wr, i);
         W(Wx, i) = yi;
@@ -595,7 +617,7 @@ __global__ __launch_bounds__(256) void eig_back_kernel(const double* __restrict_
     double s = 0.0;
 #pragma unroll
     for (int q = 0; q < Q; ++q) s += v[q] * z[q];
-    s = wave_sum(s) * tk;
+    s = wave_sum_fast(s) * tk;
 #pragma unroll
     for (int q = 0; q < Q; ++q) z[q] -= s * v[q];
   }
@@ -637,13 +659,12 @@ void launch_back(const EigWork& w, int J, const int64_t* R, double* U, hipStream
 
 }  // namespace
 
-int64_t eig_work_doubles(int64_t J) { return 2 * J * J + 6 * J * J + 3 * J + 8; }
+int64_t eig_work_doubles(int64_t J) { return 2 * J * J + 3 * J + 8; }
 
 void eig_work_carve(double* base, int64_t J, EigWork& w) {
   w.A = base;
   w.Zt = w.A + J * J;
-  w.work = w.Zt + J * J;
-  w.d = w.work + 6 * J * J;
+  w.d = w.Zt + J * J;
   w.e = w.d + J;
   w.tau = w.e + J;
   w.scal = w.tau + J;
@@ -652,17 +673,28 @@ void eig_work_carve(double* base, int64_t J, EigWork& w) {
 hipError_t launch_eig_truncate(const double* S, int J, double thr, const double* nx2, const EigWork& w,
                                double* lam, double* U, int64_t* R, double* disc, hipStream_t stream) {
   if (J <= kRegMaxJ) {
-#define TRI_LAUNCH(NW, NG, NC)                                                                                 \
-  hipLaunchKernelGGL((eig_tridiag_reg_kernel<NW, NG, NC>), dim3(1), dim3(64 * NW), 0, stream, S, J, w.A, w.d, \
-                     w.e, w.tau)
-    // rows: 4 * NW * NG >= J; columns: 16 * NC >= J
-    if (J <= 64) TRI_LAUNCH(16, 1, 4);
-    else if (J <= 128) TRI_LAUNCH(16, 2, 8);
-    else if (J <= 192) TRI_LAUNCH(8, 6, 12);
-    else if (J <= 208) TRI_LAUNCH(4, 13, 13);
-    else if (J <= 224) TRI_LAUNCH(8, 7, 14);
-    else TRI_LAUNCH(8, 8, 16);
+    // phases: each register configuration reduces until the trailing block
+    // fits the next smaller one
+    const double* src = S;
+    int ld = J, k0 = 0;
+    while (J - k0 > 2 || k0 == 0) {
+      const int Jl = J - k0;
+      int next;
+#define TRI_LAUNCH(NW, NG, NC)                                                                                    \
+  hipLaunchKernelGGL((eig_tridiag_reg_kernel<NW, NG, NC>), dim3(1), dim3(64 * NW), 0, stream, src, ld, k0, Jl, \
+                     Jl - next, w.A, w.A, w.d, w.e, w.tau)
+      if (Jl <= 32) { next = 0; TRI_LAUNCH(8, 1, 2); }
+      else if (Jl <= 64) { next = 32; TRI_LAUNCH(16, 1, 4); }
+      else if (Jl <= 96) { next = 64; TRI_LAUNCH(16, 2, 6); }
+      else if (Jl <= 128) { next = 96; TRI_LAUNCH(16, 2, 8); }
+      else if (Jl <= 192) { next = 128; TRI_LAUNCH(8, 6, 12); }
+      else if (Jl <= 208) { next = 192; TRI_LAUNCH(4, 13, 13); }
+      else { next = 208; TRI_LAUNCH(8, 8, 16); }
 #undef TRI_LAUNCH
+      if (next == 0) break;
+      src = w.A;
+      k0 += Jl - next;
+    }
   } else {
     hipError_t err = hipMemcpyAsync(w.A, S, sizeof(double) * (size_t)J * J, hipMemcpyDeviceToDevice, stream);
     if (err != hipSuccess) return err;
@@ -673,8 +705,12 @@ hipError_t launch_eig_truncate(const double* S, int J, double thr, const double*
   hipLaunchKernelGGL(eig_bisect_kernel, dim3(ceil_div(J, 256 / kBisLanes)), dim3(256), shb, stream, w.d, w.e, J,
                      lam, w.scal);
   hipLaunchKernelGGL(eig_truncate_kernel, dim3(1), dim3(64), 0, stream, lam, J, thr, nx2, R, disc);
-  hipLaunchKernelGGL(eig_invit_kernel, dim3(ceil_div(J, 64)), dim3(64), 0, stream, w.d, w.e, J, lam, R, w.scal,
-                     w.Zt, w.work, J);
+  {
+    const int nvw = (int)std::max<int64_t>(1, std::min<int64_t>(64, (128 * 1024) / (32 * (int64_t)J)));
+    const size_t shi = sizeof(double) * 4 * (size_t)J * nvw;
+    hipLaunchKernelGGL(eig_invit_kernel, dim3(ceil_div(J, nvw)), dim3(64), shi, stream, w.d, w.e, J, lam, R,
+                       w.scal, w.Zt, nvw);
+  }
   const size_t sh1 = sizeof(double) * ((size_t)J + 16);
   hipLaunchKernelGGL(eig_orth_kernel, dim3(1), dim3(kEigThreads), sh1, stream, w.Zt, J, lam, R, w.scal);
   const int q = (int)ceil_div(J, 64);

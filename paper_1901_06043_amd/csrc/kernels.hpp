@@ -62,7 +62,6 @@ struct EigWork {
   double* e;      // J
   double* tau;    // J
   double* Zt;     // J*J   eigenvectors of the tridiagonal, column-major
-  double* work;   // 6*J*J inverse-iteration scratch
   double* scal;   // 8 scalars (tnorm, ...)
 };
 int64_t eig_work_doubles(int64_t J);
