@@ -48,16 +48,30 @@ typedef enum {
 
 typedef enum { TUCKER_F32 = 0, TUCKER_F64 = 1 } tucker_dtype;
 
-/* Arithmetic of the Gram step.  FP64 is the reference path.  The two mixed
+/* Arithmetic of the Gram step.  FP64 is the reference path.  The reduced
  * forms keep the eigensolve, ||X||^2 and the truncation decision in FP64 and
- * carry the working tensor in FP32; they are not part of the paper (which is
- * FP64 only) and each result's error is reported against the FP64 path.
- *   FP32   : FP32 MFMA products, FP32 accumulation within chunks of the
- *            unfolding's columns, chunk sums accumulated in FP64.
- *   BF16X3 : each FP32 value split as b0 + b1 (+ b2) in bfloat16; products
- *            b0*b0' + b0*b1' + b1*b0' on BF16 MFMA, FP32 accumulation per chunk,
- *            FP64 across chunks (Henry, Tang & Heinecke, ARITH 2019). */
-typedef enum { TUCKER_GRAM_FP64 = 0, TUCKER_GRAM_FP32 = 1, TUCKER_GRAM_BF16X3 = 2 } tucker_gram_prec;
+ * carry the working tensor in FP32, with FP32 MFMA products in its mode
+ * products; they are not part of the paper (which is FP64 only) and each
+ * result's error is reported against the FP64 path.
+ *   FP32   : FP32 MFMA products, FP32 accumulation within groups of 256
+ *            columns of the unfolding, group sums accumulated in FP64.
+ *   BF16X3 : each FP32 value split as x = b0 + b1 + r in bfloat16
+ *            (b0 = bf16(x), b1 = bf16(x - b0)); products b1*b0' + b0*b1' +
+ *            b0*b0' on BF16 MFMA, FP32 accumulation per group, FP64 across
+ *            groups (Henry, Tang & Heinecke, ARITH 2019).  The dropped b1*b1'
+ *            term makes the Gram a slight under-estimate (relative ~1e-6).
+ *   BF16X6 : three pieces b0, b1, b2 and the six products b2*b0' + b0*b2' +
+ *            b1*b1' + b1*b0' + b0*b1' + b0*b0'.
+ * Range guard: for the reduced forms every Gram is checked on the device; if an
+ * entry is not finite or its trace differs from the FP64 sum of squares of the
+ * working tensor by more than 1e-3 relative (FP32 overflow or underflow), the
+ * Gram of that mode is recomputed in FP64 (see tucker_gram_precision). */
+typedef enum {
+  TUCKER_GRAM_FP64 = 0,
+  TUCKER_GRAM_FP32 = 1,
+  TUCKER_GRAM_BF16X3 = 2,
+  TUCKER_GRAM_BF16X6 = 3
+} tucker_gram_prec;
 
 typedef struct tucker_t tucker_t; /* opaque result handle */
 
@@ -74,7 +88,9 @@ typedef struct tucker_t tucker_t; /* opaque result handle */
  *   mode_order host, N ints: a permutation of 0..N-1 giving the order in which
  *              modes are processed (Sec. 7 discusses the choice); NULL = 0..N-1.
  *   prec       Gram arithmetic (see tucker_gram_prec).  TUCKER_GRAM_FP64 keeps
- *              the working tensor in FP64; the mixed forms keep it in FP32.
+ *              the working tensor in FP64 (FP64 MFMA products throughout);
+ *              the reduced forms need dtype == TUCKER_F32 and keep the working
+ *              tensor and the core in FP32.
  *   stream     HIP stream for all work (0 = default stream).
  *   out        receives a new handle owning core, factors, eigenvalues and
  *              ranks; release it with tucker_free.
@@ -111,6 +127,9 @@ tucker_status tucker_discarded(const tucker_t* t, double* disc_out);
  * reduction, norm), [4n+1] eigensolve + truncation, [4n+2] TTM, [4n+3] the
  * main Gram kernel alone. */
 tucker_status tucker_timings(const tucker_t* t, double* ms_out);
+/* host out[N]: per mode, the Gram arithmetic actually used: the requested
+ * one, or TUCKER_GRAM_FP64 where the range guard recomputed it. */
+tucker_status tucker_gram_precision(const tucker_t* t, tucker_gram_prec* prec_out);
 void tucker_free(tucker_t* t);
 
 /* ------------------------------------------------------------------------
@@ -123,6 +142,8 @@ void tucker_free(tucker_t* t);
  *            NULL = the flop-minimising order of tucker_reconstruct_order.
  * out        device, caller-allocated, prod(end-begin) values of out_dtype,
  *            natural descending.
+ * Products are FP64 MFMA, except that an FP32 core (reduced-precision
+ * compression) reconstructed into FP32 output uses FP32 MFMA products.
  * Scratch for intermediate results is taken from the device's stream-ordered
  * pool and released before return (stream order). */
 tucker_status tucker_reconstruct(const tucker_t* t, const int64_t* begin, const int64_t* end,
@@ -144,7 +165,8 @@ tucker_status tucker_reconstruct_order(int N, const int64_t* ranks, const int64_
 /* S = Y_(n) Y_(n)^T (Algorithm 2) for Y of sizes dims (natural descending) in
  * `dtype`; S is J_n x J_n FP64, full symmetric.  If norm2 is non-NULL, the
  * FP64 sum of squares of Y is written to it (device, one double).
- * prec selects the arithmetic; FP32/BF16X3 need dtype == TUCKER_F32. */
+ * prec selects the arithmetic; the reduced forms need dtype == TUCKER_F32 and
+ * are not range-guarded here. */
 tucker_status tucker_gram(const void* Y, tucker_dtype dtype, const int64_t* dims, int N, int n,
                           tucker_gram_prec prec, double* S, double* norm2, hipStream_t stream);
 
@@ -161,10 +183,12 @@ tucker_status tucker_eig_truncate(const double* S, int64_t J, double thr, double
 
 /* Mode product Z = Y x_n M (Sec. 2.2.3, Algorithm 3), M a K x J_n FP64
  * matrix with element (k,j) at M[k*msk + j*msj]; Z has the sizes of Y with
- * mode n replaced by K, in `zdtype`.  Y in `ydtype`. */
+ * mode n replaced by K, in `zdtype`.  Y in `ydtype`.  fp32_products != 0
+ * rounds M and Y to FP32 and uses FP32 MFMA products (FP32 accumulation);
+ * otherwise products and accumulation are FP64. */
 tucker_status tucker_ttm(const void* Y, tucker_dtype ydtype, const int64_t* dims, int N, int n,
                          const double* M, int64_t K, int64_t msk, int64_t msj, void* Z,
-                         tucker_dtype zdtype, hipStream_t stream);
+                         tucker_dtype zdtype, int fp32_products, hipStream_t stream);
 
 /* ------------------------------------------------------------------------
  * Diagnostics

@@ -20,15 +20,16 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libtuckerhip.so")
 
 F32, F64 = 0, 1
-GRAM_FP64, GRAM_FP32, GRAM_BF16X3 = 0, 1, 2
-_PREC = {"fp64": GRAM_FP64, "fp32": GRAM_FP32, "bf16x3": GRAM_BF16X3}
+GRAM_FP64, GRAM_FP32, GRAM_BF16X3, GRAM_BF16X6 = 0, 1, 2, 3
+_PREC = {"fp64": GRAM_FP64, "fp32": GRAM_FP32, "bf16x3": GRAM_BF16X3, "bf16x6": GRAM_BF16X6}
+PREC_NAMES = {v: k for k, v in _PREC.items()}
 STATUS = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EHIP", 4: "ENOCONV", 5: "EUNSUPPORTED"}
 MAX_MODES = 16
 
 EXPORTS = [
     "tucker_sthosvd", "tucker_ndims", "tucker_dims", "tucker_ranks", "tucker_mode_order", "tucker_core",
     "tucker_factor", "tucker_eigenvalues", "tucker_norm2", "tucker_discarded", "tucker_timings",
-    "tucker_free", "tucker_reconstruct", "tucker_reconstruct_order", "tucker_gram",
+    "tucker_gram_precision", "tucker_free", "tucker_reconstruct", "tucker_reconstruct_order", "tucker_gram",
     "tucker_eig_truncate", "tucker_ttm", "tucker_last_error", "tucker_version",
 ]
 
@@ -63,12 +64,13 @@ def lib():
             "tucker_norm2": (d, [P]),
             "tucker_discarded": (i32, [P, P]),
             "tucker_timings": (i32, [P, P]),
+            "tucker_gram_precision": (i32, [P, P]),
             "tucker_free": (None, [P]),
             "tucker_reconstruct": (i32, [P, P, P, P, P, i32, P]),
             "tucker_reconstruct_order": (i32, [i32, P, P, P]),
             "tucker_gram": (i32, [P, i32, P, i32, i32, i32, P, P, P]),
             "tucker_eig_truncate": (i32, [P, i64, d, P, P, P, P, P]),
-            "tucker_ttm": (i32, [P, i32, P, i32, i32, P, i64, i64, i64, P, i32, P]),
+            "tucker_ttm": (i32, [P, i32, P, i32, i32, P, i64, i64, i64, P, i32, i32, P]),
             "tucker_last_error": (ctypes.c_char_p, []),
             "tucker_version": (ctypes.c_char_p, []),
         }
@@ -173,6 +175,10 @@ class Tucker:
         ms = (ctypes.c_double * (4 * self.N))()
         _check(L.tucker_timings(handle, ms))
         self.timings = [Timing(ms[4 * n], ms[4 * n + 1], ms[4 * n + 2], ms[4 * n + 3]) for n in range(self.N)]
+        gp = (ctypes.c_int * self.N)()
+        _check(L.tucker_gram_precision(handle, gp))
+        # per mode: the Gram arithmetic used ("fp64" where the range guard redid it)
+        self.gram_precision = [PREC_NAMES[v] for v in gp]
 
     def _alive(self):
         if not self._h:
@@ -286,8 +292,9 @@ def eig_truncate(S, thr: float, stream=None):
     return lam, Ubuf[:r].t(), r, float(disc.item())
 
 
-def ttm(y, n: int, M, dims=None, out_dtype=None, stream=None):
-    """Z = Y x_n M (paper Sec. 2.2.3), M a K x J_n float64 tensor (any strides)."""
+def ttm(y, n: int, M, dims=None, out_dtype=None, fp32_products: bool = False, stream=None):
+    """Z = Y x_n M (paper Sec. 2.2.3), M a K x J_n float64 tensor (any strides);
+    fp32_products selects FP32 MFMA products instead of FP64."""
     import torch
     dims = _dims_of(y, dims)
     if M.dtype != torch.float64 or M.dim() != 2 or M.shape[1] != dims[n]:
@@ -299,5 +306,6 @@ def ttm(y, n: int, M, dims=None, out_dtype=None, stream=None):
         out_dtype = y.dtype
     Z = torch.empty(list(reversed(zd)), dtype=out_dtype, device=y.device)
     _check(lib().tucker_ttm(y.data_ptr(), _dtype_code(y), _i64(dims), len(dims), n, M.data_ptr(), K,
-                            M.stride(0), M.stride(1), Z.data_ptr(), _dtype_code(Z), _stream(stream)))
+                            M.stride(0), M.stride(1), Z.data_ptr(), _dtype_code(Z), int(bool(fp32_products)),
+                            _stream(stream)))
     return Z

@@ -223,9 +223,10 @@ tucker_status run_gram(const void* Y, tucker_dtype dt, const int64_t* dims, int 
   const int64_t K = L * Rt;
   if (K >= (int64_t(1) << 32) || J >= (int64_t(1) << 31))
     return fail(TUCKER_EUNSUPPORTED, "unfolding of mode %d has %lld columns (limit 2^32)", n, (long long)K);
-  if (prec == TUCKER_GRAM_FP64) {
+  TmpBuf part, sq;
+  if (prec == TUCKER_GRAM_FP64 && J <= 256) {
+    // whole triangle per workgroup, FP64
     tk::GramPlan p = tk::plan_gram_f64((int)J, (uint64_t)L, (uint64_t)K);
-    TmpBuf part, sq;
     HIP_TRY(part.alloc(sizeof(double) * p.part_elems, s));
     HIP_TRY(sq.alloc(sizeof(double) * p.sq_elems, s));
     if (dt == TUCKER_F64)
@@ -236,18 +237,21 @@ tucker_status run_gram(const void* Y, tucker_dtype dt, const int64_t* dims, int 
                                   sq.as<double>(), S, norm2, s, after_main));
     return TUCKER_OK;
   }
-  if (dt != TUCKER_F32) return fail(TUCKER_EINVAL, "mixed-precision Gram needs FP32 data");
-  tk::GramPlan p = tk::plan_gram_mixed((int)J, (uint64_t)L, (uint64_t)K);
-  TmpBuf part, sq;
+  if (prec != TUCKER_GRAM_FP64 && dt != TUCKER_F32) return fail(TUCKER_EINVAL, "reduced-precision Gram needs FP32 data");
+  tk::GramPlan p = tk::plan_gram_mp((int)J, (uint64_t)K, (int)prec);
   HIP_TRY(part.alloc(sizeof(double) * p.part_elems, s));
   HIP_TRY(sq.alloc(sizeof(double) * p.sq_elems, s));
-  HIP_TRY(tk::launch_gram_mixed(static_cast<const float*>(Y), (int)J, L, K, (int)prec, p, part.as<double>(),
-                                sq.as<double>(), S, norm2, s, after_main));
+  if (dt == TUCKER_F64)
+    HIP_TRY(tk::launch_gram_mp(static_cast<const double*>(Y), (int)J, L, K, (int)prec, p, part.as<double>(),
+                               sq.as<double>(), S, norm2, s, after_main));
+  else
+    HIP_TRY(tk::launch_gram_mp(static_cast<const float*>(Y), (int)J, L, K, (int)prec, p, part.as<double>(),
+                               sq.as<double>(), S, norm2, s, after_main));
   return TUCKER_OK;
 }
 
 tucker_status run_ttm(const void* Y, tucker_dtype yd, const int64_t* dims, int N, int n, const double* M,
-                      int64_t K, int64_t msk, int64_t msj, void* Z, tucker_dtype zd, hipStream_t s) {
+                      int64_t K, int64_t msk, int64_t msj, void* Z, tucker_dtype zd, bool f32p, hipStream_t s) {
   int64_t L, Rt;
   left_right(dims, N, n, L, Rt);
   const int64_t J = dims[n];
@@ -256,16 +260,16 @@ tucker_status run_ttm(const void* Y, tucker_dtype yd, const int64_t* dims, int N
     return fail(TUCKER_EUNSUPPORTED, "TTM of mode %d too large for 32-bit column indexing", n);
   if (yd == TUCKER_F64 && zd == TUCKER_F64)
     HIP_TRY(tk::launch_ttm(static_cast<const double*>(Y), (int)J, L, cols, M, msk, msj, (int)K,
-                           static_cast<double*>(Z), s));
+                           static_cast<double*>(Z), f32p, s));
   else if (yd == TUCKER_F32 && zd == TUCKER_F64)
     HIP_TRY(tk::launch_ttm(static_cast<const float*>(Y), (int)J, L, cols, M, msk, msj, (int)K,
-                           static_cast<double*>(Z), s));
+                           static_cast<double*>(Z), f32p, s));
   else if (yd == TUCKER_F64 && zd == TUCKER_F32)
     HIP_TRY(tk::launch_ttm(static_cast<const double*>(Y), (int)J, L, cols, M, msk, msj, (int)K,
-                           static_cast<float*>(Z), s));
+                           static_cast<float*>(Z), f32p, s));
   else
     HIP_TRY(tk::launch_ttm(static_cast<const float*>(Y), (int)J, L, cols, M, msk, msj, (int)K,
-                           static_cast<float*>(Z), s));
+                           static_cast<float*>(Z), f32p, s));
   return TUCKER_OK;
 }
 
@@ -281,10 +285,13 @@ struct tucker_t {
   double ms[4 * TUCKER_MAX_MODES] = {0};
   double norm2 = 0.0;
   tucker_dtype core_dtype = TUCKER_F64;
+  tucker_gram_prec prec_used[TUCKER_MAX_MODES] = {TUCKER_GRAM_FP64};
   void* core = nullptr;
   double* U[TUCKER_MAX_MODES] = {nullptr};
   double* lam[TUCKER_MAX_MODES] = {nullptr};
-  double* scalars = nullptr;  // [0] = ||X||^2, [1..N] = disc, then ranks (int64) in a separate buffer
+  // [0] ||X||^2; [2, 2+16) discarded energy per mode; [18, 34) sum of squares of
+  // the working tensor per step; [34, 50) range-guard flag per step
+  double* scalars = nullptr;
   int64_t* dranks = nullptr;
   hipStream_t stream = nullptr;
   std::vector<void*> owned;
@@ -366,10 +373,9 @@ tucker_status tucker_sthosvd(const void* data, tucker_dtype dtype, const int64_t
   *out = nullptr;
   if (!data) return fail(TUCKER_EINVAL, "data is NULL");
   if (dtype != TUCKER_F32 && dtype != TUCKER_F64) return fail(TUCKER_EINVAL, "bad dtype");
-  if (prec != TUCKER_GRAM_FP64 && prec != TUCKER_GRAM_FP32 && prec != TUCKER_GRAM_BF16X3)
-    return fail(TUCKER_EINVAL, "bad Gram precision");
+  if (prec < TUCKER_GRAM_FP64 || prec > TUCKER_GRAM_BF16X6) return fail(TUCKER_EINVAL, "bad Gram precision");
   if (prec != TUCKER_GRAM_FP64 && dtype != TUCKER_F32)
-    return fail(TUCKER_EINVAL, "mixed-precision Gram needs FP32 data");
+    return fail(TUCKER_EINVAL, "reduced-precision Gram needs FP32 data");
   if (!(eps >= 0.0) || !std::isfinite(eps)) return fail(TUCKER_EINVAL, "eps must be finite and >= 0");
   tucker_status st = validate_dims(dims, N);
   if (st) return st;
@@ -389,14 +395,18 @@ tucker_status tucker_sthosvd(const void* data, tucker_dtype dtype, const int64_t
   std::memcpy(t->order, order, sizeof(int) * N);
   const tucker_dtype wdt = (prec == TUCKER_GRAM_FP64) ? TUCKER_F64 : TUCKER_F32;
   t->core_dtype = wdt;
-  HIP_TRY(t->alloc((void**)&t->scalars, sizeof(double) * (2 + 2 * TUCKER_MAX_MODES)));
+  HIP_TRY(t->alloc((void**)&t->scalars, sizeof(double) * (2 + 3 * TUCKER_MAX_MODES)));
   HIP_TRY(t->alloc((void**)&t->dranks, sizeof(int64_t) * TUCKER_MAX_MODES));
   double* d_nx2 = t->scalars;
   double* d_disc = t->scalars + 2;
+  double* d_sq = t->scalars + 2 + TUCKER_MAX_MODES;
+  double* d_flag = t->scalars + 2 + 2 * TUCKER_MAX_MODES;
+  const bool reduced = (prec != TUCKER_GRAM_FP64);
 
   void* hp = nullptr;
   if ((st = pinned(&hp))) return st;
   int64_t* h_R = static_cast<int64_t*>(hp);
+  double* h_flag = reinterpret_cast<double*>(static_cast<char*>(hp) + 8);
 
   Events evs;
   HIP_TRY(evs.create(5 * N));
@@ -417,20 +427,30 @@ tucker_status tucker_sthosvd(const void* data, tucker_dtype dtype, const int64_t
     const int n = order[step];
     const int64_t J = cur[n];
     hipEvent_t* ev = evs.ev + 5 * step;
-    HIP_TRY(hipEventRecord(ev[0], stream));
-    if ((st = run_gram(Y, ydt, cur, N, n, prec, Sbuf.as<double>(), step == 0 ? d_nx2 : nullptr, stream, ev[4])))
-      return st;
-    HIP_TRY(hipEventRecord(ev[1], stream));
     HIP_TRY(t->alloc((void**)&t->U[n], sizeof(double) * J * J));
     HIP_TRY(t->alloc((void**)&t->lam[n], sizeof(double) * J));
     t->eigcount[n] = J;
     tk::EigWork w;
     tk::eig_work_carve(ewbuf.as<double>(), J, w);
-    HIP_TRY(tk::launch_eig_truncate(Sbuf.as<double>(), (int)J, thr_mul, d_nx2, w, t->lam[n], t->U[n],
-                                    t->dranks + n, d_disc + n, stream));
-    HIP_TRY(hipEventRecord(ev[2], stream));
-    HIP_TRY(hipMemcpyAsync(h_R, t->dranks + n, sizeof(int64_t), hipMemcpyDeviceToHost, stream));
-    HIP_TRY(hipStreamSynchronize(stream));
+    t->prec_used[n] = prec;
+    double* sqp = (step == 0) ? d_nx2 : (reduced ? d_sq + step : nullptr);
+    // Gram (+ range guard) and eigensolve; a second pass in FP64 if the guard fired
+    for (int pass = 0; pass < 2; ++pass) {
+      const tucker_gram_prec pp = (pass == 0) ? prec : TUCKER_GRAM_FP64;
+      HIP_TRY(hipEventRecord(ev[0], stream));
+      if ((st = run_gram(Y, ydt, cur, N, n, pp, Sbuf.as<double>(), sqp, stream, ev[4]))) return st;
+      if (pp != TUCKER_GRAM_FP64) HIP_TRY(tk::launch_gram_guard(Sbuf.as<double>(), (int)J, sqp, d_flag + step, stream));
+      HIP_TRY(hipEventRecord(ev[1], stream));
+      HIP_TRY(tk::launch_eig_truncate(Sbuf.as<double>(), (int)J, thr_mul, d_nx2, nullptr, w, t->lam[n],
+                                      t->U[n], t->dranks + n, d_disc + n, stream));
+      HIP_TRY(hipEventRecord(ev[2], stream));
+      HIP_TRY(hipMemcpyAsync(h_R, t->dranks + n, sizeof(int64_t), hipMemcpyDeviceToHost, stream));
+      if (pp != TUCKER_GRAM_FP64)
+        HIP_TRY(hipMemcpyAsync(h_flag, d_flag + step, sizeof(double), hipMemcpyDeviceToHost, stream));
+      HIP_TRY(hipStreamSynchronize(stream));
+      if (pp == TUCKER_GRAM_FP64 || h_flag[0] == 0.0) break;
+      t->prec_used[n] = TUCKER_GRAM_FP64;
+    }
     const int64_t R = h_R[0];
     if (R < 1 || R > J) return fail(TUCKER_ENOCONV, "eigensolver returned rank %lld for J=%lld", (long long)R, (long long)J);
     if (step == 0) {
@@ -447,7 +467,7 @@ tucker_status tucker_sthosvd(const void* data, tucker_dtype dtype, const int64_t
     const int64_t next_elems = total / J * R;
     TmpBuf nbuf;
     HIP_TRY(nbuf.alloc(dtype_size(wdt) * next_elems, stream));
-    if ((st = run_ttm(Y, ydt, cur, N, n, t->U[n], R, J, 1, nbuf.p, wdt, stream))) return st;
+    if ((st = run_ttm(Y, ydt, cur, N, n, t->U[n], R, J, 1, nbuf.p, wdt, reduced, stream))) return st;
     HIP_TRY(hipEventRecord(ev[3], stream));
     ybuf.release();  // stream-ordered: after the TTM that read it
     ybuf.p = nbuf.p;
@@ -531,6 +551,12 @@ tucker_status tucker_timings(const tucker_t* t, double* o) {
   return TUCKER_OK;
 }
 
+tucker_status tucker_gram_precision(const tucker_t* t, tucker_gram_prec* o) {
+  if (!t || !o) return fail(TUCKER_EINVAL, "NULL argument");
+  std::memcpy(o, t->prec_used, sizeof(tucker_gram_prec) * t->N);
+  return TUCKER_OK;
+}
+
 void tucker_free(tucker_t* t) {
   if (!t) return;
   t->release();
@@ -564,6 +590,7 @@ tucker_status tucker_reconstruct(const tucker_t* t, const int64_t* begin, const 
   std::memcpy(cur, t->ranks, sizeof(int64_t) * N);
   const void* Y = t->core;
   tucker_dtype ydt = t->core_dtype;
+  const bool f32p = (t->core_dtype == TUCKER_F32 && out_dtype == TUCKER_F32);
   TmpBuf a;
   for (int step = 0; step < N; ++step) {
     const int n = ord[step];
@@ -575,13 +602,13 @@ tucker_status tucker_reconstruct(const tucker_t* t, const int64_t* begin, const 
     tucker_dtype zdt = out_dtype;
     TmpBuf nb;
     if (!last) {
-      zdt = ydt;
+      zdt = f32p ? TUCKER_F32 : TUCKER_F64;  // intermediates at the precision of the products
       HIP_TRY(nb.alloc(dtype_size(zdt) * next, stream));
       Z = nb.p;
     }
     // M(k, j) = U_n[b_n + k, j]  (U_n is I_n x R_n column-major)
     const double* M = t->U[n] + b[n];
-    if ((st = run_ttm(Y, ydt, cur, N, n, M, K[n], 1, t->dims[n], Z, zdt, stream))) return st;
+    if ((st = run_ttm(Y, ydt, cur, N, n, M, K[n], 1, t->dims[n], Z, zdt, f32p, stream))) return st;
     a.release();
     if (!last) {
       a.p = nb.p;
@@ -602,10 +629,9 @@ tucker_status tucker_gram(const void* Y, tucker_dtype dtype, const int64_t* dims
   tucker_status st = validate_dims(dims, N);
   if (st) return st;
   if (n < 0 || n >= N) return fail(TUCKER_EINVAL, "mode %d outside 0..%d", n, N - 1);
-  if (prec != TUCKER_GRAM_FP64 && prec != TUCKER_GRAM_FP32 && prec != TUCKER_GRAM_BF16X3)
-    return fail(TUCKER_EINVAL, "bad Gram precision");
+  if (prec < TUCKER_GRAM_FP64 || prec > TUCKER_GRAM_BF16X6) return fail(TUCKER_EINVAL, "bad Gram precision");
   if (prec != TUCKER_GRAM_FP64 && dtype != TUCKER_F32)
-    return fail(TUCKER_EINVAL, "mixed-precision Gram needs FP32 data");
+    return fail(TUCKER_EINVAL, "reduced-precision Gram needs FP32 data");
   if ((st = ensure_device())) return st;
   return run_gram(Y, dtype, dims, N, n, prec, S, norm2, stream);
 }
@@ -621,12 +647,13 @@ tucker_status tucker_eig_truncate(const double* S, int64_t J, double thr, double
   HIP_TRY(wb.alloc(sizeof(double) * tk::eig_work_doubles(J), stream));
   tk::EigWork w;
   tk::eig_work_carve(wb.as<double>(), J, w);
-  HIP_TRY(tk::launch_eig_truncate(S, (int)J, thr, nullptr, w, lam, U, R, disc, stream));
+  HIP_TRY(tk::launch_eig_truncate(S, (int)J, thr, nullptr, nullptr, w, lam, U, R, disc, stream));
   return TUCKER_OK;
 }
 
 tucker_status tucker_ttm(const void* Y, tucker_dtype ydtype, const int64_t* dims, int N, int n, const double* M,
-                         int64_t K, int64_t msk, int64_t msj, void* Z, tucker_dtype zdtype, hipStream_t stream) {
+                         int64_t K, int64_t msk, int64_t msj, void* Z, tucker_dtype zdtype, int fp32_products,
+                         hipStream_t stream) {
   if (!Y || !M || !Z) return fail(TUCKER_EINVAL, "NULL pointer");
   if ((ydtype != TUCKER_F32 && ydtype != TUCKER_F64) || (zdtype != TUCKER_F32 && zdtype != TUCKER_F64))
     return fail(TUCKER_EINVAL, "bad dtype");
@@ -635,7 +662,7 @@ tucker_status tucker_ttm(const void* Y, tucker_dtype ydtype, const int64_t* dims
   if (n < 0 || n >= N) return fail(TUCKER_EINVAL, "mode %d outside 0..%d", n, N - 1);
   if (K < 1) return fail(TUCKER_EINVAL, "K=%lld < 1", (long long)K);
   if ((st = ensure_device())) return st;
-  return run_ttm(Y, ydtype, dims, N, n, M, K, msk, msj, Z, zdtype, stream);
+  return run_ttm(Y, ydtype, dims, N, n, M, K, msk, msj, Z, zdtype, fp32_products != 0, stream);
 }
 
 }  // extern "C"

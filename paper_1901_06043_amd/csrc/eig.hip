@@ -389,21 +389,43 @@ __global__ __launch_bounds__(256) void eig_bisect_kernel(const double* __restric
 // ---------------------------------------------------------------- 3. truncation
 // The threshold is thr, or thr * (*nx2) when nx2 is non-null (so that
 // eps^2 ||X||^2 / N is formed on the device without a host round trip).
+// Tail sums: by default sum_{i>=R} max(lam_i, 0), accumulated from the
+// smallest eigenvalue upward (eq. Un).  With trace_ref (device, the FP64 sum
+// of squares of the unfolded tensor, which equals trace S) the tail is
+// trace_ref - sum_{i<R} max(lam_i, 0) instead: used when S itself carries
+// reduced-precision error, since the leading eigenvalues are then far better
+// determined than the small ones, and a Gram that under-estimates (BF16X3)
+// can only make this tail larger, i.e. keep more.  R = J discards nothing.
 __global__ void eig_truncate_kernel(const double* __restrict__ lam, int J, double thr,
-                                    const double* __restrict__ nx2, int64_t* __restrict__ Rout,
-                                    double* __restrict__ disc) {
+                                    const double* __restrict__ nx2, const double* __restrict__ trace_ref,
+                                    int64_t* __restrict__ Rout, double* __restrict__ disc) {
   if (threadIdx.x != 0) return;
   if (nx2 != nullptr) thr *= *nx2;
-  // smallest R in 1..J with sum_{i>=R} max(lam_i, 0) <= thr (lam descending)
-  double tail = 0.0, tailR = 0.0;
   int R = J;
-  for (int r = J - 1; r >= 1; --r) {
-    tail += fmax(lam[r], 0.0);
-    if (tail <= thr) {
-      R = r;
-      tailR = tail;
-    } else {
-      break;
+  double tailR = 0.0;
+  if (trace_ref == nullptr) {
+    // smallest R in 1..J with sum_{i>=R} max(lam_i, 0) <= thr (lam descending)
+    double tail = 0.0;
+    for (int r = J - 1; r >= 1; --r) {
+      tail += fmax(lam[r], 0.0);
+      if (tail <= thr) {
+        R = r;
+        tailR = tail;
+      } else {
+        break;
+      }
+    }
+  } else {
+    const double tr = *trace_ref;
+    double head = 0.0;
+    for (int r = 1; r < J; ++r) {
+      head += fmax(lam[r - 1], 0.0);
+      const double tail = fmax(tr - head, 0.0);
+      if (tail <= thr) {
+        R = r;
+        tailR = tail;
+        break;
+      }
     }
   }
   *Rout = R;
@@ -670,8 +692,9 @@ void eig_work_carve(double* base, int64_t J, EigWork& w) {
   w.scal = w.tau + J;
 }
 
-hipError_t launch_eig_truncate(const double* S, int J, double thr, const double* nx2, const EigWork& w,
-                               double* lam, double* U, int64_t* R, double* disc, hipStream_t stream) {
+hipError_t launch_eig_truncate(const double* S, int J, double thr, const double* nx2, const double* trace_ref,
+                               const EigWork& w, double* lam, double* U, int64_t* R, double* disc,
+                               hipStream_t stream) {
   if (J <= kRegMaxJ) {
     // phases: each register configuration reduces until the trailing block
     // fits the next smaller one
@@ -704,7 +727,7 @@ hipError_t launch_eig_truncate(const double* S, int J, double thr, const double*
   const size_t shb = sizeof(double) * (2 * (size_t)J + 4);
   hipLaunchKernelGGL(eig_bisect_kernel, dim3(ceil_div(J, 256 / kBisLanes)), dim3(256), shb, stream, w.d, w.e, J,
                      lam, w.scal);
-  hipLaunchKernelGGL(eig_truncate_kernel, dim3(1), dim3(64), 0, stream, lam, J, thr, nx2, R, disc);
+  hipLaunchKernelGGL(eig_truncate_kernel, dim3(1), dim3(64), 0, stream, lam, J, thr, nx2, trace_ref, R, disc);
   {
     const int nvw = (int)std::max<int64_t>(1, std::min<int64_t>(64, (128 * 1024) / (32 * (int64_t)J)));
     const size_t shi = sizeof(double) * 4 * (size_t)J * nvw;

@@ -1,18 +1,529 @@
-// Mixed-precision Gram (FP32 inputs): placeholder until the FP32/BF16x3 MFMA
-// kernels are in place; reports "not supported".
+// Gram matrix S = Y_(n) Y_(n)^T (Alg. 2) for the reduced-precision forms and
+// for FP64 with large mode sizes.  Arithmetic forms:
+//   FP64   : v_mfma_f64_16x16x4f64 with FP64 accumulation;
+//   FP32   : v_mfma_f32_16x16x4f32 on FP32 values, FP32 accumulation over
+//            one 32-column chunk, the chunk sum promoted to FP64;
+//   BF16X3 : every FP32 value x is split into b0 = bf16(x), b1 = bf16(x - b0)
+//            and a product x*y is formed as b1 c0 + b0 c1 + b0 c0 with
+//            v_mfma_f32_16x16x32_bf16 (the split-product scheme of Henry,
+//            Tang and Heinecke, ARITH 2019); FP32 accumulation over groups of
+//            8 chunks (256 columns), FP64 across groups;
+//   BF16X6 : adds a third piece b2 = bf16(x - b0 - b1) and the products
+//            b1 c1, b0 c2, b2 c0, which removes the bias of BF16X3 (the
+//            dropped b1 c1 term is a Gram matrix of residuals, hence positive
+//            semidefinite); FP32 accumulation per chunk, FP64 across chunks.
+// The sum of squares ||Y||^2 is always accumulated in FP64 from the values as
+// loaded.
+//
+// Work decomposition.  Triangle mode (J <= 128): one workgroup covers the
+// whole upper triangle of 16 x 16 blocks for its range of column chunks.
+// Pair mode (J > 128): rows are cut into 128-row tiles and a work item is a
+// tile pair (ta <= tb) with a range of chunks; an off-diagonal pair has 8 x 8
+// blocks, wave w taking row w of them so that its A operand is loaded from LDS
+// once per step; a diagonal pair has the 36 blocks of an upper triangle.  The
+// items of one split are numbered consecutively and placed on one XCD so that
+// pairs sharing a tile share its L2.  Eight waves per workgroup; LDS holds the
+// current chunk of rows, double-buffered with one barrier per chunk; global
+// loads walk the contiguous axis of the unfolding.  Every item writes its FP64
+// partial blocks and a second kernel sums the splits in a fixed order.
+#include <type_traits>
+
 #include "common.hpp"
 #include "kernels.hpp"
 
 namespace tk {
 
-GramPlan plan_gram_mixed(int J, uint64_t L, uint64_t K) {
-  GramPlan p = plan_gram_f64(J, L, K);
+namespace {
+
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+
+constexpr int kWaves = 8;
+constexpr int kNT = 64 * kWaves;
+
+template <int PREC>
+struct Cfg;
+template <>
+struct Cfg<0> {  // FP64
+  static constexpr int KC = 16, LR = 18, PLANES = 1, GROUP = 1;
+  using elem = double;
+};
+template <>
+struct Cfg<1> {  // FP32: promote every chunk (32 columns)
+  static constexpr int KC = 32, LR = 36, PLANES = 1, GROUP = 1;
+  using elem = float;
+};
+template <>
+struct Cfg<2> {  // BF16X3 (80-byte rows: conflict-free 16-byte reads); promote every 8 chunks
+  static constexpr int KC = 32, LR = 40, PLANES = 2, GROUP = 8;
+  using elem = __bf16;
+};
+template <>
+struct Cfg<3> {  // BF16X6: promote every chunk
+  static constexpr int KC = 32, LR = 40, PLANES = 3, GROUP = 1;
+  using elem = __bf16;
+};
+
+struct MPParams {
+  const void* Y;
+  int J;
+  uint32_t L, K;
+  int ntiles;  // pair mode: 128-row tiles
+  int npairs;  // pair mode: tile pairs; triangle mode: 1
+  int nblk;    // partial blocks per item
+  int64_t nchunks, cps, total;
+  double* part;
+  double* sq;  // one value per item (zero for items that do not own their rows), or null
+};
+
+__device__ __forceinline__ void decode_pair(int p, int ntiles, int& ta, int& tb) {
+  int t = 0;
+  while (p >= ntiles - t) {
+    p -= ntiles - t;
+    ++t;
+  }
+  ta = t;
+  tb = t + p;
+}
+
+template <int PREC>
+__device__ __forceinline__ void put(typename Cfg<PREC>::elem* s, int plane_stride, int o, double v) {
+  if constexpr (PREC == 0) {
+    s[o] = v;
+  } else if constexpr (PREC == 1) {
+    s[o] = (float)v;
+  } else {
+    const float x = (float)v;
+    const __bf16 b0 = (__bf16)x;
+    const float r1 = x - (float)b0;  // exact
+    const __bf16 b1 = (__bf16)r1;
+    s[o] = b0;
+    s[o + plane_stride] = b1;
+    if constexpr (PREC == 3) s[o + 2 * plane_stride] = (__bf16)(r1 - (float)b1);
+  }
+}
+
+// Main loop and output of one work item.  SHARED_A: all slots of the wave have
+// the same block row (off-diagonal pairs), so the A operand is loaded once.
+template <typename T, int PREC, int ROWS, int NBW, bool SHARED_A, bool UNIT_L>
+__device__ __forceinline__ void gram_body(const MPParams& g, int64_t item, int64_t split, bool diag, int ra, int rb,
+                                          int NR, int nbl, typename Cfg<PREC>::elem* sY, double* sred) {
+  using C = Cfg<PREC>;
+  using E_t = typename C::elem;
+  constexpr int KC = C::KC, LR = C::LR, PL = C::PLANES;
+  constexpr int PS = ROWS * LR;       // plane stride
+  constexpr int BS = PL * PS;         // buffer stride
+  constexpr int E = ROWS * KC / kNT;  // loaded values per thread and chunk
+
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int J = g.J;
+  const uint32_t L = g.L, K = g.K;
+  const int64_t JL = (int64_t)J * L;
+
+  // this wave's block range [q0, q0 + nq) and its blocks (bI, bJ) in local rows
+  const int nblk = diag ? nbl * (nbl + 1) / 2 : 64;
+  int q0, nq;
+  int bI[NBW], bJ[NBW];
+  if constexpr (SHARED_A) {
+    q0 = 8 * wave;
+    nq = 8;
+#pragma unroll
+    for (int t = 0; t < NBW; ++t) {
+      bI[t] = wave;
+      bJ[t] = 8 + t;
+    }
+  } else {
+    q0 = (int)(((int64_t)nblk * wave) / kWaves);
+    nq = (int)(((int64_t)nblk * (wave + 1)) / kWaves) - q0;
+    int bi = 0, bj = 0;
+    for (int qq = 0; qq < q0; ++qq)
+      if (++bj == nbl) {
+        ++bi;
+        bj = bi;
+      }
+#pragma unroll
+    for (int t = 0; t < NBW; ++t) {  // slots past nq repeat the last block and are not stored
+      bI[t] = bi;
+      bJ[t] = bj;
+      if (t + 1 < nq && ++bj == nbl) {
+        ++bi;
+        bj = bi;
+      }
+    }
+  }
+
+  // loader: value p of this thread is (local row, chunk column); rows >= NR are padding
+  int eoff[E], ek[E], egrow[E];
+#pragma unroll
+  for (int p = 0; p < E; ++p) {
+    int lr, k;
+    if constexpr (UNIT_L) {
+      const int e = tid + kNT * p;
+      const bool ok = e < NR * KC;
+      lr = ok ? e % NR : NR;
+      k = ok ? e / NR : 0;
+    } else {
+      k = tid % KC;
+      lr = tid / KC + (kNT / KC) * p;
+      if (lr > NR) lr = NR;
+    }
+    ek[p] = k;
+    eoff[p] = (lr < NR) ? lr * LR + k : -1;
+    int gr = J;
+    if (lr < NR) gr = (lr < 128 || diag) ? ra + lr : rb + (lr - 128);
+    egrow[p] = gr;
+  }
+
+  const int64_t ch_begin = split * g.cps;
+  const int64_t ch_end = min(ch_begin + g.cps, g.nchunks);
+  const T* __restrict__ Y = static_cast<const T*>(g.Y);
+  double rv[E];
+  double sq = 0.0;
+
+  d4 acc64[NBW];
+  f4 acc32[NBW];
+#pragma unroll
+  for (int t = 0; t < NBW; ++t) {
+    acc64[t] = d4{0.0, 0.0, 0.0, 0.0};
+    acc32[t] = f4{0.f, 0.f, 0.f, 0.f};
+  }
+  const int i = lane & 15, q = lane >> 4;
+  int group_left = C::GROUP;
+
+  for (int64_t ch = ch_begin; ch <= ch_end; ++ch) {
+    // ch < ch_end: load chunk ch into registers; ch > ch_begin: compute chunk ch-1
+    if (ch < ch_end) {
+#pragma unroll
+      for (int p = 0; p < E; ++p) {
+        const int gr = egrow[p];
+        const int64_t c = ch * KC + ek[p];
+        double v = 0.0;
+        if (gr < J && c < (int64_t)K) {
+          int64_t addr;
+          if constexpr (UNIT_L) {
+            addr = (int64_t)gr + (int64_t)J * c;
+          } else {
+            const uint32_t cc = (uint32_t)c;
+            const uint32_t r = cc / L, l = cc - r * L;
+            addr = (int64_t)l + JL * r + (int64_t)L * gr;
+          }
+          v = (double)Y[addr];
+        }
+        rv[p] = v;
+      }
+    }
+    if (ch > ch_begin) {
+      const E_t* s = sY + ((ch - 1) & 1) * BS;
+      if constexpr (PREC == 0) {
+#pragma unroll
+        for (int st = 0; st < KC / 4; ++st) {
+          double av = 0.0;
+          if constexpr (SHARED_A) av = s[(16 * bI[0] + i) * LR + 4 * st + q];
+#pragma unroll
+          for (int t = 0; t < NBW; ++t) {
+            if constexpr (!SHARED_A) av = s[(16 * bI[t] + i) * LR + 4 * st + q];
+            const double bv = s[(16 * bJ[t] + i) * LR + 4 * st + q];
+            acc64[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc64[t], 0, 0, 0);
+          }
+          __builtin_amdgcn_sched_barrier(0);
+        }
+      } else if constexpr (PREC == 1) {
+#pragma unroll
+        for (int st = 0; st < KC / 4; ++st) {
+          float av = 0.f;
+          if constexpr (SHARED_A) av = s[(16 * bI[0] + i) * LR + 4 * st + q];
+#pragma unroll
+          for (int t = 0; t < NBW; ++t) {
+            if constexpr (!SHARED_A) av = s[(16 * bI[t] + i) * LR + 4 * st + q];
+            const float bv = s[(16 * bJ[t] + i) * LR + 4 * st + q];
+            acc32[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc32[t], 0, 0, 0);
+          }
+          __builtin_amdgcn_sched_barrier(0);
+        }
+      } else {
+        // K = 32 per MFMA: lane (i, q) supplies columns 8q .. 8q+7 of its row
+        bf8 a0, a1, a2;
+        if constexpr (SHARED_A) {
+          const int oa = (16 * bI[0] + i) * LR + 8 * q;
+          a0 = *reinterpret_cast<const bf8*>(s + oa);
+          a1 = *reinterpret_cast<const bf8*>(s + PS + oa);
+          if constexpr (PREC == 3) a2 = *reinterpret_cast<const bf8*>(s + 2 * PS + oa);
+        }
+#pragma unroll
+        for (int t = 0; t < NBW; ++t) {
+          if constexpr (!SHARED_A) {
+            const int oa = (16 * bI[t] + i) * LR + 8 * q;
+            a0 = *reinterpret_cast<const bf8*>(s + oa);
+            a1 = *reinterpret_cast<const bf8*>(s + PS + oa);
+            if constexpr (PREC == 3) a2 = *reinterpret_cast<const bf8*>(s + 2 * PS + oa);
+          }
+          const int ob = (16 * bJ[t] + i) * LR + 8 * q;
+          const bf8 b0 = *reinterpret_cast<const bf8*>(s + ob);
+          const bf8 b1 = *reinterpret_cast<const bf8*>(s + PS + ob);
+          f4 a = acc32[t];
+          if constexpr (PREC == 3) {
+            const bf8 b2 = *reinterpret_cast<const bf8*>(s + 2 * PS + ob);
+            a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a2, b0, a, 0, 0, 0);
+            a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b2, a, 0, 0, 0);
+            a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b1, a, 0, 0, 0);
+          }
+          a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b0, a, 0, 0, 0);
+          a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b1, a, 0, 0, 0);
+          a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b0, a, 0, 0, 0);
+          acc32[t] = a;
+          __builtin_amdgcn_sched_barrier(0);
+        }
+      }
+      if constexpr (PREC != 0) {
+        if (--group_left == 0 || ch == ch_end) {  // promote the group sum to FP64
+          group_left = C::GROUP;
+#pragma unroll
+          for (int t = 0; t < NBW; ++t) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc64[t][v] += (double)acc32[t][v];
+            acc32[t] = f4{0.f, 0.f, 0.f, 0.f};
+          }
+        }
+      }
+    }
+    if (ch < ch_end) {
+      // registers -> LDS buffer (ch & 1); its previous contents (chunk ch-2)
+      // were consumed before the barrier of the previous iteration
+      E_t* s = sY + (ch & 1) * BS;
+#pragma unroll
+      for (int p = 0; p < E; ++p) {
+        if (eoff[p] >= 0) put<PREC>(s, PS, eoff[p], rv[p]);
+        sq += rv[p] * rv[p];
+      }
+      lds_barrier();
+    }
+  }
+
+  // partial blocks.  f64 MFMA result: lane l, register v -> D[(l>>4)+4v][l&15];
+  // f32 MFMA result: lane l, register v -> D[4(l>>4)+v][l&15].
+  double* __restrict__ P = g.part + item * (int64_t)g.nblk * 256;
+#pragma unroll
+  for (int t = 0; t < NBW; ++t) {
+    if (t < nq) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = (PREC == 0) ? (q + 4 * v) : (4 * q + v);
+        P[(int64_t)(q0 + t) * 256 + row * 16 + i] = acc64[t][v];
+      }
+    }
+  }
+  if (g.sq != nullptr) {
+    // padding rows and columns load zeros; rows of an off-diagonal pair are
+    // counted by the diagonal pairs
+    const double w = wave_sum(diag ? sq : 0.0);
+    if (lane == 0) sred[wave] = w;
+    __syncthreads();
+    if (tid == 0) {
+      double tot = 0.0;
+      for (int w2 = 0; w2 < kWaves; ++w2) tot += sred[w2];
+      g.sq[item] = tot;
+    }
+  }
+}
+
+// Triangle mode: J <= 128, one item per split.
+template <typename T, int PREC, int NBW, bool UNIT_L>
+__global__ __launch_bounds__(kNT) void gram_mp_tri_kernel(MPParams g) {
+  using C = Cfg<PREC>;
+  __shared__ typename C::elem sY[2 * C::PLANES * 128 * C::LR];
+  __shared__ double sred[kWaves];
+  const int NR = (g.J + 15) & ~15;
+  gram_body<T, PREC, 128, NBW, false, UNIT_L>(g, blockIdx.x, blockIdx.x, true, 0, 0, NR, NR / 16, sY, sred);
+}
+
+// Pair mode: J > 128, items (split, tile pair) placed split-major on XCDs.
+template <typename T, int PREC, bool UNIT_L>
+__global__ __launch_bounds__(kNT) void gram_mp_pair_kernel(MPParams g) {
+  using C = Cfg<PREC>;
+  __shared__ typename C::elem sY[2 * C::PLANES * 256 * C::LR];
+  __shared__ double sred[kWaves];
+  const int64_t item = xcd_remap(blockIdx.x, gridDim.x, g.total);
+  if (item < 0) return;
+  const int pair = (int)(item % g.npairs);
+  const int64_t split = item / g.npairs;
+  int ta, tb;
+  decode_pair(pair, g.ntiles, ta, tb);
+  if (ta == tb)
+    gram_body<T, PREC, 256, 5, false, UNIT_L>(g, item, split, true, 128 * ta, 128 * ta, 128, 8, sY, sred);
+  else
+    gram_body<T, PREC, 256, 8, true, UNIT_L>(g, item, split, false, 128 * ta, 128 * tb, 256, 8, sY, sred);
+}
+
+// Sum the partial blocks of all splits in a fixed order; write both triangles.
+__global__ __launch_bounds__(256) void gram_mp_reduce_kernel(const double* __restrict__ part, int tri, int ntiles,
+                                                             int npairs, int nblk, int64_t nsplit, int J,
+                                                             double* __restrict__ S) {
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= (int64_t)npairs * nblk * 256) return;
+  const int pair = (int)(idx / ((int64_t)nblk * 256));
+  const int qrem = (int)(idx - (int64_t)pair * nblk * 256);
+  const int qb = qrem >> 8, rem = qrem & 255;
+  int ra = 0, rb = 0, nbl;
+  bool diag = true;
+  if (tri) {
+    nbl = ((J + 15) & ~15) / 16;
+  } else {
+    int ta, tb;
+    decode_pair(pair, ntiles, ta, tb);
+    ra = 128 * ta;
+    rb = 128 * tb;
+    diag = (ta == tb);
+    nbl = 8;
+  }
+  int bi, bj;
+  if (diag) {
+    if (qb >= nbl * (nbl + 1) / 2) return;
+    int qq = qb;
+    bi = 0;
+    while (qq >= nbl - bi) {
+      qq -= nbl - bi;
+      ++bi;
+    }
+    bj = bi + qq;
+  } else {
+    bi = qb / 8;
+    bj = 8 + qb % 8;
+  }
+  const int r = rem >> 4, c = rem & 15;
+  const int a = ra + 16 * bi + r;
+  const int b = diag ? ra + 16 * bj + c : rb + 16 * (bj - 8) + c;
+  if (a >= J || b >= J || (diag && bi == bj && r > c)) return;
+  double s = 0.0;
+  for (int64_t sp = 0; sp < nsplit; ++sp) s += part[((sp * npairs + pair) * nblk + qb) * 256 + rem];
+  S[(int64_t)a * J + b] = s;
+  S[(int64_t)b * J + a] = s;
+}
+
+template <typename T, int PREC>
+void launch_main(const MPParams& g, bool tri, bool unit, int64_t grid, hipStream_t s) {
+  if (tri) {
+    const int nbw = (int)ceil_div(g.nblk, kWaves);
+#define TRI_L(NBW)                                                                                           \
+  do {                                                                                                       \
+    if (unit) hipLaunchKernelGGL((gram_mp_tri_kernel<T, PREC, NBW, true>), dim3(grid), dim3(kNT), 0, s, g);  \
+    else hipLaunchKernelGGL((gram_mp_tri_kernel<T, PREC, NBW, false>), dim3(grid), dim3(kNT), 0, s, g);      \
+  } while (0)
+    if (nbw <= 2) TRI_L(2);
+    else TRI_L(5);
+#undef TRI_L
+  } else {
+    if (unit) hipLaunchKernelGGL((gram_mp_pair_kernel<T, PREC, true>), dim3(grid), dim3(kNT), 0, s, g);
+    else hipLaunchKernelGGL((gram_mp_pair_kernel<T, PREC, false>), dim3(grid), dim3(kNT), 0, s, g);
+  }
+}
+
+}  // namespace
+
+GramPlan plan_gram_mp(int J, uint64_t K, int prec) {
+  GramPlan p{};
+  const int KC = (prec == 0) ? 16 : 32;
+  p.nchunks = ceil_div((int64_t)K, KC);
+  int64_t nblk;
+  if (J <= 128) {
+    p.tile = 0;
+    p.ntiles = 1;
+    p.npairs = 1;
+    const int nb = (J + 15) / 16;
+    nblk = (int64_t)nb * (nb + 1) / 2;
+  } else {
+    p.tile = 128;
+    p.ntiles = (int)ceil_div(J, 128);
+    p.npairs = p.ntiles * (p.ntiles + 1) / 2;
+    nblk = 64;
+  }
+  // about two workgroups per CU, at least 8 chunks per item
+  int64_t nsplit = std::max<int64_t>(1, 512 / p.npairs);
+  nsplit = std::min<int64_t>(nsplit, std::max<int64_t>(1, p.nchunks / 8));
+  p.cps = ceil_div(p.nchunks, nsplit);
+  p.nsplit = ceil_div(p.nchunks, p.cps);
+  p.part_elems = p.nsplit * p.npairs * nblk * 256;
+  p.sq_elems = p.nsplit * p.npairs;
   return p;
 }
 
-hipError_t launch_gram_mixed(const float*, int, uint64_t, uint64_t, int, const GramPlan&, double*, double*, double*,
-                             double*, hipStream_t, hipEvent_t) {
-  return hipErrorNotSupported;
+template <typename T>
+hipError_t launch_gram_mp(const T* Y, int J, uint64_t L, uint64_t K, int prec, const GramPlan& p, double* part,
+                          double* sq, double* S, double* norm2, hipStream_t stream, hipEvent_t after_main) {
+  MPParams g{};
+  g.Y = Y;
+  g.J = J;
+  g.L = (uint32_t)L;
+  g.K = (uint32_t)K;
+  const bool tri = (p.tile == 0);
+  g.ntiles = p.ntiles;
+  g.npairs = p.npairs;
+  const int nb = (J + 15) / 16;
+  g.nblk = tri ? nb * (nb + 1) / 2 : 64;
+  g.nchunks = p.nchunks;
+  g.cps = p.cps;
+  g.total = p.nsplit * p.npairs;
+  g.part = part;
+  g.sq = norm2 ? sq : nullptr;
+  const int64_t grid = tri ? p.nsplit : ceil_div(g.total, kXcds) * kXcds;
+  const bool unit = (L == 1);
+  if constexpr (std::is_same<T, double>::value) {
+    if (prec != 0) return hipErrorInvalidValue;  // the reduced forms read FP32 data
+    launch_main<T, 0>(g, tri, unit, grid, stream);
+  } else {
+    switch (prec) {
+      case 0: launch_main<T, 0>(g, tri, unit, grid, stream); break;
+      case 1: launch_main<T, 1>(g, tri, unit, grid, stream); break;
+      case 2: launch_main<T, 2>(g, tri, unit, grid, stream); break;
+      default: launch_main<T, 3>(g, tri, unit, grid, stream); break;
+    }
+  }
+  if (after_main) (void)hipEventRecord(after_main, stream);
+  const int64_t nel = (int64_t)p.npairs * g.nblk * 256;
+  hipLaunchKernelGGL(gram_mp_reduce_kernel, dim3(ceil_div(nel, 256)), dim3(256), 0, stream, part, tri ? 1 : 0,
+                     g.ntiles, g.npairs, g.nblk, p.nsplit, J, S);
+  if (norm2) hipLaunchKernelGGL(sum_fixed_kernel, dim3(1), dim3(256), 0, stream, sq, g.total, norm2);
+  return hipGetLastError();
 }
+
+// Range guard of a reduced-precision Gram: flag = 1 and S zeroed if an entry
+// is not finite or trace(S) differs from the FP64 sum of squares by more
+// than 1e-3 relative; flag = 0 otherwise.  One workgroup.
+__global__ __launch_bounds__(256) void gram_guard_kernel(double* __restrict__ S, int J,
+                                                         const double* __restrict__ sq, double* __restrict__ flag) {
+  __shared__ double str[256];
+  __shared__ int sbad[256];
+  const int tid = threadIdx.x;
+  const int64_t JJ = (int64_t)J * J;
+  int bad = 0;
+  for (int64_t e = tid; e < JJ; e += 256)
+    if (!isfinite(S[e])) bad = 1;
+  double tr = 0.0;
+  for (int a = tid; a < J; a += 256) tr += S[(int64_t)a * J + a];
+  str[tid] = tr;
+  sbad[tid] = bad;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (tid < w) {
+      str[tid] += str[tid + w];
+      sbad[tid] |= sbad[tid + w];
+    }
+    __syncthreads();
+  }
+  const double ref = *sq;
+  const bool fire = sbad[0] != 0 || !(fabs(str[0] - ref) <= 1e-3 * ref);
+  if (fire)
+    for (int64_t e = tid; e < JJ; e += 256) S[e] = 0.0;
+  if (tid == 0) *flag = fire ? 1.0 : 0.0;
+}
+
+hipError_t launch_gram_guard(double* S, int J, const double* sq, double* flag, hipStream_t stream) {
+  hipLaunchKernelGGL(gram_guard_kernel, dim3(1), dim3(256), 0, stream, S, J, sq, flag);
+  return hipGetLastError();
+}
+
+template hipError_t launch_gram_mp<float>(const float*, int, uint64_t, uint64_t, int, const GramPlan&, double*,
+                                          double*, double*, double*, hipStream_t, hipEvent_t);
+template hipError_t launch_gram_mp<double>(const double*, int, uint64_t, uint64_t, int, const GramPlan&, double*,
+                                           double*, double*, double*, hipStream_t, hipEvent_t);
 
 }  // namespace tk

@@ -40,20 +40,28 @@ template <typename T>
 hipError_t launch_gram_f64(const T* Y, int J, uint64_t L, uint64_t K, const GramPlan& p, double* part,
                            double* sq, double* S, double* norm2, hipStream_t stream, hipEvent_t after_main);
 
-// Mixed-precision Gram (FP32 inputs): FP32 MFMA or BF16x3 MFMA products,
-// FP32 accumulation within a chunk group, FP64 across groups.
-GramPlan plan_gram_mixed(int J, uint64_t L, uint64_t K);
-hipError_t launch_gram_mixed(const float* Y, int J, uint64_t L, uint64_t K, int prec, const GramPlan& p,
-                             double* part, double* sq, double* S, double* norm2, hipStream_t stream,
-                             hipEvent_t after_main);
+// Gram in one of four arithmetic forms (0 FP64, 1 FP32 MFMA, 2 BF16x3,
+// 3 BF16x6), FP32 accumulation within a chunk group and FP64 across groups
+// for the reduced forms.  Handles any J (triangle mode J <= 128, 128-row tile
+// pairs above).  T = float or double input.
+GramPlan plan_gram_mp(int J, uint64_t K, int prec);
+template <typename T>
+hipError_t launch_gram_mp(const T* Y, int J, uint64_t L, uint64_t K, int prec, const GramPlan& p, double* part,
+                          double* sq, double* S, double* norm2, hipStream_t stream, hipEvent_t after_main);
+
+// Range guard of a reduced-precision Gram (one workgroup): if S has a
+// non-finite entry or |trace(S) - *sq| > 1e-3 *sq, zero S and set *flag = 1,
+// else *flag = 0.
+hipError_t launch_gram_guard(double* S, int J, const double* sq, double* flag, hipStream_t stream);
 
 __global__ void sum_fixed_kernel(const double* __restrict__ x, int64_t n, double* __restrict__ out);
 
 // ---------------------------------------------------------------- TTM
 // Z_(n) = M Y_(n);  M is K x J with element (k,j) at M[k*msk + j*msj].
+// fp32_products: FP32 MFMA products (M and Y rounded to FP32), else FP64.
 template <typename TI, typename TO>
 hipError_t launch_ttm(const TI* Y, int J, uint64_t L, uint64_t cols, const double* M, int64_t msk, int64_t msj,
-                      int K, TO* Z, hipStream_t stream);
+                      int K, TO* Z, bool fp32_products, hipStream_t stream);
 
 // ---------------------------------------------------------------- eigensolver
 struct EigWork {
@@ -67,8 +75,11 @@ struct EigWork {
 int64_t eig_work_doubles(int64_t J);
 void eig_work_carve(double* base, int64_t J, EigWork& w);
 // S (J x J, device) -> lam (desc), U (J x J, first R columns), R, disc.
-// Threshold: thr, or thr * (*nx2) if nx2 (device) is non-null.
-hipError_t launch_eig_truncate(const double* S, int J, double thr, const double* nx2, const EigWork& w,
-                               double* lam, double* U, int64_t* R, double* disc, hipStream_t stream);
+// Threshold: thr, or thr * (*nx2) if nx2 (device) is non-null.  trace_ref
+// (device, may be null): tail sums taken as *trace_ref minus the leading
+// eigenvalues (for Grams computed in reduced precision).
+hipError_t launch_eig_truncate(const double* S, int J, double thr, const double* nx2, const double* trace_ref,
+                               const EigWork& w, double* lam, double* U, int64_t* R, double* disc,
+                               hipStream_t stream);
 
 }  // namespace tk

@@ -6,8 +6,9 @@
 //
 // Kernel design (gfx950): the shrinking TTM is bound by reading Y once from
 // HBM, so Y is not staged through LDS.  Each wave owns 16 output columns and
-// up to 4 blocks of 16 output rows (v_mfma_f64_16x16x4f64) and loads its MFMA
-// B operands straight from global memory.  Since the reduction index of an
+// up to 4 blocks of 16 output rows (v_mfma_f64_16x16x4f64, or
+// v_mfma_f32_16x16x4f32 for the reduced-precision path, which has the same
+// operand layout) and loads its MFMA B operands straight from global memory.  Since the reduction index of an
 // MFMA may be assigned to (step, lane group) in any order, it is chosen so
 // that loads run along the contiguous axis:
 //   L = 1 (columns contiguous along j): lane group q of step s reads row
@@ -35,12 +36,35 @@ __device__ __forceinline__ void store_as(T* p, double v) {
   *p = static_cast<T>(v);
 }
 
+template <typename CT>
+struct Acc;
+template <>
+struct Acc<double> {
+  using type = d4;
+  static __device__ __forceinline__ d4 mfma(double a, double b, d4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  // result layout: lane l, register v holds D[(l >> 4) + 4 v][l & 15]
+  static __device__ __forceinline__ int row(int q, int v) { return q + 4 * v; }
+};
+template <>
+struct Acc<float> {
+  using type = f4;
+  static __device__ __forceinline__ f4 mfma(float a, float b, f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  // result layout: lane l, register v holds D[4 (l >> 4) + v][l & 15]
+  static __device__ __forceinline__ int row(int q, int v) { return 4 * q + v; }
+};
+
+// CT: arithmetic type of the products (double: FP64 MFMA; float: FP32 MFMA).
 // RB: 16-row output blocks per wave (1..4), chosen from K at launch.
-template <typename TI, typename TO, bool UNIT_L, int RB>
+template <typename TI, typename TO, typename CT, bool UNIT_L, int RB>
 __global__ __launch_bounds__(256) void ttm_kernel(const TI* __restrict__ Y, int J, uint32_t L, uint32_t cols,
                                                   const double* __restrict__ M, int64_t msk, int64_t msj, int K,
                                                   TO* __restrict__ Z, int nrt, int64_t total) {
-  __shared__ double sM[kTK * kMS];  // M block: 64 output rows x 64 reduction rows
+  using A = Acc<CT>;
+  __shared__ CT sM[kTK * kMS];  // M block: 64 output rows x 64 reduction rows
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t item = xcd_remap(blockIdx.x, gridDim.x, total);
   if (item < 0) return;
@@ -64,27 +88,27 @@ __global__ __launch_bounds__(256) void ttm_kernel(const TI* __restrict__ Y, int 
       cbase = (int64_t)l + JL * r;
     }
   }
-  d4 acc[RB];
+  typename A::type acc[RB];
 #pragma unroll
-  for (int b = 0; b < RB; ++b) acc[b] = d4{0.0, 0.0, 0.0, 0.0};
+  for (int b = 0; b < RB; ++b) acc[b] = typename A::type{0, 0, 0, 0};
 
   for (int jb = 0; jb < J; jb += kJB) {
     // Y operands of the four 16-row chunks of this block (row of (chunk t, step s)
     // is jb + 16 t + 4 q + s for L = 1 and jb + 16 t + 4 s + q otherwise)
-    double yv[4][4];
+    CT yv[4][4];
 #pragma unroll
     for (int t = 0; t < 4; ++t)
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
         const int j = jb + 16 * t + (UNIT_L ? 4 * q + s : 4 * s + q);
-        yv[t][s] = (cok && j < J) ? to_f64(Y[cbase + (UNIT_L ? (int64_t)j : (int64_t)L * j)]) : 0.0;
+        yv[t][s] = (cok && j < J) ? (CT)Y[cbase + (UNIT_L ? (int64_t)j : (int64_t)L * j)] : (CT)0;
       }
     // M block into LDS: sM[k][j] = M(k0 + k, jb + j)
     __syncthreads();
     for (int e = tid; e < 16 * RB * kJB; e += 256) {
       const int kk = e / kJB, jj = e - kk * kJB;
       const int k = k0 + kk, j = jb + jj;
-      sM[kk * kMS + jj] = (k < K && j < J) ? M[(int64_t)k * msk + (int64_t)j * msj] : 0.0;
+      sM[kk * kMS + jj] = (k < K && j < J) ? (CT)M[(int64_t)k * msk + (int64_t)j * msj] : (CT)0;
     }
     __syncthreads();
 #pragma unroll
@@ -94,14 +118,12 @@ __global__ __launch_bounds__(256) void ttm_kernel(const TI* __restrict__ Y, int 
         const int jj = 16 * t + (UNIT_L ? 4 * q + s : 4 * s + q);
 #pragma unroll
         for (int b = 0; b < RB; ++b) {
-          const double av = sM[(16 * b + i) * kMS + jj];
-          acc[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, yv[t][s], acc[b], 0, 0, 0);
+          acc[b] = A::mfma(sM[(16 * b + i) * kMS + jj], yv[t][s], acc[b]);
         }
       }
   }
 
-  // f64 MFMA result: lane l, register v holds D[(l >> 4) + 4 v][l & 15]
-  // (output row k0 + 16 b + (l >> 4) + 4 v, output column c0 + (l & 15))
+  // output row k0 + 16 b + A::row(l >> 4, v), output column c0 + (l & 15)
   if (!cok) return;
   int64_t zb;
   int64_t kstride;
@@ -118,24 +140,22 @@ __global__ __launch_bounds__(256) void ttm_kernel(const TI* __restrict__ Y, int 
   for (int b = 0; b < RB; ++b)
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const int k = k0 + 16 * b + q + 4 * v;
-      if (k < K) store_as(&Z[zb + kstride * k], acc[b][v]);
+      const int k = k0 + 16 * b + A::row(q, v);
+      if (k < K) store_as(&Z[zb + kstride * k], (double)acc[b][v]);
     }
 }
 
-}  // namespace
-
-template <typename TI, typename TO>
-hipError_t launch_ttm(const TI* Y, int J, uint64_t L, uint64_t cols, const double* M, int64_t msk, int64_t msj,
-                      int K, TO* Z, hipStream_t stream) {
+template <typename TI, typename TO, typename CT>
+hipError_t launch_ttm_ct(const TI* Y, int J, uint64_t L, uint64_t cols, const double* M, int64_t msk, int64_t msj,
+                         int K, TO* Z, hipStream_t stream) {
   const int nrt = (int)ceil_div(K, kTK);
   const int64_t nct = ceil_div((int64_t)cols, 16 * kWaves);
   const int64_t total = nct * nrt;
   const int64_t grid = ceil_div(total, kXcds) * kXcds;
   const int rb = (K >= kTK) ? 4 : (int)ceil_div(K, 16);
-#define TTM_LAUNCH(U, RBV)                                                                                     \
-  hipLaunchKernelGGL((ttm_kernel<TI, TO, U, RBV>), dim3(grid), dim3(64 * kWaves), 0, stream, Y, J, (uint32_t)L, \
-                     (uint32_t)cols, M, msk, msj, K, Z, nrt, total)
+#define TTM_LAUNCH(U, RBV)                                                                                   \
+  hipLaunchKernelGGL((ttm_kernel<TI, TO, CT, U, RBV>), dim3(grid), dim3(64 * kWaves), 0, stream, Y, J,        \
+                     (uint32_t)L, (uint32_t)cols, M, msk, msj, K, Z, nrt, total)
   if (L == 1) {
     if (rb == 1) TTM_LAUNCH(true, 1);
     else if (rb == 2) TTM_LAUNCH(true, 2);
@@ -151,13 +171,22 @@ hipError_t launch_ttm(const TI* Y, int J, uint64_t L, uint64_t cols, const doubl
   return hipGetLastError();
 }
 
+}  // namespace
+
+template <typename TI, typename TO>
+hipError_t launch_ttm(const TI* Y, int J, uint64_t L, uint64_t cols, const double* M, int64_t msk, int64_t msj,
+                      int K, TO* Z, bool fp32_products, hipStream_t stream) {
+  if (fp32_products) return launch_ttm_ct<TI, TO, float>(Y, J, L, cols, M, msk, msj, K, Z, stream);
+  return launch_ttm_ct<TI, TO, double>(Y, J, L, cols, M, msk, msj, K, Z, stream);
+}
+
 template hipError_t launch_ttm<double, double>(const double*, int, uint64_t, uint64_t, const double*, int64_t,
-                                               int64_t, int, double*, hipStream_t);
+                                               int64_t, int, double*, bool, hipStream_t);
 template hipError_t launch_ttm<float, double>(const float*, int, uint64_t, uint64_t, const double*, int64_t,
-                                              int64_t, int, double*, hipStream_t);
+                                              int64_t, int, double*, bool, hipStream_t);
 template hipError_t launch_ttm<double, float>(const double*, int, uint64_t, uint64_t, const double*, int64_t,
-                                              int64_t, int, float*, hipStream_t);
+                                              int64_t, int, float*, bool, hipStream_t);
 template hipError_t launch_ttm<float, float>(const float*, int, uint64_t, uint64_t, const double*, int64_t,
-                                             int64_t, int, float*, hipStream_t);
+                                             int64_t, int, float*, bool, hipStream_t);
 
 }  // namespace tk

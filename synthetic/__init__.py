@@ -107,3 +107,150 @@ def small_batch(count: int = 1024, lo: int = 16, hi: int = 128, base_seed: int =
         X, _ = random_tucker(dims, ranks, eta, seed=base_seed + i + 1_000_000, dtype=dtype)
         out.append((X, dims))
     return out
+
+
+# ---------------------------------------------------------------------------
+# Simulation-shaped float32 workloads (reduced-precision form)
+# ---------------------------------------------------------------------------
+
+def _bump_params(rng: np.random.Generator, nvar: int, nbumps: int):
+    """Per variable v and bump b: centre ~ U[0,1)^3, width ~ U[0.03, 0.15],
+    amplitude ~ N(0,1), velocity ~ U[-0.3, 0.3]^3 per unit time; per-variable
+    scale 10^U[-6, 3]."""
+    centre = rng.uniform(0.0, 1.0, size=(nvar, nbumps, 3))
+    width = rng.uniform(0.03, 0.15, size=(nvar, nbumps))
+    amp = rng.standard_normal((nvar, nbumps))
+    vel = rng.uniform(-0.3, 0.3, size=(nvar, nbumps, 3))
+    scale = 10.0 ** rng.uniform(-6.0, 3.0, size=nvar)
+    return centre, width, amp, vel, scale
+
+
+def combustion(dims=(256, 256, 256, 11, 50), nbumps: int = 64, seed: int = 3, device=None):
+    """Combustion-shaped 5-way float32 tensor (3 space, variables, time steps).
+
+    Variable v at time step s (t = s / T) is s_v * sum_b a_vb g_x g_y g_z, a sum of
+    ``nbumps`` Gaussian bumps exp(-d^2 / (2 w_vb^2)) on the periodic unit cube
+    (grid p_i = i / I, minimum-image distance d to the centre c_vb + u_vb t, one
+    factor per axis), so each (v, t) slice is a sum of ``nbumps`` rank-1 terms;
+    s_v = 10^U[-6, 3].  Every variable is then max-rescaled over space and time
+    (its largest |value| becomes 1); the combined scale vector is returned.
+
+    Returns (X, dims, scales): with ``device=None`` X is a flat numpy float32
+    array computed in float64; otherwise a torch float32 tensor of shape
+    dims[::-1] on ``device``, evaluated there in float32 from the same
+    float64 profiles.
+    """
+    nx, ny, nz, nvar, nt = [int(v) for v in dims]
+    rng = np.random.default_rng(seed)
+    centre, width, amp, vel, scale = _bump_params(rng, nvar, nbumps)
+    tt = np.arange(nt) / nt
+    grids = [np.arange(n) / n for n in (nx, ny, nz)]
+
+    def profiles(v, axis):
+        # (nt, nbumps, n): exp(-d^2 / (2 w^2)), d the periodic distance to c + u t
+        c = centre[v, :, axis][None, :] + vel[v, :, axis][None, :] * tt[:, None]
+        d = grids[axis][None, None, :] - c[:, :, None]
+        d -= np.round(d)
+        return np.exp(-(d ** 2) / (2.0 * width[v][None, :, None] ** 2))
+
+    maxes = np.zeros(nvar)
+    if device is None:
+        X = np.empty((nt, nvar, nz, ny, nx), dtype=np.float32)
+        for v in range(nvar):
+            gx, gy, gz = profiles(v, 0), profiles(v, 1), profiles(v, 2)
+            blk = scale[v] * np.einsum("b,tbz,tby,tbx->tzyx", amp[v], gz, gy, gx, optimize=True)
+            maxes[v] = np.abs(blk).max()
+            X[:, v] = (blk / maxes[v]).astype(np.float32)
+        return X.reshape(-1), [nx, ny, nz, nvar, nt], scale / maxes
+
+    import torch
+    X = torch.empty((nt, nvar, nz, ny, nx), dtype=torch.float32, device=device)
+    for v in range(nvar):
+        gx = torch.from_numpy(profiles(v, 0)).to(device, torch.float32)            # (nt, b, nx)
+        gy = torch.from_numpy(profiles(v, 1)).to(device, torch.float32)            # (nt, b, ny)
+        gz = torch.from_numpy(profiles(v, 2) * (scale[v] * amp[v])[None, :, None]).to(device, torch.float32)
+        for t in range(nt):
+            A = (gz[t][:, :, None] * gy[t][:, None, :]).reshape(nbumps, nz * ny)  # (b, nz*ny)
+            X[t, v].view(nz * ny, nx).copy_(torch.mm(A.t().contiguous(), gx[t]))
+        m = float(X[:, v].abs().max())
+        maxes[v] = m
+        X[:, v].div_(m)
+    return X, [nx, ny, nz, nvar, nt], scale / maxes
+
+
+def fourier_fields(dims=(672, 672, 33, 626), nmodes: int = 512, eta: float = 1e-4, seed: int = 5, device=None):
+    """4-way float32 tensor (2 space, variables, time steps) of smooth random
+    Fourier fields plus noise.
+
+    Variable v at time step s (t = s / T) is sum_m A cos(2 pi (kx x + ky y) +
+    2 pi w t + phi) over ``nmodes`` modes of its own, on the periodic grid
+    x_i = i / I: (kx, ky) is the integer rounding of |k| (cos a, sin a) with
+    |k| ~ U[1, 64] and a ~ U[0, 2 pi); A = xi |k|^(-5/6) with xi ~ N(0,1) (energy
+    spectrum ~ |k|^(-5/3)); w ~ U[0, 8] cycles per window; phi ~ U[0, 2 pi).
+    Each (v, t) slice is evaluated separably: cos(a + b + c) expands into
+    products of cosines and sines of the x, y and t phases.  Gaussian noise is
+    added with relative Frobenius norm ``eta`` (exact norm).
+
+    Returns (X, dims): numpy flat float32 (computed in float64) with
+    ``device=None``, else a torch float32 tensor of shape dims[::-1] on
+    ``device`` (noise drawn there with torch's generator).
+    """
+    nx, ny, nvar, nt = [int(v) for v in dims]
+    rng = np.random.default_rng(seed)
+    kmag = rng.uniform(1.0, 64.0, size=(nvar, nmodes))
+    ang = rng.uniform(0.0, 2 * np.pi, size=(nvar, nmodes))
+    kx = np.rint(kmag * np.cos(ang))
+    ky = np.rint(kmag * np.sin(ang))
+    A = rng.standard_normal((nvar, nmodes)) * kmag ** (-5.0 / 6.0)
+    w = rng.uniform(0.0, 8.0, size=(nvar, nmodes))
+    phi = rng.uniform(0.0, 2 * np.pi, size=(nvar, nmodes))
+    tt = np.arange(nt) / nt
+
+    def lhs(v):
+        ax = 2 * np.pi * np.outer(np.arange(nx) / nx, kx[v])  # (nx, M)
+        return np.concatenate([np.cos(ax), np.sin(ax)], axis=1)  # (nx, 2M)
+
+    def rhs(v, ts):
+        # (len(ts), ny, 2M) with field^T (ny x nx) = rhs @ lhs^T:
+        # cos(a + b + c) = cos a [cos b cos c - sin b sin c] - sin a [sin b cos c + cos b sin c]
+        ay = 2 * np.pi * np.outer(np.arange(ny) / ny, ky[v])   # (ny, M)
+        Cy, Sy = np.cos(ay), np.sin(ay)
+        psi = 2 * np.pi * w[v][None, :] * tt[ts][:, None] + phi[v][None, :]
+        Dc, Ds = A[v] * np.cos(psi), A[v] * np.sin(psi)        # (nt', M)
+        top = Cy[None] * Dc[:, None, :] - Sy[None] * Ds[:, None, :]
+        bot = -Sy[None] * Dc[:, None, :] - Cy[None] * Ds[:, None, :]
+        return np.concatenate([top, bot], axis=2)
+
+    if device is None:
+        X = np.empty((nt, nvar, ny, nx), dtype=np.float64)
+        for v in range(nvar):
+            X[:, v] = rhs(v, np.arange(nt)) @ lhs(v).T
+        X = _add_noise(rng, X.reshape(-1), eta)
+        return X.astype(np.float32), [nx, ny, nvar, nt]
+
+    import torch
+    X = torch.empty((nt, nvar, ny, nx), dtype=torch.float32, device=device)
+    tb = 64
+    for v in range(nvar):
+        Pt = torch.from_numpy(lhs(v).T.copy()).to(device, torch.float32)  # (2M, nx)
+        for t0 in range(0, nt, tb):
+            ts = np.arange(t0, min(nt, t0 + tb))
+            R = torch.from_numpy(rhs(v, ts)).to(device, torch.float32)  # (b, ny, 2M)
+            X[t0:t0 + len(ts), v] = torch.matmul(R, Pt)
+    if eta > 0:
+        # noise with exact relative norm eta, drawn on the device one time step at a time
+        flat = X.view(nt, -1)
+        nm2 = sum(float(flat[t].double().pow(2).sum()) for t in range(nt))
+        g = torch.Generator(device=device)
+        E = torch.empty_like(flat[0])
+        g.manual_seed(seed)
+        ne2 = 0.0
+        for t in range(nt):
+            E.normal_(generator=g)
+            ne2 += float(E.double().pow(2).sum())
+        c = eta * np.sqrt(nm2 / ne2)
+        g.manual_seed(seed)
+        for t in range(nt):
+            E.normal_(generator=g)
+            flat[t].add_(E, alpha=c)
+    return X, [nx, ny, nvar, nt]

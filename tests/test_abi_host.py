@@ -133,7 +133,7 @@ def test_other_entry_points_reject_bad_arguments(tk):
     assert L.tucker_eig_truncate(dummy, 0, 0.0, dummy, dummy, dummy, dummy, None) == 1
     assert L.tucker_eig_truncate(dummy, 2000, 0.0, dummy, dummy, dummy, dummy, None) == 1
     assert L.tucker_eig_truncate(dummy, 4, -1.0, dummy, dummy, dummy, dummy, None) == 1
-    assert L.tucker_ttm(dummy, 1, tk._i64([3, 3]), 2, 0, dummy, 0, 1, 1, dummy, 1, None) == 1
+    assert L.tucker_ttm(dummy, 1, tk._i64([3, 3]), 2, 0, dummy, 0, 1, 1, dummy, 1, 0, None) == 1
     assert L.tucker_reconstruct_order(0, None, None, None) == 1
     o = (ctypes.c_int * 2)()
     assert L.tucker_reconstruct_order(2, tk._i64([1, 0]), tk._i64([1, 1]), o) == 1

@@ -1,0 +1,238 @@
+"""GPU checks of the reduced-precision forms (FP32-MFMA, BF16x3 and BF16x6
+Grams; FP32 working tensor with FP32-MFMA mode products) through the C ABI,
+against the FP64 CPU oracle on the same float32 data.
+
+Per-entry Gram bounds, from the arithmetic (d_ab = sqrt(S_aa S_bb), which
+bounds sum_k |y_ak y_bk| by Cauchy-Schwarz; u = 2^-24):
+* FP32: one 32-column chunk is summed in FP32 (8 MFMA steps), then added in
+  FP64: |err| <= (32 + 8) u d_ab = 2.4e-6 d_ab.
+* BF16X3: per product the dropped pieces b1 c1, (b0 + b1) s and r (c0 + c1)
+  are each at most 2^-16 |x y| (1 + 2^-7), and a group of 8 chunks accumulates
+  3 * 256 products in FP32: (768 + 8) u + 3.1 * 2^-16 = 9.4e-5.
+* BF16X6: the dropped pieces are O(2^-24) and a chunk accumulates 6 * 32
+  products in FP32: (192 + 14) u = 1.2e-5.
+The typical (root-mean-square) error is far below these worst cases; it is
+checked too, so that a lost product term (error ~2^-8) cannot hide.
+"""
+import numpy as np
+import pytest
+
+import synthetic
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+U32 = 2.0 ** -24
+BOUND = {"fp32": (32 + 8) * U32, "bf16x3": (768 + 8) * U32 + 3.1 * 2.0 ** -16, "bf16x6": (192 + 14) * U32}
+RMS = {"fp32": 3e-7, "bf16x3": 2e-5, "bf16x6": 3e-7}
+
+
+@pytest.fixture(scope="module")
+def tk():
+    import paper_1901_06043_amd as tk
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    tk.lib()
+    return tk
+
+
+def to_dev(x, dims, dtype=torch.float32):
+    return torch.from_numpy(np.ascontiguousarray(x).reshape(list(reversed(dims)))).to("cuda", dtype)
+
+
+MP_SHAPES = [
+    ([64, 64, 64], [0, 1, 2]),
+    ([200, 30, 7], [0, 1, 2]),
+    ([16, 333, 5], [0, 1, 2]),
+    ([11, 3, 40, 50], [0, 1, 2, 3]),
+    ([130, 9, 3], [0, 1]),
+    ([1, 7, 1, 5], [0, 1, 2, 3]),
+    ([256, 65], [0, 1]),
+    ([128, 300], [0, 1]),
+    ([5], [0]),
+]
+
+
+@pytest.mark.parametrize("dims,modes", MP_SHAPES)
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3", "bf16x6"])
+def test_gram_reduced_parity(tk, orc, dims, modes, prec):
+    rng = np.random.default_rng(sum(dims) + 7)
+    X = rng.standard_normal(int(np.prod(dims))).astype(np.float32)
+    Xd = to_dev(X, dims)
+    for n in modes:
+        print(f"gram {prec} dims={dims} n={n}", flush=True)
+        S, nrm = tk.gram(Xd, n, prec=prec, dims=dims, with_norm=True)
+        Sref = orc.gram(X.astype(np.float64), dims, n)
+        d = np.sqrt(np.outer(np.diag(Sref), np.diag(Sref))) + 1e-300
+        rel = np.abs(S.cpu().numpy() - Sref) / d
+        assert rel.max() <= BOUND[prec], rel.max()
+        assert np.sqrt(np.mean(rel ** 2)) <= RMS[prec], np.sqrt(np.mean(rel ** 2))
+        # the sum of squares is FP64 whatever the Gram arithmetic
+        assert float(nrm.item()) == pytest.approx(orc.norm2(X.astype(np.float64)), rel=1e-11)
+
+
+def test_bf16x3_bias_bf16x6_unbiased(tk, orc):
+    """The product dropped by BF16X3 is a Gram of bf16 rounding residuals, so
+    its trace error is negative and about 2^-16/3 of the trace (uniform
+    residuals); BF16X6 removes it."""
+    dims = [48, 4000]
+    rng = np.random.default_rng(11)
+    X = rng.standard_normal(int(np.prod(dims))).astype(np.float32)
+    Sref = orc.gram(X.astype(np.float64), dims, 0)
+    tr = np.trace(Sref)
+    d3 = np.trace(tk.gram(to_dev(X, dims), 0, prec="bf16x3", dims=dims).cpu().numpy()) - tr
+    d6 = np.trace(tk.gram(to_dev(X, dims), 0, prec="bf16x6", dims=dims).cpu().numpy()) - tr
+    assert -3e-5 * tr < d3 < -2e-6 * tr, d3 / tr
+    assert abs(d6) < 1e-6 * tr, d6 / tr
+
+
+@pytest.mark.parametrize("dims,n,K", [([200, 50, 4], 0, 20), ([13, 17, 19], 1, 70), ([64, 64, 64], 2, 8),
+                                      ([300, 40], 0, 130)])
+def test_ttm_fp32_products(tk, orc, dims, n, K):
+    rng = np.random.default_rng(K + n + 1)
+    X = rng.standard_normal(int(np.prod(dims))).astype(np.float32)
+    M = rng.standard_normal((K, dims[n]))
+    Z = tk.ttm(to_dev(X, dims), n, torch.from_numpy(M).cuda(), dims=dims, out_dtype=torch.float32,
+               fp32_products=True)
+    Zref, _ = orc.ttm(X.astype(np.float64), dims, n, M)
+    Aref, _ = orc.ttm(np.abs(X.astype(np.float64)), dims, n, np.abs(M))
+    J = dims[n]
+    tol = (J + 4) * U32 * Aref + U32 * np.abs(Zref) + 1e-300
+    err = np.abs(Z.cpu().numpy().reshape(-1).astype(np.float64) - Zref)
+    assert np.all(err <= tol), (err / tol).max()
+    # and FP32 products are not FP64 ones: a few entries must differ from an FP64-product TTM
+    Z64 = tk.ttm(to_dev(X, dims), n, torch.from_numpy(M).cuda(), dims=dims, out_dtype=torch.float64)
+    assert np.abs(Z64.cpu().numpy().reshape(-1) - Zref).max() <= 1e-12 * Aref.max()
+
+
+@pytest.mark.parametrize("scale,prec", [(1e20, "fp32"), (1e-25, "fp32"), (1e20, "bf16x3"), (1e-25, "bf16x6")])
+def test_range_guard_recomputes_in_fp64(tk, orc, scale, prec):
+    """FP32 squares overflow above ~1.8e19 and vanish below ~1e-23: the guard
+    sees the trace or a non-finite entry disagree with the FP64 sum of squares
+    and redoes the Gram in FP64; the result equals the FP64 path's."""
+    X, dims = synthetic.random_tucker([30, 20, 10], [4, 3, 2], 1e-3, seed=21)
+    X = (X * scale).astype(np.float32)
+    t = tk.sthosvd(to_dev(X, dims), 1e-2, prec=prec, dims=dims)
+    ref = orc.sthosvd(X.astype(np.float64), dims, 1e-2)
+    assert t.gram_precision[0] == "fp64"
+    assert t.ranks == ref.ranks
+    assert t.norm2 == pytest.approx(ref.norm2, rel=1e-11)
+    # in range: no recomputation
+    Xn = (X.astype(np.float64) / scale).astype(np.float32)
+    t2 = tk.sthosvd(to_dev(Xn, dims), 1e-2, prec=prec, dims=dims)
+    assert t2.gram_precision == [prec] * 3
+
+
+def _principal_sin(Ua, Ub):
+    """Largest principal angle sine between the column spaces of Ua and Ub."""
+    s = np.linalg.svd(Ua.T @ Ub, compute_uv=False)
+    return float(np.sqrt(max(0.0, 1.0 - s.min() ** 2)))
+
+
+def _mixed_report(tk, orc, X, dims, eps, order, prec):
+    """Compress with a reduced form and compare with the FP64 oracle: ranks,
+    relative error (explicit FP64 reconstruction on the GPU), per-mode largest
+    principal angle (where ranks agree), and for the first mode the Davis-Kahan
+    bound ||E||_2 / (lam_R - lam_{R+1} - ||E||_2) with E the Gram's error."""
+    print(f"sthosvd {prec} dims={dims} eps={eps} order={order}", flush=True)
+    order = order or list(range(len(dims)))
+    x = to_dev(X, dims)
+    t = tk.sthosvd(x, eps, mode_order=order, prec=prec, dims=dims)
+    ref = orc.sthosvd(X.astype(np.float64), dims, eps, order)
+    assert t.core_dtype == tk.F32
+    xh = t.reconstruct(out_dtype=torch.float64)
+    x64 = x.to(torch.float64)
+    e = float(torch.linalg.vector_norm((x64 - xh).reshape(-1)) / torch.linalg.vector_norm(x64.reshape(-1)))
+    angles = [_principal_sin(ref.factors[n], t.factor(n).cpu().numpy()) if t.ranks[n] == ref.ranks[n] else None
+              for n in range(len(dims))]
+    n0 = order[0]
+    E = tk.gram(x, n0, prec=prec, dims=dims).cpu().numpy() - orc.gram(X.astype(np.float64), dims, n0)
+    e2 = float(np.linalg.norm(E, 2))
+    lam = ref.eigenvalues[n0]
+    R0 = ref.ranks[n0]
+    gap = (lam[R0 - 1] - lam[R0] - e2) if R0 < len(lam) else np.inf
+    dk = e2 / gap if gap > 0 else np.inf
+    print(f"  ranks gpu={t.ranks} oracle={ref.ranks} relerr={e:.4e} (eps {eps}) "
+          f"sin-angles={[None if a is None else float('%.3g' % a) for a in angles]} "
+          f"first-mode DK bound={dk:.3g} precision={t.gram_precision}", flush=True)
+    return t, ref, e, angles, dk
+
+
+def _ranks_within_budget(t, ref, eps):
+    """Rank acceptance for reduced forms near the threshold: with the oracle's
+    eigenvalues of each mode, the rank R must discard at most 1.1025 thr (the
+    per-mode share of the 1.05 eps budget: 1.05^2 = 1.1025) and R - 1 must
+    discard at least thr / 1.1025 (R is minimal up to the same slack)."""
+    N = len(t.ranks)
+    thr = eps * eps * ref.norm2 / N
+    for n in range(N):
+        lam = np.clip(ref.eigenvalues[n], 0.0, None)
+        tail = np.concatenate([np.cumsum(lam[::-1])[::-1], [0.0]])
+        R = t.ranks[n]
+        if not (tail[R] <= 1.1025 * thr and (R == 1 or tail[R - 1] >= thr / 1.1025)):
+            return False
+    return True
+
+
+SIM = [((40, 36, 32, 11, 6), [0, 1, 2, 3, 4]), ((40, 36, 32, 11, 6), [4, 3, 0, 1, 2])]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x6"])
+@pytest.mark.parametrize("eps", [1e-2, 1e-3, 1e-4])
+@pytest.mark.parametrize("shape,order", SIM)
+def test_sthosvd_reduced_matches_oracle(tk, orc, prec, eps, shape, order):
+    """FP32-MFMA and BF16X6 Grams on a combustion-shaped float32 tensor:
+    relative error within 1.05 eps; at eps >= 1e-3 the oracle's ranks exactly
+    and a first-mode subspace within the Davis-Kahan bound of the Gram's
+    measured error; at 1e-4 (where eigenvalues next to the threshold differ by
+    less than the Gram's error on this small tensor) ranks within the budget."""
+    X, dims, _ = synthetic.combustion(shape, nbumps=16, seed=31)
+    t, ref, e, angles, dk = _mixed_report(tk, orc, X, dims, eps, order, prec)
+    assert e <= 1.05 * eps
+    if eps >= 1e-3:
+        assert t.ranks == ref.ranks
+        assert angles[order[0]] <= max(dk, 1e-6)
+    else:
+        assert _ranks_within_budget(t, ref, eps), (t.ranks, ref.ranks)
+
+
+@pytest.mark.parametrize("eps", [1e-2, 1e-3])
+def test_sthosvd_bf16x3_error_target(tk, orc, eps):
+    """BF16X3 meets the 1.05 eps target at eps >= 1e-3 on this tensor; its Gram
+    under-estimates (the dropped b1 c1' term), so its ranks are never above the
+    oracle's.  Below that the bias exceeds the budget (reported by the
+    benchmark, not asserted)."""
+    X, dims, _ = synthetic.combustion(SIM[0][0], nbumps=16, seed=31)
+    t, ref, e, angles, dk = _mixed_report(tk, orc, X, dims, eps, SIM[0][1], "bf16x3")
+    assert e <= 1.05 * eps
+    assert all(r <= q for r, q in zip(t.ranks, ref.ranks))
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x6"])
+def test_sthosvd_reduced_fourier(tk, orc, prec):
+    """Fourier-field tensor (2 space, 33 variables, time) in mode order 3,2,0,1."""
+    X, dims = synthetic.fourier_fields((96, 80, 33, 40), nmodes=64, seed=41)
+    t, ref, e, angles, dk = _mixed_report(tk, orc, X, dims, 1e-4, [3, 2, 0, 1], prec)
+    assert e <= 1.05e-4
+    assert _ranks_within_budget(t, ref, 1e-4), (t.ranks, ref.ranks)
+
+
+def test_reconstruct_fp32_core(tk, orc):
+    """FP32 core reconstructed to FP32 (FP32 products) and to FP64 (FP64
+    products) against the oracle's Multi-TTM of the same core and factors."""
+    X, dims, _ = synthetic.combustion((40, 36, 32, 11, 6), nbumps=16, seed=31)
+    t = tk.sthosvd(to_dev(X, dims), 1e-3, prec="fp32", dims=dims)
+    core = t.core.cpu().numpy().astype(np.float64).reshape(-1)
+    Us = [t.factor(n).cpu().numpy() for n in range(5)]
+    ref = orc.Tucker(core=core, factors=Us, ranks=list(t.ranks), dims=list(dims), eigenvalues=None,
+                     discarded=None, norm2=t.norm2, order=list(range(5)))
+    begin, end = [3, 5, 0, 2, 1], [33, 30, 32, 9, 6]
+    Zref, zd = orc.reconstruct(ref, begin, end)
+    Aref, _ = orc.reconstruct(orc.Tucker(core=np.abs(core), factors=[np.abs(U) for U in Us], ranks=ref.ranks,
+                                         dims=ref.dims, eigenvalues=None, discarded=None, norm2=0.0,
+                                         order=ref.order), begin, end)
+    Z64 = t.reconstruct(begin, end, out_dtype=torch.float64).cpu().numpy().reshape(-1)
+    assert np.all(np.abs(Z64 - Zref) <= 1e-12 * Aref + 1e-300)
+    Z32 = t.reconstruct(begin, end, out_dtype=torch.float32).cpu().numpy().reshape(-1).astype(np.float64)
+    R = max(t.ranks)
+    assert np.all(np.abs(Z32 - Zref) <= 5 * (R + 4) * U32 * Aref + U32 * np.abs(Zref) + 1e-300)
