@@ -224,7 +224,21 @@ tucker_status run_gram(const void* Y, tucker_dtype dt, const int64_t* dims, int 
   if (K >= (int64_t(1) << 32) || J >= (int64_t(1) << 31))
     return fail(TUCKER_EUNSUPPORTED, "unfolding of mode %d has %lld columns (limit 2^32)", n, (long long)K);
   TmpBuf part, sq;
-  if (prec == TUCKER_GRAM_FP64 && J <= 256) {
+  if (prec != TUCKER_GRAM_FP64 && dt != TUCKER_F32) return fail(TUCKER_EINVAL, "reduced-precision Gram needs FP32 data");
+  if (J <= tk::kStreamMaxJ) {
+    // small modes: HBM-bound streaming kernel, any arithmetic form
+    tk::GramPlan p = tk::plan_gram_stream((int)J, (uint64_t)K, (int)prec);
+    HIP_TRY(part.alloc(sizeof(double) * p.part_elems, s));
+    HIP_TRY(sq.alloc(sizeof(double) * p.sq_elems, s));
+    if (dt == TUCKER_F64)
+      HIP_TRY(tk::launch_gram_stream(static_cast<const double*>(Y), (int)J, L, K, (int)prec, p, part.as<double>(),
+                                     sq.as<double>(), S, norm2, s, after_main));
+    else
+      HIP_TRY(tk::launch_gram_stream(static_cast<const float*>(Y), (int)J, L, K, (int)prec, p, part.as<double>(),
+                                     sq.as<double>(), S, norm2, s, after_main));
+    return TUCKER_OK;
+  }
+  if (prec == TUCKER_GRAM_FP64 && J <= tk::kTriMaxJ) {
     // whole triangle per workgroup, FP64
     tk::GramPlan p = tk::plan_gram_f64((int)J, (uint64_t)L, (uint64_t)K);
     HIP_TRY(part.alloc(sizeof(double) * p.part_elems, s));
@@ -237,7 +251,6 @@ tucker_status run_gram(const void* Y, tucker_dtype dt, const int64_t* dims, int 
                                   sq.as<double>(), S, norm2, s, after_main));
     return TUCKER_OK;
   }
-  if (prec != TUCKER_GRAM_FP64 && dt != TUCKER_F32) return fail(TUCKER_EINVAL, "reduced-precision Gram needs FP32 data");
   tk::GramPlan p = tk::plan_gram_mp((int)J, (uint64_t)K, (int)prec);
   HIP_TRY(part.alloc(sizeof(double) * p.part_elems, s));
   HIP_TRY(sq.alloc(sizeof(double) * p.sq_elems, s));

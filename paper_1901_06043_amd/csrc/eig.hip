@@ -17,11 +17,13 @@
 //     eigenvalue test 32 interior points at once; many workgroups.
 //  3. Truncation: tail sums of the clamped eigenvalues from the smallest upward.
 //  4. Leading R eigenvectors of T by two steps of inverse iteration
-//     (tridiagonal LU with partial pivoting, factors in LDS), one thread per vector; eigenvalues closer than
-//     1e-10 ||T|| are handled as one cluster by one thread with Gram-Schmidt
-//     inside the iteration.
+//     (tridiagonal LU with partial pivoting, factors in LDS), one thread per
+//     vector, every vector from its own pseudo-random start.  For eigenvalues
+//     that coincide to rounding the iterates are independent random vectors of
+//     the common invariant subspace.
 //  5. Re-orthogonalisation (classical Gram-Schmidt, twice) of each vector
 //     against the preceding ones whose eigenvalue lies within 1e-2 ||T||;
+//     this turns such iterates into an orthonormal basis of the subspace, and
 //     beyond that gap inverse iteration already yields orthogonality at the
 //     level of rounding.
 //  6. Back-transformation V = Q Z, one wave per vector, followed by the sign
@@ -466,11 +468,8 @@ __global__ __launch_bounds__(64) void eig_invit_kernel(const double* __restrict_
   const int R = (int)*Rp;
   if (tid >= nvw || t >= R) return;
   const double tnorm = scal[0];
-  const double ctol = 1e-10 * tnorm;
-  if (t > 0 && lam[t - 1] - lam[t] <= ctol) return;  // handled by its cluster leader
   if (tnorm == 0.0) {
-    for (int vec = t; vec < R && (vec == t || lam[vec - 1] - lam[vec] <= ctol); ++vec)
-      for (int i = 0; i < J; ++i) Zt[(int64_t)vec * J + i] = (i == vec) ? 1.0 : 0.0;
+    for (int i = 0; i < J; ++i) Zt[(int64_t)t * J + i] = (i == t) ? 1.0 : 0.0;
     return;
   }
   const double inv = 1.0 / tnorm;
@@ -480,12 +479,9 @@ __global__ __launch_bounds__(64) void eig_invit_kernel(const double* __restrict_
   double* W2 = sh + 2 * (size_t)J * nvw + tid;  // u_{i,i+2}
   double* Wx = sh + 3 * (size_t)J * nvw + tid;  // iterate
 #define W(arr, i) arr[(size_t)(i) * nvw]
-  double prev_shift = 0.0;
-  for (int vec = t; vec < R; ++vec) {
-    if (vec > t && !(lam[vec - 1] - lam[vec] <= ctol)) break;
-    double shift = lam[vec] * inv;
-    if (vec > t && prev_shift - shift < 10.0 * eps) shift = prev_shift - 10.0 * eps;
-    prev_shift = shift;
+  {
+    const int vec = t;
+    const double shift = lam[vec] * inv;
     for (int i = 0; i < J; ++i) W(Wx, i) = hash_unit((uint32_t)i, (uint32_t)vec);
     double xscale = 1.0;
     for (int it = 0; it < 2; ++it) {
@@ -541,17 +537,6 @@ __global__ __launch_bounds__(64) void eig_invit_kernel(const double* __restrict_
         nrm += yi * yi;
         y2 = y1;
         y1 = yi;
-      }
-      if (vec > t) {
-        // Gram-Schmidt against the finished members of this cluster
-        for (int j = t; j < vec; ++j) {
-          const double* zj = Zt + (int64_t)j * J;
-          double h = 0.0;
-          for (int i = 0; i < J; ++i) h += zj[i] * W(Wx, i);
-          for (int i = 0; i < J; ++i) W(Wx, i) = W(Wx, i) - h * zj[i];
-        }
-        nrm = 0.0;
-        for (int i = 0; i < J; ++i) nrm += W(Wx, i) * W(Wx, i);
       }
       xscale = 1.0 / sqrt(nrm);
     }

@@ -24,8 +24,10 @@
 // items of one split are numbered consecutively and placed on one XCD so that
 // pairs sharing a tile share its L2.  Eight waves per workgroup; LDS holds the
 // current chunk of rows, double-buffered with one barrier per chunk; global
-// loads walk the contiguous axis of the unfolding.  Every item writes its FP64
-// partial blocks and a second kernel sums the splits in a fixed order.
+// loads walk the contiguous axis of the unfolding.  Split s takes chunks s,
+// s + nsplit, ..., so that the workgroups stream neighbouring addresses.  Every
+// item writes its FP64 partial blocks and a second kernel sums the splits in a
+// fixed order.
 #include <type_traits>
 
 #include "common.hpp"
@@ -70,7 +72,7 @@ struct MPParams {
   int ntiles;  // pair mode: 128-row tiles
   int npairs;  // pair mode: tile pairs; triangle mode: 1
   int nblk;    // partial blocks per item
-  int64_t nchunks, cps, total;
+  int64_t nchunks, nsplit, total;  // split s takes chunks s, s + nsplit, ...
   double* part;
   double* sq;  // one value per item (zero for items that do not own their rows), or null
 };
@@ -102,35 +104,214 @@ __device__ __forceinline__ void put(typename Cfg<PREC>::elem* s, int plane_strid
   }
 }
 
-// Main loop and output of one work item.  SHARED_A: all slots of the wave have
-// the same block row (off-diagonal pairs), so the A operand is loaded once.
-template <typename T, int PREC, int ROWS, int NBW, bool SHARED_A, bool UNIT_L>
-__device__ __forceinline__ void gram_body(const MPParams& g, int64_t item, int64_t split, bool diag, int ra, int rb,
-                                          int NR, int nbl, typename Cfg<PREC>::elem* sY, double* sred) {
+// One work item: the blocks of one wave, the chunk loader, the products of a
+// chunk and the output.  SHARED_A: all slots of the wave have the same block
+// row (off-diagonal pairs), so the A operand is read from LDS once per step.
+//
+// Pipelining: global loads run two chunks ahead (two register sets), LDS is
+// double-buffered with one barrier per chunk, and the MFMA operands of the
+// next step (FP64/FP32) or next slot (BF16 forms) are read from LDS while the
+// current step's MFMAs run.
+// PAIR: rows are the 128-row tiles of a pair (NR = 128 or 256, a power of two),
+// so the loader's (row, column) of each value follows from the thread index
+// with shifts instead of per-value index registers.
+template <typename T, int PREC, int ROWS, int NBW, bool SHARED_A, bool UNIT_L, bool PAIR>
+struct GramItem {
   using C = Cfg<PREC>;
   using E_t = typename C::elem;
-  constexpr int KC = C::KC, LR = C::LR, PL = C::PLANES;
-  constexpr int PS = ROWS * LR;       // plane stride
-  constexpr int BS = PL * PS;         // buffer stride
-  constexpr int E = ROWS * KC / kNT;  // loaded values per thread and chunk
+  static constexpr int KC = C::KC, LR = C::LR, PL = C::PLANES;
+  static constexpr int PS = ROWS * LR;       // plane stride
+  static constexpr int BS = PL * PS;         // buffer stride
+  static constexpr int E = ROWS * KC / kNT;  // loaded values per thread and chunk
+  static constexpr int NA = SHARED_A ? 1 : NBW;
+  using O = typename std::conditional<PREC == 0, double, float>::type;  // FP64 / FP32 operands
 
+  const T* __restrict__ Y;
+  int J;
+  uint32_t L, K;
+  int64_t JL;
+  int i, q;
+  int bI[NBW], bJ[NBW];
+  static constexpr int EA = PAIR ? 1 : E;  // per-value index arrays (triangle mode)
+  int eoff[EA], ek[EA], egrow[EA];
+  // pair mode: UNIT_L -> one row per thread (lr0, gr0) and columns kb + kstep p;
+  // otherwise one column per thread (kb) and rows lr0 + (kNT / KC) p
+  int lr0, gr0, kb, kstep, nr, ra, rb;
+  bool diag;
+  d4 acc64[NBW];
+  f4 acc32[NBW];
+  double sq;
+  int group_left;
+
+  __device__ __forceinline__ int pair_grow(int lr) const {
+    return lr < nr ? ((lr < 128 || diag) ? ra + lr : rb + (lr - 128)) : J;
+  }
+
+  __device__ __forceinline__ void load(T (&rv)[E], int64_t ch) const {
+#pragma unroll
+    for (int p = 0; p < E; ++p) {
+      int gr, k;
+      if constexpr (PAIR) {
+        if constexpr (UNIT_L) {
+          k = kb + kstep * p;
+          gr = (k < KC) ? gr0 : J;  // diagonal pairs (NR = 128) need half the values
+        } else {
+          gr = pair_grow(lr0 + (kNT / KC) * p);
+          k = kb;
+        }
+      } else {
+        gr = egrow[p];
+        k = ek[p];
+      }
+      const int64_t c = ch * KC + k;
+      T v = (T)0;
+      if (gr < J && c < (int64_t)K) {
+        int64_t addr;
+        if constexpr (UNIT_L) {
+          addr = (int64_t)gr + (int64_t)J * c;
+        } else {
+          const uint32_t cc = (uint32_t)c;
+          const uint32_t r = cc / L, l = cc - r * L;
+          addr = (int64_t)l + JL * r + (int64_t)L * gr;
+        }
+        v = Y[addr];
+      }
+      rv[p] = v;
+    }
+  }
+
+  __device__ __forceinline__ void store(const T (&rv)[E], E_t* s) {
+#pragma unroll
+    for (int p = 0; p < E; ++p) {
+      const double v = (double)rv[p];
+      int o;
+      if constexpr (PAIR) {
+        if constexpr (UNIT_L) {
+          const int k = kb + kstep * p;
+          o = (lr0 < nr && k < KC) ? lr0 * LR + k : -1;
+        } else {
+          const int lr = lr0 + (kNT / KC) * p;
+          o = (lr < nr) ? lr * LR + kb : -1;
+        }
+      } else {
+        o = eoff[p];
+      }
+      if (o >= 0) put<PREC>(s, PS, o, v);
+      sq += v * v;
+    }
+  }
+
+  __device__ __forceinline__ void read_ops(const E_t* s, int st, O (&a)[NA], O (&b)[NBW]) const {
+#pragma unroll
+    for (int t = 0; t < NA; ++t) a[t] = s[(16 * bI[t] + i) * LR + 4 * st + q];
+#pragma unroll
+    for (int t = 0; t < NBW; ++t) b[t] = s[(16 * bJ[t] + i) * LR + 4 * st + q];
+  }
+
+  __device__ __forceinline__ void read_bf(const E_t* s, int blk, bf8 (&v)[PL]) const {
+    const int o = (16 * blk + i) * LR + 8 * q;
+#pragma unroll
+    for (int pl = 0; pl < PL; ++pl) v[pl] = *reinterpret_cast<const bf8*>(s + pl * PS + o);
+  }
+
+  __device__ __forceinline__ void compute(const E_t* s, bool last) {
+    if constexpr (PREC <= 1) {
+      O a[NA], b[NBW];
+      read_ops(s, 0, a, b);
+#pragma unroll
+      for (int st = 0; st < KC / 4; ++st) {
+        O an[NA], bn[NBW];
+        if (st + 1 < KC / 4) read_ops(s, st + 1, an, bn);
+#pragma unroll
+        for (int t = 0; t < NBW; ++t) {
+          if constexpr (PREC == 0)
+            acc64[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[SHARED_A ? 0 : t], b[t], acc64[t], 0, 0, 0);
+          else
+            acc32[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[SHARED_A ? 0 : t], b[t], acc32[t], 0, 0, 0);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        if (st + 1 < KC / 4) {
+#pragma unroll
+          for (int t = 0; t < NA; ++t) a[t] = an[t];
+#pragma unroll
+          for (int t = 0; t < NBW; ++t) b[t] = bn[t];
+        }
+      }
+    } else {
+      // K = 32 per MFMA: lane (i, q) supplies columns 8q .. 8q+7 of its row
+      bf8 A[PL], B[PL];
+      if constexpr (SHARED_A) read_bf(s, bI[0], A);
+      else read_bf(s, bI[0], A);
+      read_bf(s, bJ[0], B);
+#pragma unroll
+      for (int t = 0; t < NBW; ++t) {
+        bf8 An[PL], Bn[PL];
+        if (t + 1 < NBW) {
+          if constexpr (!SHARED_A) read_bf(s, bI[t + 1], An);
+          read_bf(s, bJ[t + 1], Bn);
+        }
+        f4 acc = acc32[t];
+        if constexpr (PREC == 3) {
+          acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[2], B[0], acc, 0, 0, 0);
+          acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[0], B[2], acc, 0, 0, 0);
+          acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[1], B[1], acc, 0, 0, 0);
+        }
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[1], B[0], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[0], B[1], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[0], B[0], acc, 0, 0, 0);
+        acc32[t] = acc;
+        __builtin_amdgcn_sched_barrier(0);
+        if (t + 1 < NBW) {
+#pragma unroll
+          for (int pl = 0; pl < PL; ++pl) {
+            if constexpr (!SHARED_A) A[pl] = An[pl];
+            B[pl] = Bn[pl];
+          }
+        }
+      }
+    }
+    if constexpr (PREC != 0) {
+      if (--group_left == 0 || last) {  // promote the group sum to FP64
+        group_left = C::GROUP;
+#pragma unroll
+        for (int t = 0; t < NBW; ++t) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) acc64[t][v] += (double)acc32[t][v];
+          acc32[t] = f4{0.f, 0.f, 0.f, 0.f};
+        }
+      }
+    }
+  }
+};
+
+template <typename T, int PREC, int ROWS, int NBW, bool SHARED_A, bool UNIT_L, bool PAIR>
+__device__ __forceinline__ void gram_body(const MPParams& g, int64_t item, int64_t split, bool diag, int ra, int rb,
+                                          int NR, int nbl, typename Cfg<PREC>::elem* sY, double* sred) {
+  using W = GramItem<T, PREC, ROWS, NBW, SHARED_A, UNIT_L, PAIR>;
+  constexpr int E = W::E, KC = W::KC, LR = W::LR;
+  W w;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int J = g.J;
-  const uint32_t L = g.L, K = g.K;
-  const int64_t JL = (int64_t)J * L;
+  w.Y = static_cast<const T*>(g.Y);
+  w.J = g.J;
+  w.L = g.L;
+  w.K = g.K;
+  w.JL = (int64_t)g.J * g.L;
+  w.i = lane & 15;
+  w.q = lane >> 4;
+  w.sq = 0.0;
+  w.group_left = W::C::GROUP;
 
   // this wave's block range [q0, q0 + nq) and its blocks (bI, bJ) in local rows
   const int nblk = diag ? nbl * (nbl + 1) / 2 : 64;
   int q0, nq;
-  int bI[NBW], bJ[NBW];
   if constexpr (SHARED_A) {
     q0 = 8 * wave;
     nq = 8;
 #pragma unroll
     for (int t = 0; t < NBW; ++t) {
-      bI[t] = wave;
-      bJ[t] = 8 + t;
+      w.bI[t] = wave;
+      w.bJ[t] = 8 + t;
     }
   } else {
     q0 = (int)(((int64_t)nblk * wave) / kWaves);
@@ -143,8 +324,8 @@ __device__ __forceinline__ void gram_body(const MPParams& g, int64_t item, int64
       }
 #pragma unroll
     for (int t = 0; t < NBW; ++t) {  // slots past nq repeat the last block and are not stored
-      bI[t] = bi;
-      bJ[t] = bj;
+      w.bI[t] = bi;
+      w.bJ[t] = bj;
       if (t + 1 < nq && ++bj == nbl) {
         ++bi;
         bj = bi;
@@ -153,9 +334,26 @@ __device__ __forceinline__ void gram_body(const MPParams& g, int64_t item, int64
   }
 
   // loader: value p of this thread is (local row, chunk column); rows >= NR are padding
-  int eoff[E], ek[E], egrow[E];
+  w.nr = NR;
+  w.ra = ra;
+  w.rb = rb;
+  w.diag = diag;
+  if constexpr (PAIR) {
+    const int sh = (NR == 256) ? 8 : 7;  // log2(NR)
+    if constexpr (UNIT_L) {
+      w.lr0 = tid & (NR - 1);
+      w.kb = tid >> sh;
+      w.kstep = kNT >> sh;
+    } else {
+      w.kb = tid % KC;
+      w.lr0 = tid / KC;
+      w.kstep = 0;
+    }
+    w.gr0 = w.pair_grow(w.lr0);
+  }
 #pragma unroll
-  for (int p = 0; p < E; ++p) {
+  for (int p = 0; p < W::EA; ++p) {
+    if constexpr (PAIR) break;
     int lr, k;
     if constexpr (UNIT_L) {
       const int e = tid + kNT * p;
@@ -167,136 +365,42 @@ __device__ __forceinline__ void gram_body(const MPParams& g, int64_t item, int64
       lr = tid / KC + (kNT / KC) * p;
       if (lr > NR) lr = NR;
     }
-    ek[p] = k;
-    eoff[p] = (lr < NR) ? lr * LR + k : -1;
-    int gr = J;
+    w.ek[p] = k;
+    w.eoff[p] = (lr < NR) ? lr * LR + k : -1;
+    int gr = g.J;
     if (lr < NR) gr = (lr < 128 || diag) ? ra + lr : rb + (lr - 128);
-    egrow[p] = gr;
+    w.egrow[p] = gr;
   }
-
-  const int64_t ch_begin = split * g.cps;
-  const int64_t ch_end = min(ch_begin + g.cps, g.nchunks);
-  const T* __restrict__ Y = static_cast<const T*>(g.Y);
-  double rv[E];
-  double sq = 0.0;
-
-  d4 acc64[NBW];
-  f4 acc32[NBW];
 #pragma unroll
   for (int t = 0; t < NBW; ++t) {
-    acc64[t] = d4{0.0, 0.0, 0.0, 0.0};
-    acc32[t] = f4{0.f, 0.f, 0.f, 0.f};
+    w.acc64[t] = d4{0.0, 0.0, 0.0, 0.0};
+    w.acc32[t] = f4{0.f, 0.f, 0.f, 0.f};
   }
-  const int i = lane & 15, q = lane >> 4;
-  int group_left = C::GROUP;
 
-  for (int64_t ch = ch_begin; ch <= ch_end; ++ch) {
-    // ch < ch_end: load chunk ch into registers; ch > ch_begin: compute chunk ch-1
-    if (ch < ch_end) {
-#pragma unroll
-      for (int p = 0; p < E; ++p) {
-        const int gr = egrow[p];
-        const int64_t c = ch * KC + ek[p];
-        double v = 0.0;
-        if (gr < J && c < (int64_t)K) {
-          int64_t addr;
-          if constexpr (UNIT_L) {
-            addr = (int64_t)gr + (int64_t)J * c;
-          } else {
-            const uint32_t cc = (uint32_t)c;
-            const uint32_t r = cc / L, l = cc - r * L;
-            addr = (int64_t)l + JL * r + (int64_t)L * gr;
-          }
-          v = (double)Y[addr];
-        }
-        rv[p] = v;
-      }
-    }
-    if (ch > ch_begin) {
-      const E_t* s = sY + ((ch - 1) & 1) * BS;
-      if constexpr (PREC == 0) {
-#pragma unroll
-        for (int st = 0; st < KC / 4; ++st) {
-          double av = 0.0;
-          if constexpr (SHARED_A) av = s[(16 * bI[0] + i) * LR + 4 * st + q];
-#pragma unroll
-          for (int t = 0; t < NBW; ++t) {
-            if constexpr (!SHARED_A) av = s[(16 * bI[t] + i) * LR + 4 * st + q];
-            const double bv = s[(16 * bJ[t] + i) * LR + 4 * st + q];
-            acc64[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc64[t], 0, 0, 0);
-          }
-          __builtin_amdgcn_sched_barrier(0);
-        }
-      } else if constexpr (PREC == 1) {
-#pragma unroll
-        for (int st = 0; st < KC / 4; ++st) {
-          float av = 0.f;
-          if constexpr (SHARED_A) av = s[(16 * bI[0] + i) * LR + 4 * st + q];
-#pragma unroll
-          for (int t = 0; t < NBW; ++t) {
-            if constexpr (!SHARED_A) av = s[(16 * bI[t] + i) * LR + 4 * st + q];
-            const float bv = s[(16 * bJ[t] + i) * LR + 4 * st + q];
-            acc32[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc32[t], 0, 0, 0);
-          }
-          __builtin_amdgcn_sched_barrier(0);
-        }
-      } else {
-        // K = 32 per MFMA: lane (i, q) supplies columns 8q .. 8q+7 of its row
-        bf8 a0, a1, a2;
-        if constexpr (SHARED_A) {
-          const int oa = (16 * bI[0] + i) * LR + 8 * q;
-          a0 = *reinterpret_cast<const bf8*>(s + oa);
-          a1 = *reinterpret_cast<const bf8*>(s + PS + oa);
-          if constexpr (PREC == 3) a2 = *reinterpret_cast<const bf8*>(s + 2 * PS + oa);
-        }
-#pragma unroll
-        for (int t = 0; t < NBW; ++t) {
-          if constexpr (!SHARED_A) {
-            const int oa = (16 * bI[t] + i) * LR + 8 * q;
-            a0 = *reinterpret_cast<const bf8*>(s + oa);
-            a1 = *reinterpret_cast<const bf8*>(s + PS + oa);
-            if constexpr (PREC == 3) a2 = *reinterpret_cast<const bf8*>(s + 2 * PS + oa);
-          }
-          const int ob = (16 * bJ[t] + i) * LR + 8 * q;
-          const bf8 b0 = *reinterpret_cast<const bf8*>(s + ob);
-          const bf8 b1 = *reinterpret_cast<const bf8*>(s + PS + ob);
-          f4 a = acc32[t];
-          if constexpr (PREC == 3) {
-            const bf8 b2 = *reinterpret_cast<const bf8*>(s + 2 * PS + ob);
-            a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a2, b0, a, 0, 0, 0);
-            a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b2, a, 0, 0, 0);
-            a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b1, a, 0, 0, 0);
-          }
-          a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b0, a, 0, 0, 0);
-          a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b1, a, 0, 0, 0);
-          a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b0, a, 0, 0, 0);
-          acc32[t] = a;
-          __builtin_amdgcn_sched_barrier(0);
-        }
-      }
-      if constexpr (PREC != 0) {
-        if (--group_left == 0 || ch == ch_end) {  // promote the group sum to FP64
-          group_left = C::GROUP;
-#pragma unroll
-          for (int t = 0; t < NBW; ++t) {
-#pragma unroll
-            for (int v = 0; v < 4; ++v) acc64[t][v] += (double)acc32[t][v];
-            acc32[t] = f4{0.f, 0.f, 0.f, 0.f};
-          }
-        }
-      }
-    }
-    if (ch < ch_end) {
-      // registers -> LDS buffer (ch & 1); its previous contents (chunk ch-2)
-      // were consumed before the barrier of the previous iteration
-      E_t* s = sY + (ch & 1) * BS;
-#pragma unroll
-      for (int p = 0; p < E; ++p) {
-        if (eoff[p] >= 0) put<PREC>(s, PS, eoff[p], rv[p]);
-        sq += rv[p] * rv[p];
-      }
-      lds_barrier();
-    }
+  // chunks split, split + nsplit, ...; chunk j is staged in LDS buffer j & 1
+  const int64_t nsplit = g.nsplit;
+  const int64_t niter = (g.nchunks - split + nsplit - 1) / nsplit;
+  typename W::E_t* buf0 = sY;
+  typename W::E_t* buf1 = sY + W::BS;
+  T rv0[E], rv1[E];
+  if (niter > 0) w.load(rv0, split);
+  if (niter > 1) w.load(rv1, split + nsplit);
+  if (niter > 0) {
+    w.store(rv0, buf0);
+    lds_barrier();
+  }
+  for (int64_t it = 0; it < niter; it += 2) {
+    // chunk it in buf0, chunk it + 1 in rv1; rv0 is free
+    if (it + 2 < niter) w.load(rv0, split + (it + 2) * nsplit);
+    w.compute(buf0, it + 1 == niter);
+    if (it + 1 < niter) w.store(rv1, buf1);
+    lds_barrier();
+    if (it + 1 >= niter) break;
+    // chunk it + 1 in buf1, chunk it + 2 in rv0; rv1 is free
+    if (it + 3 < niter) w.load(rv1, split + (it + 3) * nsplit);
+    w.compute(buf1, it + 2 == niter);
+    if (it + 2 < niter) w.store(rv0, buf0);
+    lds_barrier();
   }
 
   // partial blocks.  f64 MFMA result: lane l, register v -> D[(l>>4)+4v][l&15];
@@ -307,16 +411,16 @@ __device__ __forceinline__ void gram_body(const MPParams& g, int64_t item, int64
     if (t < nq) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int row = (PREC == 0) ? (q + 4 * v) : (4 * q + v);
-        P[(int64_t)(q0 + t) * 256 + row * 16 + i] = acc64[t][v];
+        const int row = (PREC == 0) ? (w.q + 4 * v) : (4 * w.q + v);
+        P[(int64_t)(q0 + t) * 256 + row * 16 + w.i] = w.acc64[t][v];
       }
     }
   }
   if (g.sq != nullptr) {
     // padding rows and columns load zeros; rows of an off-diagonal pair are
     // counted by the diagonal pairs
-    const double w = wave_sum(diag ? sq : 0.0);
-    if (lane == 0) sred[wave] = w;
+    const double sw = wave_sum(diag ? w.sq : 0.0);
+    if (lane == 0) sred[wave] = sw;
     __syncthreads();
     if (tid == 0) {
       double tot = 0.0;
@@ -333,7 +437,7 @@ __global__ __launch_bounds__(kNT) void gram_mp_tri_kernel(MPParams g) {
   __shared__ typename C::elem sY[2 * C::PLANES * 128 * C::LR];
   __shared__ double sred[kWaves];
   const int NR = (g.J + 15) & ~15;
-  gram_body<T, PREC, 128, NBW, false, UNIT_L>(g, blockIdx.x, blockIdx.x, true, 0, 0, NR, NR / 16, sY, sred);
+  gram_body<T, PREC, 128, NBW, false, UNIT_L, false>(g, blockIdx.x, blockIdx.x, true, 0, 0, NR, NR / 16, sY, sred);
 }
 
 // Pair mode: J > 128, items (split, tile pair) placed split-major on XCDs.
@@ -349,9 +453,9 @@ __global__ __launch_bounds__(kNT) void gram_mp_pair_kernel(MPParams g) {
   int ta, tb;
   decode_pair(pair, g.ntiles, ta, tb);
   if (ta == tb)
-    gram_body<T, PREC, 256, 5, false, UNIT_L>(g, item, split, true, 128 * ta, 128 * ta, 128, 8, sY, sred);
+    gram_body<T, PREC, 256, 5, false, UNIT_L, true>(g, item, split, true, 128 * ta, 128 * ta, 128, 8, sY, sred);
   else
-    gram_body<T, PREC, 256, 8, true, UNIT_L>(g, item, split, false, 128 * ta, 128 * tb, 256, 8, sY, sred);
+    gram_body<T, PREC, 256, 8, true, UNIT_L, true>(g, item, split, false, 128 * ta, 128 * tb, 256, 8, sY, sred);
 }
 
 // Sum the partial blocks of all splits in a fixed order; write both triangles.
@@ -460,7 +564,7 @@ hipError_t launch_gram_mp(const T* Y, int J, uint64_t L, uint64_t K, int prec, c
   const int nb = (J + 15) / 16;
   g.nblk = tri ? nb * (nb + 1) / 2 : 64;
   g.nchunks = p.nchunks;
-  g.cps = p.cps;
+  g.nsplit = p.nsplit;
   g.total = p.nsplit * p.npairs;
   g.part = part;
   g.sq = norm2 ? sq : nullptr;

@@ -17,7 +17,8 @@ struct GramParams {
   int ntiles;
   int npairs;
   int64_t nchunks;
-  int64_t cps;    // chunks per split
+  int64_t cps;    // chunks per split (at most)
+  int64_t nsplit; // splits; split s takes chunks s, s + nsplit, ...
   int64_t total;  // work items = nsplit * npairs
   double* part;   // nsplit * npairs * tile * tile partial tiles
   double* sq;     // nsplit * ntiles partial sums of squares (or null)
@@ -34,6 +35,8 @@ struct GramPlan {
   int64_t sq_elems;    // doubles of sum-of-squares workspace
 };
 
+// FP64 Gram with the whole triangle per workgroup, J <= kTriMaxJ.
+constexpr int kTriMaxJ = 240;
 GramPlan plan_gram_f64(int J, uint64_t L, uint64_t K);
 // `after_main` (may be null) is recorded right after the main Gram kernel.
 template <typename T>
@@ -48,6 +51,14 @@ GramPlan plan_gram_mp(int J, uint64_t K, int prec);
 template <typename T>
 hipError_t launch_gram_mp(const T* Y, int J, uint64_t L, uint64_t K, int prec, const GramPlan& p, double* part,
                           double* sq, double* S, double* norm2, hipStream_t stream, hipEvent_t after_main);
+
+// Streaming Gram for J <= kStreamMaxJ (HBM-bound small modes): no LDS, the
+// loaded values feed both MFMA operands; any arithmetic form.
+constexpr int kStreamMaxJ = 64;
+GramPlan plan_gram_stream(int J, uint64_t K, int prec);
+template <typename T>
+hipError_t launch_gram_stream(const T* Y, int J, uint64_t L, uint64_t K, int prec, const GramPlan& p, double* part,
+                              double* sq, double* S, double* norm2, hipStream_t stream, hipEvent_t after_main);
 
 // Range guard of a reduced-precision Gram (one workgroup): if S has a
 // non-finite entry or |trace(S) - *sq| > 1e-3 *sq, zero S and set *flag = 1,
