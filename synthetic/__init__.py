@@ -193,7 +193,8 @@ def fourier_fields(dims=(672, 672, 33, 626), nmodes: int = 512, eta: float = 1e-
 
     Returns (X, dims): numpy flat float32 (computed in float64) with
     ``device=None``, else a torch float32 tensor of shape dims[::-1] on
-    ``device`` (noise drawn there with torch's generator).
+    ``device`` (phases in float64 there, the separable products in float32,
+    noise drawn with torch's generator).
     """
     nx, ny, nvar, nt = [int(v) for v in dims]
     rng = np.random.default_rng(seed)
@@ -230,13 +231,27 @@ def fourier_fields(dims=(672, 672, 33, 626), nmodes: int = 512, eta: float = 1e-
 
     import torch
     X = torch.empty((nt, nvar, ny, nx), dtype=torch.float32, device=device)
-    tb = 64
+    f64 = dict(dtype=torch.float64, device=device)
+    xs = torch.arange(nx, **f64) / nx
+    ys = torch.arange(ny, **f64) / ny
+    tts = torch.from_numpy(tt).to(**f64)
+    tb = 32
     for v in range(nvar):
-        Pt = torch.from_numpy(lhs(v).T.copy()).to(device, torch.float32)  # (2M, nx)
+        ax = 2 * np.pi * xs[:, None] * torch.from_numpy(kx[v]).to(**f64)[None, :]
+        Pt = torch.cat([torch.cos(ax), torch.sin(ax)], dim=1).t().contiguous().float()  # (2M, nx)
+        ay = 2 * np.pi * ys[:, None] * torch.from_numpy(ky[v]).to(**f64)[None, :]
+        Cy, Sy = torch.cos(ay), torch.sin(ay)                                            # (ny, M)
+        Av = torch.from_numpy(A[v]).to(**f64)
+        wv = torch.from_numpy(w[v]).to(**f64)
+        pv = torch.from_numpy(phi[v]).to(**f64)
         for t0 in range(0, nt, tb):
-            ts = np.arange(t0, min(nt, t0 + tb))
-            R = torch.from_numpy(rhs(v, ts)).to(device, torch.float32)  # (b, ny, 2M)
-            X[t0:t0 + len(ts), v] = torch.matmul(R, Pt)
+            t1 = min(nt, t0 + tb)
+            psi = 2 * np.pi * wv[None, :] * tts[t0:t1, None] + pv[None, :]
+            Dc, Ds = Av * torch.cos(psi), Av * torch.sin(psi)                             # (b, M)
+            top = Cy[None] * Dc[:, None, :] - Sy[None] * Ds[:, None, :]
+            bot = -Sy[None] * Dc[:, None, :] - Cy[None] * Ds[:, None, :]
+            R = torch.cat([top, bot], dim=2).float()                                      # (b, ny, 2M)
+            X[t0:t1, v] = torch.matmul(R, Pt)
     if eta > 0:
         # noise with exact relative norm eta, drawn on the device one time step at a time
         flat = X.view(nt, -1)
