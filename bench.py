@@ -22,7 +22,10 @@ Also reported on the same JSON line:
   against 1.05 eps, largest principal-angle sine against the FP64 factors;
 * large_share: the 672x672x33x626 float32 Fourier-field tensor in mode order
   3,2,0,1 at eps 1e-4 with every Gram form, plus full and subrange
-  reconstruction.
+  reconstruction;
+* batched_form: 1024 independent float32 3-way tensors (sizes U{16..128},
+  ranks U{2..I/4}, noise 1e-4) at eps 1e-3, one batched run replayed from a
+  captured HIP graph against a loop of single-tensor calls, per Gram form.
 """
 from __future__ import annotations
 
@@ -215,6 +218,78 @@ def large_section(tk, torch, synthetic, reps):
             "dims": dims, "bytes": nbytes, "generate_s": round(gen, 2), "reps": reps, "results": rows}
 
 
+def batched_section(tk, torch, synthetic, reps):
+    t0 = time.perf_counter()
+    data = synthetic.small_batch(count=1024)
+    gen = time.perf_counter() - t0
+    xs = [torch.from_numpy(X.reshape(d[::-1])).to("cuda") for X, d in data]
+    dims = [d for _, d in data]
+    nbytes = sum(x.numel() * 4 for x in xs)
+    eps = 1e-3
+    rows = []
+    for prec in ["fp64", "fp32", "bf16x6"]:
+        print(f"# batched {prec}", file=sys.stderr, flush=True)
+        t0 = time.perf_counter()
+        b = tk.Batch(xs, eps, prec=prec, dims=dims)
+        create_s = time.perf_counter() - t0
+        b.run()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            b.run()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        eager_ms = sorted(ts)[len(ts) // 2] * 1e3
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            b.run()
+        g.replay()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(max(reps, 5)):
+            t0 = time.perf_counter()
+            g.replay()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        graph_ms = sorted(ts)[len(ts) // 2] * 1e3
+        ranks = b.ranks()
+        # loop of single-tensor calls (same arithmetic)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        single_ranks = []
+        for x, d in zip(xs, dims):
+            t = tk.sthosvd(x, eps, prec=prec, dims=d)
+            single_ranks.append(list(t.ranks))
+            t.free()
+        torch.cuda.synchronize()
+        loop_ms = (time.perf_counter() - t0) * 1e3
+        worst = 0.0
+        for i in range(0, len(xs), 16):  # relative error on every 16th tensor
+            t = b.item(i)
+            xh = t.reconstruct(out_dtype=torch.float64)
+            x64 = xs[i].to(torch.float64)
+            e = float(torch.linalg.vector_norm((x64 - xh).reshape(-1)) / torch.linalg.vector_norm(x64.reshape(-1)))
+            worst = max(worst, e)
+            t.free()
+        rows.append({"gram": prec, "graph_ms": round(graph_ms, 3), "eager_run_ms": round(eager_ms, 3),
+                     "loop_of_single_calls_ms": round(loop_ms, 2), "speedup_vs_loop": round(loop_ms / graph_ms, 2),
+                     "input_GBs": round(nbytes / graph_ms / 1e6, 2), "plan_create_s": round(create_s, 3),
+                     "tiles_gram_chunks_ttm_tiles": list(b.tiles()),
+                     "ranks_match_single_calls": sum(r == q for r, q in zip(ranks, single_ranks)),
+                     "worst_relerr_sampled": worst, "within_1.05eps": bool(worst <= 1.05 * eps)})
+        del g
+        b.free()
+    fp64_graph = rows[0]["graph_ms"]
+    for r in rows:
+        r["speedup_vs_fp64_graph"] = round(fp64_graph / r["graph_ms"], 3)
+    del xs
+    torch.cuda.empty_cache()
+    return {"workload": "1024 float32 3-way tensors, sizes U{16..128}, Tucker ranks U{2..I/4}, noise 1e-4 "
+                        "(seeds 4000+i), eps 1e-3, mode order 0,1,2", "count": 1024, "bytes": nbytes,
+            "generate_s": round(gen, 2), "results": rows}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -222,8 +297,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--eps", type=float, default=1e-4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--sections", default="precision,large",
-                    help="extra sections after the headline line's own workload: precision,large (or none)")
+    ap.add_argument("--sections", default="precision,large,batched",
+                    help="extra sections after the headline line's own workload: precision,large,batched "
+                         "(or none)")
     ap.add_argument("--form-reps", type=int, default=3, help="timed compressions per form in extra sections")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -303,6 +379,8 @@ def main():
         line["precision_form"] = precision_section(tk, torch, synthetic, args.form_reps)
     if "large" in sections:
         line["large_share"] = large_section(tk, torch, synthetic, max(1, args.form_reps - 1))
+    if "batched" in sections:
+        line["batched_form"] = batched_section(tk, torch, synthetic, args.form_reps)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(X, dims, args.eps, order, begin, end, nbytes)
     print(json.dumps(line), flush=True)

@@ -158,6 +158,50 @@ tucker_status tucker_reconstruct_order(int N, const int64_t* ranks, const int64_
                                        int* order_out);
 
 /* ------------------------------------------------------------------------
+ * Batching form (not in the paper): many independent tensors of the same
+ * order N, every mode size <= 128, compressed together.  A plan binds the
+ * data pointers and sizes and owns all device memory; running it only
+ * enqueues kernels on the stream (no allocation, no synchronisation, no
+ * memset), so a run may be captured in a HIP graph and replayed.  Ranks are
+ * decided on the device (device-side sizes); each step is one batched Gram,
+ * one batched eigensolve + truncation and one batched TTM over all tensors.
+ * Tile sizes of the batched Gram and TTM are chosen by timing candidates on
+ * the first plan of a shape class (count, N, precision, input type, total
+ * size to within 2x) and remembered for the process.
+ * ------------------------------------------------------------------------ */
+typedef struct tucker_batch tucker_batch;
+
+/*   count      number of tensors, >= 1.
+ *   data       host array of `count` device pointers (natural descending, `dtype`).
+ *   dims       host, count x N sizes (tensor t's sizes at dims + t*N), each 1..128.
+ *   eps, mode_order, prec: as for tucker_sthosvd (the order is shared).
+ *   stream     used for the plan's uploads and its tuning runs; synchronised.
+ * Errors: EINVAL (arguments), EUNSUPPORTED (a size above 128), ENOMEM, EHIP. */
+tucker_status tucker_batch_create(int count, const void* const* data, tucker_dtype dtype,
+                                  const int64_t* dims, int N, double eps, const int* mode_order,
+                                  tucker_gram_prec prec, hipStream_t stream, tucker_batch** out);
+/* Enqueue the whole compression on `stream` (capturable; reads the data
+ * pointers given at creation each time it runs). */
+tucker_status tucker_batch_run(tucker_batch* b, hipStream_t stream);
+/* tucker_batch_create followed by tucker_batch_run. */
+tucker_status tucker_sthosvd_batched(int count, const void* const* data, tucker_dtype dtype,
+                                     const int64_t* dims, int N, double eps, const int* mode_order,
+                                     tucker_gram_prec prec, hipStream_t stream, tucker_batch** out);
+/* Results of the last run; each call synchronises the stream given to the
+ * last tucker_batch_run (after replaying a captured run on another stream,
+ * synchronise that stream first).  host out[count*N] ranks; host out[count]
+ * ||X_t||^2. */
+tucker_status tucker_batch_ranks(tucker_batch* b, int64_t* ranks_out);
+tucker_status tucker_batch_norm2(tucker_batch* b, double* norm2_out);
+/* Tensor i of the last run as a standalone handle (copies of its core,
+ * factors and eigenvalues); release with tucker_free. */
+tucker_status tucker_batch_item(tucker_batch* b, int i, tucker_t** out);
+/* The chosen tiles: Gram chunks per work item, TTM 64-column tiles per item. */
+tucker_status tucker_batch_tiles(const tucker_batch* b, int* gram_chunks, int* ttm_tiles);
+/* Synchronises the last run's stream, then releases everything. */
+void tucker_batch_free(tucker_batch* b);
+
+/* ------------------------------------------------------------------------
  * Single steps of the path, for testing and for callers composing their own
  * loop.  All pointers are device pointers except dims (host).
  * ------------------------------------------------------------------------ */

@@ -31,6 +31,8 @@ EXPORTS = [
     "tucker_factor", "tucker_eigenvalues", "tucker_norm2", "tucker_discarded", "tucker_timings",
     "tucker_gram_precision", "tucker_free", "tucker_reconstruct", "tucker_reconstruct_order", "tucker_gram",
     "tucker_eig_truncate", "tucker_ttm", "tucker_last_error", "tucker_version",
+    "tucker_batch_create", "tucker_batch_run", "tucker_sthosvd_batched", "tucker_batch_ranks",
+    "tucker_batch_norm2", "tucker_batch_item", "tucker_batch_tiles", "tucker_batch_free",
 ]
 
 _lib = None
@@ -71,6 +73,14 @@ def lib():
             "tucker_gram": (i32, [P, i32, P, i32, i32, i32, P, P, P]),
             "tucker_eig_truncate": (i32, [P, i64, d, P, P, P, P, P]),
             "tucker_ttm": (i32, [P, i32, P, i32, i32, P, i64, i64, i64, P, i32, i32, P]),
+            "tucker_batch_create": (i32, [i32, P, i32, P, i32, d, P, i32, P, PP]),
+            "tucker_batch_run": (i32, [P, P]),
+            "tucker_sthosvd_batched": (i32, [i32, P, i32, P, i32, d, P, i32, P, PP]),
+            "tucker_batch_ranks": (i32, [P, P]),
+            "tucker_batch_norm2": (i32, [P, P]),
+            "tucker_batch_item": (i32, [P, i32, PP]),
+            "tucker_batch_tiles": (i32, [P, P, P]),
+            "tucker_batch_free": (None, [P]),
             "tucker_last_error": (ctypes.c_char_p, []),
             "tucker_version": (ctypes.c_char_p, []),
         }
@@ -309,3 +319,65 @@ def ttm(y, n: int, M, dims=None, out_dtype=None, fp32_products: bool = False, st
                             M.stride(0), M.stride(1), Z.data_ptr(), _dtype_code(Z), int(bool(fp32_products)),
                             _stream(stream)))
     return Z
+
+
+class Batch:
+    """Batched ST-HOSVD plan over many GPU tensors of the same order (every mode
+    size <= 128): one run enqueues the whole compression (capturable in a HIP
+    graph)."""
+
+    def __init__(self, tensors, eps: float, mode_order=None, prec: str = "fp64", dims=None, stream=None):
+        if len(tensors) == 0:
+            raise ValueError("empty batch")
+        dts = {_dtype_code(x) for x in tensors}
+        if len(dts) != 1:
+            raise ValueError("all tensors must have the same dtype")
+        self.dims = [_dims_of(x, None if dims is None else dims[i]) for i, x in enumerate(tensors)]
+        Ns = {len(dm) for dm in self.dims}
+        if len(Ns) != 1:
+            raise ValueError("all tensors must have the same order")
+        self.N = Ns.pop()
+        self.count = len(tensors)
+        self._tensors = list(tensors)  # keep the inputs alive: the plan reads them at every run
+        ptrs = (ctypes.c_void_p * self.count)(*[x.data_ptr() for x in tensors])
+        flat = [v for dm in self.dims for v in dm]
+        h = ctypes.c_void_p(0)
+        _check(lib().tucker_batch_create(self.count, ptrs, dts.pop(), _i64(flat), self.N, float(eps),
+                                         _i32(mode_order) if mode_order is not None else None, _PREC[prec],
+                                         _stream(stream), ctypes.byref(h)))
+        self._h = h.value
+
+    def run(self, stream=None):
+        _check(lib().tucker_batch_run(self._h, _stream(stream)))
+
+    def ranks(self):
+        out = (ctypes.c_int64 * (self.count * self.N))()
+        _check(lib().tucker_batch_ranks(self._h, out))
+        return [list(out[i * self.N:(i + 1) * self.N]) for i in range(self.count)]
+
+    def norm2(self):
+        out = (ctypes.c_double * self.count)()
+        _check(lib().tucker_batch_norm2(self._h, out))
+        return list(out)
+
+    def item(self, i: int) -> Tucker:
+        h = ctypes.c_void_p(0)
+        _check(lib().tucker_batch_item(self._h, int(i), ctypes.byref(h)))
+        return Tucker(h.value, 0)
+
+    def tiles(self):
+        g, t = ctypes.c_int(0), ctypes.c_int(0)
+        _check(lib().tucker_batch_tiles(self._h, ctypes.byref(g), ctypes.byref(t)))
+        return g.value, t.value
+
+    def free(self):
+        if self._h:
+            lib().tucker_batch_free(self._h)
+            self._h = 0
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+

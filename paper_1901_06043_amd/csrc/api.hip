@@ -679,3 +679,560 @@ tucker_status tucker_ttm(const void* Y, tucker_dtype ydtype, const int64_t* dims
 }
 
 }  // extern "C"
+
+// ======================================================================
+// Batching form: many independent tensors, device-side sizes, no host
+// synchronisation between steps (tucker_batch_run only enqueues kernels).
+// ======================================================================
+namespace {
+
+__global__ void batch_reset_cur_kernel(const int64_t* __restrict__ dims0, int64_t* __restrict__ cur, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) cur[i] = dims0[i];
+}
+
+__global__ void batch_set_rank_kernel(const int64_t* __restrict__ R, int count, int N, int n,
+                                      int64_t* __restrict__ cur) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < count) cur[(int64_t)t * N + n] = R[t];
+}
+
+// Tile choices of the batched kernels, picked by timing candidates on the
+// first plan of a given shape class and remembered for the process.
+struct BatchTiles {
+  int gram_chunks;  // Gram chunks per work item
+  int ttm_tiles;    // TTM column tiles (64 columns) per work item
+};
+std::mutex g_tune_mu;
+std::vector<std::pair<std::string, BatchTiles>> g_tuned;
+
+}  // namespace
+
+struct tucker_batch {
+  int count = 0, N = 0;
+  int order[TUCKER_MAX_MODES] = {0};
+  tucker_gram_prec prec = TUCKER_GRAM_FP64;
+  tucker_dtype in_dt = TUCKER_F64, wdt = TUCKER_F64;
+  double eps = 0.0;
+  hipStream_t alloc_stream = nullptr, run_stream = nullptr;
+  bool ran = false;
+  BatchTiles tiles{64, 8};
+  std::vector<int64_t> dims;      // host, count x N
+  std::vector<int64_t> off;       // element offset of tensor t in the work buffers
+  int Jmax[TUCKER_MAX_MODES] = {0};
+  std::vector<void*> owned;
+  // device
+  int64_t *dims0 = nullptr, *cur = nullptr;
+  void* buf[2] = {nullptr, nullptr};
+  const void** ptrY[TUCKER_MAX_MODES] = {nullptr};
+  void** ptrZ[TUCKER_MAX_MODES] = {nullptr};
+  int* Jd[TUCKER_MAX_MODES] = {nullptr};
+  int64_t* gitems[TUCKER_MAX_MODES] = {nullptr};
+  int* gfirst[TUCKER_MAX_MODES] = {nullptr};
+  int gn[TUCKER_MAX_MODES] = {0}, gsmall[TUCKER_MAX_MODES] = {0};
+  int64_t* titems[TUCKER_MAX_MODES] = {nullptr};
+  int tn[TUCKER_MAX_MODES] = {0};
+  double *part = nullptr, *sq = nullptr, *S = nullptr, *A = nullptr, *Zt = nullptr, *dd = nullptr, *ee = nullptr,
+         *tau = nullptr, *scal = nullptr, *nx2 = nullptr;
+  double* U[TUCKER_MAX_MODES] = {nullptr};
+  double* lam[TUCKER_MAX_MODES] = {nullptr};
+  int64_t* R[TUCKER_MAX_MODES] = {nullptr};
+  double* disc[TUCKER_MAX_MODES] = {nullptr};
+  // host copies, refreshed by every result query
+  std::vector<int64_t> hR;     // count x N
+  std::vector<double> hnorm2;  // count
+  std::vector<double> hdisc;   // count x N
+
+  hipError_t alloc(void** p, size_t bytes) {
+    hipError_t e = dev_alloc(p, bytes, alloc_stream);
+    if (e == hipSuccess) owned.push_back(*p);
+    return e;
+  }
+  template <typename T>
+  hipError_t upload(T** dst, const std::vector<T>& v) {
+    hipError_t e = alloc((void**)dst, sizeof(T) * std::max<size_t>(1, v.size()));
+    if (e != hipSuccess) return e;
+    if (v.empty()) return hipSuccess;
+    // the host vector is temporary: wait for the copy
+    e = hipMemcpyAsync(*dst, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, alloc_stream);
+    return e == hipSuccess ? hipStreamSynchronize(alloc_stream) : e;
+  }
+  void release() {
+    if (run_stream) (void)hipStreamSynchronize(run_stream);
+    for (void* p : owned) dev_free(p, alloc_stream);
+    owned.clear();
+  }
+};
+
+namespace {
+
+size_t wsize(tucker_dtype t) { return t == TUCKER_F64 ? 8 : 4; }
+
+// Host plan of the work items of step s (sizes bounded by the original ones).
+void plan_step_items(const tucker_batch* b, int s, const BatchTiles& tiles, std::vector<int64_t>& gitems,
+                     std::vector<int>& gfirst, int& nsmall, std::vector<int64_t>& titems, int64_t& part_elems) {
+  const int N = b->N, n = b->order[s];
+  const int KC = (b->prec == TUCKER_GRAM_FP64) ? 16 : 32;
+  gitems.clear();
+  titems.clear();
+  gfirst.assign(2 * (size_t)b->count, 0);
+  part_elems = 0;
+  nsmall = 0;
+  for (int pass = 0; pass < 2; ++pass) {  // tensors with J <= 80 first
+    for (int t = 0; t < b->count; ++t) {
+      const int64_t* d = &b->dims[(size_t)t * N];
+      const int64_t J = d[n];
+      if ((J <= 80) != (pass == 0)) continue;
+      int64_t K = 1;
+      for (int k = 0; k < N; ++k)
+        if (k != n) K *= d[k];
+      const int64_t nch = ceil_div(K, KC);
+      const int64_t nb = (J + 15) / 16, nblk = nb * (nb + 1) / 2;
+      gfirst[2 * t] = (int)(gitems.size() / 4);
+      for (int64_t c0 = 0; c0 < nch; c0 += tiles.gram_chunks) {
+        gitems.push_back(t);
+        gitems.push_back(c0);
+        gitems.push_back(std::min<int64_t>(nch, c0 + tiles.gram_chunks));
+        gitems.push_back(part_elems);
+        part_elems += nblk * 256;
+      }
+      gfirst[2 * t + 1] = (int)(gitems.size() / 4);
+      const int64_t nct = ceil_div(K, 64);
+      for (int64_t c0 = 0; c0 < nct; c0 += tiles.ttm_tiles) {
+        titems.push_back(t);
+        titems.push_back(c0);
+        titems.push_back(std::min<int64_t>(nct, c0 + tiles.ttm_tiles));
+      }
+    }
+    if (pass == 0) nsmall = (int)(gitems.size() / 4);
+  }
+}
+
+tucker_status batch_enqueue_gram(tucker_batch* b, int s, hipStream_t stream) {
+  const int n = b->order[s];
+  tk::GramBatch g{};
+  g.count = b->count;
+  g.N = b->N;
+  g.n = n;
+  g.Jmax = b->Jmax[s];
+  g.Y = b->ptrY[s];
+  g.cur = b->cur;
+  g.J = b->Jd[s];
+  g.items = b->gitems[s];
+  g.nitems = b->gn[s];
+  g.nsmall = b->gsmall[s];
+  g.ifirst = b->gfirst[s];
+  g.part = b->part;
+  g.sq = b->sq;
+  g.S = b->S;
+  g.nx2 = (s == 0) ? b->nx2 : nullptr;
+  const tucker_dtype ydt = (s == 0) ? b->in_dt : b->wdt;
+  if (ydt == TUCKER_F64) HIP_TRY(tk::launch_gram_batched<double>(g, (int)b->prec, n == 0, stream));
+  else HIP_TRY(tk::launch_gram_batched<float>(g, (int)b->prec, n == 0, stream));
+  return TUCKER_OK;
+}
+
+tucker_status batch_enqueue_ttm(tucker_batch* b, int s, hipStream_t stream) {
+  const int n = b->order[s];
+  tk::TtmBatch m{};
+  m.count = b->count;
+  m.N = b->N;
+  m.n = n;
+  m.Jmax = b->Jmax[s];
+  m.Y = b->ptrY[s];
+  m.Z = b->ptrZ[s];
+  m.cur = b->cur;
+  m.J = b->Jd[s];
+  m.R = b->R[n];
+  m.U = b->U[n];
+  m.items = b->titems[s];
+  m.nitems = b->tn[s];
+  const bool f32p = (b->prec != TUCKER_GRAM_FP64);
+  const tucker_dtype ydt = (s == 0) ? b->in_dt : b->wdt;
+  if (ydt == TUCKER_F32 && b->wdt == TUCKER_F32) HIP_TRY((tk::launch_ttm_batched<float, float>(m, f32p, n == 0, stream)));
+  else if (ydt == TUCKER_F32) HIP_TRY((tk::launch_ttm_batched<float, double>(m, f32p, n == 0, stream)));
+  else HIP_TRY((tk::launch_ttm_batched<double, double>(m, f32p, n == 0, stream)));
+  return TUCKER_OK;
+}
+
+tucker_status batch_enqueue_eig(tucker_batch* b, int s, hipStream_t stream) {
+  const int n = b->order[s];
+  tk::EigBatch e{};
+  e.count = b->count;
+  e.Jmax = b->Jmax[s];
+  e.J = b->Jd[s];
+  e.S = b->S;
+  e.A = b->A;
+  e.Zt = b->Zt;
+  e.d = b->dd;
+  e.e = b->ee;
+  e.tau = b->tau;
+  e.lam = b->lam[n];
+  e.scal = b->scal;
+  e.U = b->U[n];
+  e.R = b->R[n];
+  e.disc = b->disc[n];
+  e.nx2 = b->nx2;
+  HIP_TRY(tk::launch_eig_truncate_batched(e, b->eps * b->eps / b->N, stream));
+  hipLaunchKernelGGL(batch_set_rank_kernel, dim3(ceil_div(b->count, 256)), dim3(256), 0, stream, b->R[n], b->count,
+                     b->N, n, b->cur);
+  HIP_TRY(hipGetLastError());
+  return TUCKER_OK;
+}
+
+tucker_status batch_enqueue_all(tucker_batch* b, hipStream_t stream) {
+  const int64_t nc = (int64_t)b->count * b->N;
+  hipLaunchKernelGGL(batch_reset_cur_kernel, dim3(ceil_div(nc, 256)), dim3(256), 0, stream, b->dims0, b->cur, nc);
+  HIP_TRY(hipGetLastError());
+  tucker_status st;
+  for (int s = 0; s < b->N; ++s) {
+    if ((st = batch_enqueue_gram(b, s, stream))) return st;
+    if ((st = batch_enqueue_eig(b, s, stream))) return st;
+    if ((st = batch_enqueue_ttm(b, s, stream))) return st;
+  }
+  return TUCKER_OK;
+}
+
+// Upload the step plans for `tiles` (items, first-item table).
+tucker_status batch_upload_plans(tucker_batch* b, const BatchTiles& tiles, int64_t& part_max, int& items_max) {
+  part_max = 0;
+  items_max = 0;
+  for (int s = 0; s < b->N; ++s) {
+    std::vector<int64_t> gi, ti;
+    std::vector<int> gf;
+    int nsmall = 0;
+    int64_t pe = 0;
+    plan_step_items(b, s, tiles, gi, gf, nsmall, ti, pe);
+    HIP_TRY(b->upload(&b->gitems[s], gi));
+    HIP_TRY(b->upload(&b->gfirst[s], gf));
+    HIP_TRY(b->upload(&b->titems[s], ti));
+    b->gn[s] = (int)(gi.size() / 4);
+    b->gsmall[s] = nsmall;
+    b->tn[s] = (int)(ti.size() / 3);
+    part_max = std::max(part_max, pe);
+    items_max = std::max(items_max, b->gn[s]);
+  }
+  return TUCKER_OK;
+}
+
+std::string tune_key(const tucker_batch* b) {
+  // shape class: count, N, precision, input type and the total size to within 2x
+  int64_t tot = 0;
+  for (int t = 0; t < b->count; ++t) {
+    int64_t e = 1;
+    for (int k = 0; k < b->N; ++k) e *= b->dims[(size_t)t * b->N + k];
+    tot += e;
+  }
+  int lg = 0;
+  while ((int64_t(1) << lg) < tot) ++lg;
+  char buf[128];
+  snprintf(buf, sizeof buf, "%d/%d/%d/%d/%d", b->count, b->N, (int)b->prec, (int)b->in_dt, lg);
+  return buf;
+}
+
+}  // namespace
+
+extern "C" {
+
+tucker_status tucker_batch_create(int count, const void* const* data, tucker_dtype dtype, const int64_t* dims, int N,
+                                  double eps, const int* mode_order, tucker_gram_prec prec, hipStream_t stream,
+                                  tucker_batch** out) {
+  if (!out) return fail(TUCKER_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (count < 1) return fail(TUCKER_EINVAL, "count=%d < 1", count);
+  if (!data || !dims) return fail(TUCKER_EINVAL, "NULL argument");
+  if (dtype != TUCKER_F32 && dtype != TUCKER_F64) return fail(TUCKER_EINVAL, "bad dtype");
+  if (prec < TUCKER_GRAM_FP64 || prec > TUCKER_GRAM_BF16X6) return fail(TUCKER_EINVAL, "bad Gram precision");
+  if (prec != TUCKER_GRAM_FP64 && dtype != TUCKER_F32)
+    return fail(TUCKER_EINVAL, "reduced-precision Gram needs FP32 data");
+  if (!(eps >= 0.0) || !std::isfinite(eps)) return fail(TUCKER_EINVAL, "eps must be finite and >= 0");
+  tucker_status st;
+  if (N < 1 || N > TUCKER_MAX_MODES) return fail(TUCKER_EINVAL, "N=%d outside 1..%d", N, TUCKER_MAX_MODES);
+  for (int t = 0; t < count; ++t) {
+    if (!data[t]) return fail(TUCKER_EINVAL, "data[%d] is NULL", t);
+    if ((st = validate_dims(dims + (size_t)t * N, N))) return st;
+    for (int k = 0; k < N; ++k)
+      if (dims[(size_t)t * N + k] > tk::kBatchMaxJ)
+        return fail(TUCKER_EUNSUPPORTED, "tensor %d mode %d has size %lld; the batched form supports up to %d", t, k,
+                    (long long)dims[(size_t)t * N + k], tk::kBatchMaxJ);
+  }
+  int order[TUCKER_MAX_MODES];
+  if ((st = validate_order(mode_order, N, order))) return st;
+  if ((st = ensure_device())) return st;
+
+  struct Guard {
+    tucker_batch* b;
+    ~Guard() {
+      if (b) {
+        b->release();
+        delete b;
+      }
+    }
+  } g{new tucker_batch};
+  tucker_batch* b = g.b;
+  b->count = count;
+  b->N = N;
+  std::memcpy(b->order, order, sizeof(int) * N);
+  b->prec = prec;
+  b->in_dt = dtype;
+  b->wdt = (prec == TUCKER_GRAM_FP64) ? TUCKER_F64 : TUCKER_F32;
+  b->eps = eps;
+  b->alloc_stream = stream;
+  b->dims.assign(dims, dims + (size_t)count * N);
+  b->off.resize(count + 1);
+  b->off[0] = 0;
+  for (int t = 0; t < count; ++t) {
+    int64_t e = 1;
+    for (int k = 0; k < N; ++k) e *= dims[(size_t)t * N + k];
+    b->off[t + 1] = b->off[t] + e;
+  }
+  const int64_t total = b->off[count];
+  int Jall = 0;
+  for (int s = 0; s < N; ++s) {
+    int m = 0;
+    for (int t = 0; t < count; ++t) m = std::max<int>(m, (int)dims[(size_t)t * N + order[s]]);
+    b->Jmax[s] = m;
+    Jall = std::max(Jall, m);
+  }
+  const size_t ws = wsize(b->wdt);
+  HIP_TRY(b->upload(&b->dims0, b->dims));
+  HIP_TRY(b->alloc((void**)&b->cur, sizeof(int64_t) * (size_t)count * N));
+  HIP_TRY(b->alloc(&b->buf[0], ws * (size_t)total));
+  if (N > 1) HIP_TRY(b->alloc(&b->buf[1], ws * (size_t)total));
+  // per-step operand and result pointers
+  for (int s = 0; s < N; ++s) {
+    std::vector<const void*> py(count);
+    std::vector<void*> pz(count);
+    std::vector<int> Jv(count);
+    for (int t = 0; t < count; ++t) {
+      py[t] = (s == 0) ? data[t] : static_cast<const char*>(b->buf[(s - 1) % 2]) + ws * b->off[t];
+      pz[t] = static_cast<char*>(b->buf[s % 2]) + ws * b->off[t];
+      Jv[t] = (int)dims[(size_t)t * N + order[s]];
+    }
+    HIP_TRY(b->upload((const void***)&b->ptrY[s], py));
+    HIP_TRY(b->upload(&b->ptrZ[s], pz));
+    HIP_TRY(b->upload(&b->Jd[s], Jv));
+  }
+  const size_t J2 = (size_t)Jall * Jall;
+  HIP_TRY(b->alloc((void**)&b->S, sizeof(double) * J2 * count));
+  HIP_TRY(b->alloc((void**)&b->A, sizeof(double) * J2 * count));
+  HIP_TRY(b->alloc((void**)&b->Zt, sizeof(double) * J2 * count));
+  HIP_TRY(b->alloc((void**)&b->dd, sizeof(double) * Jall * count));
+  HIP_TRY(b->alloc((void**)&b->ee, sizeof(double) * Jall * count));
+  HIP_TRY(b->alloc((void**)&b->tau, sizeof(double) * Jall * count));
+  HIP_TRY(b->alloc((void**)&b->scal, sizeof(double) * 8 * count));
+  HIP_TRY(b->alloc((void**)&b->nx2, sizeof(double) * count));
+  for (int s = 0; s < N; ++s) {
+    const int n = order[s];
+    const size_t Jn = (size_t)b->Jmax[s];
+    HIP_TRY(b->alloc((void**)&b->U[n], sizeof(double) * Jn * Jn * count));
+    HIP_TRY(b->alloc((void**)&b->lam[n], sizeof(double) * Jn * count));
+    HIP_TRY(b->alloc((void**)&b->R[n], sizeof(int64_t) * count));
+    HIP_TRY(b->alloc((void**)&b->disc[n], sizeof(double) * count));
+  }
+  // tile choice: remembered per shape class, else tuned on this batch's first step
+  const std::string key = tune_key(b);
+  bool have = false;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (auto& kv : g_tuned)
+      if (kv.first == key) {
+        b->tiles = kv.second;
+        have = true;
+      }
+  }
+  const BatchTiles cands[] = {{16, 2}, {64, 8}, {256, 32}};
+  int64_t part_max = 0;
+  int items_max = 0;
+  if (!have) {
+    // allocate for the largest plan among the candidates
+    int64_t pm = 0;
+    int im = 0;
+    for (const BatchTiles& c : cands) {
+      for (int s = 0; s < N; ++s) {
+        std::vector<int64_t> gi, ti;
+        std::vector<int> gf;
+        int ns = 0;
+        int64_t pe = 0;
+        plan_step_items(b, s, c, gi, gf, ns, ti, pe);
+        pm = std::max(pm, pe);
+        im = std::max(im, (int)(gi.size() / 4));
+      }
+    }
+    HIP_TRY(b->alloc((void**)&b->part, sizeof(double) * std::max<int64_t>(pm, 1)));
+    HIP_TRY(b->alloc((void**)&b->sq, sizeof(double) * std::max(im, 1)));
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    float bestg = 1e30f, bestt = 1e30f;
+    BatchTiles best = cands[1];
+    int64_t nc = (int64_t)count * N;
+    for (const BatchTiles& c : cands) {
+      if ((st = batch_upload_plans(b, c, part_max, items_max))) return st;
+      hipLaunchKernelGGL(batch_reset_cur_kernel, dim3(ceil_div(nc, 256)), dim3(256), 0, stream, b->dims0, b->cur, nc);
+      float tg = 0.f, tt = 0.f;
+      for (int rep = 0; rep < 3; ++rep) {  // first repetition warms up
+        HIP_TRY(hipEventRecord(e0, stream));
+        if ((st = batch_enqueue_gram(b, 0, stream))) return st;
+        HIP_TRY(hipEventRecord(e1, stream));
+        HIP_TRY(hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+        if (rep > 0) tg += ms;
+        if (rep == 0 && (st = batch_enqueue_eig(b, 0, stream))) return st;
+        HIP_TRY(hipEventRecord(e0, stream));
+        if ((st = batch_enqueue_ttm(b, 0, stream))) return st;
+        HIP_TRY(hipEventRecord(e1, stream));
+        HIP_TRY(hipEventSynchronize(e1));
+        HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+        if (rep > 0) tt += ms;
+      }
+      if (tg < bestg) {
+        bestg = tg;
+        best.gram_chunks = c.gram_chunks;
+      }
+      if (tt < bestt) {
+        bestt = tt;
+        best.ttm_tiles = c.ttm_tiles;
+      }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    b->tiles = best;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tuned.push_back({key, best});
+  }
+  if ((st = batch_upload_plans(b, b->tiles, part_max, items_max))) return st;
+  if (have) {
+    HIP_TRY(b->alloc((void**)&b->part, sizeof(double) * std::max<int64_t>(part_max, 1)));
+    HIP_TRY(b->alloc((void**)&b->sq, sizeof(double) * std::max(items_max, 1)));
+  }
+  HIP_TRY(hipStreamSynchronize(stream));  // uploads done; host vectors may go
+  *out = g.b;
+  g.b = nullptr;
+  return TUCKER_OK;
+}
+
+tucker_status tucker_batch_run(tucker_batch* b, hipStream_t stream) {
+  if (!b) return fail(TUCKER_EINVAL, "batch is NULL");
+  b->run_stream = stream;
+  b->ran = true;
+  return batch_enqueue_all(b, stream);
+}
+
+tucker_status tucker_sthosvd_batched(int count, const void* const* data, tucker_dtype dtype, const int64_t* dims,
+                                     int N, double eps, const int* mode_order, tucker_gram_prec prec,
+                                     hipStream_t stream, tucker_batch** out) {
+  tucker_status st = tucker_batch_create(count, data, dtype, dims, N, eps, mode_order, prec, stream, out);
+  if (st) return st;
+  st = tucker_batch_run(*out, stream);
+  if (st) {
+    tucker_batch_free(*out);
+    *out = nullptr;
+  }
+  return st;
+}
+
+}  // extern "C"
+
+namespace {
+
+tucker_status batch_sync(tucker_batch* b) {
+  // re-read every time: a captured run may have been replayed since
+  if (!b->ran) return fail(TUCKER_EINVAL, "the batch has not been run");
+  HIP_TRY(hipStreamSynchronize(b->run_stream));
+  const int C = b->count, N = b->N;
+  b->hR.assign((size_t)C * N, 0);
+  b->hdisc.assign((size_t)C * N, 0.0);
+  b->hnorm2.assign(C, 0.0);
+  std::vector<int64_t> r(C);
+  std::vector<double> d(C);
+  for (int n = 0; n < N; ++n) {
+    HIP_TRY(hipMemcpy(r.data(), b->R[n], sizeof(int64_t) * C, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(d.data(), b->disc[n], sizeof(double) * C, hipMemcpyDeviceToHost));
+    for (int t = 0; t < C; ++t) {
+      b->hR[(size_t)t * N + n] = r[t];
+      b->hdisc[(size_t)t * N + n] = d[t];
+    }
+  }
+  HIP_TRY(hipMemcpy(b->hnorm2.data(), b->nx2, sizeof(double) * C, hipMemcpyDeviceToHost));
+  return TUCKER_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+tucker_status tucker_batch_ranks(tucker_batch* b, int64_t* ranks_out) {
+  if (!b || !ranks_out) return fail(TUCKER_EINVAL, "NULL argument");
+  tucker_status st = batch_sync(b);
+  if (st) return st;
+  std::memcpy(ranks_out, b->hR.data(), sizeof(int64_t) * b->hR.size());
+  return TUCKER_OK;
+}
+
+tucker_status tucker_batch_norm2(tucker_batch* b, double* norm2_out) {
+  if (!b || !norm2_out) return fail(TUCKER_EINVAL, "NULL argument");
+  tucker_status st = batch_sync(b);
+  if (st) return st;
+  std::memcpy(norm2_out, b->hnorm2.data(), sizeof(double) * b->count);
+  return TUCKER_OK;
+}
+
+tucker_status tucker_batch_tiles(const tucker_batch* b, int* gram_chunks, int* ttm_tiles) {
+  if (!b || !gram_chunks || !ttm_tiles) return fail(TUCKER_EINVAL, "NULL argument");
+  *gram_chunks = b->tiles.gram_chunks;
+  *ttm_tiles = b->tiles.ttm_tiles;
+  return TUCKER_OK;
+}
+
+tucker_status tucker_batch_item(tucker_batch* b, int i, tucker_t** out) {
+  if (!b || !out) return fail(TUCKER_EINVAL, "NULL argument");
+  *out = nullptr;
+  if (i < 0 || i >= b->count) return fail(TUCKER_EINVAL, "item %d outside 0..%d", i, b->count - 1);
+  tucker_status st = batch_sync(b);
+  if (st) return st;
+  const int N = b->N;
+  hipStream_t s = b->run_stream;
+  HandleGuard g(new tucker_t);
+  tucker_t* t = g.t;
+  t->N = N;
+  t->stream = s;
+  std::memcpy(t->dims, &b->dims[(size_t)i * N], sizeof(int64_t) * N);
+  std::memcpy(t->order, b->order, sizeof(int) * N);
+  std::memcpy(t->ranks, &b->hR[(size_t)i * N], sizeof(int64_t) * N);
+  std::memcpy(t->disc, &b->hdisc[(size_t)i * N], sizeof(double) * N);
+  t->norm2 = b->hnorm2[i];
+  t->core_dtype = b->wdt;
+  for (int k = 0; k < N; ++k) t->prec_used[k] = b->prec;
+  int64_t cur[TUCKER_MAX_MODES];
+  std::memcpy(cur, t->dims, sizeof(int64_t) * N);
+  for (int s2 = 0; s2 < N; ++s2) {
+    const int n = b->order[s2];
+    const int64_t J = cur[n], R = t->ranks[n], Jm = b->Jmax[s2];
+    HIP_TRY(t->alloc((void**)&t->U[n], sizeof(double) * J * J));
+    HIP_TRY(t->alloc((void**)&t->lam[n], sizeof(double) * J));
+    t->eigcount[n] = J;
+    HIP_TRY(hipMemcpyAsync(t->U[n], b->U[n] + (size_t)i * Jm * Jm, sizeof(double) * J * R, hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipMemcpyAsync(t->lam[n], b->lam[n] + (size_t)i * Jm, sizeof(double) * J, hipMemcpyDeviceToDevice, s));
+    cur[n] = R;
+  }
+  int64_t ce = 1;
+  for (int k = 0; k < N; ++k) ce *= cur[k];
+  const size_t ws = wsize(b->wdt);
+  HIP_TRY(t->alloc(&t->core, ws * ce));
+  HIP_TRY(hipMemcpyAsync(t->core, static_cast<char*>(b->buf[(N - 1) % 2]) + ws * b->off[i], ws * ce,
+                         hipMemcpyDeviceToDevice, s));
+  HIP_TRY(t->alloc((void**)&t->scalars, sizeof(double) * 2));
+  HIP_TRY(hipStreamSynchronize(s));
+  *out = g.take();
+  return TUCKER_OK;
+}
+
+void tucker_batch_free(tucker_batch* b) {
+  if (!b) return;
+  b->release();
+  delete b;
+}
+
+}  // extern "C"

@@ -97,10 +97,10 @@ __device__ __forceinline__ void write_row(int k, int wave, int rs, int c, const 
 // trailing block is written to A (leading dimension ld, same global indices)
 // for the next, smaller, phase.  d, e, tau and H use global indices.
 template <int NW, int NG, int NC>
-__global__ __launch_bounds__(64 * NW) void eig_tridiag_reg_kernel(const double* __restrict__ S, int ld, int k0,
-                                                                  int J, int nsteps, double* __restrict__ A,
-                                                                  double* __restrict__ H, double* __restrict__ d,
-                                                                  double* __restrict__ e, double* __restrict__ tau) {
+__device__ __forceinline__ void tridiag_reg_body(const double* __restrict__ S, int ld, int k0, int J, int nsteps,
+                                                 double* __restrict__ A, double* __restrict__ H,
+                                                 double* __restrict__ d, double* __restrict__ e,
+                                                 double* __restrict__ tau) {
   __shared__ double sx[16 * NC];  // column k of the current matrix
   __shared__ double sp[16 * NC];  // p = tau A v
   const int tid = threadIdx.x, lane = tid & 63;
@@ -230,6 +230,14 @@ __global__ __launch_bounds__(64 * NW) void eig_tridiag_reg_kernel(const double* 
   }
 }
 
+template <int NW, int NG, int NC>
+__global__ __launch_bounds__(64 * NW) void eig_tridiag_reg_kernel(const double* __restrict__ S, int ld, int k0,
+                                                                  int J, int nsteps, double* __restrict__ A,
+                                                                  double* __restrict__ H, double* __restrict__ d,
+                                                                  double* __restrict__ e, double* __restrict__ tau) {
+  tridiag_reg_body<NW, NG, NC>(S, ld, k0, J, nsteps, A, H, d, e, tau);
+}
+
 // ---------------------------------------------------------------- 1b. tridiagonalisation, any J
 // A: J x J symmetric in global memory, overwritten; row k receives v_k.
 __global__ __launch_bounds__(kEigThreads) void eig_tridiag_kernel(double* __restrict__ A, int J,
@@ -356,9 +364,8 @@ __device__ __forceinline__ int sturm_count(const double* sd, const double* se2, 
 
 // 256 threads: 8 eigenvalues per workgroup, 32 lanes each.
 constexpr int kBisLanes = 32;
-__global__ __launch_bounds__(256) void eig_bisect_kernel(const double* __restrict__ d, const double* __restrict__ e,
-                                                         int J, double* __restrict__ lam,
-                                                         double* __restrict__ scal) {
+__device__ __forceinline__ void bisect_body(const double* __restrict__ d, const double* __restrict__ e, int J,
+                                            double* __restrict__ lam, double* __restrict__ scal, int bx) {
   extern __shared__ double sh[];
   double* sd = sh;            // J
   double* se2 = sh + J;       // J
@@ -366,8 +373,8 @@ __global__ __launch_bounds__(256) void eig_bisect_kernel(const double* __restric
   const TriBounds b = tri_bounds(d, e, J, sd, se2, sred);
   const int tid = threadIdx.x, lane = tid & 63;
   const int q = lane & (kBisLanes - 1), gbase = lane & ~(kBisLanes - 1);
-  const int a = blockIdx.x * (256 / kBisLanes) + tid / kBisLanes;  // ascending index
-  if (blockIdx.x == 0 && tid == 0) {
+  const int a = bx * (256 / kBisLanes) + tid / kBisLanes;  // ascending index
+  if (bx == 0 && tid == 0) {
     scal[0] = b.tnorm;
     scal[1] = b.pivmin;
   }
@@ -388,6 +395,12 @@ __global__ __launch_bounds__(256) void eig_bisect_kernel(const double* __restric
   if (q == 0) lam[J - 1 - a] = 0.5 * (lo + hi);
 }
 
+__global__ __launch_bounds__(256) void eig_bisect_kernel(const double* __restrict__ d, const double* __restrict__ e,
+                                                         int J, double* __restrict__ lam,
+                                                         double* __restrict__ scal) {
+  bisect_body(d, e, J, lam, scal, blockIdx.x);
+}
+
 // ---------------------------------------------------------------- 3. truncation
 // The threshold is thr, or thr * (*nx2) when nx2 is non-null (so that
 // eps^2 ||X||^2 / N is formed on the device without a host round trip).
@@ -398,10 +411,9 @@ __global__ __launch_bounds__(256) void eig_bisect_kernel(const double* __restric
 // reduced-precision error, since the leading eigenvalues are then far better
 // determined than the small ones, and a Gram that under-estimates (BF16X3)
 // can only make this tail larger, i.e. keep more.  R = J discards nothing.
-__global__ void eig_truncate_kernel(const double* __restrict__ lam, int J, double thr,
-                                    const double* __restrict__ nx2, const double* __restrict__ trace_ref,
-                                    int64_t* __restrict__ Rout, double* __restrict__ disc) {
-  if (threadIdx.x != 0) return;
+__device__ __forceinline__ void truncate_body(const double* __restrict__ lam, int J, double thr,
+                                              const double* __restrict__ nx2, const double* __restrict__ trace_ref,
+                                              int64_t* __restrict__ Rout, double* __restrict__ disc) {
   if (nx2 != nullptr) thr *= *nx2;
   int R = J;
   double tailR = 0.0;
@@ -434,6 +446,13 @@ __global__ void eig_truncate_kernel(const double* __restrict__ lam, int J, doubl
   *disc = tailR;
 }
 
+__global__ void eig_truncate_kernel(const double* __restrict__ lam, int J, double thr,
+                                    const double* __restrict__ nx2, const double* __restrict__ trace_ref,
+                                    int64_t* __restrict__ Rout, double* __restrict__ disc) {
+  if (threadIdx.x != 0) return;
+  truncate_body(lam, J, thr, nx2, trace_ref, Rout, disc);
+}
+
 // ---------------------------------------------------------------- 4. inverse iteration
 __device__ __forceinline__ double hash_unit(uint32_t a, uint32_t b) {
   uint32_t x = a * 0x9E3779B1u ^ (b + 0x7F4A7C15u) * 0x85EBCA77u;
@@ -458,13 +477,12 @@ __device__ __forceinline__ double rcp_refined(double x) {
 // iteration factors and forward-substitutes in one pass (the multipliers and
 // interchanges are applied to the right-hand side as they are produced) and
 // back-substitutes in a second pass.
-__global__ __launch_bounds__(64) void eig_invit_kernel(const double* __restrict__ d, const double* __restrict__ e, int J,
-                                                       const double* __restrict__ lam, const int64_t* __restrict__ Rp,
-                                                       const double* __restrict__ scal, double* __restrict__ Zt,
-                                                       int nvw) {
-  extern __shared__ double sh[];
+__device__ __forceinline__ void invit_body(const double* __restrict__ d, const double* __restrict__ e, int J,
+                                           const double* __restrict__ lam, const int64_t* __restrict__ Rp,
+                                           const double* __restrict__ scal, double* __restrict__ Zt, int nvw,
+                                           double* sh, int bx) {
   const int tid = threadIdx.x;
-  const int t = blockIdx.x * nvw + tid;
+  const int t = bx * nvw + tid;
   const int R = (int)*Rp;
   if (tid >= nvw || t >= R) return;
   const double tnorm = scal[0];
@@ -545,12 +563,18 @@ __global__ __launch_bounds__(64) void eig_invit_kernel(const double* __restrict_
 #undef W
 }
 
-// ---------------------------------------------------------------- 5. re-orthogonalisation
-__global__ __launch_bounds__(kEigThreads) void eig_orth_kernel(double* __restrict__ Zt, int J,
-                                                               const double* __restrict__ lam,
-                                                               const int64_t* __restrict__ Rp,
-                                                               const double* __restrict__ scal) {
+__global__ __launch_bounds__(64) void eig_invit_kernel(const double* __restrict__ d, const double* __restrict__ e, int J,
+                                                       const double* __restrict__ lam, const int64_t* __restrict__ Rp,
+                                                       const double* __restrict__ scal, double* __restrict__ Zt,
+                                                       int nvw) {
   extern __shared__ double sh[];
+  invit_body(d, e, J, lam, Rp, scal, Zt, nvw, sh, blockIdx.x);
+}
+
+// ---------------------------------------------------------------- 5. re-orthogonalisation
+__device__ __forceinline__ void orth_body(double* __restrict__ Zt, int J, const double* __restrict__ lam,
+                                          const int64_t* __restrict__ Rp, const double* __restrict__ scal,
+                                          double* sh) {
   double* hs = sh;        // J
   double* sred = sh + J;  // 16
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -586,13 +610,21 @@ __global__ __launch_bounds__(kEigThreads) void eig_orth_kernel(double* __restric
   }
 }
 
+__global__ __launch_bounds__(kEigThreads) void eig_orth_kernel(double* __restrict__ Zt, int J,
+                                                               const double* __restrict__ lam,
+                                                               const int64_t* __restrict__ Rp,
+                                                               const double* __restrict__ scal) {
+  extern __shared__ double sh[];
+  orth_body(Zt, J, lam, Rp, scal, sh);
+}
+
 // ---------------------------------------------------------------- 6. back-transformation + signs
 template <int Q>
-__global__ __launch_bounds__(256) void eig_back_kernel(const double* __restrict__ H, const double* __restrict__ tau,
-                                                       int J, const double* __restrict__ Zt,
-                                                       const int64_t* __restrict__ Rp, double* __restrict__ U) {
+__device__ __forceinline__ void back_body(const double* __restrict__ H, const double* __restrict__ tau, int J,
+                                          const double* __restrict__ Zt, const int64_t* __restrict__ Rp,
+                                          double* __restrict__ U, int bx) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int vec = blockIdx.x * 4 + wave;
+  const int vec = bx * 4 + wave;
   if (vec >= (int)*Rp) return;
   double z[Q], v[Q], vn[Q];
 #pragma unroll
@@ -660,8 +692,81 @@ __global__ __launch_bounds__(256) void eig_back_kernel(const double* __restrict_
 }
 
 template <int Q>
+__global__ __launch_bounds__(256) void eig_back_kernel(const double* __restrict__ H, const double* __restrict__ tau,
+                                                       int J, const double* __restrict__ Zt,
+                                                       const int64_t* __restrict__ Rp, double* __restrict__ U) {
+  back_body<Q>(H, tau, J, Zt, Rp, U, blockIdx.x);
+}
+
+template <int Q>
 void launch_back(const EigWork& w, int J, const int64_t* R, double* U, hipStream_t s) {
   hipLaunchKernelGGL((eig_back_kernel<Q>), dim3(ceil_div(J, 4)), dim3(256), 0, s, w.A, w.tau, J, w.Zt, R, U);
+}
+
+// ---------------------------------------------------------------- batched form
+// Many independent matrices of sizes J_m <= kBatchMaxJ in one launch per step:
+// blockIdx.y selects the matrix, J_m is read from the device (0 = no matrix),
+// and every per-matrix array sits at a fixed stride (Jmax^2 or Jmax) with the
+// matrix stored contiguously (leading dimension J_m) at its start.
+__device__ __forceinline__ bool batch_matrix(const EigBatch& b, int& m, int& J) {
+  m = blockIdx.y;
+  J = (m < b.count) ? b.J[m] : 0;
+  return J > 0;
+}
+
+// Tridiagonalisation phase (hi, lo]: matrices with J_m > lo reduce the rows of
+// their trailing block of size min(J_m, hi) down to lo (to the end for lo = 0).
+template <int NW, int NG, int NC>
+__global__ __launch_bounds__(64 * NW) void eig_tridiag_reg_batched(EigBatch b, int hi, int lo) {
+  int m, J;
+  if (!batch_matrix(b, m, J) || J <= lo) return;
+  const int64_t o2 = (int64_t)m * b.Jmax * b.Jmax, o1 = (int64_t)m * b.Jmax;
+  const int Jl = min(J, hi);
+  const int k0 = J - Jl;
+  const double* src = (J <= hi) ? b.S + o2 : b.A + o2;
+  tridiag_reg_body<NW, NG, NC>(src, J, k0, Jl, lo > 0 ? Jl - lo : Jl, b.A + o2, b.A + o2, b.d + o1, b.e + o1,
+                               b.tau + o1);
+}
+
+__global__ __launch_bounds__(256) void eig_bisect_batched(EigBatch b) {
+  extern __shared__ double sh[];
+  int m, J;
+  if (!batch_matrix(b, m, J) || (int)blockIdx.x * (256 / kBisLanes) >= J) return;
+  const int64_t o1 = (int64_t)m * b.Jmax;
+  bisect_body(b.d + o1, b.e + o1, J, b.lam + o1, b.scal + 8 * (int64_t)m, blockIdx.x);
+}
+
+__global__ void eig_truncate_batched(EigBatch b, double thr_mul) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= b.count) return;
+  const int J = b.J[m];
+  if (J <= 0) return;
+  truncate_body(b.lam + (int64_t)m * b.Jmax, J, thr_mul, b.nx2 ? b.nx2 + m : nullptr, nullptr, b.R + m,
+                b.disc + m);
+}
+
+__global__ __launch_bounds__(64) void eig_invit_batched(EigBatch b, int nvw) {
+  extern __shared__ double sh[];
+  int m, J;
+  if (!batch_matrix(b, m, J)) return;
+  const int64_t o2 = (int64_t)m * b.Jmax * b.Jmax, o1 = (int64_t)m * b.Jmax;
+  invit_body(b.d + o1, b.e + o1, J, b.lam + o1, b.R + m, b.scal + 8 * (int64_t)m, b.Zt + o2, nvw, sh, blockIdx.x);
+}
+
+__global__ __launch_bounds__(kEigThreads) void eig_orth_batched(EigBatch b) {
+  extern __shared__ double sh[];
+  int m, J;
+  if (!batch_matrix(b, m, J)) return;
+  const int64_t o2 = (int64_t)m * b.Jmax * b.Jmax, o1 = (int64_t)m * b.Jmax;
+  orth_body(b.Zt + o2, J, b.lam + o1, b.R + m, b.scal + 8 * (int64_t)m, sh);
+}
+
+template <int Q>
+__global__ __launch_bounds__(256) void eig_back_batched(EigBatch b) {
+  int m, J;
+  if (!batch_matrix(b, m, J)) return;
+  const int64_t o2 = (int64_t)m * b.Jmax * b.Jmax, o1 = (int64_t)m * b.Jmax;
+  back_body<Q>(b.A + o2, b.tau + o1, J, b.Zt + o2, b.R + m, b.U + o2, blockIdx.x);
 }
 
 }  // namespace
@@ -728,6 +833,28 @@ hipError_t launch_eig_truncate(const double* S, int J, double thr, const double*
   else if (q <= 8) launch_back<8>(w, J, R, U, stream);
   else if (q <= 11) launch_back<11>(w, J, R, U, stream);
   else launch_back<16>(w, J, R, U, stream);
+  return hipGetLastError();
+}
+
+hipError_t launch_eig_truncate_batched(const EigBatch& b, double thr_mul, hipStream_t stream) {
+  if (b.Jmax > kBatchMaxJ || b.count <= 0) return hipErrorInvalidValue;
+  const int nb = b.count;
+  // tridiagonalisation phases, largest first (as in the single-matrix path)
+  hipLaunchKernelGGL((eig_tridiag_reg_batched<16, 2, 8>), dim3(1, nb), dim3(64 * 16), 0, stream, b, 128, 96);
+  hipLaunchKernelGGL((eig_tridiag_reg_batched<16, 2, 6>), dim3(1, nb), dim3(64 * 16), 0, stream, b, 96, 64);
+  hipLaunchKernelGGL((eig_tridiag_reg_batched<16, 1, 4>), dim3(1, nb), dim3(64 * 16), 0, stream, b, 64, 32);
+  hipLaunchKernelGGL((eig_tridiag_reg_batched<8, 1, 2>), dim3(1, nb), dim3(64 * 8), 0, stream, b, 32, 0);
+  const int J = b.Jmax;
+  const size_t shb = sizeof(double) * (2 * (size_t)J + 4);
+  hipLaunchKernelGGL(eig_bisect_batched, dim3(ceil_div(J, 256 / kBisLanes), nb), dim3(256), shb, stream, b);
+  hipLaunchKernelGGL(eig_truncate_batched, dim3(ceil_div(nb, 64)), dim3(64), 0, stream, b, thr_mul);
+  const int nvw = (int)std::max<int64_t>(1, std::min<int64_t>(64, (128 * 1024) / (32 * (int64_t)J)));
+  hipLaunchKernelGGL(eig_invit_batched, dim3(ceil_div(J, nvw), nb), dim3(64), sizeof(double) * 4 * (size_t)J * nvw,
+                     stream, b, nvw);
+  hipLaunchKernelGGL(eig_orth_batched, dim3(1, nb), dim3(kEigThreads), sizeof(double) * ((size_t)J + 16), stream,
+                     b);
+  if (J <= 64) hipLaunchKernelGGL((eig_back_batched<1>), dim3(ceil_div(J, 4), nb), dim3(256), 0, stream, b);
+  else hipLaunchKernelGGL((eig_back_batched<2>), dim3(ceil_div(J, 4), nb), dim3(256), 0, stream, b);
   return hipGetLastError();
 }
 

@@ -284,9 +284,21 @@ struct GramItem {
   }
 };
 
+// What one work item reads and writes: the unfolding (Y, J, L, K), the chunks
+// ch0, ch0 + chstep, ... (niter of them), its partial blocks P and, if sqo is
+// non-null, the sum of squares of the rows it owns.
+struct BodyArgs {
+  const void* Y;
+  int J;
+  uint32_t L, K;
+  int64_t ch0, chstep, niter;
+  double* P;
+  double* sqo;
+};
+
 template <typename T, int PREC, int ROWS, int NBW, bool SHARED_A, bool UNIT_L, bool PAIR>
-__device__ __forceinline__ void gram_body(const MPParams& g, int64_t item, int64_t split, bool diag, int ra, int rb,
-                                          int NR, int nbl, typename Cfg<PREC>::elem* sY, double* sred) {
+__device__ __forceinline__ void gram_body(const BodyArgs& g, bool diag, int ra, int rb, int NR, int nbl,
+                                          typename Cfg<PREC>::elem* sY, double* sred) {
   using W = GramItem<T, PREC, ROWS, NBW, SHARED_A, UNIT_L, PAIR>;
   constexpr int E = W::E, KC = W::KC, LR = W::LR;
   W w;
@@ -297,6 +309,7 @@ __device__ __forceinline__ void gram_body(const MPParams& g, int64_t item, int64
   w.L = g.L;
   w.K = g.K;
   w.JL = (int64_t)g.J * g.L;
+  const int64_t split = g.ch0, nsplit = g.chstep, niter = g.niter;
   w.i = lane & 15;
   w.q = lane >> 4;
   w.sq = 0.0;
@@ -378,8 +391,6 @@ __device__ __forceinline__ void gram_body(const MPParams& g, int64_t item, int64
   }
 
   // chunks split, split + nsplit, ...; chunk j is staged in LDS buffer j & 1
-  const int64_t nsplit = g.nsplit;
-  const int64_t niter = (g.nchunks - split + nsplit - 1) / nsplit;
   typename W::E_t* buf0 = sY;
   typename W::E_t* buf1 = sY + W::BS;
   T rv0[E], rv1[E];
@@ -405,7 +416,7 @@ __device__ __forceinline__ void gram_body(const MPParams& g, int64_t item, int64
 
   // partial blocks.  f64 MFMA result: lane l, register v -> D[(l>>4)+4v][l&15];
   // f32 MFMA result: lane l, register v -> D[4(l>>4)+v][l&15].
-  double* __restrict__ P = g.part + item * (int64_t)g.nblk * 256;
+  double* __restrict__ P = g.P;
 #pragma unroll
   for (int t = 0; t < NBW; ++t) {
     if (t < nq) {
@@ -416,7 +427,7 @@ __device__ __forceinline__ void gram_body(const MPParams& g, int64_t item, int64
       }
     }
   }
-  if (g.sq != nullptr) {
+  if (g.sqo != nullptr) {
     // padding rows and columns load zeros; rows of an off-diagonal pair are
     // counted by the diagonal pairs
     const double sw = wave_sum(diag ? w.sq : 0.0);
@@ -425,7 +436,7 @@ __device__ __forceinline__ void gram_body(const MPParams& g, int64_t item, int64
     if (tid == 0) {
       double tot = 0.0;
       for (int w2 = 0; w2 < kWaves; ++w2) tot += sred[w2];
-      g.sq[item] = tot;
+      *g.sqo = tot;
     }
   }
 }
@@ -437,7 +448,10 @@ __global__ __launch_bounds__(kNT) void gram_mp_tri_kernel(MPParams g) {
   __shared__ typename C::elem sY[2 * C::PLANES * 128 * C::LR];
   __shared__ double sred[kWaves];
   const int NR = (g.J + 15) & ~15;
-  gram_body<T, PREC, 128, NBW, false, UNIT_L, false>(g, blockIdx.x, blockIdx.x, true, 0, 0, NR, NR / 16, sY, sred);
+  const int64_t split = blockIdx.x;
+  const BodyArgs a{g.Y, g.J, g.L, g.K, split, g.nsplit, (g.nchunks - split + g.nsplit - 1) / g.nsplit,
+                   g.part + split * (int64_t)g.nblk * 256, g.sq ? g.sq + split : nullptr};
+  gram_body<T, PREC, 128, NBW, false, UNIT_L, false>(a, true, 0, 0, NR, NR / 16, sY, sred);
 }
 
 // Pair mode: J > 128, items (split, tile pair) placed split-major on XCDs.
@@ -452,10 +466,12 @@ __global__ __launch_bounds__(kNT) void gram_mp_pair_kernel(MPParams g) {
   const int64_t split = item / g.npairs;
   int ta, tb;
   decode_pair(pair, g.ntiles, ta, tb);
+  const BodyArgs a{g.Y, g.J, g.L, g.K, split, g.nsplit, (g.nchunks - split + g.nsplit - 1) / g.nsplit,
+                   g.part + item * (int64_t)g.nblk * 256, g.sq ? g.sq + item : nullptr};
   if (ta == tb)
-    gram_body<T, PREC, 256, 5, false, UNIT_L, true>(g, item, split, true, 128 * ta, 128 * ta, 128, 8, sY, sred);
+    gram_body<T, PREC, 256, 5, false, UNIT_L, true>(a, true, 128 * ta, 128 * ta, 128, 8, sY, sred);
   else
-    gram_body<T, PREC, 256, 8, true, UNIT_L, true>(g, item, split, false, 128 * ta, 128 * tb, 256, 8, sY, sred);
+    gram_body<T, PREC, 256, 8, true, UNIT_L, true>(a, false, 128 * ta, 128 * tb, 256, 8, sY, sred);
 }
 
 // Sum the partial blocks of all splits in a fixed order; write both triangles.
@@ -501,6 +517,79 @@ __global__ __launch_bounds__(256) void gram_mp_reduce_kernel(const double* __res
   for (int64_t sp = 0; sp < nsplit; ++sp) s += part[((sp * npairs + pair) * nblk + qb) * 256 + rem];
   S[(int64_t)a * J + b] = s;
   S[(int64_t)b * J + a] = s;
+}
+
+// Batched form: work item i (host-planned from upper bounds of the sizes)
+// covers chunks [cb, ce) of tensor t; the current sizes are read from the
+// device, so items beyond a tensor's actual column count do nothing.
+template <typename T, int PREC, int NBW, bool UNIT_L>
+__global__ __launch_bounds__(kNT) void gram_batch_kernel(GramBatch b, int item0) {
+  using C = Cfg<PREC>;
+  __shared__ typename C::elem sY[2 * C::PLANES * 128 * C::LR];
+  __shared__ double sred[kWaves];
+  const int it = item0 + blockIdx.x;
+  const int64_t* d = b.items + 4 * (int64_t)it;
+  const int t = (int)d[0];
+  const int J = b.J[t];
+  uint64_t L = 1, Rt = 1;
+  for (int k = 0; k < b.N; ++k) {
+    const uint64_t c = (uint64_t)b.cur[(int64_t)t * b.N + k];
+    if (k < b.n) L *= c;
+    else if (k > b.n) Rt *= c;
+  }
+  const uint64_t K = L * Rt;
+  const int64_t nch = (int64_t)((K + C::KC - 1) / C::KC);
+  const int64_t cb = d[1], ce = min(d[2], nch);
+  const BodyArgs a{b.Y[t], J, (uint32_t)L, (uint32_t)K, cb, 1, ce > cb ? ce - cb : 0, b.part + d[3],
+                   b.sq ? b.sq + it : nullptr};
+  const int NR = (J + 15) & ~15;
+  gram_body<T, PREC, 128, NBW, false, UNIT_L, false>(a, true, 0, 0, NR, NR / 16, sY, sred);
+}
+
+// Per tensor: sum its items' partial blocks (in item order) into S_t (J x J,
+// both triangles) and, when nx2 is set, its items' sums of squares.
+__global__ __launch_bounds__(256) void gram_batch_reduce_kernel(GramBatch b) {
+  const int t = blockIdx.y;
+  const int J = b.J[t];
+  if (J <= 0) return;
+  const int nb = (J + 15) / 16, nblk = nb * (nb + 1) / 2;
+  const int idx = blockIdx.x * 256 + threadIdx.x;
+  const int i0 = b.ifirst[2 * t], i1 = b.ifirst[2 * t + 1];
+  if (idx == 0 && b.nx2 != nullptr) {
+    double s = 0.0;
+    for (int i = i0; i < i1; ++i) s += b.sq[i];
+    b.nx2[t] = s;
+  }
+  if (idx >= nblk * 256) return;
+  const int qb = idx >> 8, rem = idx & 255;
+  int bi = 0, qq = qb;
+  while (qq >= nb - bi) {
+    qq -= nb - bi;
+    ++bi;
+  }
+  const int bj = bi + qq;
+  const int r = rem >> 4, c = rem & 15;
+  const int ra = 16 * bi + r, cb = 16 * bj + c;
+  if (ra >= J || cb >= J || (bi == bj && r > c)) return;
+  double s = 0.0;
+  for (int i = i0; i < i1; ++i) s += b.part[b.items[4 * (int64_t)i + 3] + idx];
+  double* S = b.S + (int64_t)t * b.Jmax * b.Jmax;
+  S[(int64_t)ra * J + cb] = s;
+  S[(int64_t)cb * J + ra] = s;
+}
+
+template <typename T, int PREC>
+void launch_batch(const GramBatch& b, bool unit, hipStream_t s) {
+  // items [0, nsmall) belong to tensors with J <= 80 (at most 16 blocks), the rest to larger ones
+  const int nsmall = b.nsmall, nbig = b.nitems - b.nsmall;
+  if (nsmall > 0) {
+    if (unit) hipLaunchKernelGGL((gram_batch_kernel<T, PREC, 2, true>), dim3(nsmall), dim3(kNT), 0, s, b, 0);
+    else hipLaunchKernelGGL((gram_batch_kernel<T, PREC, 2, false>), dim3(nsmall), dim3(kNT), 0, s, b, 0);
+  }
+  if (nbig > 0) {
+    if (unit) hipLaunchKernelGGL((gram_batch_kernel<T, PREC, 5, true>), dim3(nbig), dim3(kNT), 0, s, b, nsmall);
+    else hipLaunchKernelGGL((gram_batch_kernel<T, PREC, 5, false>), dim3(nbig), dim3(kNT), 0, s, b, nsmall);
+  }
 }
 
 template <typename T, int PREC>
@@ -588,6 +677,27 @@ hipError_t launch_gram_mp(const T* Y, int J, uint64_t L, uint64_t K, int prec, c
   if (norm2) hipLaunchKernelGGL(sum_fixed_kernel, dim3(1), dim3(256), 0, stream, sq, g.total, norm2);
   return hipGetLastError();
 }
+
+template <typename T>
+hipError_t launch_gram_batched(const GramBatch& b, int prec, bool unit_l, hipStream_t stream) {
+  if (b.Jmax > 128 || b.nitems <= 0) return hipErrorInvalidValue;
+  if constexpr (std::is_same<T, double>::value) {
+    if (prec != 0) return hipErrorInvalidValue;
+    launch_batch<T, 0>(b, unit_l, stream);
+  } else {
+    switch (prec) {
+      case 0: launch_batch<T, 0>(b, unit_l, stream); break;
+      case 1: launch_batch<T, 1>(b, unit_l, stream); break;
+      case 2: launch_batch<T, 2>(b, unit_l, stream); break;
+      default: launch_batch<T, 3>(b, unit_l, stream); break;
+    }
+  }
+  hipLaunchKernelGGL(gram_batch_reduce_kernel, dim3(36, b.count), dim3(256), 0, stream, b);
+  return hipGetLastError();
+}
+
+template hipError_t launch_gram_batched<float>(const GramBatch&, int, bool, hipStream_t);
+template hipError_t launch_gram_batched<double>(const GramBatch&, int, bool, hipStream_t);
 
 // Range guard of a reduced-precision Gram: flag = 1 and S zeroed if an entry
 // is not finite or trace(S) differs from the FP64 sum of squares by more

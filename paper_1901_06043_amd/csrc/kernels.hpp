@@ -93,4 +93,67 @@ hipError_t launch_eig_truncate(const double* S, int J, double thr, const double*
                                const EigWork& w, double* lam, double* U, int64_t* R, double* disc,
                                hipStream_t stream);
 
+// ---------------------------------------------------------------- batched form
+// `count` independent matrices; matrix m has size J[m] (device; 0 = none),
+// J[m] <= Jmax <= kBatchMaxJ, and occupies the first J[m]^2 (resp. J[m])
+// entries of its slot of Jmax^2 (resp. Jmax) doubles in every array below.
+constexpr int kBatchMaxJ = 128;
+struct EigBatch {
+  int count;
+  int Jmax;
+  const int* J;
+  const double* S;  // Gram matrices
+  double* A;        // workspace / Householder vectors
+  double* Zt;       // eigenvectors of the tridiagonal matrices
+  double* d;
+  double* e;
+  double* tau;
+  double* lam;      // eigenvalues, descending
+  double* scal;     // 8 per matrix
+  double* U;        // leading eigenvectors, column-major J[m] x R[m]
+  int64_t* R;       // ranks
+  double* disc;     // discarded energies
+  const double* nx2;  // per matrix: threshold multiplier source (||X_m||^2), or null
+};
+hipError_t launch_eig_truncate_batched(const EigBatch& b, double thr_mul, hipStream_t stream);
+
+// Batched Gram of mode n (J[t] <= 128 for every tensor t).  items: 4 int64
+// per work item (tensor, first chunk, end chunk, offset of its partial blocks
+// in `part`, in doubles), contiguous per tensor (items ifirst[2t] ..
+// ifirst[2t+1] - 1) and ordered so that items [0, nsmall) have J <= 80.  Chunks are 32 columns for
+// the reduced forms and 16 for FP64.  S: count x Jmax^2 (matrix t stored
+// contiguously, J[t] x J[t]); nx2 (may be null): per-tensor sum of squares.
+struct GramBatch {
+  int count, N, n, Jmax;
+  const void* const* Y;
+  const int64_t* cur;
+  const int* J;
+  const int64_t* items;
+  int nitems, nsmall;
+  const int* ifirst;
+  double* part;
+  double* sq;  // per item (needed when nx2 is set)
+  double* S;
+  double* nx2;
+};
+template <typename T>
+hipError_t launch_gram_batched(const GramBatch& b, int prec, bool unit_l, hipStream_t stream);
+
+// Batched mode-n product Z_t = Y_t x_n U_t^T with K = R[t] output rows.
+// items: 3 int64 per work item (tensor, first column tile, end column tile),
+// tiles of 64 columns.  U: count x Jmax^2 (U_t column-major J[t] x R[t]).
+struct TtmBatch {
+  int count, N, n, Jmax;
+  const void* const* Y;
+  void* const* Z;
+  const int64_t* cur;
+  const int* J;
+  const int64_t* R;
+  const double* U;
+  const int64_t* items;
+  int nitems;
+};
+template <typename TI, typename TO>
+hipError_t launch_ttm_batched(const TtmBatch& b, bool fp32_products, bool unit_l, hipStream_t stream);
+
 }  // namespace tk

@@ -59,17 +59,15 @@ struct Acc<float> {
 
 // CT: arithmetic type of the products (double: FP64 MFMA; float: FP32 MFMA).
 // RB: 16-row output blocks per wave (1..4), chosen from K at launch.
+// One workgroup tile: output rows [64 rt, 64 rt + 16 RB) and columns
+// [64 ct, 64 ct + 64) (16 per wave).
 template <typename TI, typename TO, typename CT, bool UNIT_L, int RB>
-__global__ __launch_bounds__(256) void ttm_kernel(const TI* __restrict__ Y, int J, uint32_t L, uint32_t cols,
-                                                  const double* __restrict__ M, int64_t msk, int64_t msj, int K,
-                                                  TO* __restrict__ Z, int nrt, int64_t total) {
+__device__ __forceinline__ void ttm_tile(const TI* __restrict__ Y, int J, uint32_t L, uint32_t cols,
+                                         const double* __restrict__ M, int64_t msk, int64_t msj, int K,
+                                         TO* __restrict__ Z, int64_t ct, int rt) {
   using A = Acc<CT>;
   __shared__ CT sM[kTK * kMS];  // M block: 64 output rows x 64 reduction rows
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int64_t item = xcd_remap(blockIdx.x, gridDim.x, total);
-  if (item < 0) return;
-  const int rt = (int)(item % nrt);
-  const int64_t ct = item / nrt;
   const int64_t c0 = (ct * kWaves + wave) * 16;  // this wave's first column
   const int k0 = rt * kTK;
   const int q = lane >> 4, i = lane & 15;
@@ -145,6 +143,40 @@ __global__ __launch_bounds__(256) void ttm_kernel(const TI* __restrict__ Y, int 
     }
 }
 
+template <typename TI, typename TO, typename CT, bool UNIT_L, int RB>
+__global__ __launch_bounds__(256) void ttm_kernel(const TI* __restrict__ Y, int J, uint32_t L, uint32_t cols,
+                                                  const double* __restrict__ M, int64_t msk, int64_t msj, int K,
+                                                  TO* __restrict__ Z, int nrt, int64_t total) {
+  const int64_t item = xcd_remap(blockIdx.x, gridDim.x, total);
+  if (item < 0) return;
+  ttm_tile<TI, TO, CT, UNIT_L, RB>(Y, J, L, cols, M, msk, msj, K, Z, item / nrt, (int)(item % nrt));
+}
+
+// Batched form: item i covers column tiles [ct0, ct1) of tensor t (planned
+// from upper bounds of the sizes); the current sizes and the rank R_t come
+// from the device, every row tile of R_t is computed, and M = U_t^T.
+template <typename TI, typename TO, typename CT, bool UNIT_L>
+__global__ __launch_bounds__(256) void ttm_batch_kernel(TtmBatch b) {
+  const int64_t* d = b.items + 3 * (int64_t)blockIdx.x;
+  const int t = (int)d[0];
+  const int J = b.J[t];
+  const int K = (int)b.R[t];
+  uint64_t L = 1, Rt = 1;
+  for (int k = 0; k < b.N; ++k) {
+    const uint64_t c = (uint64_t)b.cur[(int64_t)t * b.N + k];
+    if (k < b.n) L *= c;
+    else if (k > b.n) Rt *= c;
+  }
+  const uint64_t cols = L * Rt;
+  const int64_t ct1 = min(d[2], (int64_t)((cols + 16 * kWaves - 1) / (16 * kWaves)));
+  const TI* Y = static_cast<const TI*>(b.Y[t]);
+  TO* Z = static_cast<TO*>(b.Z[t]);
+  const double* U = b.U + (int64_t)t * b.Jmax * b.Jmax;
+  for (int64_t ct = d[1]; ct < ct1; ++ct)
+    for (int rt = 0; rt * kTK < K; ++rt)
+      ttm_tile<TI, TO, CT, UNIT_L, 4>(Y, J, (uint32_t)L, (uint32_t)cols, U, J, 1, K, Z, ct, rt);
+}
+
 template <typename TI, typename TO, typename CT>
 hipError_t launch_ttm_ct(const TI* Y, int J, uint64_t L, uint64_t cols, const double* M, int64_t msk, int64_t msj,
                          int K, TO* Z, hipStream_t stream) {
@@ -179,6 +211,26 @@ hipError_t launch_ttm(const TI* Y, int J, uint64_t L, uint64_t cols, const doubl
   if (fp32_products) return launch_ttm_ct<TI, TO, float>(Y, J, L, cols, M, msk, msj, K, Z, stream);
   return launch_ttm_ct<TI, TO, double>(Y, J, L, cols, M, msk, msj, K, Z, stream);
 }
+
+template <typename TI, typename TO>
+hipError_t launch_ttm_batched(const TtmBatch& b, bool fp32_products, bool unit_l, hipStream_t stream) {
+  if (b.nitems <= 0) return hipErrorInvalidValue;
+#define TB_LAUNCH(CT, U) \
+  hipLaunchKernelGGL((ttm_batch_kernel<TI, TO, CT, U>), dim3(b.nitems), dim3(64 * kWaves), 0, stream, b)
+  if (fp32_products) {
+    if (unit_l) TB_LAUNCH(float, true);
+    else TB_LAUNCH(float, false);
+  } else {
+    if (unit_l) TB_LAUNCH(double, true);
+    else TB_LAUNCH(double, false);
+  }
+#undef TB_LAUNCH
+  return hipGetLastError();
+}
+
+template hipError_t launch_ttm_batched<float, float>(const TtmBatch&, bool, bool, hipStream_t);
+template hipError_t launch_ttm_batched<float, double>(const TtmBatch&, bool, bool, hipStream_t);
+template hipError_t launch_ttm_batched<double, double>(const TtmBatch&, bool, bool, hipStream_t);
 
 template hipError_t launch_ttm<double, double>(const double*, int, uint64_t, uint64_t, const double*, int64_t,
                                                int64_t, int, double*, bool, hipStream_t);

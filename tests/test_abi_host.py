@@ -141,3 +141,24 @@ def test_other_entry_points_reject_bad_arguments(tk):
     assert L.tucker_core(None, None) is None
     assert L.tucker_factor(None, 0) is None
     L.tucker_free(None)
+
+
+def test_batch_create_rejects_bad_arguments_without_gpu(tk):
+    L = tk.lib()
+    h = ctypes.c_void_p(0)
+    ptrs = (ctypes.c_void_p * 2)(16, 32)  # never dereferenced: validation precedes device work
+    good = tk._i64([16, 20, 30, 40, 50, 60])
+    assert L.tucker_batch_create(0, ptrs, 0, good, 3, 1e-3, None, 0, None, ctypes.byref(h)) == 1
+    assert L.tucker_batch_create(2, None, 0, good, 3, 1e-3, None, 0, None, ctypes.byref(h)) == 1
+    assert L.tucker_batch_create(2, ptrs, 0, tk._i64([16, 20, 0, 40, 50, 60]), 3, 1e-3, None, 0, None,
+                                 ctypes.byref(h)) == 1
+    assert L.tucker_batch_create(2, ptrs, 0, good, 3, -1.0, None, 0, None, ctypes.byref(h)) == 1
+    assert L.tucker_batch_create(2, ptrs, 1, good, 3, 1e-3, None, 2, None, ctypes.byref(h)) == 1  # bf16 on f64
+    assert L.tucker_batch_create(2, ptrs, 0, good, 3, 1e-3, tk._i32([0, 0, 1]), 0, None, ctypes.byref(h)) == 1
+    # mode sizes above 128 are outside the batched form
+    assert L.tucker_batch_create(2, ptrs, 0, tk._i64([16, 20, 30, 40, 129, 60]), 3, 1e-3, None, 0, None,
+                                 ctypes.byref(h)) == 5
+    assert b"128" in L.tucker_last_error()
+    assert h.value is None
+    L.tucker_batch_free(None)
+

@@ -1,0 +1,142 @@
+"""GPU checks of the batching form (tucker_batch_*) through the C ABI.
+
+* FP64 Grams: every tensor of the batch gets the oracle's ranks (ties within
+  rounding accepted, as for the single-tensor path) and a relative error within
+  1e-10 of the oracle's, and the same ranks as the single-tensor GPU call.
+* Reduced forms: relative error within 1.05 eps for every tensor.
+* A run captured in a HIP graph and replayed gives the eager run's results.
+"""
+import numpy as np
+import pytest
+
+import synthetic
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def tk():
+    import paper_1901_06043_amd as tk
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    tk.lib()
+    return tk
+
+
+def to_dev(x, dims, dtype=torch.float32):
+    return torch.from_numpy(np.ascontiguousarray(x).reshape(list(reversed(dims)))).to("cuda", dtype)
+
+
+def relerr(t, x):
+    xh = t.reconstruct(out_dtype=torch.float64)
+    x64 = x.to(torch.float64)
+    return float(torch.linalg.vector_norm((x64 - xh).reshape(-1)) / torch.linalg.vector_norm(x64.reshape(-1)))
+
+
+def rank_ok(ref, n, R, eps, N):
+    """R equals the oracle's rank, or both lie on a threshold tie within rounding."""
+    lam = np.clip(ref.eigenvalues[n], 0.0, None)
+    thr = eps * eps * ref.norm2 / N
+    tail = np.concatenate([np.cumsum(lam[::-1])[::-1], [0.0]])
+    tol = 64 * np.finfo(float).eps * tail[0]
+    ok = {r for r in range(1, len(lam) + 1) if tail[r] <= thr + tol and (r == 1 or tail[r - 1] >= thr - tol)}
+    return R == ref.ranks[n] or (R in ok and ref.ranks[n] in ok)
+
+
+@pytest.fixture(scope="module")
+def batch48():
+    return synthetic.small_batch(count=48, base_seed=7000)
+
+
+def test_batched_fp64_matches_oracle_and_single(tk, orc, batch48):
+    eps = 1e-3
+    xs = [to_dev(X, d) for X, d in batch48]
+    b = tk.Batch(xs, eps, prec="fp64", dims=[d for _, d in batch48])
+    b.run()
+    ranks = b.ranks()
+    norms = b.norm2()
+    print("tiles", b.tiles(), flush=True)
+    for i, (X, d) in enumerate(batch48):
+        ref = orc.sthosvd(X.astype(np.float64), d, eps)
+        for n in range(3):
+            assert rank_ok(ref, n, ranks[i][n], eps, 3), (i, ranks[i], ref.ranks)
+        assert norms[i] == pytest.approx(ref.norm2, rel=1e-11)
+        t = b.item(i)
+        assert t.ranks == ranks[i]
+        if t.ranks == ref.ranks:
+            e = relerr(t, xs[i])
+            assert abs(e - orc.relerr(X.astype(np.float64), ref)) <= 1e-10, i
+            assert e <= eps * (1 + 1e-9)
+        U = t.factor(0).cpu().numpy()
+        assert np.abs(U.T @ U - np.eye(t.ranks[0])).max() <= 1e-12
+        single = tk.sthosvd(xs[i], eps, dims=d)
+        assert single.ranks == t.ranks
+        np.testing.assert_allclose(t.eigenvalues(0).cpu().numpy(), single.eigenvalues(0).cpu().numpy(),
+                                   atol=1e-12 * float(single.eigenvalues(0)[0]))
+        t.free()
+        single.free()
+    b.free()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x6", "bf16x3"])
+def test_batched_reduced_error_target(tk, batch48, prec):
+    eps = 1e-3 if prec != "bf16x3" else 1e-2
+    xs = [to_dev(X, d) for X, d in batch48]
+    b = tk.Batch(xs, eps, prec=prec, dims=[d for _, d in batch48])
+    b.run()
+    worst = 0.0
+    for i in range(len(xs)):
+        t = b.item(i)
+        assert t.core_dtype == tk.F32
+        e = relerr(t, xs[i])
+        worst = max(worst, e / eps)
+        assert e <= 1.05 * eps, (i, e)
+        t.free()
+    print(f"{prec}: worst relerr / eps = {worst:.4f}", flush=True)
+    b.free()
+
+
+def test_batched_mode_order_and_edge_sizes(tk, orc):
+    """Sizes 1, 2, 16, 17, 128; 4-way tensors; a non-natural mode order."""
+    shapes = [[1, 5, 7, 3], [2, 2, 2, 2], [16, 17, 3, 4], [128, 3, 2, 5], [9, 128, 4, 2], [17, 1, 33, 6]]
+    data = [synthetic.random_tucker(s, [max(1, v // 3) for v in s], 1e-4, seed=100 + i, dtype=np.float32)
+            for i, s in enumerate(shapes)]
+    xs = [to_dev(X, d) for X, d in data]
+    order = [2, 0, 3, 1]
+    b = tk.Batch(xs, 1e-2, mode_order=order, prec="fp64", dims=[d for _, d in data])
+    b.run()
+    ranks = b.ranks()
+    for i, (X, d) in enumerate(data):
+        ref = orc.sthosvd(X.astype(np.float64), d, 1e-2, order)
+        for n in range(4):
+            assert rank_ok(ref, n, ranks[i][n], 1e-2, 4), (i, ranks[i], ref.ranks)
+        t = b.item(i)
+        if t.ranks == ref.ranks:
+            assert abs(relerr(t, xs[i]) - orc.relerr(X.astype(np.float64), ref)) <= 1e-10
+        t.free()
+    b.free()
+
+
+def test_batched_graph_replay(tk, batch48):
+    """Capture one run in a HIP graph; replays with eager work in between give
+    the eager run's ranks and cores."""
+    xs = [to_dev(X, d) for X, d in batch48[:24]]
+    dims = [d for _, d in batch48[:24]]
+    b = tk.Batch(xs, 1e-3, prec="fp32", dims=dims)
+    b.run()
+    torch.cuda.synchronize()
+    ref_ranks = b.ranks()
+    ref_cores = [b.item(i).core.clone() for i in range(len(xs))]
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        b.run()
+    for rep in range(3):
+        junk = torch.randn(1 << 20, device="cuda").sum()  # eager work between replays
+        g.replay()
+        torch.cuda.synchronize()
+        assert b.ranks() == ref_ranks
+        for i in range(len(xs)):
+            assert torch.equal(b.item(i).core, ref_cores[i]), (rep, i)
+        del junk
+    b.free()
