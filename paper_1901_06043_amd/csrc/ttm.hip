@@ -177,9 +177,155 @@ __global__ __launch_bounds__(256) void ttm_batch_kernel(TtmBatch b) {
       ttm_tile<TI, TO, CT, UNIT_L, 4>(Y, J, (uint32_t)L, (uint32_t)cols, U, J, 1, K, Z, ct, rt);
 }
 
+// Resident-M variant for K <= 64 with M (K_pad x J) small enough for LDS:
+// each workgroup (8 waves, 128 columns per tile) stages M once and then walks
+// column tiles t = blockIdx.x, blockIdx.x + gridDim.x, ... (all workgroups
+// stream neighbouring columns); the Y operands are loaded two blocks of 16
+// reduction rows ahead of the MFMAs.  No barrier inside the loop.
+constexpr int kResidentLds = 128 * 1024;
+constexpr int kResWaves = 8;
+
+// VEC (L = 1, J % 4 == 0, Y 16-byte aligned): the 4 consecutive rows of a
+// lane are one 16-byte load (two for doubles).
+template <typename TI, typename CT, bool UNIT_L, bool VEC>
+__device__ __forceinline__ void ttm_load4(const TI* __restrict__ Y, int64_t cbase, bool cok, int J, uint32_t L,
+                                          int jb, int q, CT (&y)[4]) {
+  if constexpr (VEC) {
+    const int j = 16 * jb + 4 * q;
+    if (cok && j < J) {
+      const TI* src = Y + cbase + j;
+      if constexpr (sizeof(TI) == 4) {
+        const float4 f = *reinterpret_cast<const float4*>(src);
+        y[0] = (CT)f.x;
+        y[1] = (CT)f.y;
+        y[2] = (CT)f.z;
+        y[3] = (CT)f.w;
+      } else {
+        const double2 a = *reinterpret_cast<const double2*>(src);
+        const double2 b = *reinterpret_cast<const double2*>(src + 2);
+        y[0] = (CT)a.x;
+        y[1] = (CT)a.y;
+        y[2] = (CT)b.x;
+        y[3] = (CT)b.y;
+      }
+    } else {
+      y[0] = y[1] = y[2] = y[3] = (CT)0;
+    }
+  } else {
+#pragma unroll
+    for (int s2 = 0; s2 < 4; ++s2) {
+      const int j = 16 * jb + (UNIT_L ? 4 * q + s2 : 4 * s2 + q);
+      y[s2] = (cok && j < J) ? (CT)Y[cbase + (UNIT_L ? (int64_t)j : (int64_t)L * j)] : (CT)0;
+    }
+  }
+}
+
+template <typename TI, typename TO, typename CT, bool UNIT_L, int RB, bool VEC>
+__global__ __launch_bounds__(64 * kResWaves) void ttm_resident_kernel(const TI* __restrict__ Y, int J, uint32_t L,
+                                                                      uint32_t cols, const double* __restrict__ M,
+                                                                      int64_t msk, int64_t msj, int K,
+                                                                      TO* __restrict__ Z, int64_t nct) {
+  using A = Acc<CT>;
+  extern __shared__ unsigned char smem[];
+  const int nj = (J + 15) / 16;
+  const int jp = 16 * nj;        // reduction rows padded to whole MFMA blocks (zeros)
+  const int ldm = jp + 1;
+  CT* sM = reinterpret_cast<CT*>(smem);  // [16 RB][ldm]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int e = tid; e < 16 * RB * jp; e += 64 * kResWaves) {
+    const int k = e / jp, j = e - k * jp;
+    sM[k * ldm + j] = (k < K && j < J) ? (CT)M[(int64_t)k * msk + (int64_t)j * msj] : (CT)0;
+  }
+  __syncthreads();
+  const int q = lane >> 4, i = lane & 15;
+  const int64_t JL = (int64_t)J * L;
+  for (int64_t ct = blockIdx.x; ct < nct; ct += gridDim.x) {
+    const int64_t c = (ct * kResWaves + wave) * 16 + i;  // this lane's column
+    const bool cok = c < (int64_t)cols;
+    int64_t cbase = 0;
+    if (cok) {
+      if constexpr (UNIT_L) {
+        cbase = (int64_t)J * c;
+      } else {
+        const uint32_t cc = (uint32_t)c;
+        const uint32_t r = cc / L, l = cc - r * L;
+        cbase = (int64_t)l + JL * r;
+      }
+    }
+    typename A::type acc[RB];
+#pragma unroll
+    for (int b = 0; b < RB; ++b) acc[b] = typename A::type{0, 0, 0, 0};
+    // reduction row of (block jb, step s) for this lane: 16 jb + (UNIT_L ? 4q + s : 4s + q)
+    CT y0[4], y1[4], y2[4];
+    ttm_load4<TI, CT, UNIT_L, VEC>(Y, cbase, cok, J, L, 0, q, y0);
+    ttm_load4<TI, CT, UNIT_L, VEC>(Y, cbase, cok && nj > 1, J, L, 1, q, y1);
+    for (int jb = 0; jb < nj; ++jb) {
+      ttm_load4<TI, CT, UNIT_L, VEC>(Y, cbase, cok && jb + 2 < nj, J, L, jb + 2, q, y2);
+#pragma unroll
+      for (int s2 = 0; s2 < 4; ++s2) {
+        const int jj = 16 * jb + (UNIT_L ? 4 * q + s2 : 4 * s2 + q);
+#pragma unroll
+        for (int b = 0; b < RB; ++b) acc[b] = A::mfma(sM[(16 * b + i) * ldm + jj], y0[s2], acc[b]);
+      }
+#pragma unroll
+      for (int s2 = 0; s2 < 4; ++s2) {
+        y0[s2] = y1[s2];
+        y1[s2] = y2[s2];
+      }
+    }
+    if (cok) {
+      int64_t zb, kstride;
+      if constexpr (UNIT_L) {
+        zb = (int64_t)K * c;
+        kstride = 1;
+      } else {
+        const uint32_t cc = (uint32_t)c;
+        const uint32_t r = cc / L, l = cc - r * L;
+        zb = (int64_t)l + (int64_t)L * K * r;
+        kstride = L;
+      }
+#pragma unroll
+      for (int b = 0; b < RB; ++b)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int k = 16 * b + A::row(q, v);
+          if (k < K) store_as(&Z[zb + kstride * k], (double)acc[b][v]);
+        }
+    }
+  }
+}
+
 template <typename TI, typename TO, typename CT>
 hipError_t launch_ttm_ct(const TI* Y, int J, uint64_t L, uint64_t cols, const double* M, int64_t msk, int64_t msj,
                          int K, TO* Z, hipStream_t stream) {
+  const int rbr = (int)ceil_div(K, 16);
+  const size_t lds = sizeof(CT) * (size_t)(16 * rbr) * (size_t)(16 * ceil_div(J, 16) + 1);
+  if (K <= 64 && lds <= (size_t)kResidentLds) {
+    const int64_t nct = ceil_div((int64_t)cols, 16 * kResWaves);
+    const int64_t grid = std::min<int64_t>(nct, 2 * 256);
+#define TR_LAUNCH(U, RBV, V)                                                                                   \
+  hipLaunchKernelGGL((ttm_resident_kernel<TI, TO, CT, U, RBV, V>), dim3(grid), dim3(64 * kResWaves), lds,       \
+                     stream, Y, J, (uint32_t)L, (uint32_t)cols, M, msk, msj, K, Z, nct)
+    const bool vec = (L == 1) && (J % 4 == 0) && (reinterpret_cast<uintptr_t>(Y) % 16 == 0);
+    if (vec) {
+      if (rbr == 1) TR_LAUNCH(true, 1, true);
+      else if (rbr == 2) TR_LAUNCH(true, 2, true);
+      else if (rbr == 3) TR_LAUNCH(true, 3, true);
+      else TR_LAUNCH(true, 4, true);
+    } else if (L == 1) {
+      if (rbr == 1) TR_LAUNCH(true, 1, false);
+      else if (rbr == 2) TR_LAUNCH(true, 2, false);
+      else if (rbr == 3) TR_LAUNCH(true, 3, false);
+      else TR_LAUNCH(true, 4, false);
+    } else {
+      if (rbr == 1) TR_LAUNCH(false, 1, false);
+      else if (rbr == 2) TR_LAUNCH(false, 2, false);
+      else if (rbr == 3) TR_LAUNCH(false, 3, false);
+      else TR_LAUNCH(false, 4, false);
+    }
+#undef TR_LAUNCH
+    return hipGetLastError();
+  }
   const int nrt = (int)ceil_div(K, kTK);
   const int64_t nct = ceil_div((int64_t)cols, 16 * kWaves);
   const int64_t total = nct * nrt;
