@@ -92,17 +92,64 @@ __device__ __forceinline__ void write_row(int k, int wave, int rs, int c, const 
   }
 }
 
+// Row kk of the matrix becomes the column of step kk: its owner wave writes
+// it to LDS and computes that step's reflector scalars from the values in its
+// registers (sigma = sum_{j >= kk+2} a_kk,j^2, alpha = a_kk,kk+1,
+// beta = -sign(alpha) sqrt(alpha^2 + sigma), tau = (beta - alpha) / beta,
+// scale = 1 / (alpha - beta)), published in ssn[0..2].  Called by every wave;
+// only the owner acts.
+template <int NW, int NG, int NC>
+__device__ __forceinline__ void publish_row(int kk, int J, int wave, int rs, int c, const double (&a)[NG][NC],
+                                            double* sxn, double* ssn) {
+  const int blk = kk >> 2;
+  if (wave != blk % NW) return;  // uniform
+  const int gk = blk / NW;
+  const bool mine = (rs == (kk & 3));
+  double part = 0.0;
+#pragma unroll
+  for (int g = 0; g < NG; ++g)
+    if (g == gk) {
+#pragma unroll
+      for (int cc = 0; cc < NC; ++cc) {
+        const int j = c + 16 * cc;
+        const double x = a[g][cc];
+        if (mine) sxn[j] = x;
+        part += (j >= kk + 2 && j < J) ? x * x : 0.0;
+      }
+    }
+  const double sigma = row16_sum(part);  // the owner slot's 16 lanes hold row kk
+  if (kk + 1 >= J) return;
+  const double alpha = sxn[kk + 1];  // written above by this wave (LDS operations of a wave are ordered)
+  double beta = alpha, tk = 0.0;
+  if (sigma != 0.0) {
+    beta = -copysign(sqrt(alpha * alpha + sigma), alpha);
+    tk = (beta - alpha) / beta;
+  }
+  if (mine && c == 0) {
+    ssn[0] = beta;
+    ssn[1] = tk;
+    ssn[2] = (tk != 0.0) ? 1.0 / (alpha - beta) : 0.0;
+  }
+}
+
 // Phase of the reduction: the matrix block S[k0.., k0..] (leading dimension
 // ld) of size J is reduced for at most `nsteps` steps; if rows remain, the
 // trailing block is written to A (leading dimension ld, same global indices)
 // for the next, smaller, phase.  d, e, tau and H use global indices.
+// Look-ahead: during the update of step k the wave owning row k + 1 (in its
+// first live group) writes that row to LDS as soon as it is updated and
+// computes the scalars of step k + 1 from its registers, so a step starts
+// from LDS values instead of a reduction, square root and divisions on every
+// wave.  Columns and scalars are double-buffered by the parity of k: one
+// barrier after the matrix-vector product and one at the end of each step.
 template <int NW, int NG, int NC>
 __device__ __forceinline__ void tridiag_reg_body(const double* __restrict__ S, int ld, int k0, int J, int nsteps,
                                                  double* __restrict__ A, double* __restrict__ H,
                                                  double* __restrict__ d, double* __restrict__ e,
                                                  double* __restrict__ tau) {
-  __shared__ double sx[16 * NC];  // column k of the current matrix
-  __shared__ double sp[16 * NC];  // p = tau A v
+  __shared__ double sxb[2][16 * NC];  // column k of the current matrix (by parity of k)
+  __shared__ double ssc[2][4];        // beta, tau, scale of step k (by parity of k)
+  __shared__ double sp[16 * NC];      // p = tau A v
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int c = lane & 15, rs = lane >> 4;
@@ -120,26 +167,15 @@ __device__ __forceinline__ void tridiag_reg_body(const double* __restrict__ S, i
   e += k0;
   tau += k0;
   H += (int64_t)k0 * ld + k0;
-  write_row<NW, NG, NC>(0, wave, rs, c, a, sx);
+  publish_row<NW, NG, NC>(0, J, wave, rs, c, a, sxb[0], ssc[0]);
   lds_barrier();
 
   int k = 0;
   for (; k + 2 < J && k < nsteps; ++k) {
-    double part = 0.0;
-#pragma unroll
-    for (int cc = 0; cc < NC; ++cc) {
-      const int j = c + 16 * cc;
-      const double x = sx[j];
-      part += (j >= k + 2 && j < J) ? x * x : 0.0;
-    }
-    const double sigma = row16_sum(part);
-    const double alpha = sx[k + 1];
-    double beta = alpha, tk = 0.0;
-    if (sigma != 0.0) {
-      beta = -copysign(sqrt(alpha * alpha + sigma), alpha);
-      tk = (beta - alpha) / beta;
-    }
-    const double scale = (tk != 0.0) ? 1.0 / (alpha - beta) : 0.0;
+    const double* sx = sxb[k & 1];
+    double* sxn = sxb[(k + 1) & 1];
+    double* ssn = ssc[(k + 1) & 1];
+    const double beta = ssc[k & 1][0], tk = ssc[k & 1][1], scale = ssc[k & 1][2];
     if (tid == 0) {
       d[k] = sx[k];
       e[k] = beta;
@@ -147,17 +183,14 @@ __device__ __forceinline__ void tridiag_reg_body(const double* __restrict__ S, i
     }
     if (wave == 0)
       for (int j = k + 2 + lane; j < J; j += 64) H[(int64_t)k * ld + j] = sx[j] * scale;
-    if (tk == 0.0) {
-      lds_barrier();
-      write_row<NW, NG, NC>(k + 1, wave, rs, c, a, sx);
-      lds_barrier();
-      continue;
-    }
+    // (tau = 0 needs no special case: p, w and the update vanish).  LDS reads
+    // are unconditional (then selected) so that they are issued together.
     double vj[NC];
 #pragma unroll
     for (int cc = 0; cc < NC; ++cc) {
       const int j = c + 16 * cc;
-      vj[cc] = (j <= k || j >= J) ? 0.0 : (j == k + 1 ? 1.0 : sx[j] * scale);
+      const double x = sx[j];
+      vj[cc] = (j <= k || j >= J) ? 0.0 : (j == k + 1 ? 1.0 : x * scale);
     }
     // p_i = tau * sum_j a_ij v_j
 #pragma unroll
@@ -180,23 +213,53 @@ __device__ __forceinline__ void tridiag_reg_body(const double* __restrict__ S, i
     for (int cc = 0; cc < NC; ++cc) pv += sp[c + 16 * cc] * vj[cc];
     pv = row16_sum(pv);
     const double c2 = 0.5 * tk * pv;
-    // A <- A - v w^T - w v^T on the live rows and column slots, w = p - c2 v
+    // A <- A - v w^T - w v^T on the live rows and column slots, w = p - c2 v.
+    // The owner of row k + 1 (whose first live group holds it) writes that row
+    // to LDS as soon as it is updated and sums the squares of its tail.
+    const int kn = k + 1, blkn = kn >> 2;
+    const int gkn = (wave == blkn % NW) ? blkn / NW : -1;  // uniform
+    const bool slot = (rs == (kn & 3));
+    double part = 0.0;
 #pragma unroll
     for (int g = 0; g < NG; ++g) {
       if (4 * (NW * g + wave) + 3 <= k) continue;  // uniform
       const int i = 4 * (NW * g + wave) + rs;
-      const double vi = (i <= k || i >= J) ? 0.0 : (i == k + 1 ? 1.0 : sx[i] * scale);
-      const double wi = (i < J) ? sp[i] - c2 * vi : 0.0;
+      const int ic = min(i, 16 * NC - 1);  // rows beyond the columns are padding
+      const double sxi = sx[ic], spi = sp[ic];
+      const double vi = (i <= k || i >= J) ? 0.0 : (i == k + 1 ? 1.0 : sxi * scale);
+      const double wi = (i < J) ? spi - c2 * vi : 0.0;
 #pragma unroll
       for (int cc = 0; cc < NC; ++cc) {
         const double wj = sp[c + 16 * cc] - c2 * vj[cc];  // w_j; zero for reduced columns
         a[g][cc] = fma(-vi, wj, fma(-wi, vj[cc], a[g][cc]));
       }
+      if (g == gkn) {
+#pragma unroll
+        for (int cc = 0; cc < NC; ++cc) {
+          const int j = c + 16 * cc;
+          if (slot) sxn[j] = a[g][cc];
+          part += (j >= kn + 2 && j < J) ? a[g][cc] * a[g][cc] : 0.0;
+        }
+      }
+    }
+    if (gkn >= 0 && kn + 1 < J) {
+      // scalars of step k + 1 from the owner slot's 16 lanes
+      const double sigma = row16_sum(part);
+      const double alpha = sxn[kn + 1];  // written above by this wave (LDS operations of a wave are ordered)
+      double nbeta = alpha, ntk = 0.0;
+      if (sigma != 0.0) {
+        nbeta = -copysign(sqrt(alpha * alpha + sigma), alpha);
+        ntk = (nbeta - alpha) / nbeta;
+      }
+      if (slot && c == 0) {
+        ssn[0] = nbeta;
+        ssn[1] = ntk;
+        ssn[2] = (ntk != 0.0) ? 1.0 / (alpha - nbeta) : 0.0;
+      }
     }
     lds_barrier();
-    write_row<NW, NG, NC>(k + 1, wave, rs, c, a, sx);
-    lds_barrier();
   }
+  const double* sx = sxb[k & 1];
   if (k + 2 < J) {
     // stopped early: hand the trailing block (rows and columns >= k) to the next phase
 #pragma unroll
@@ -849,8 +912,8 @@ hipError_t launch_eig_truncate_batched(const EigBatch& b, double thr_mul, hipStr
   hipLaunchKernelGGL(eig_bisect_batched, dim3(ceil_div(J, 256 / kBisLanes), nb), dim3(256), shb, stream, b);
   hipLaunchKernelGGL(eig_truncate_batched, dim3(ceil_div(nb, 64)), dim3(64), 0, stream, b, thr_mul);
   const int nvw = (int)std::max<int64_t>(1, std::min<int64_t>(64, (128 * 1024) / (32 * (int64_t)J)));
-  hipLaunchKernelGGL(eig_invit_batched, dim3(ceil_div(J, nvw), nb), dim3(64), sizeof(double) * 4 * (size_t)J * nvw,
-                     stream, b, nvw);
+  hipLaunchKernelGGL(eig_invit_batched, dim3(ceil_div(J, nvw), nb), dim3(64),
+                     sizeof(double) * 4 * (size_t)J * nvw, stream, b, nvw);
   hipLaunchKernelGGL(eig_orth_batched, dim3(1, nb), dim3(kEigThreads), sizeof(double) * ((size_t)J + 16), stream,
                      b);
   if (J <= 64) hipLaunchKernelGGL((eig_back_batched<1>), dim3(ceil_div(J, 4), nb), dim3(256), 0, stream, b);
