@@ -66,14 +66,22 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// Wave-wide sum: 16-lane DPP reduction, then two cross-row exchanges; all
-// lanes get the same (bit-identical) total.
-__device__ __forceinline__ double wave_sum_fast(double v) {
-  v = row16_sum(v);
-  v += __shfl_xor(v, 16, 64);
-  v += __shfl_xor(v, 32, 64);
-  return v;
+// Wave-wide sum without LDS: 16-lane DPP reduction, then the gfx950 permlane
+// swaps.  permlane16_swap of a value returns the pair (rows 0,0,2,2 ; rows
+// 1,1,3,3) and permlane32_swap the pair (lanes 0-31 twice ; lanes 32-63
+// twice), so adding each pair sums rows 0+1 and 2+3, then the two halves.
+// Every lane gets the same (bit-identical) total.
+__device__ __forceinline__ double swap_add16(double v) {
+  const auto lo = __builtin_amdgcn_permlane16_swap(__double2loint(v), __double2loint(v), false, false);
+  const auto hi = __builtin_amdgcn_permlane16_swap(__double2hiint(v), __double2hiint(v), false, false);
+  return __hiloint2double(hi[0], lo[0]) + __hiloint2double(hi[1], lo[1]);
 }
+__device__ __forceinline__ double swap_add32(double v) {
+  const auto lo = __builtin_amdgcn_permlane32_swap(__double2loint(v), __double2loint(v), false, false);
+  const auto hi = __builtin_amdgcn_permlane32_swap(__double2hiint(v), __double2hiint(v), false, false);
+  return __hiloint2double(hi[0], lo[0]) + __hiloint2double(hi[1], lo[1]);
+}
+__device__ __forceinline__ double wave_sum_fast(double v) { return swap_add32(swap_add16(row16_sum(v))); }
 
 __device__ __forceinline__ float wave_sum(float v) {
 #pragma unroll

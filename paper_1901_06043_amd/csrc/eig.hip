@@ -425,8 +425,9 @@ __device__ __forceinline__ int sturm_count(const double* sd, const double* se2, 
   return cnt;
 }
 
-// 256 threads: 8 eigenvalues per workgroup, 32 lanes each.
-constexpr int kBisLanes = 32;
+// 256 threads: 4 eigenvalues per workgroup, one wave (64 lanes, 64 interior
+// points per round) each.
+constexpr int kBisLanes = 64;
 __device__ __forceinline__ void bisect_body(const double* __restrict__ d, const double* __restrict__ e, int J,
                                             double* __restrict__ lam, double* __restrict__ scal, int bx) {
   extern __shared__ double sh[];
@@ -448,7 +449,7 @@ __device__ __forceinline__ void bisect_body(const double* __restrict__ d, const 
     const double sig = lo + h * (q + 1);
     const int cnt = sturm_count(sd, se2, J, sig, b.pivmin);
     const uint64_t bal = __ballot(cnt > a);
-    const uint64_t m = (bal >> gbase) & 0xffffffffull;
+    const uint64_t m = (kBisLanes == 64) ? bal : ((bal >> gbase) & ((1ull << (kBisLanes & 63)) - 1));
     const int f = m ? (__ffsll((long long)m) - 1) : kBisLanes;
     const double nlo = (f == 0) ? lo : lo + h * f;
     const double nhi = (f == kBisLanes) ? hi : lo + h * (f + 1);
@@ -480,40 +481,47 @@ __device__ __forceinline__ void truncate_body(const double* __restrict__ lam, in
   if (nx2 != nullptr) thr *= *nx2;
   int R = J;
   double tailR = 0.0;
+  // (the loops run over all entries without an early exit, so that the loads
+  // can be issued ahead; the tails are monotone in r)
   if (trace_ref == nullptr) {
     // smallest R in 1..J with sum_{i>=R} max(lam_i, 0) <= thr (lam descending)
     double tail = 0.0;
+    bool ok = true;
+#pragma unroll 8
     for (int r = J - 1; r >= 1; --r) {
       tail += fmax(lam[r], 0.0);
-      if (tail <= thr) {
-        R = r;
-        tailR = tail;
-      } else {
-        break;
-      }
+      ok = ok && (tail <= thr);
+      R = ok ? r : R;
+      tailR = ok ? tail : tailR;
     }
   } else {
     const double tr = *trace_ref;
     double head = 0.0;
+    bool found = false;
+#pragma unroll 8
     for (int r = 1; r < J; ++r) {
       head += fmax(lam[r - 1], 0.0);
       const double tail = fmax(tr - head, 0.0);
-      if (tail <= thr) {
-        R = r;
-        tailR = tail;
-        break;
-      }
+      const bool take = !found && (tail <= thr);
+      R = take ? r : R;
+      tailR = take ? tail : tailR;
+      found = found || take;
     }
   }
   *Rout = R;
   *disc = tailR;
 }
 
+// One workgroup of 64 threads: the eigenvalues are staged in LDS (dynamic,
+// J doubles), then thread 0 runs the sequential tail sums over LDS.
 __global__ void eig_truncate_kernel(const double* __restrict__ lam, int J, double thr,
                                     const double* __restrict__ nx2, const double* __restrict__ trace_ref,
                                     int64_t* __restrict__ Rout, double* __restrict__ disc) {
+  extern __shared__ double sl[];
+  for (int i = threadIdx.x; i < J; i += blockDim.x) sl[i] = lam[i];
+  __syncthreads();
   if (threadIdx.x != 0) return;
-  truncate_body(lam, J, thr, nx2, trace_ref, Rout, disc);
+  truncate_body(sl, J, thr, nx2, trace_ref, Rout, disc);
 }
 
 // ---------------------------------------------------------------- 4. inverse iteration
@@ -533,13 +541,60 @@ __device__ __forceinline__ double rcp_refined(double x) {
   return fma(r, fma(-x, r, 1.0), r);
 }
 
-// One thread per vector; a workgroup of 64 threads serves `nvw` vectors and
-// keeps, per vector, the upper factor of the pivoted LU of (T - lambda I)/||T||
-// (reciprocal pivots, first and second superdiagonal) and the iterate in LDS,
-// interleaved by thread so that accesses are bank-conflict free.  Each
-// iteration factors and forward-substitutes in one pass (the multipliers and
-// interchanges are applied to the right-hand side as they are produced) and
-// back-substitutes in a second pass.
+// Inverse iteration state in LDS, one thread per vector; every array holds J
+// entries per vector, interleaved by thread (entry i of thread t at
+// i * nvw + t) so that accesses are bank-conflict free.
+constexpr int kInvitArrays = 7;
+// vectors per workgroup: the arrays of all its vectors fit in 128 KB of LDS
+inline int invit_vectors_per_group(int64_t J) {
+  return (int)std::max<int64_t>(1, std::min<int64_t>(64, (128 * 1024) / (8 * kInvitArrays * J)));
+}
+
+// Back substitution y = U^{-1} x (U upper triangular with two superdiagonals,
+// reciprocal pivots) and ||y||^2.  x and y are distinct arrays, so that the
+// loads of the unrolled loop are issued ahead of the stores.
+__device__ __forceinline__ double invit_back(const double* __restrict__ x, const double* __restrict__ wr,
+                                             const double* __restrict__ w1, const double* __restrict__ w2,
+                                             double* __restrict__ y, int J, int nvw) {
+  double y1 = 0.0, y2 = 0.0, nrm = 0.0;
+#pragma unroll 8
+  for (int i = J - 1; i >= 0; --i) {
+    const size_t o = (size_t)i * nvw;
+    const double yi = (x[o] - w1[o] * y1 - w2[o] * y2) * wr[o];
+    y[o] = yi;
+    nrm += yi * yi;
+    y2 = y1;
+    y1 = yi;
+  }
+  return nrm;
+}
+
+// Forward substitution with the stored multipliers and interchanges:
+// y = L^{-1} P (s x).
+__device__ __forceinline__ void invit_forward(const double* __restrict__ x, const double* __restrict__ wf,
+                                              const double* __restrict__ wp, double* __restrict__ y, double s,
+                                              int J, int nvw) {
+  double xc = x[0] * s;
+#pragma unroll 8
+  for (int i = 0; i + 1 < J; ++i) {
+    const size_t o = (size_t)i * nvw;
+    const double xn = x[o + nvw] * s;
+    const double f = wf[o];
+    const bool sw = wp[o] != 0.0;
+    y[o] = sw ? xn : xc;
+    xc = sw ? fma(-f, xn, xc) : fma(-f, xc, xn);
+  }
+  y[(size_t)(J - 1) * nvw] = xc;
+}
+
+// One thread per vector; a workgroup of 64 threads serves `nvw` vectors.
+// Two steps of inverse iteration with (T - lambda I)/||T|| from a pseudo-random
+// start.  The first step factors it (LU with partial pivoting, rows i and i+1
+// interchanged when |l_i| > |u_ii|; tiny pivots replaced by +-eps) while it
+// forward-substitutes the start vector, keeping the reciprocal pivots, the two
+// superdiagonals of U, the multipliers and the interchanges; the second step
+// reuses them (one forward and one back substitution, no division).  The
+// pivoting is written without branches, so the lanes of a wave stay together.
 __device__ __forceinline__ void invit_body(const double* __restrict__ d, const double* __restrict__ e, int J,
                                            const double* __restrict__ lam, const int64_t* __restrict__ Rp,
                                            const double* __restrict__ scal, double* __restrict__ Zt, int nvw,
@@ -555,75 +610,56 @@ __device__ __forceinline__ void invit_body(const double* __restrict__ d, const d
   }
   const double inv = 1.0 / tnorm;
   const double eps = DBL_EPSILON;
-  double* Wr = sh + 0 * (size_t)J * nvw + tid;  // 1 / u_ii
-  double* W1 = sh + 1 * (size_t)J * nvw + tid;  // u_{i,i+1}
-  double* W2 = sh + 2 * (size_t)J * nvw + tid;  // u_{i,i+2}
-  double* Wx = sh + 3 * (size_t)J * nvw + tid;  // iterate
-#define W(arr, i) arr[(size_t)(i) * nvw]
-  {
-    const int vec = t;
-    const double shift = lam[vec] * inv;
-    for (int i = 0; i < J; ++i) W(Wx, i) = hash_unit((uint32_t)i, (uint32_t)vec);
-    double xscale = 1.0;
-    for (int it = 0; it < 2; ++it) {
-      // factor + forward substitution; the running row (dd, du) and its
-      // right-hand side xc are carried in registers
-      double dd = d[0] * inv - shift;
-      double du = (J > 1) ? e[0] * inv : 0.0;
-      double xc = W(Wx, 0) * xscale;
-      for (int i = 0; i + 1 < J; ++i) {
-        const double li = e[i] * inv;
-        const double dn = d[i + 1] * inv - shift;
-        const double un = (i + 2 < J) ? e[i + 1] * inv : 0.0;
-        double xn = W(Wx, i + 1) * xscale;
-        double u1, u2, ndd, ndu, rp;
-        if (fabs(dd) >= fabs(li)) {
-          if (fabs(dd) < eps) dd = (dd < 0.0) ? -eps : eps;
-          rp = rcp_refined(dd);
-          const double f = li * rp;
-          u1 = du;
-          u2 = 0.0;
-          ndd = dn - f * du;
-          ndu = un;
-          xn -= f * xc;
-        } else {  // interchange rows i and i+1
-          rp = rcp_refined(li);
-          const double f = dd * rp;
-          u1 = dn;
-          u2 = un;
-          ndd = du - f * dn;
-          ndu = -f * un;
-          const double tmp = xc;
-          xc = xn;
-          xn = tmp - f * xn;
-        }
-        W(Wr, i) = rp;
-        W(W1, i) = u1;
-        W(W2, i) = u2;
-        W(Wx, i) = xc;
-        dd = ndd;
-        du = ndu;
-        xc = xn;
-      }
-      if (fabs(dd) < eps) dd = (dd < 0.0) ? -eps : eps;
-      W(Wr, J - 1) = rcp_refined(dd);
-      W(W1, J - 1) = 0.0;
-      W(W2, J - 1) = 0.0;
-      W(Wx, J - 1) = xc;
-      // back substitution
-      double y1 = 0.0, y2 = 0.0, nrm = 0.0;
-      for (int i = J - 1; i >= 0; --i) {
-        const double yi = (W(Wx, i) - W(W1, i) * y1 - W(W2, i) * y2) * W(Wr, i);
-        W(Wx, i) = yi;
-        nrm += yi * yi;
-        y2 = y1;
-        y1 = yi;
-      }
-      xscale = 1.0 / sqrt(nrm);
-    }
-    for (int i = 0; i < J; ++i) Zt[(int64_t)vec * J + i] = W(Wx, i) * xscale;
+  const size_t JN = (size_t)J * nvw;
+  double* Wr = sh + 0 * JN + tid;  // 1 / u_ii
+  double* W1 = sh + 1 * JN + tid;  // u_{i,i+1}
+  double* W2 = sh + 2 * JN + tid;  // u_{i,i+2}
+  double* Wf = sh + 3 * JN + tid;  // multiplier of step i
+  double* Wp = sh + 4 * JN + tid;  // 1 if rows i, i+1 were interchanged
+  double* Xa = sh + 5 * JN + tid;  // iterates
+  double* Xb = sh + 6 * JN + tid;
+  const int vec = t;
+  const double shift = lam[vec] * inv;
+  // step 1: factor + forward substitution of the start vector; the running
+  // row (dd, du) and its right-hand side xc are carried in registers
+  double dd = d[0] * inv - shift;
+  double du = (J > 1) ? e[0] * inv : 0.0;
+  double xc = hash_unit(0u, (uint32_t)vec);
+  for (int i = 0; i + 1 < J; ++i) {
+    const size_t o = (size_t)i * nvw;
+    const double li = e[i] * inv;
+    const double dn = d[i + 1] * inv - shift;
+    const double un = (i + 2 < J) ? e[i + 1] * inv : 0.0;
+    const double xn = hash_unit((uint32_t)(i + 1), (uint32_t)vec);
+    const bool sw = fabs(dd) < fabs(li);
+    const double dg = (fabs(dd) < eps) ? ((dd < 0.0) ? -eps : eps) : dd;
+    const double rp = rcp_refined(sw ? li : dg);
+    const double f = (sw ? dd : li) * rp;
+    Wr[o] = rp;
+    W1[o] = sw ? dn : du;
+    W2[o] = sw ? un : 0.0;
+    Wf[o] = f;
+    Wp[o] = sw ? 1.0 : 0.0;
+    Xa[o] = sw ? xn : xc;
+    const double ndd = sw ? du - f * dn : dn - f * du;
+    const double ndu = sw ? -f * un : un;
+    xc = sw ? xc - f * xn : xn - f * xc;
+    dd = ndd;
+    du = ndu;
   }
-#undef W
+  if (fabs(dd) < eps) dd = (dd < 0.0) ? -eps : eps;
+  {
+    const size_t o = (size_t)(J - 1) * nvw;
+    Wr[o] = rcp_refined(dd);
+    W1[o] = 0.0;
+    W2[o] = 0.0;
+    Xa[o] = xc;
+  }
+  const double s1 = 1.0 / sqrt(invit_back(Xa, Wr, W1, W2, Xb, J, nvw));
+  // step 2
+  invit_forward(Xb, Wf, Wp, Xa, s1, J, nvw);
+  const double s2 = 1.0 / sqrt(invit_back(Xa, Wr, W1, W2, Xb, J, nvw));
+  for (int i = 0; i < J; ++i) Zt[(int64_t)vec * J + i] = Xb[(size_t)i * nvw] * s2;
 }
 
 __global__ __launch_bounds__(64) void eig_invit_kernel(const double* __restrict__ d, const double* __restrict__ e, int J,
@@ -635,31 +671,29 @@ __global__ __launch_bounds__(64) void eig_invit_kernel(const double* __restrict_
 }
 
 // ---------------------------------------------------------------- 5. re-orthogonalisation
-__device__ __forceinline__ void orth_body(double* __restrict__ Zt, int J, const double* __restrict__ lam,
-                                          const int64_t* __restrict__ Rp, const double* __restrict__ scal,
-                                          double* sh) {
-  double* hs = sh;        // J
-  double* sred = sh + J;  // 16
+// Classical Gram-Schmidt, twice, of vector i against the preceding vectors
+// whose eigenvalue lies within otol of lambda_i, then normalisation.  Z points
+// either to the vectors in global memory or to a copy in LDS.
+__device__ __forceinline__ void orth_loop(double* __restrict__ Z, int J, int R, const double* __restrict__ lam,
+                                          double otol, double* hs, double* sred) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int R = (int)*Rp;
-  const double otol = 1e-2 * scal[0];
   int jlo = 0;
   for (int i = 1; i < R; ++i) {
     while (jlo < i && lam[jlo] - lam[i] >= otol) ++jlo;
     if (jlo == i) continue;  // uniform
-    double* zi = Zt + (int64_t)i * J;
+    double* zi = Z + (int64_t)i * J;
     for (int pass = 0; pass < 2; ++pass) {
       for (int j = jlo + wave; j < i; j += 16) {
-        const double* zj = Zt + (int64_t)j * J;
+        const double* zj = Z + (int64_t)j * J;
         double h = 0.0;
         for (int r = lane; r < J; r += 64) h += zj[r] * zi[r];
-        h = wave_sum(h);
+        h = wave_sum_fast(h);
         if (lane == 0) hs[j - jlo] = h;
       }
       __syncthreads();
       for (int r = tid; r < J; r += kEigThreads) {
         double v = zi[r];
-        for (int j = jlo; j < i; ++j) v -= hs[j - jlo] * Zt[(int64_t)j * J + r];
+        for (int j = jlo; j < i; ++j) v -= hs[j - jlo] * Z[(int64_t)j * J + r];
         zi[r] = v;
       }
       __syncthreads();
@@ -673,56 +707,156 @@ __device__ __forceinline__ void orth_body(double* __restrict__ Zt, int J, const 
   }
 }
 
+// LDS capacity (doubles) for the LDS copy of the R leading vectors.
+constexpr int kOrthCap = 14336;
+inline size_t orth_lds_bytes(int64_t J) {
+  return sizeof(double) * ((size_t)J + 16 + (size_t)std::min<int64_t>(J * J, kOrthCap));
+}
+
+// The vectors are copied to LDS when R * J fits in `cap` doubles (the rounds
+// then cost LDS latency instead of global-memory round trips), and only the
+// vectors from the first one that changes onward are written back.
+__device__ __forceinline__ void orth_body(double* __restrict__ Zt, int J, const double* __restrict__ lam,
+                                          const int64_t* __restrict__ Rp, const double* __restrict__ scal,
+                                          double* sh, int cap) {
+  double* hs = sh;        // J
+  double* sred = sh + J;  // 16
+  const int R = (int)*Rp;
+  const double otol = 1e-2 * scal[0];
+  int first = 1;  // first vector with a neighbour within otol
+  while (first < R && lam[first - 1] - lam[first] >= otol) ++first;
+  if (first >= R) return;  // uniform: nothing to do
+  if ((int64_t)R * J > cap) {
+    orth_loop(Zt, J, R, lam, otol, hs, sred);
+    return;
+  }
+  double* Zs = sh + J + 16;
+  for (int x = threadIdx.x; x < R * J; x += kEigThreads) Zs[x] = Zt[x];
+  __syncthreads();
+  orth_loop(Zs, J, R, lam, otol, hs, sred);
+  for (int x = (first - 1) * J + threadIdx.x; x < R * J; x += kEigThreads) Zt[x] = Zs[x];
+}
+
 __global__ __launch_bounds__(kEigThreads) void eig_orth_kernel(double* __restrict__ Zt, int J,
                                                                const double* __restrict__ lam,
                                                                const int64_t* __restrict__ Rp,
                                                                const double* __restrict__ scal) {
   extern __shared__ double sh[];
-  orth_body(Zt, J, lam, Rp, scal, sh);
+  orth_body(Zt, J, lam, Rp, scal, sh, (int)std::min<int64_t>((int64_t)J * J, kOrthCap));
 }
 
 // ---------------------------------------------------------------- 6. back-transformation + signs
+// z <- H_0 H_1 ... H_{J-3} z, one wave per vector, four vectors per workgroup.
+// The reflectors are staged through LDS in chunks of kc rows, double-buffered:
+// the global loads of the next chunk are in flight (in registers) while the
+// current chunk is applied, so the sequential loop reads LDS only.  Each
+// reflector costs one dot product (VALU-only wave sum) and one axpy.
+constexpr int kBackCap = 6400;  // doubles of one chunk buffer (kc * J <= kBackCap)
+
+__host__ __device__ constexpr int back_rows_max(int Q) { return 32 / ((Q + 3) / 4); }
+__host__ __device__ inline int back_chunk(int Q, int J) {
+  const int k = kBackCap / J;
+  return k < 1 ? 1 : (k > back_rows_max(Q) ? back_rows_max(Q) : k);
+}
+__host__ __device__ constexpr size_t back_lds_bytes(int Q) {
+  return sizeof(double) * (2 * (size_t)(kBackCap + 64) + 2 * (size_t)back_rows_max(Q));
+}
+
 template <int Q>
 __device__ __forceinline__ void back_body(const double* __restrict__ H, const double* __restrict__ tau, int J,
                                           const double* __restrict__ Zt, const int64_t* __restrict__ Rp,
-                                          double* __restrict__ U, int bx) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+                                          double* __restrict__ U, int bx, double* sh) {
+  constexpr int UQ = (Q + 3) / 4;          // row entries per thread (256 threads)
+  constexpr int KCM = back_rows_max(Q);    // rows per chunk, bounded by the register staging
+  constexpr int kStride = kBackCap + 64;   // buffer stride (reads of the last row may run 63 past kc * J)
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int R = (int)*Rp;
+  if (bx * 4 >= R || J < 1) return;  // uniform per workgroup
   const int vec = bx * 4 + wave;
-  if (vec >= (int)*Rp) return;
-  double z[Q], v[Q], vn[Q];
+  const bool active = vec < R;
+  const int kc = back_chunk(Q, J);
+  double* stau = sh + 2 * kStride;  // [2][KCM]
+  double z[Q];
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
     const int r = lane + 64 * q;
-    z[q] = (r < J) ? Zt[(int64_t)vec * J + r] : 0.0;
+    z[q] = (active && r < J) ? Zt[(int64_t)vec * J + r] : 0.0;
   }
-  auto load_v = [&](int k, double* dst) {
+  // chunk with first (highest) reflector hi: rows k = hi - kk, kk < kc, k >= 0;
+  // row kk holds v_k (implicit 1 at k + 1, zero above)
+  double stage[KCM][UQ];
+  double stt = 0.0;
+  // fetch() only issues the loads (the staged values are not touched until
+  // put(), so the loads stay in flight while a chunk is applied); put() masks
+  // on the bits (no select on a loaded value, which the compiler would turn
+  // into a branch around the load) and stores every staged entry: entries
+  // outside the chunk go to distinct padding slots past the data, which only
+  // masked lanes ever read.
+  auto fetch = [&](int hi) {
 #pragma unroll
-    for (int q = 0; q < Q; ++q) {
-      const int r = lane + 64 * q;
-      dst[q] = (r == k + 1) ? 1.0 : ((r > k + 1 && r < J) ? H[(int64_t)k * J + r] : 0.0);
+    for (int kk = 0; kk < KCM; ++kk) {
+      const int kx = max(hi - kk, 0);
+#pragma unroll
+      for (int u = 0; u < UQ; ++u) stage[kk][u] = H[(int64_t)kx * J + min(tid + 256 * u, J - 1)];  // in bounds
     }
+    stt = tau[max(hi - min(tid, kc - 1), 0)];
   };
-  double tn = 0.0;
-  if (J >= 3) {
-    load_v(J - 3, vn);
-    tn = tau[J - 3];
-  }
-  for (int k = J - 3; k >= 0; --k) {
-    const double tk = tn;
+  auto put = [&](int b, int hi) {
+    double* buf = sh + b * kStride;
 #pragma unroll
-    for (int q = 0; q < Q; ++q) v[q] = vn[q];
-    if (k > 0) {  // prefetch the next reflector, independent of z
-      load_v(k - 1, vn);
-      tn = tau[k - 1];
+    for (int kk = 0; kk < KCM; ++kk) {
+      const int k = hi - kk;
+#pragma unroll
+      for (int u = 0; u < UQ; ++u) {
+        const int r = tid + 256 * u;
+        const bool row = (kk < kc && k >= 0 && r < J);
+        const unsigned long long keep = (row && r > k + 1) ? ~0ull : 0ull;
+        const unsigned long long one = (row && r == k + 1) ? 0x3FF0000000000000ull : 0ull;
+        buf[row ? kk * J + r : kBackCap + (tid & 63)] =
+            __longlong_as_double((__double_as_longlong(stage[kk][u]) & keep) | one);
+      }
     }
-    if (tk == 0.0) continue;
-    double s = 0.0;
+    stau[b * KCM + min(tid, KCM - 1)] = stt;
+  };
+  int hi = J - 3;
+  // unconditional, so that every path into the loop has waited for the loads
+  // of z and of the first chunk (the loop then only waits on LDS)
+  fetch(max(hi, 0));
+  put(0, hi);
+  __syncthreads();
+  int b = 0;
+  for (; hi >= 0; hi -= kc) {
+    const int nhi = hi - kc;
+    if (nhi >= 0) fetch(nhi);  // in flight while this chunk is applied
+    if (active) {
+      const double* buf = sh + b * kStride;
+      const int n = min(kc, hi + 1);
+      double v[Q], vn[Q];
+      double tn = stau[b * KCM];
 #pragma unroll
-    for (int q = 0; q < Q; ++q) s += v[q] * z[q];
-    s = wave_sum_fast(s) * tk;
+      for (int q = 0; q < Q; ++q) vn[q] = buf[lane + 64 * q];
+      for (int kk = 0; kk < n; ++kk) {
+        const double tk = tn;
 #pragma unroll
-    for (int q = 0; q < Q; ++q) z[q] -= s * v[q];
+        for (int q = 0; q < Q; ++q) v[q] = (lane + 64 * q < J) ? vn[q] : 0.0;
+        if (kk + 1 < n) {  // next row, independent of z
+          tn = stau[b * KCM + kk + 1];
+#pragma unroll
+          for (int q = 0; q < Q; ++q) vn[q] = buf[(kk + 1) * J + lane + 64 * q];
+        }
+        double s = 0.0;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) s = fma(v[q], z[q], s);
+        s = wave_sum_fast(s) * tk;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) z[q] = fma(-s, v[q], z[q]);
+      }
+    }
+    if (nhi >= 0) put(b ^ 1, nhi);
+    __syncthreads();
+    b ^= 1;
   }
+  if (!active) return;
   // sign convention: entry of largest magnitude (lowest index on ties) positive
   double ba = -1.0, bv = 0.0;
   int bi = J;
@@ -758,12 +892,14 @@ template <int Q>
 __global__ __launch_bounds__(256) void eig_back_kernel(const double* __restrict__ H, const double* __restrict__ tau,
                                                        int J, const double* __restrict__ Zt,
                                                        const int64_t* __restrict__ Rp, double* __restrict__ U) {
-  back_body<Q>(H, tau, J, Zt, Rp, U, blockIdx.x);
+  extern __shared__ double sh[];
+  back_body<Q>(H, tau, J, Zt, Rp, U, blockIdx.x, sh);
 }
 
 template <int Q>
 void launch_back(const EigWork& w, int J, const int64_t* R, double* U, hipStream_t s) {
-  hipLaunchKernelGGL((eig_back_kernel<Q>), dim3(ceil_div(J, 4)), dim3(256), 0, s, w.A, w.tau, J, w.Zt, R, U);
+  hipLaunchKernelGGL((eig_back_kernel<Q>), dim3(ceil_div(J, 4)), dim3(256), back_lds_bytes(Q), s, w.A, w.tau, J,
+                     w.Zt, R, U);
 }
 
 // ---------------------------------------------------------------- batched form
@@ -821,7 +957,8 @@ __global__ __launch_bounds__(kEigThreads) void eig_orth_batched(EigBatch b) {
   int m, J;
   if (!batch_matrix(b, m, J)) return;
   const int64_t o2 = (int64_t)m * b.Jmax * b.Jmax, o1 = (int64_t)m * b.Jmax;
-  orth_body(b.Zt + o2, J, b.lam + o1, b.R + m, b.scal + 8 * (int64_t)m, sh);
+  orth_body(b.Zt + o2, J, b.lam + o1, b.R + m, b.scal + 8 * (int64_t)m, sh,
+            (int)min((int64_t)b.Jmax * b.Jmax, (int64_t)kOrthCap));
 }
 
 template <int Q>
@@ -829,7 +966,8 @@ __global__ __launch_bounds__(256) void eig_back_batched(EigBatch b) {
   int m, J;
   if (!batch_matrix(b, m, J)) return;
   const int64_t o2 = (int64_t)m * b.Jmax * b.Jmax, o1 = (int64_t)m * b.Jmax;
-  back_body<Q>(b.A + o2, b.tau + o1, J, b.Zt + o2, b.R + m, b.U + o2, blockIdx.x);
+  extern __shared__ double sh[];
+  back_body<Q>(b.A + o2, b.tau + o1, J, b.Zt + o2, b.R + m, b.U + o2, blockIdx.x, sh);
 }
 
 }  // namespace
@@ -880,15 +1018,16 @@ hipError_t launch_eig_truncate(const double* S, int J, double thr, const double*
   const size_t shb = sizeof(double) * (2 * (size_t)J + 4);
   hipLaunchKernelGGL(eig_bisect_kernel, dim3(ceil_div(J, 256 / kBisLanes)), dim3(256), shb, stream, w.d, w.e, J,
                      lam, w.scal);
-  hipLaunchKernelGGL(eig_truncate_kernel, dim3(1), dim3(64), 0, stream, lam, J, thr, nx2, trace_ref, R, disc);
+  hipLaunchKernelGGL(eig_truncate_kernel, dim3(1), dim3(64), sizeof(double) * (size_t)J, stream, lam, J, thr, nx2,
+                     trace_ref, R, disc);
   {
-    const int nvw = (int)std::max<int64_t>(1, std::min<int64_t>(64, (128 * 1024) / (32 * (int64_t)J)));
-    const size_t shi = sizeof(double) * 4 * (size_t)J * nvw;
+    const int nvw = invit_vectors_per_group(J);
+    const size_t shi = sizeof(double) * kInvitArrays * (size_t)J * nvw;
     hipLaunchKernelGGL(eig_invit_kernel, dim3(ceil_div(J, nvw)), dim3(64), shi, stream, w.d, w.e, J, lam, R,
                        w.scal, w.Zt, nvw);
   }
-  const size_t sh1 = sizeof(double) * ((size_t)J + 16);
-  hipLaunchKernelGGL(eig_orth_kernel, dim3(1), dim3(kEigThreads), sh1, stream, w.Zt, J, lam, R, w.scal);
+  hipLaunchKernelGGL(eig_orth_kernel, dim3(1), dim3(kEigThreads), orth_lds_bytes(J), stream, w.Zt, J, lam, R,
+                     w.scal);
   const int q = (int)ceil_div(J, 64);
   if (q <= 1) launch_back<1>(w, J, R, U, stream);
   else if (q <= 2) launch_back<2>(w, J, R, U, stream);
@@ -911,13 +1050,14 @@ hipError_t launch_eig_truncate_batched(const EigBatch& b, double thr_mul, hipStr
   const size_t shb = sizeof(double) * (2 * (size_t)J + 4);
   hipLaunchKernelGGL(eig_bisect_batched, dim3(ceil_div(J, 256 / kBisLanes), nb), dim3(256), shb, stream, b);
   hipLaunchKernelGGL(eig_truncate_batched, dim3(ceil_div(nb, 64)), dim3(64), 0, stream, b, thr_mul);
-  const int nvw = (int)std::max<int64_t>(1, std::min<int64_t>(64, (128 * 1024) / (32 * (int64_t)J)));
+  const int nvw = invit_vectors_per_group(J);
   hipLaunchKernelGGL(eig_invit_batched, dim3(ceil_div(J, nvw), nb), dim3(64),
-                     sizeof(double) * 4 * (size_t)J * nvw, stream, b, nvw);
-  hipLaunchKernelGGL(eig_orth_batched, dim3(1, nb), dim3(kEigThreads), sizeof(double) * ((size_t)J + 16), stream,
-                     b);
-  if (J <= 64) hipLaunchKernelGGL((eig_back_batched<1>), dim3(ceil_div(J, 4), nb), dim3(256), 0, stream, b);
-  else hipLaunchKernelGGL((eig_back_batched<2>), dim3(ceil_div(J, 4), nb), dim3(256), 0, stream, b);
+                     sizeof(double) * kInvitArrays * (size_t)J * nvw, stream, b, nvw);
+  hipLaunchKernelGGL(eig_orth_batched, dim3(1, nb), dim3(kEigThreads), orth_lds_bytes(J), stream, b);
+  if (J <= 64)
+    hipLaunchKernelGGL((eig_back_batched<1>), dim3(ceil_div(J, 4), nb), dim3(256), back_lds_bytes(1), stream, b);
+  else
+    hipLaunchKernelGGL((eig_back_batched<2>), dim3(ceil_div(J, 4), nb), dim3(256), back_lds_bytes(2), stream, b);
   return hipGetLastError();
 }
 
