@@ -185,40 +185,64 @@ __global__ __launch_bounds__(256) void ttm_batch_kernel(TtmBatch b) {
 constexpr int kResidentLds = 128 * 1024;
 constexpr int kResWaves = 8;
 
-// VEC (L = 1, J % 4 == 0, Y 16-byte aligned): the 4 consecutive rows of a
-// lane are one 16-byte load (two for doubles).
-template <typename TI, typename CT, bool UNIT_L, bool VEC>
-__device__ __forceinline__ void ttm_load4(const TI* __restrict__ Y, int64_t cbase, bool cok, int J, uint32_t L,
-                                          int jb, int q, CT (&y)[4]) {
+// Raw operand data of one 16-row block for one lane: 4 reduction rows of its
+// column.  VEC (L = 1, J % 4 == 0, Y 16-byte aligned): the 4 consecutive rows
+// are one 16-byte load (two for doubles).
+template <typename TI>
+struct Raw4 {
+  TI v[4];
+};
+
+// Issues the loads of block jb without any condition: the row and column are
+// clamped into the tensor, and use4() masks what lies outside.  (A load under
+// a condition, or converted right after it, would have to complete at once.)
+template <typename TI, bool UNIT_L, bool VEC>
+__device__ __forceinline__ void issue4(const TI* __restrict__ Y, int64_t cbase, int J, uint32_t L, int jb, int q,
+                                       Raw4<TI>& r) {
   if constexpr (VEC) {
-    const int j = 16 * jb + 4 * q;
-    if (cok && j < J) {
-      const TI* src = Y + cbase + j;
-      if constexpr (sizeof(TI) == 4) {
-        const float4 f = *reinterpret_cast<const float4*>(src);
-        y[0] = (CT)f.x;
-        y[1] = (CT)f.y;
-        y[2] = (CT)f.z;
-        y[3] = (CT)f.w;
-      } else {
-        const double2 a = *reinterpret_cast<const double2*>(src);
-        const double2 b = *reinterpret_cast<const double2*>(src + 2);
-        y[0] = (CT)a.x;
-        y[1] = (CT)a.y;
-        y[2] = (CT)b.x;
-        y[3] = (CT)b.y;
-      }
+    const int j = min(16 * jb + 4 * q, J - 4);
+    const TI* src = Y + cbase + j;
+    if constexpr (sizeof(TI) == 4) {
+      const float4 f = *reinterpret_cast<const float4*>(src);
+      r.v[0] = f.x;
+      r.v[1] = f.y;
+      r.v[2] = f.z;
+      r.v[3] = f.w;
     } else {
-      y[0] = y[1] = y[2] = y[3] = (CT)0;
+      const double2 a = *reinterpret_cast<const double2*>(src);
+      const double2 b = *reinterpret_cast<const double2*>(src + 2);
+      r.v[0] = a.x;
+      r.v[1] = a.y;
+      r.v[2] = b.x;
+      r.v[3] = b.y;
     }
   } else {
 #pragma unroll
     for (int s2 = 0; s2 < 4; ++s2) {
-      const int j = 16 * jb + (UNIT_L ? 4 * q + s2 : 4 * s2 + q);
-      y[s2] = (cok && j < J) ? (CT)Y[cbase + (UNIT_L ? (int64_t)j : (int64_t)L * j)] : (CT)0;
+      const int j = min(16 * jb + (UNIT_L ? 4 * q + s2 : 4 * s2 + q), J - 1);
+      r.v[s2] = Y[cbase + (UNIT_L ? (int64_t)j : (int64_t)L * j)];
     }
   }
 }
+
+// Converts block jb's raw data to the product type, zero outside the tensor.
+template <typename TI, typename CT, bool UNIT_L>
+__device__ __forceinline__ void use4(const Raw4<TI>& r, bool cok, int J, int jb, int q, CT (&y)[4]) {
+#pragma unroll
+  for (int s2 = 0; s2 < 4; ++s2) {
+    const int j = 16 * jb + (UNIT_L ? 4 * q + s2 : 4 * s2 + q);
+    const CT x = (CT)r.v[s2];
+    y[s2] = (cok && j < J) ? x : (CT)0;
+  }
+}
+
+// TTM with the whole factor resident in LDS (K <= 64): each wave computes
+// 16 output columns at a time, Z[0:K, cols] = M Y[:, cols], with the factor
+// rows as the MFMA A operand (from LDS) and the tensor columns as the B
+// operand (from HBM, straight into registers).  kDepth blocks of 16 rows are
+// in flight per lane; the block loop is unrolled by kDepth so that each
+// buffer keeps its registers (no moves that would wait for a load).
+constexpr int kDepth = 3;
 
 template <typename TI, typename TO, typename CT, bool UNIT_L, int RB, bool VEC>
 __global__ __launch_bounds__(64 * kResWaves) void ttm_resident_kernel(const TI* __restrict__ Y, int J, uint32_t L,
@@ -242,35 +266,73 @@ __global__ __launch_bounds__(64 * kResWaves) void ttm_resident_kernel(const TI* 
   for (int64_t ct = blockIdx.x; ct < nct; ct += gridDim.x) {
     const int64_t c = (ct * kResWaves + wave) * 16 + i;  // this lane's column
     const bool cok = c < (int64_t)cols;
-    int64_t cbase = 0;
-    if (cok) {
-      if constexpr (UNIT_L) {
-        cbase = (int64_t)J * c;
-      } else {
-        const uint32_t cc = (uint32_t)c;
-        const uint32_t r = cc / L, l = cc - r * L;
-        cbase = (int64_t)l + JL * r;
-      }
+    const int64_t ca = cok ? c : (int64_t)cols - 1;      // clamped, for addresses only
+    int64_t cbase;
+    if constexpr (UNIT_L) {
+      cbase = (int64_t)J * ca;
+    } else {
+      const uint32_t cc = (uint32_t)ca;
+      const uint32_t r = cc / L, l = cc - r * L;
+      cbase = (int64_t)l + JL * r;
     }
     typename A::type acc[RB];
 #pragma unroll
     for (int b = 0; b < RB; ++b) acc[b] = typename A::type{0, 0, 0, 0};
     // reduction row of (block jb, step s) for this lane: 16 jb + (UNIT_L ? 4q + s : 4s + q)
-    CT y0[4], y1[4], y2[4];
-    ttm_load4<TI, CT, UNIT_L, VEC>(Y, cbase, cok, J, L, 0, q, y0);
-    ttm_load4<TI, CT, UNIT_L, VEC>(Y, cbase, cok && nj > 1, J, L, 1, q, y1);
-    for (int jb = 0; jb < nj; ++jb) {
-      ttm_load4<TI, CT, UNIT_L, VEC>(Y, cbase, cok && jb + 2 < nj, J, L, jb + 2, q, y2);
+    Raw4<TI> raw[kDepth];
+    auto mma = [&](int jb, const CT (&y)[4]) {
 #pragma unroll
       for (int s2 = 0; s2 < 4; ++s2) {
         const int jj = 16 * jb + (UNIT_L ? 4 * q + s2 : 4 * s2 + q);
 #pragma unroll
-        for (int b = 0; b < RB; ++b) acc[b] = A::mfma(sM[(16 * b + i) * ldm + jj], y0[s2], acc[b]);
+        for (int b = 0; b < RB; ++b) acc[b] = A::mfma(sM[(16 * b + i) * ldm + jj], y[s2], acc[b]);
+      }
+    };
+    if (nj < kDepth) {
+      // fewer blocks than buffers: issue them all, then use them
+#pragma unroll
+      for (int u = 0; u < kDepth - 1; ++u)
+        if (u < nj) issue4<TI, UNIT_L, VEC>(Y, cbase, J, L, u, q, raw[u]);
+#pragma unroll
+      for (int u = 0; u < kDepth - 1; ++u)
+        if (u < nj) {
+          CT y[4];
+          use4<TI, CT, UNIT_L>(raw[u], cok, J, u, q, y);
+          mma(u, y);
+        }
+    } else {
+#pragma unroll
+      for (int u = 0; u < kDepth; ++u) issue4<TI, UNIT_L, VEC>(Y, cbase, J, L, u, q, raw[u]);
+      // main loop: whole groups of kDepth blocks whose refills all lie inside
+      // the tensor; every path issues the same loads in the same order, so each
+      // use waits only for its own block
+      int jb0 = 0;
+      for (; jb0 + 2 * kDepth <= nj; jb0 += kDepth) {
+#pragma unroll
+        for (int u = 0; u < kDepth; ++u) {
+          CT y[4];
+          use4<TI, CT, UNIT_L>(raw[u], cok, J, jb0 + u, q, y);
+          issue4<TI, UNIT_L, VEC>(Y, cbase, J, L, jb0 + u + kDepth, q, raw[u]);
+          mma(jb0 + u, y);
+        }
+      }
+      // the last nj - jb0 < 2 kDepth blocks: raw[u] holds block jb0 + u
+#pragma unroll
+      for (int u = 0; u < kDepth; ++u) {
+        if (jb0 + u < nj) {  // uniform
+          CT y[4];
+          use4<TI, CT, UNIT_L>(raw[u], cok, J, jb0 + u, q, y);
+          if (jb0 + u + kDepth < nj) issue4<TI, UNIT_L, VEC>(Y, cbase, J, L, jb0 + u + kDepth, q, raw[u]);
+          mma(jb0 + u, y);
+        }
       }
 #pragma unroll
-      for (int s2 = 0; s2 < 4; ++s2) {
-        y0[s2] = y1[s2];
-        y1[s2] = y2[s2];
+      for (int u = 0; u < kDepth - 1; ++u) {
+        if (jb0 + kDepth + u < nj) {  // uniform
+          CT y[4];
+          use4<TI, CT, UNIT_L>(raw[u], cok, J, jb0 + kDepth + u, q, y);
+          mma(jb0 + kDepth + u, y);
+        }
       }
     }
     if (cok) {
