@@ -707,15 +707,159 @@ __device__ __forceinline__ void orth_loop(double* __restrict__ Z, int J, int R, 
   }
 }
 
+// Blocked form, for R * J beyond the LDS copy: blocks of kOB consecutive
+// vectors.  A block is first projected, twice, against the preceding (final)
+// vectors of its window, kOC of them at a time, with FP64 MFMA products: the
+// chunk's coefficients C = Z_chunk Z_blk^T (masked to each vector's window),
+// then Z_blk -= C^T Z_chunk.  Then each vector of the block is orthogonalised
+// (classical Gram-Schmidt, twice) against the block's earlier vectors of its
+// window and normalised.  The block lives in LDS; the chunks are read from
+// global memory.  In exact arithmetic this is the same projection as the
+// vector-by-vector loop.
+constexpr int kOB = 16;  // vectors per block
+constexpr int kOC = 64;  // preceding vectors per chunk
+__host__ __device__ constexpr int orth_ksplit(int J) { return J <= 768 ? 4 : 2; }
+
+__device__ __forceinline__ void orth_blocked(double* __restrict__ Z, int J, int R, int first,
+                                             const double* __restrict__ lam, double otol, double* sh) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int il = lane & 15, q = lane >> 4;
+  const int Jp = (J + 15) & ~15;
+  const int KS = orth_ksplit(J);
+  double* hs = sh;                                    // kOB (in-block coefficients)
+  double* sred = sh + J;                              // 16
+  int* sjlo = reinterpret_cast<int*>(sh + J + 16);    // kOB window starts
+  double* Zb = sh + J + 32;                           // [kOB][Jp], zero-padded
+  double* sC = Zb + kOB * Jp;                         // [KS][kOC][kOB] partial coefficients
+  for (int i0 = first; i0 < R; i0 += kOB) {
+    const int nb = min(kOB, R - i0);
+    if (tid < kOB) {
+      // window start: smallest j <= i with lam_j - lam_i < otol (lam descending)
+      const int i = i0 + tid;
+      int lo = i < R ? 0 : i, hi = i;
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (lam[mid] - lam[i] < otol) hi = mid;
+        else lo = mid + 1;
+      }
+      sjlo[tid] = lo;
+    }
+    for (int x = tid; x < kOB * Jp; x += kEigThreads) {
+      const int t = x / Jp, r = x - t * Jp;
+      Zb[x] = (t < nb && r < J) ? Z[(int64_t)(i0 + t) * J + r] : 0.0;
+    }
+    __syncthreads();
+    const int jw = sjlo[0];  // window starts grow with i
+    for (int pass = 0; pass < 2 && jw < i0; ++pass) {
+      for (int jc = jw; jc < i0; jc += kOC) {
+        const int nc = min(kOC, i0 - jc);
+        // coefficients: wave -> (row tile a of the chunk, reduction split ks)
+        {
+          const int a = wave & 3, ks = wave >> 2;
+          if (ks < KS) {
+            const int nst = Jp / 4, s0 = nst * ks / KS, s1 = nst * (ks + 1) / KS;
+            const int jj = 16 * a + il;
+            const double* zr = Z + (int64_t)(jc + min(jj, nc - 1)) * J;
+            const bool rowok = jj < nc;
+            d4 acc = {0.0, 0.0, 0.0, 0.0};
+            // reduction steps in groups of 8 loads (in bounds, masked here); the
+            // other waves of the SIMD cover a group's load latency
+            for (int g0 = s0; g0 < s1; g0 += 8) {
+              double x[8];
+#pragma unroll
+              for (int u = 0; u < 8; ++u) x[u] = zr[min(4 * (g0 + u) + q, J - 1)];
+#pragma unroll
+              for (int u = 0; u < 8; ++u) {
+                const int st = g0 + u, r = 4 * st + q;
+                const double av = (rowok && st < s1 && r < J) ? x[u] : 0.0;
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, Zb[il * Jp + min(r, Jp - 1)], acc, 0, 0, 0);
+              }
+            }
+            // D[(l >> 4) + 4v][l & 15]: chunk row 16 a + q + 4 v, block vector il
+#pragma unroll
+            for (int v = 0; v < 4; ++v) sC[(ks * kOC + 16 * a + q + 4 * v) * kOB + il] = acc[v];
+          }
+        }
+        __syncthreads();
+        {
+          // one (chunk row, block vector) per thread: sum the splits, mask to the window
+          const int jj = tid >> 4, t = tid & 15;
+          double c = 0.0;
+          for (int ks = 0; ks < KS; ++ks) c += sC[(ks * kOC + jj) * kOB + t];
+          sC[jj * kOB + t] = (jj < nc && t < nb && jc + jj >= sjlo[t]) ? c : 0.0;
+        }
+        __syncthreads();
+        // Z_blk -= C^T Z_chunk: wave -> 16-column tiles of the block
+        for (int b = wave; b < Jp / 16; b += 16) {
+          const int r = 16 * b + il;
+          d4 acc;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) acc[v] = Zb[(q + 4 * v) * Jp + r];
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {  // two halves of 8 steps (bounds the loads in flight)
+#pragma unroll
+            for (int st = 8 * h; st < 8 * h + 8; ++st) {
+              const int jj = 4 * st + q;
+              const double x = Z[(int64_t)(jc + min(jj, nc - 1)) * J + min(r, J - 1)];  // in bounds; masked below
+              const double bv = (jj < nc && r < J) ? x : 0.0;
+              acc = __builtin_amdgcn_mfma_f64_16x16x4f64(-sC[jj * kOB + il], bv, acc, 0, 0, 0);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+          }
+#pragma unroll
+          for (int v = 0; v < 4; ++v) Zb[(q + 4 * v) * Jp + r] = acc[v];
+        }
+        __syncthreads();
+      }
+    }
+    // within the block, vector by vector
+    for (int t = 0; t < nb; ++t) {
+      const int i = i0 + t;
+      if (sjlo[t] >= i) continue;  // uniform: no neighbour within otol
+      double* zt = Zb + t * Jp;
+      const int u0 = max(sjlo[t], i0) - i0;
+      for (int pass = 0; pass < 2 && u0 < t; ++pass) {
+        for (int u = u0 + wave; u < t; u += 16) {
+          double h = 0.0;
+          for (int r = lane; r < J; r += 64) h += Zb[u * Jp + r] * zt[r];
+          h = wave_sum_fast(h);
+          if (lane == 0) hs[u] = h;
+        }
+        __syncthreads();
+        for (int r = tid; r < J; r += kEigThreads) {
+          double v = zt[r];
+          for (int u = u0; u < t; ++u) v -= hs[u] * Zb[u * Jp + r];
+          zt[r] = v;
+        }
+        __syncthreads();
+      }
+      double nn = 0.0;
+      for (int r = tid; r < J; r += kEigThreads) nn += zt[r] * zt[r];
+      nn = block_sum_1024(nn, sred);
+      const double rn = 1.0 / sqrt(nn);
+      for (int r = tid; r < J; r += kEigThreads) zt[r] *= rn;
+      __syncthreads();
+    }
+    for (int x = tid; x < nb * Jp; x += kEigThreads) {
+      const int t = x / Jp, r = x - t * Jp;
+      if (r < J) Z[(int64_t)(i0 + t) * J + r] = Zb[x];
+    }
+    __syncthreads();
+  }
+}
+
 // LDS capacity (doubles) for the LDS copy of the R leading vectors.
 constexpr int kOrthCap = 14336;
 inline size_t orth_lds_bytes(int64_t J) {
-  return sizeof(double) * ((size_t)J + 16 + (size_t)std::min<int64_t>(J * J, kOrthCap));
+  const int64_t Jp = (J + 15) & ~int64_t(15);
+  const int64_t blocked = 16 + kOB * Jp + (int64_t)orth_ksplit((int)J) * kOC * kOB;
+  return sizeof(double) * ((size_t)J + 16 + (size_t)std::max<int64_t>(std::min<int64_t>(J * J, kOrthCap), blocked));
 }
 
 // The vectors are copied to LDS when R * J fits in `cap` doubles (the rounds
 // then cost LDS latency instead of global-memory round trips), and only the
-// vectors from the first one that changes onward are written back.
+// vectors from the first one that changes onward are written back; otherwise
+// the blocked form runs.
 __device__ __forceinline__ void orth_body(double* __restrict__ Zt, int J, const double* __restrict__ lam,
                                           const int64_t* __restrict__ Rp, const double* __restrict__ scal,
                                           double* sh, int cap) {
@@ -727,7 +871,7 @@ __device__ __forceinline__ void orth_body(double* __restrict__ Zt, int J, const 
   while (first < R && lam[first - 1] - lam[first] >= otol) ++first;
   if (first >= R) return;  // uniform: nothing to do
   if ((int64_t)R * J > cap) {
-    orth_loop(Zt, J, R, lam, otol, hs, sred);
+    orth_blocked(Zt, J, R, first, lam, otol, sh);
     return;
   }
   double* Zs = sh + J + 16;
