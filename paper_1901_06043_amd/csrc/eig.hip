@@ -8,13 +8,14 @@
 // This GPU version does exactly that, with published methods:
 //  1. Householder reduction to tridiagonal form T = Q^T S Q.  Per step:
 //     p = tau A v, w = p - (tau/2)(p.v) v, A <- A - v w^T - w v^T.
-//     For J <= 256 one workgroup keeps the matrix in registers (16x16 blocks of
-//     the lower triangle spread over its waves) and reduces the symmetric
-//     matrix-vector partials through LDS in a fixed order, with barriers that
-//     order LDS only; larger J use a workgroup streaming the matrix through
-//     global memory.
-//  2. All eigenvalues of T by Sturm-count multisection: 32 lanes per
-//     eigenvalue test 32 interior points at once; many workgroups.
+//     Once the trailing matrix has at most 208 rows, one workgroup keeps it in
+//     registers (each matrix row on 16 lanes of a wave), in phases of shrinking
+//     register layouts; the matrix-vector products and the rank-2 updates run
+//     from registers, with look-ahead (the owner of the next row publishes it
+//     and its reflector scalars during the update).  Larger matrices first
+//     take steps of two launches each over row blocks in global memory.
+//  2. All eigenvalues of T by Sturm-count multisection: one wave per
+//     eigenvalue tests 64 interior points at once; many workgroups.
 //  3. Truncation: tail sums of the clamped eigenvalues from the smallest upward.
 //  4. Leading R eigenvectors of T by two steps of inverse iteration
 //     (tridiagonal LU with partial pivoting, factors in LDS), one thread per
@@ -25,7 +26,8 @@
 //     against the preceding ones whose eigenvalue lies within 1e-2 ||T||;
 //     this turns such iterates into an orthonormal basis of the subspace, and
 //     beyond that gap inverse iteration already yields orthogonality at the
-//     level of rounding.
+//     level of rounding.  Large clusters are processed in blocks with FP64
+//     MFMA products.
 //  6. Back-transformation V = Q Z, one wave per vector, followed by the sign
 //     convention (largest-magnitude entry positive, lowest index on ties).
 #include <cfloat>
@@ -66,7 +68,7 @@ __device__ __forceinline__ double block_max(double v, double* sred) {
   return s;
 }
 
-// ---------------------------------------------------------------- 1a. tridiagonalisation, J <= 256
+// ---------------------------------------------------------------- 1a. tridiagonalisation, J <= 208
 // The full symmetric matrix is held in registers.  Each row of 16 lanes of a
 // wave holds one matrix row: lane l serves row slot l >> 4 and the columns
 // (l & 15) + 16 c, c < NC; wave w, group g, slot s holds row 4 (NW g + w) + s.
@@ -76,7 +78,7 @@ __device__ __forceinline__ double block_max(double v, double* sred) {
 // v_j = w_j = 0 and are processed without branches.
 // Output: d, e, tau and, in row k of H, the Householder vector v_k at
 // positions k+2..J-1 (implicit 1 at k+1).
-constexpr int kRegMaxJ = 256;
+constexpr int kRegMaxJ = 208;
 
 template <int NW, int NG, int NC>
 __device__ __forceinline__ void write_row(int k, int wave, int rs, int c, const double (&a)[NG][NC], double* sx) {
@@ -301,78 +303,104 @@ __global__ __launch_bounds__(64 * NW) void eig_tridiag_reg_kernel(const double* 
   tridiag_reg_body<NW, NG, NC>(S, ld, k0, J, nsteps, A, H, d, e, tau);
 }
 
-// ---------------------------------------------------------------- 1b. tridiagonalisation, any J
-// A: J x J symmetric in global memory, overwritten; row k receives v_k.
-__global__ __launch_bounds__(kEigThreads) void eig_tridiag_kernel(double* __restrict__ A, int J,
+// ---------------------------------------------------------------- 1b. tridiagonalisation steps, J > 208
+// While the trailing matrix is larger than the register-resident form holds,
+// each Householder step is two launches over blocks of kBigRows matrix rows
+// (A: J x J in global memory, global indices):
+//   eig_tri_big_p: every workgroup forms v_k from row k (the same fixed-order
+//     sums in each, hence the same v) and computes p_i = tau (A v)_i for its
+//     rows; workgroup 0 also saves v and the scalars;
+//   eig_tri_big_update: every workgroup forms w = p - (tau/2)(p.v) v (fixed
+//     order, the same in each) and applies A <- A - v w^T - w v^T to its rows;
+//     workgroup 0 writes d_k, e_k, tau_k and stores v_k in row k (the form the
+//     back-transformation reads).
+constexpr int kBigRows = 16;
+constexpr int kBigThreads = 256;
+
+// Fixed-order sum over a workgroup of 256 threads; every thread gets it.
+__device__ __forceinline__ double block_sum_256(double v, double* sred) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  v = wave_sum_fast(v);
+  if (lane == 0) sred[wave] = v;
+  __syncthreads();
+  const double s = (sred[0] + sred[1]) + (sred[2] + sred[3]);
+  __syncthreads();
+  return s;
+}
+
+// V, P: J doubles each; sc: beta, tau of the step.
+__global__ __launch_bounds__(kBigThreads) void eig_tri_big_p(const double* __restrict__ A, int J, int k,
+                                                             double* __restrict__ V, double* __restrict__ P,
+                                                             double* __restrict__ sc) {
+  extern __shared__ double sv[];  // J
+  __shared__ double sred[4];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const double* rk = A + (int64_t)k * J;
+  double part = 0.0;
+  for (int j = k + 2 + tid; j < J; j += kBigThreads) part += rk[j] * rk[j];
+  const double sigma = block_sum_256(part, sred);
+  const double alpha = rk[k + 1];
+  double beta = alpha, tk = 0.0, scale = 0.0;
+  if (sigma != 0.0) {
+    beta = -copysign(sqrt(alpha * alpha + sigma), alpha);
+    tk = (beta - alpha) / beta;
+    scale = 1.0 / (alpha - beta);
+  }
+  for (int j = k + 1 + tid; j < J; j += kBigThreads) {
+    const double v = (j == k + 1) ? 1.0 : rk[j] * scale;
+    sv[j] = v;
+    if (blockIdx.x == 0) V[j] = v;
+  }
+  if (blockIdx.x == 0 && tid == 0) {
+    sc[0] = beta;
+    sc[1] = tk;
+  }
+  __syncthreads();
+  const int r0 = k + 1 + (int)blockIdx.x * kBigRows, r1 = min(r0 + kBigRows, J);
+  for (int i = r0 + wave; i < r1; i += kBigThreads / 64) {  // one wave per row
+    const double* row = A + (int64_t)i * J;
+    double t = 0.0;
+    for (int j = k + 1 + lane; j < J; j += 64) t += row[j] * sv[j];
+    t = wave_sum_fast(t);
+    if (lane == 0) P[i] = tk * t;
+  }
+}
+
+__global__ __launch_bounds__(kBigThreads) void eig_tri_big_update(double* __restrict__ A, int J, int k,
+                                                                  const double* __restrict__ V,
+                                                                  const double* __restrict__ P,
+                                                                  const double* __restrict__ sc,
                                                                   double* __restrict__ d, double* __restrict__ e,
                                                                   double* __restrict__ tau) {
   extern __shared__ double sh[];
-  double* sv = sh;            // J
-  double* sp = sh + J;        // J
-  double* sred = sh + 2 * J;  // 16
+  double* sv = sh;      // J
+  double* sw = sh + J;  // J
+  __shared__ double sred[4];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  for (int k = 0; k + 2 < J; ++k) {
-    const int m = J - k - 1;
-    const double* rowk = A + (int64_t)k * J + (k + 1);
-    double part = 0.0;
-    for (int i = tid; i < m; i += kEigThreads) {
-      const double x = rowk[i];
-      sv[i] = x;
-      if (i >= 1) part += x * x;
-    }
-    const double sigma = block_sum_1024(part, sred);
-    const double alpha = sv[0];
-    double beta, tk;
-    if (sigma == 0.0) {
-      tk = 0.0;
-      beta = alpha;
-    } else {
-      beta = -copysign(sqrt(alpha * alpha + sigma), alpha);
-      tk = (beta - alpha) / beta;
-    }
+  const double tk = sc[1];
+  double part = 0.0;
+  for (int j = k + 1 + tid; j < J; j += kBigThreads) {
+    const double v = V[j], pj = P[j];
+    sv[j] = v;
+    sw[j] = pj;
+    part += pj * v;
+  }
+  const double c2 = 0.5 * tk * block_sum_256(part, sred);  // (the sum's barriers publish sv, sw)
+  for (int j = k + 1 + tid; j < J; j += kBigThreads) sw[j] -= c2 * sv[j];
+  __syncthreads();
+  const int r0 = k + 1 + (int)blockIdx.x * kBigRows, r1 = min(r0 + kBigRows, J);
+  for (int i = r0 + wave; i < r1; i += kBigThreads / 64) {
+    double* row = A + (int64_t)i * J;
+    const double vi = sv[i], wi = sw[i];
+    for (int j = k + 1 + lane; j < J; j += 64) row[j] -= vi * sw[j] + wi * sv[j];
+  }
+  if (blockIdx.x == 0) {
     if (tid == 0) {
       d[k] = A[(int64_t)k * J + k];
-      e[k] = beta;
+      e[k] = sc[0];
       tau[k] = tk;
     }
-    __syncthreads();
-    if (tk == 0.0) continue;
-    const double scale = 1.0 / (alpha - beta);
-    for (int i = tid; i < m; i += kEigThreads) {
-      const double v = (i == 0) ? 1.0 : sv[i] * scale;
-      sv[i] = v;
-      if (i >= 1) A[(int64_t)k * J + k + 1 + i] = v;
-    }
-    __syncthreads();
-    for (int i = wave; i < m; i += 16) {
-      const double* row = A + (int64_t)(k + 1 + i) * J + (k + 1);
-      double s = 0.0;
-      for (int j = lane; j < m; j += 64) s += row[j] * sv[j];
-      s = wave_sum(s);
-      if (lane == 0) sp[i] = tk * s;
-    }
-    __syncthreads();
-    double pv = 0.0;
-    for (int i = tid; i < m; i += kEigThreads) pv += sp[i] * sv[i];
-    pv = block_sum_1024(pv, sred);
-    const double cc = 0.5 * tk * pv;
-    for (int i = tid; i < m; i += kEigThreads) sp[i] -= cc * sv[i];
-    __syncthreads();
-    for (int i = wave; i < m; i += 16) {
-      double* row = A + (int64_t)(k + 1 + i) * J + (k + 1);
-      const double vi = sv[i], wi = sp[i];
-      for (int j = lane; j < m; j += 64) row[j] -= vi * sp[j] + wi * sv[j];
-    }
-    __syncthreads();
-  }
-  if (tid == 0) {
-    if (J >= 2) {
-      d[J - 2] = A[(int64_t)(J - 2) * J + (J - 2)];
-      e[J - 2] = A[(int64_t)(J - 2) * J + (J - 1)];
-      d[J - 1] = A[(int64_t)(J - 1) * J + (J - 1)];
-    } else {
-      d[0] = A[0];
-    }
+    for (int j = k + 2 + tid; j < J; j += kBigThreads) A[(int64_t)k * J + j] = sv[j];
   }
 }
 
@@ -1130,11 +1158,29 @@ void eig_work_carve(double* base, int64_t J, EigWork& w) {
 hipError_t launch_eig_truncate(const double* S, int J, double thr, const double* nx2, const double* trace_ref,
                                const EigWork& w, double* lam, double* U, int64_t* R, double* disc,
                                hipStream_t stream) {
-  if (J <= kRegMaxJ) {
-    // phases: each register configuration reduces until the trailing block
-    // fits the next smaller one
+  {
     const double* src = S;
     int ld = J, k0 = 0;
+    if (J > kRegMaxJ) {
+      // steps over the whole device until the trailing block fits the registers
+      hipError_t err = hipMemcpyAsync(w.A, S, sizeof(double) * (size_t)J * J, hipMemcpyDeviceToDevice, stream);
+      if (err != hipSuccess) return err;
+      double* V = w.Zt;  // the eigenvector buffer is free until inverse iteration
+      double* P = w.Zt + J;
+      double* sc = w.Zt + 2 * (size_t)J;
+      const int nbig = J - kRegMaxJ;
+      for (int k = 0; k < nbig; ++k) {
+        const int grid = (int)ceil_div(J - k - 1, kBigRows);
+        hipLaunchKernelGGL(eig_tri_big_p, dim3(grid), dim3(kBigThreads), sizeof(double) * (size_t)J, stream, w.A, J,
+                           k, V, P, sc);
+        hipLaunchKernelGGL(eig_tri_big_update, dim3(grid), dim3(kBigThreads), sizeof(double) * 2 * (size_t)J, stream,
+                           w.A, J, k, V, P, sc, w.d, w.e, w.tau);
+      }
+      src = w.A;
+      k0 = nbig;
+    }
+    // phases: each register configuration reduces until the trailing block
+    // fits the next smaller one
     while (J - k0 > 2 || k0 == 0) {
       const int Jl = J - k0;
       int next;
@@ -1146,18 +1192,12 @@ hipError_t launch_eig_truncate(const double* S, int J, double thr, const double*
       else if (Jl <= 96) { next = 64; TRI_LAUNCH(16, 2, 6); }
       else if (Jl <= 128) { next = 96; TRI_LAUNCH(16, 2, 8); }
       else if (Jl <= 192) { next = 128; TRI_LAUNCH(8, 6, 12); }
-      else if (Jl <= 208) { next = 192; TRI_LAUNCH(4, 13, 13); }
-      else { next = 208; TRI_LAUNCH(8, 8, 16); }
+      else { next = 192; TRI_LAUNCH(4, 13, 13); }  // Jl <= kRegMaxJ
 #undef TRI_LAUNCH
       if (next == 0) break;
       src = w.A;
       k0 += Jl - next;
     }
-  } else {
-    hipError_t err = hipMemcpyAsync(w.A, S, sizeof(double) * (size_t)J * J, hipMemcpyDeviceToDevice, stream);
-    if (err != hipSuccess) return err;
-    const size_t sh2 = sizeof(double) * (2 * (size_t)J + 16);
-    hipLaunchKernelGGL(eig_tridiag_kernel, dim3(1), dim3(kEigThreads), sh2, stream, w.A, J, w.d, w.e, w.tau);
   }
   const size_t shb = sizeof(double) * (2 * (size_t)J + 4);
   hipLaunchKernelGGL(eig_bisect_kernel, dim3(ceil_div(J, 256 / kBisLanes)), dim3(256), shb, stream, w.d, w.e, J,
