@@ -19,6 +19,8 @@
 // the workgroup's four waves and follows the same assignment.  Four 16-row
 // chunks of Y are loaded before they are consumed, keeping enough bytes in
 // flight per CU.
+#include <type_traits>
+
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -73,18 +75,18 @@ __device__ __forceinline__ void ttm_tile(const TI* __restrict__ Y, int J, uint32
   const int q = lane >> 4, i = lane & 15;
   const int64_t JL = (int64_t)J * L;
 
-  // the column this lane reads (B operand: column c0 + i)
+  // the column this lane reads (B operand: column c0 + i; clamped into the
+  // tensor for the addresses, masked where it lies beyond)
   const int64_t c = c0 + i;
   const bool cok = c < (int64_t)cols;
-  int64_t cbase = 0;
-  if (cok) {
-    if constexpr (UNIT_L) {
-      cbase = (int64_t)J * c;
-    } else {
-      const uint32_t cc = (uint32_t)c;
-      const uint32_t r = cc / L, l = cc - r * L;
-      cbase = (int64_t)l + JL * r;
-    }
+  const int64_t ca = cok ? c : (int64_t)cols - 1;
+  int64_t cbase;
+  if constexpr (UNIT_L) {
+    cbase = (int64_t)J * ca;
+  } else {
+    const uint32_t cc = (uint32_t)ca;
+    const uint32_t r = cc / L, l = cc - r * L;
+    cbase = (int64_t)l + JL * r;
   }
   typename A::type acc[RB];
 #pragma unroll
@@ -92,14 +94,23 @@ __device__ __forceinline__ void ttm_tile(const TI* __restrict__ Y, int J, uint32
 
   for (int jb = 0; jb < J; jb += kJB) {
     // Y operands of the four 16-row chunks of this block (row of (chunk t, step s)
-    // is jb + 16 t + 4 q + s for L = 1 and jb + 16 t + 4 s + q otherwise)
-    CT yv[4][4];
+    // is jb + 16 t + 4 q + s for L = 1 and jb + 16 t + 4 s + q otherwise).
+    // When the products take another type than the tensor, the loads are
+    // unconditional (row clamped) and masked and converted where they are
+    // used, so that no conversion waits for a load right after it is issued.
+    constexpr bool kConv = !std::is_same<TI, CT>::value;
+    TI yr[4][4];
 #pragma unroll
     for (int t = 0; t < 4; ++t)
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
         const int j = jb + 16 * t + (UNIT_L ? 4 * q + s : 4 * s + q);
-        yv[t][s] = (cok && j < J) ? (CT)Y[cbase + (UNIT_L ? (int64_t)j : (int64_t)L * j)] : (CT)0;
+        if constexpr (kConv) {
+          const int jc = min(j, J - 1);
+          yr[t][s] = Y[cbase + (UNIT_L ? (int64_t)jc : (int64_t)L * jc)];
+        } else {
+          yr[t][s] = (cok && j < J) ? Y[cbase + (UNIT_L ? (int64_t)j : (int64_t)L * j)] : (TI)0;
+        }
       }
     // M block into LDS: sM[k][j] = M(k0 + k, jb + j)
     __syncthreads();
@@ -114,9 +125,11 @@ __device__ __forceinline__ void ttm_tile(const TI* __restrict__ Y, int J, uint32
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
         const int jj = 16 * t + (UNIT_L ? 4 * q + s : 4 * s + q);
+        const CT yv = (CT)yr[t][s];
+        const CT y = (!kConv || (cok && jb + jj < J)) ? yv : (CT)0;
 #pragma unroll
         for (int b = 0; b < RB; ++b) {
-          acc[b] = A::mfma(sM[(16 * b + i) * kMS + jj], yv[t][s], acc[b]);
+          acc[b] = A::mfma(sM[(16 * b + i) * kMS + jj], y, acc[b]);
         }
       }
   }
