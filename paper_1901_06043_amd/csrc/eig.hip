@@ -453,9 +453,12 @@ __device__ __forceinline__ int sturm_count(const double* sd, const double* se2, 
   return cnt;
 }
 
-// 256 threads: 4 eigenvalues per workgroup, one wave (64 lanes, 64 interior
-// points per round) each.
+// 256 threads, LANES per eigenvalue (LANES interior points per round): the
+// single-matrix form takes a wave per eigenvalue (fewer, latency-bound rounds),
+// the batched form 32 lanes (less work in total, throughput-bound).
 constexpr int kBisLanes = 64;
+constexpr int kBisLanesBatched = 32;
+template <int LANES>
 __device__ __forceinline__ void bisect_body(const double* __restrict__ d, const double* __restrict__ e, int J,
                                             double* __restrict__ lam, double* __restrict__ scal, int bx) {
   extern __shared__ double sh[];
@@ -464,8 +467,8 @@ __device__ __forceinline__ void bisect_body(const double* __restrict__ d, const 
   double* sred = sh + 2 * J;  // 4
   const TriBounds b = tri_bounds(d, e, J, sd, se2, sred);
   const int tid = threadIdx.x, lane = tid & 63;
-  const int q = lane & (kBisLanes - 1), gbase = lane & ~(kBisLanes - 1);
-  const int a = bx * (256 / kBisLanes) + tid / kBisLanes;  // ascending index
+  const int q = lane & (LANES - 1), gbase = lane & ~(LANES - 1);
+  const int a = bx * (256 / LANES) + tid / LANES;  // ascending index
   if (bx == 0 && tid == 0) {
     scal[0] = b.tnorm;
     scal[1] = b.pivmin;
@@ -473,14 +476,14 @@ __device__ __forceinline__ void bisect_body(const double* __restrict__ d, const 
   if (a >= J) return;
   double lo = b.glo, hi = b.ghi;
   for (int it = 0; it < 64 && (hi - lo) > b.atol; ++it) {
-    const double h = (hi - lo) / (kBisLanes + 1);
+    const double h = (hi - lo) / (LANES + 1);
     const double sig = lo + h * (q + 1);
     const int cnt = sturm_count(sd, se2, J, sig, b.pivmin);
     const uint64_t bal = __ballot(cnt > a);
-    const uint64_t m = (kBisLanes == 64) ? bal : ((bal >> gbase) & ((1ull << (kBisLanes & 63)) - 1));
-    const int f = m ? (__ffsll((long long)m) - 1) : kBisLanes;
+    const uint64_t m = (LANES == 64) ? bal : ((bal >> gbase) & ((1ull << (LANES & 63)) - 1));
+    const int f = m ? (__ffsll((long long)m) - 1) : LANES;
     const double nlo = (f == 0) ? lo : lo + h * f;
-    const double nhi = (f == kBisLanes) ? hi : lo + h * (f + 1);
+    const double nhi = (f == LANES) ? hi : lo + h * (f + 1);
     lo = nlo;
     hi = nhi;
   }
@@ -490,7 +493,7 @@ __device__ __forceinline__ void bisect_body(const double* __restrict__ d, const 
 __global__ __launch_bounds__(256) void eig_bisect_kernel(const double* __restrict__ d, const double* __restrict__ e,
                                                          int J, double* __restrict__ lam,
                                                          double* __restrict__ scal) {
-  bisect_body(d, e, J, lam, scal, blockIdx.x);
+  bisect_body<kBisLanes>(d, e, J, lam, scal, blockIdx.x);
 }
 
 // ---------------------------------------------------------------- 3. truncation
@@ -878,6 +881,10 @@ __device__ __forceinline__ void orth_blocked(double* __restrict__ Z, int J, int 
 
 // LDS capacity (doubles) for the LDS copy of the R leading vectors.
 constexpr int kOrthCap = 14336;
+constexpr int kOrthCapBatched = 4096;
+__host__ __device__ inline int orth_cap_batched(int64_t Jmax) {
+  return (int)(Jmax * Jmax < kOrthCapBatched ? Jmax * Jmax : kOrthCapBatched);
+}
 inline size_t orth_lds_bytes(int64_t J) {
   const int64_t Jp = (J + 15) & ~int64_t(15);
   const int64_t blocked = 16 + kOB * Jp + (int64_t)orth_ksplit((int)J) * kOC * kOB;
@@ -887,10 +894,12 @@ inline size_t orth_lds_bytes(int64_t J) {
 // The vectors are copied to LDS when R * J fits in `cap` doubles (the rounds
 // then cost LDS latency instead of global-memory round trips), and only the
 // vectors from the first one that changes onward are written back; otherwise
-// the blocked form runs.
+// the blocked form runs (`blocked`, which needs orth_lds_bytes of LDS) or the
+// vector-by-vector loop on global memory (the batched form, whose workgroups
+// keep their LDS small).
 __device__ __forceinline__ void orth_body(double* __restrict__ Zt, int J, const double* __restrict__ lam,
                                           const int64_t* __restrict__ Rp, const double* __restrict__ scal,
-                                          double* sh, int cap) {
+                                          double* sh, int cap, bool blocked) {
   double* hs = sh;        // J
   double* sred = sh + J;  // 16
   const int R = (int)*Rp;
@@ -899,7 +908,8 @@ __device__ __forceinline__ void orth_body(double* __restrict__ Zt, int J, const 
   while (first < R && lam[first - 1] - lam[first] >= otol) ++first;
   if (first >= R) return;  // uniform: nothing to do
   if ((int64_t)R * J > cap) {
-    orth_blocked(Zt, J, R, first, lam, otol, sh);
+    if (blocked) orth_blocked(Zt, J, R, first, lam, otol, sh);
+    else orth_loop(Zt, J, R, lam, otol, hs, sred);
     return;
   }
   double* Zs = sh + J + 16;
@@ -914,7 +924,7 @@ __global__ __launch_bounds__(kEigThreads) void eig_orth_kernel(double* __restric
                                                                const int64_t* __restrict__ Rp,
                                                                const double* __restrict__ scal) {
   extern __shared__ double sh[];
-  orth_body(Zt, J, lam, Rp, scal, sh, (int)std::min<int64_t>((int64_t)J * J, kOrthCap));
+  orth_body(Zt, J, lam, Rp, scal, sh, (int)std::min<int64_t>((int64_t)J * J, kOrthCap), true);
 }
 
 // ---------------------------------------------------------------- 6. back-transformation + signs
@@ -923,30 +933,31 @@ __global__ __launch_bounds__(kEigThreads) void eig_orth_kernel(double* __restric
 // the global loads of the next chunk are in flight (in registers) while the
 // current chunk is applied, so the sequential loop reads LDS only.  Each
 // reflector costs one dot product (VALU-only wave sum) and one axpy.
-constexpr int kBackCap = 6400;  // doubles of one chunk buffer (kc * J <= kBackCap)
+// cap: doubles of one chunk buffer (kc * J <= cap).
+constexpr int kBackCap = 6400;
 
 __host__ __device__ constexpr int back_rows_max(int Q) { return 32 / ((Q + 3) / 4); }
-__host__ __device__ inline int back_chunk(int Q, int J) {
-  const int k = kBackCap / J;
+__host__ __device__ inline int back_chunk(int Q, int J, int cap) {
+  const int k = cap / J;
   return k < 1 ? 1 : (k > back_rows_max(Q) ? back_rows_max(Q) : k);
 }
-__host__ __device__ constexpr size_t back_lds_bytes(int Q) {
-  return sizeof(double) * (2 * (size_t)(kBackCap + 64) + 2 * (size_t)back_rows_max(Q));
+__host__ __device__ constexpr size_t back_lds_bytes(int Q, int cap) {
+  return sizeof(double) * (2 * (size_t)(cap + 64) + 2 * (size_t)back_rows_max(Q));
 }
 
 template <int Q>
 __device__ __forceinline__ void back_body(const double* __restrict__ H, const double* __restrict__ tau, int J,
                                           const double* __restrict__ Zt, const int64_t* __restrict__ Rp,
-                                          double* __restrict__ U, int bx, double* sh) {
+                                          double* __restrict__ U, int bx, double* sh, int cap) {
   constexpr int UQ = (Q + 3) / 4;          // row entries per thread (256 threads)
   constexpr int KCM = back_rows_max(Q);    // rows per chunk, bounded by the register staging
-  constexpr int kStride = kBackCap + 64;   // buffer stride (reads of the last row may run 63 past kc * J)
+  const int kStride = cap + 64;  // buffer stride (reads of the last row may run 63 past kc * J)
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int R = (int)*Rp;
   if (bx * 4 >= R || J < 1) return;  // uniform per workgroup
   const int vec = bx * 4 + wave;
   const bool active = vec < R;
-  const int kc = back_chunk(Q, J);
+  const int kc = back_chunk(Q, J, cap);
   double* stau = sh + 2 * kStride;  // [2][KCM]
   double z[Q];
 #pragma unroll
@@ -984,7 +995,7 @@ __device__ __forceinline__ void back_body(const double* __restrict__ H, const do
         const bool row = (kk < kc && k >= 0 && r < J);
         const unsigned long long keep = (row && r > k + 1) ? ~0ull : 0ull;
         const unsigned long long one = (row && r == k + 1) ? 0x3FF0000000000000ull : 0ull;
-        buf[row ? kk * J + r : kBackCap + (tid & 63)] =
+        buf[row ? kk * J + r : cap + (tid & 63)] =
             __longlong_as_double((__double_as_longlong(stage[kk][u]) & keep) | one);
       }
     }
@@ -1065,13 +1076,184 @@ __global__ __launch_bounds__(256) void eig_back_kernel(const double* __restrict_
                                                        int J, const double* __restrict__ Zt,
                                                        const int64_t* __restrict__ Rp, double* __restrict__ U) {
   extern __shared__ double sh[];
-  back_body<Q>(H, tau, J, Zt, Rp, U, blockIdx.x, sh);
+  back_body<Q>(H, tau, J, Zt, Rp, U, blockIdx.x, sh, kBackCap);
 }
 
 template <int Q>
 void launch_back(const EigWork& w, int J, const int64_t* R, double* U, hipStream_t s) {
-  hipLaunchKernelGGL((eig_back_kernel<Q>), dim3(ceil_div(J, 4)), dim3(256), back_lds_bytes(Q), s, w.A, w.tau, J,
-                     w.Zt, R, U);
+  hipLaunchKernelGGL((eig_back_kernel<Q>), dim3(ceil_div(J, 4)), dim3(256), back_lds_bytes(Q, kBackCap), s, w.A,
+                     w.tau, J, w.Zt, R, U);
+}
+
+// Batched form (throughput over many small matrices, where LDS per vector
+// limits the vectors in flight): four arrays per vector, and each step
+// factors again.  One thread per vector; a workgroup of 64 threads serves
+// `nvw` vectors and
+// keeps, per vector, the upper factor of the pivoted LU of (T - lambda I)/||T||
+// (reciprocal pivots, first and second superdiagonal) and the iterate in LDS,
+// interleaved by thread so that accesses are bank-conflict free.  Each
+// iteration factors and forward-substitutes in one pass (the multipliers and
+// interchanges are applied to the right-hand side as they are produced) and
+// back-substitutes in a second pass.
+__device__ __forceinline__ void invit_body_lean(const double* __restrict__ d, const double* __restrict__ e, int J,
+                                           const double* __restrict__ lam, const int64_t* __restrict__ Rp,
+                                           const double* __restrict__ scal, double* __restrict__ Zt, int nvw,
+                                           double* sh, int bx) {
+  const int tid = threadIdx.x;
+  const int t = bx * nvw + tid;
+  const int R = (int)*Rp;
+  if (tid >= nvw || t >= R) return;
+  const double tnorm = scal[0];
+  if (tnorm == 0.0) {
+    for (int i = 0; i < J; ++i) Zt[(int64_t)t * J + i] = (i == t) ? 1.0 : 0.0;
+    return;
+  }
+  const double inv = 1.0 / tnorm;
+  const double eps = DBL_EPSILON;
+  double* Wr = sh + 0 * (size_t)J * nvw + tid;  // 1 / u_ii
+  double* W1 = sh + 1 * (size_t)J * nvw + tid;  // u_{i,i+1}
+  double* W2 = sh + 2 * (size_t)J * nvw + tid;  // u_{i,i+2}
+  double* Wx = sh + 3 * (size_t)J * nvw + tid;  // iterate
+#define W(arr, i) arr[(size_t)(i) * nvw]
+  {
+    const int vec = t;
+    const double shift = lam[vec] * inv;
+    for (int i = 0; i < J; ++i) W(Wx, i) = hash_unit((uint32_t)i, (uint32_t)vec);
+    double xscale = 1.0;
+    for (int it = 0; it < 2; ++it) {
+      // factor + forward substitution; the running row (dd, du) and its
+      // right-hand side xc are carried in registers
+      double dd = d[0] * inv - shift;
+      double du = (J > 1) ? e[0] * inv : 0.0;
+      double xc = W(Wx, 0) * xscale;
+      for (int i = 0; i + 1 < J; ++i) {
+        const double li = e[i] * inv;
+        const double dn = d[i + 1] * inv - shift;
+        const double un = (i + 2 < J) ? e[i + 1] * inv : 0.0;
+        double xn = W(Wx, i + 1) * xscale;
+        double u1, u2, ndd, ndu, rp;
+        if (fabs(dd) >= fabs(li)) {
+          if (fabs(dd) < eps) dd = (dd < 0.0) ? -eps : eps;
+          rp = rcp_refined(dd);
+          const double f = li * rp;
+          u1 = du;
+          u2 = 0.0;
+          ndd = dn - f * du;
+          ndu = un;
+          xn -= f * xc;
+        } else {  // interchange rows i and i+1
+          rp = rcp_refined(li);
+          const double f = dd * rp;
+          u1 = dn;
+          u2 = un;
+          ndd = du - f * dn;
+          ndu = -f * un;
+          const double tmp = xc;
+          xc = xn;
+          xn = tmp - f * xn;
+        }
+        W(Wr, i) = rp;
+        W(W1, i) = u1;
+        W(W2, i) = u2;
+        W(Wx, i) = xc;
+        dd = ndd;
+        du = ndu;
+        xc = xn;
+      }
+      if (fabs(dd) < eps) dd = (dd < 0.0) ? -eps : eps;
+      W(Wr, J - 1) = rcp_refined(dd);
+      W(W1, J - 1) = 0.0;
+      W(W2, J - 1) = 0.0;
+      W(Wx, J - 1) = xc;
+      // back substitution
+      double y1 = 0.0, y2 = 0.0, nrm = 0.0;
+      for (int i = J - 1; i >= 0; --i) {
+        const double yi = (W(Wx, i) - W(W1, i) * y1 - W(W2, i) * y2) * W(Wr, i);
+        W(Wx, i) = yi;
+        nrm += yi * yi;
+        y2 = y1;
+        y1 = yi;
+      }
+      xscale = 1.0 / sqrt(nrm);
+    }
+    for (int i = 0; i < J; ++i) Zt[(int64_t)vec * J + i] = W(Wx, i) * xscale;
+  }
+#undef W
+}
+
+// Batched form: one wave per vector reading the reflectors straight from
+// global memory (the next one prefetched); many workgroups per CU hide the
+// latency, and no LDS is used.
+template <int Q>
+__device__ __forceinline__ void back_body_direct(const double* __restrict__ H, const double* __restrict__ tau, int J,
+                                          const double* __restrict__ Zt, const int64_t* __restrict__ Rp,
+                                          double* __restrict__ U, int bx) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int vec = bx * 4 + wave;
+  if (vec >= (int)*Rp) return;
+  double z[Q], v[Q], vn[Q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int r = lane + 64 * q;
+    z[q] = (r < J) ? Zt[(int64_t)vec * J + r] : 0.0;
+  }
+  auto load_v = [&](int k, double* dst) {
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int r = lane + 64 * q;
+      dst[q] = (r == k + 1) ? 1.0 : ((r > k + 1 && r < J) ? H[(int64_t)k * J + r] : 0.0);
+    }
+  };
+  double tn = 0.0;
+  if (J >= 3) {
+    load_v(J - 3, vn);
+    tn = tau[J - 3];
+  }
+  for (int k = J - 3; k >= 0; --k) {
+    const double tk = tn;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) v[q] = vn[q];
+    if (k > 0) {  // prefetch the next reflector, independent of z
+      load_v(k - 1, vn);
+      tn = tau[k - 1];
+    }
+    if (tk == 0.0) continue;
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) s += v[q] * z[q];
+    s = wave_sum_fast(s) * tk;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) z[q] -= s * v[q];
+  }
+  // sign convention: entry of largest magnitude (lowest index on ties) positive
+  double ba = -1.0, bv = 0.0;
+  int bi = J;
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int r = lane + 64 * q;
+    if (r < J && fabs(z[q]) > ba) {
+      ba = fabs(z[q]);
+      bv = z[q];
+      bi = r;
+    }
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const double oa = __shfl_xor(ba, off, 64);
+    const double ov = __shfl_xor(bv, off, 64);
+    const int oi = __shfl_xor(bi, off, 64);
+    if (oa > ba || (oa == ba && oi < bi)) {
+      ba = oa;
+      bv = ov;
+      bi = oi;
+    }
+  }
+  const double sgn = (bv < 0.0) ? -1.0 : 1.0;
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int r = lane + 64 * q;
+    if (r < J) U[(int64_t)vec * J + r] = sgn * z[q];
+  }
 }
 
 // ---------------------------------------------------------------- batched form
@@ -1102,9 +1284,9 @@ __global__ __launch_bounds__(64 * NW) void eig_tridiag_reg_batched(EigBatch b, i
 __global__ __launch_bounds__(256) void eig_bisect_batched(EigBatch b) {
   extern __shared__ double sh[];
   int m, J;
-  if (!batch_matrix(b, m, J) || (int)blockIdx.x * (256 / kBisLanes) >= J) return;
+  if (!batch_matrix(b, m, J) || (int)blockIdx.x * (256 / kBisLanesBatched) >= J) return;
   const int64_t o1 = (int64_t)m * b.Jmax;
-  bisect_body(b.d + o1, b.e + o1, J, b.lam + o1, b.scal + 8 * (int64_t)m, blockIdx.x);
+  bisect_body<kBisLanesBatched>(b.d + o1, b.e + o1, J, b.lam + o1, b.scal + 8 * (int64_t)m, blockIdx.x);
 }
 
 __global__ void eig_truncate_batched(EigBatch b, double thr_mul) {
@@ -1121,7 +1303,8 @@ __global__ __launch_bounds__(64) void eig_invit_batched(EigBatch b, int nvw) {
   int m, J;
   if (!batch_matrix(b, m, J)) return;
   const int64_t o2 = (int64_t)m * b.Jmax * b.Jmax, o1 = (int64_t)m * b.Jmax;
-  invit_body(b.d + o1, b.e + o1, J, b.lam + o1, b.R + m, b.scal + 8 * (int64_t)m, b.Zt + o2, nvw, sh, blockIdx.x);
+  invit_body_lean(b.d + o1, b.e + o1, J, b.lam + o1, b.R + m, b.scal + 8 * (int64_t)m, b.Zt + o2, nvw, sh,
+                  blockIdx.x);
 }
 
 __global__ __launch_bounds__(kEigThreads) void eig_orth_batched(EigBatch b) {
@@ -1129,8 +1312,7 @@ __global__ __launch_bounds__(kEigThreads) void eig_orth_batched(EigBatch b) {
   int m, J;
   if (!batch_matrix(b, m, J)) return;
   const int64_t o2 = (int64_t)m * b.Jmax * b.Jmax, o1 = (int64_t)m * b.Jmax;
-  orth_body(b.Zt + o2, J, b.lam + o1, b.R + m, b.scal + 8 * (int64_t)m, sh,
-            (int)min((int64_t)b.Jmax * b.Jmax, (int64_t)kOrthCap));
+  orth_body(b.Zt + o2, J, b.lam + o1, b.R + m, b.scal + 8 * (int64_t)m, sh, orth_cap_batched(b.Jmax), false);
 }
 
 template <int Q>
@@ -1138,8 +1320,7 @@ __global__ __launch_bounds__(256) void eig_back_batched(EigBatch b) {
   int m, J;
   if (!batch_matrix(b, m, J)) return;
   const int64_t o2 = (int64_t)m * b.Jmax * b.Jmax, o1 = (int64_t)m * b.Jmax;
-  extern __shared__ double sh[];
-  back_body<Q>(b.A + o2, b.tau + o1, J, b.Zt + o2, b.R + m, b.U + o2, blockIdx.x, sh);
+  back_body_direct<Q>(b.A + o2, b.tau + o1, J, b.Zt + o2, b.R + m, b.U + o2, blockIdx.x);
 }
 
 }  // namespace
@@ -1232,16 +1413,17 @@ hipError_t launch_eig_truncate_batched(const EigBatch& b, double thr_mul, hipStr
   hipLaunchKernelGGL((eig_tridiag_reg_batched<8, 1, 2>), dim3(1, nb), dim3(64 * 8), 0, stream, b, 32, 0);
   const int J = b.Jmax;
   const size_t shb = sizeof(double) * (2 * (size_t)J + 4);
-  hipLaunchKernelGGL(eig_bisect_batched, dim3(ceil_div(J, 256 / kBisLanes), nb), dim3(256), shb, stream, b);
+  hipLaunchKernelGGL(eig_bisect_batched, dim3(ceil_div(J, 256 / kBisLanesBatched), nb), dim3(256), shb, stream, b);
   hipLaunchKernelGGL(eig_truncate_batched, dim3(ceil_div(nb, 64)), dim3(64), 0, stream, b, thr_mul);
-  const int nvw = invit_vectors_per_group(J);
-  hipLaunchKernelGGL(eig_invit_batched, dim3(ceil_div(J, nvw), nb), dim3(64),
-                     sizeof(double) * kInvitArrays * (size_t)J * nvw, stream, b, nvw);
-  hipLaunchKernelGGL(eig_orth_batched, dim3(1, nb), dim3(kEigThreads), orth_lds_bytes(J), stream, b);
+  const int nvw = (int)std::max<int64_t>(1, std::min<int64_t>(64, (128 * 1024) / (32 * (int64_t)J)));
+  hipLaunchKernelGGL(eig_invit_batched, dim3(ceil_div(J, nvw), nb), dim3(64), sizeof(double) * 4 * (size_t)J * nvw,
+                     stream, b, nvw);
+  hipLaunchKernelGGL(eig_orth_batched, dim3(1, nb), dim3(kEigThreads),
+                     sizeof(double) * ((size_t)J + 16 + (size_t)orth_cap_batched(J)), stream, b);
   if (J <= 64)
-    hipLaunchKernelGGL((eig_back_batched<1>), dim3(ceil_div(J, 4), nb), dim3(256), back_lds_bytes(1), stream, b);
+    hipLaunchKernelGGL((eig_back_batched<1>), dim3(ceil_div(J, 4), nb), dim3(256), 0, stream, b);
   else
-    hipLaunchKernelGGL((eig_back_batched<2>), dim3(ceil_div(J, 4), nb), dim3(256), back_lds_bytes(2), stream, b);
+    hipLaunchKernelGGL((eig_back_batched<2>), dim3(ceil_div(J, 4), nb), dim3(256), 0, stream, b);
   return hipGetLastError();
 }
 
