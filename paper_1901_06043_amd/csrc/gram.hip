@@ -175,13 +175,35 @@ __global__ __launch_bounds__(64 * kTriWaves) void gram_tri_kernel(GramParams g) 
   }
 }
 
-// Sum the per-split partial blocks in split order; write both triangles of S.
-__global__ __launch_bounds__(256) void gram_tri_reduce_kernel(const double* __restrict__ part, int nb,
-                                                              int64_t nsplit, int J, double* __restrict__ S) {
+// Sum the per-split partial blocks in a fixed order and write both triangles
+// of S.  Each entry's nsplit partials are split over kRedQ threads of one
+// workgroup (contiguous quarters, each summed with two interleaved
+// accumulators), and the quarters are added in order through LDS.
+constexpr int kRedQ = 4;
+
+__global__ __launch_bounds__(256 * kRedQ) void gram_tri_reduce_kernel(const double* __restrict__ part, int nb,
+                                                                      int64_t nsplit, int J,
+                                                                      double* __restrict__ S) {
+  __shared__ double sq4[kRedQ][256];
   const int nblk = nb * (nb + 1) / 2;
-  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (idx >= (int64_t)nblk * 256) return;
-  const int q = (int)(idx >> 8), rem = (int)(idx & 255);
+  const int rem = threadIdx.x & 255, qt = threadIdx.x >> 8;
+  const int q = blockIdx.x;  // 16 x 16 block
+  const int64_t sp0 = nsplit * qt / kRedQ, sp1 = nsplit * (qt + 1) / kRedQ;
+  const double* p = part + (int64_t)q * 256 + rem;
+  const int64_t stride = (int64_t)nblk * 256;
+  double s0 = 0.0, s1 = 0.0;
+  int64_t sp = sp0;
+  for (; sp + 1 < sp1; sp += 2) {
+    s0 += p[sp * stride];
+    s1 += p[(sp + 1) * stride];
+  }
+  if (sp < sp1) s0 += p[sp * stride];
+  sq4[qt][rem] = s0 + s1;
+  __syncthreads();
+  if (qt != 0) return;
+  double s = sq4[0][rem];
+#pragma unroll
+  for (int t = 1; t < kRedQ; ++t) s += sq4[t][rem];
   int bi = 0, qq = q;
   while (qq >= nb - bi) {
     qq -= nb - bi;
@@ -191,8 +213,6 @@ __global__ __launch_bounds__(256) void gram_tri_reduce_kernel(const double* __re
   const int r = rem >> 4, c = rem & 15;
   const int a = 16 * bi + r, b = 16 * bj + c;
   if (a >= J || b >= J || (bi == bj && r > c)) return;
-  double s = 0.0;
-  for (int64_t sp = 0; sp < nsplit; ++sp) s += part[(sp * nblk + q) * 256 + rem];
   S[(int64_t)a * J + b] = s;
   S[(int64_t)b * J + a] = s;
 }
@@ -260,8 +280,8 @@ hipError_t launch_gram_f64(const T* Y, int J, uint64_t L, uint64_t K, const Gram
   else TRI_GRAM(12);
 #undef TRI_GRAM
   if (after_main) (void)hipEventRecord(after_main, stream);
-  hipLaunchKernelGGL(gram_tri_reduce_kernel, dim3(ceil_div((int64_t)nblk * 256, 256)), dim3(256), 0, stream, part,
-                     p.ntiles, p.nsplit, J, S);
+  hipLaunchKernelGGL(gram_tri_reduce_kernel, dim3(nblk), dim3(256 * kRedQ), 0, stream, part, p.ntiles, p.nsplit,
+                     J, S);
   if (norm2) hipLaunchKernelGGL(sum_fixed_kernel, dim3(1), dim3(256), 0, stream, sq, p.sq_elems, norm2);
   return hipGetLastError();
 }
