@@ -420,6 +420,7 @@ tucker_status tucker_sthosvd(const void* data, tucker_dtype dtype, const int64_t
   if ((st = pinned(&hp))) return st;
   int64_t* h_R = static_cast<int64_t*>(hp);
   double* h_flag = reinterpret_cast<double*>(static_cast<char*>(hp) + 8);
+  double* h_nx2 = reinterpret_cast<double*>(static_cast<char*>(hp) + 16);
 
   Events evs;
   HIP_TRY(evs.create(5 * N));
@@ -460,6 +461,7 @@ tucker_status tucker_sthosvd(const void* data, tucker_dtype dtype, const int64_t
       HIP_TRY(hipMemcpyAsync(h_R, t->dranks + n, sizeof(int64_t), hipMemcpyDeviceToHost, stream));
       if (pp != TUCKER_GRAM_FP64)
         HIP_TRY(hipMemcpyAsync(h_flag, d_flag + step, sizeof(double), hipMemcpyDeviceToHost, stream));
+      if (step == 0) HIP_TRY(hipMemcpyAsync(h_nx2, d_nx2, sizeof(double), hipMemcpyDeviceToHost, stream));
       HIP_TRY(hipStreamSynchronize(stream));
       if (pp == TUCKER_GRAM_FP64 || h_flag[0] == 0.0) break;
       t->prec_used[n] = TUCKER_GRAM_FP64;
@@ -468,8 +470,7 @@ tucker_status tucker_sthosvd(const void* data, tucker_dtype dtype, const int64_t
     if (R < 1 || R > J) return fail(TUCKER_ENOCONV, "eigensolver returned rank %lld for J=%lld", (long long)R, (long long)J);
     if (step == 0) {
       // non-finite data shows up as a non-finite norm
-      double nx2 = 0.0;
-      HIP_TRY(hipMemcpy(&nx2, d_nx2, sizeof(double), hipMemcpyDeviceToHost));
+      const double nx2 = h_nx2[0];  // read back with the rank
       if (!std::isfinite(nx2)) return fail(TUCKER_EINVAL, "data contains non-finite values (||X||^2 = %g)", nx2);
       t->norm2 = nx2;
     }
