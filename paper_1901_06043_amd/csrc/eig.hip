@@ -41,6 +41,14 @@ namespace {
 
 constexpr int kEigThreads = 1024;
 
+// A launch that the runtime rejects (for instance for its LDS request) is
+// returned to the caller at once.
+#define LAUNCH_OK()                              \
+  do {                                           \
+    const hipError_t launch_err_ = hipGetLastError(); \
+    if (launch_err_ != hipSuccess) return launch_err_; \
+  } while (0)
+
 // Block-wide fixed-order sum for 1024 threads (16 waves); all threads get it.
 __device__ __forceinline__ double block_sum_1024(double v, double* sred) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -94,6 +102,48 @@ __device__ __forceinline__ void write_row(int k, int wave, int rs, int c, const 
   }
 }
 
+// Householder scalars of a step from alpha = a_k,k+1 and sigma =
+// sum_{j >= k+2} a_kj^2: beta = -sign(alpha) sqrt(alpha^2 + sigma),
+// tau = (beta - alpha) / beta, scale = 1 / (alpha - beta); tau = scale = 0
+// when sigma = 0.  When alpha^2 + sigma falls below kTinyNorm2 its square root
+// would lose precision in the subnormal range (rows of a strongly graded
+// matrix), so the caller passes the values of the row scaled by kRowScale and
+// reflector() unscales beta and scale (tau is scale-free), as LAPACK's
+// reflector generator does.
+constexpr double kTinyNorm2 = 0x1p-900;
+constexpr double kRowScale = 0x1p+600;
+__device__ __forceinline__ bool row_is_tiny(double alpha, double sigma) {
+  return sigma != 0.0 && alpha * alpha + sigma < kTinyNorm2;
+}
+__device__ __forceinline__ void reflector(double alpha, double sigma, bool scaled, double& beta, double& tk,
+                                          double& scale) {
+  beta = alpha;
+  tk = 0.0;
+  scale = 0.0;
+  if (sigma != 0.0) {
+    beta = -copysign(sqrt(alpha * alpha + sigma), alpha);
+    tk = (beta - alpha) / beta;
+    scale = 1.0 / (alpha - beta);
+  }
+  if (scaled) {
+    beta *= 1.0 / kRowScale;
+    scale *= kRowScale;
+  }
+}
+
+// Sum of (kRowScale x_j)^2 over this lane's columns j >= kk + 2 of the row x in LDS.
+template <int NC>
+__device__ __forceinline__ double scaled_tail(const double* x, int c, int kk, int J) {
+  double part = 0.0;
+#pragma unroll
+  for (int cc = 0; cc < NC; ++cc) {
+    const int j = c + 16 * cc;
+    const double y = x[j] * kRowScale;
+    part += (j >= kk + 2 && j < J) ? y * y : 0.0;
+  }
+  return part;
+}
+
 // Row kk of the matrix becomes the column of step kk: its owner wave writes
 // it to LDS and computes that step's reflector scalars from the values in its
 // registers (sigma = sum_{j >= kk+2} a_kk,j^2, alpha = a_kk,kk+1,
@@ -119,18 +169,17 @@ __device__ __forceinline__ void publish_row(int kk, int J, int wave, int rs, int
         part += (j >= kk + 2 && j < J) ? x * x : 0.0;
       }
     }
-  const double sigma = row16_sum(part);  // the owner slot's 16 lanes hold row kk
+  double sigma = row16_sum(part);  // the owner slot's 16 lanes hold row kk
   if (kk + 1 >= J) return;
-  const double alpha = sxn[kk + 1];  // written above by this wave (LDS operations of a wave are ordered)
-  double beta = alpha, tk = 0.0;
-  if (sigma != 0.0) {
-    beta = -copysign(sqrt(alpha * alpha + sigma), alpha);
-    tk = (beta - alpha) / beta;
-  }
+  double alpha = sxn[kk + 1];  // written above by this wave (LDS operations of a wave are ordered)
+  const bool tiny = row_is_tiny(alpha, sigma);  // uniform within each 16-lane row
+  if (tiny) sigma = row16_sum(scaled_tail<NC>(sxn, c, kk, J)), alpha *= kRowScale;
+  double beta, tk, scale;
+  reflector(alpha, sigma, tiny, beta, tk, scale);
   if (mine && c == 0) {
     ssn[0] = beta;
     ssn[1] = tk;
-    ssn[2] = (tk != 0.0) ? 1.0 / (alpha - beta) : 0.0;
+    ssn[2] = scale;
   }
 }
 
@@ -246,17 +295,16 @@ __device__ __forceinline__ void tridiag_reg_body(const double* __restrict__ S, i
     }
     if (gkn >= 0 && kn + 1 < J) {
       // scalars of step k + 1 from the owner slot's 16 lanes
-      const double sigma = row16_sum(part);
-      const double alpha = sxn[kn + 1];  // written above by this wave (LDS operations of a wave are ordered)
-      double nbeta = alpha, ntk = 0.0;
-      if (sigma != 0.0) {
-        nbeta = -copysign(sqrt(alpha * alpha + sigma), alpha);
-        ntk = (nbeta - alpha) / nbeta;
-      }
+      double sigma = row16_sum(part);
+      double alpha = sxn[kn + 1];  // written above by this wave (LDS operations of a wave are ordered)
+      const bool tiny = row_is_tiny(alpha, sigma);  // uniform within each 16-lane row
+      if (tiny) sigma = row16_sum(scaled_tail<NC>(sxn, c, kn, J)), alpha *= kRowScale;
+      double nbeta, ntk, nscale;
+      reflector(alpha, sigma, tiny, nbeta, ntk, nscale);
       if (slot && c == 0) {
         ssn[0] = nbeta;
         ssn[1] = ntk;
-        ssn[2] = (ntk != 0.0) ? 1.0 / (alpha - nbeta) : 0.0;
+        ssn[2] = nscale;
       }
     }
     lds_barrier();
@@ -338,14 +386,20 @@ __global__ __launch_bounds__(kBigThreads) void eig_tri_big_p(const double* __res
   const double* rk = A + (int64_t)k * J;
   double part = 0.0;
   for (int j = k + 2 + tid; j < J; j += kBigThreads) part += rk[j] * rk[j];
-  const double sigma = block_sum_256(part, sred);
-  const double alpha = rk[k + 1];
-  double beta = alpha, tk = 0.0, scale = 0.0;
-  if (sigma != 0.0) {
-    beta = -copysign(sqrt(alpha * alpha + sigma), alpha);
-    tk = (beta - alpha) / beta;
-    scale = 1.0 / (alpha - beta);
+  double sigma = block_sum_256(part, sred);
+  double alpha = rk[k + 1];
+  const bool tiny = row_is_tiny(alpha, sigma);  // uniform
+  if (tiny) {
+    part = 0.0;
+    for (int j = k + 2 + tid; j < J; j += kBigThreads) {
+      const double y = rk[j] * kRowScale;
+      part += y * y;
+    }
+    sigma = block_sum_256(part, sred);
+    alpha *= kRowScale;
   }
+  double beta, tk, scale;
+  reflector(alpha, sigma, tiny, beta, tk, scale);
   for (int j = k + 1 + tid; j < J; j += kBigThreads) {
     const double v = (j == k + 1) ? 1.0 : rk[j] * scale;
     sv[j] = v;
@@ -749,7 +803,13 @@ __device__ __forceinline__ void orth_loop(double* __restrict__ Z, int J, int R, 
 // vector-by-vector loop.
 constexpr int kOB = 16;  // vectors per block
 constexpr int kOC = 64;  // preceding vectors per chunk
-__host__ __device__ constexpr int orth_ksplit(int J) { return J <= 768 ? 4 : 2; }
+__host__ __device__ constexpr int orth_ksplit(int J) { return J <= 720 ? 4 : 2; }
+// LDS of the blocked form (doubles); it runs only while this stays within the
+// 128 KB a workgroup may use (J <= 840), larger J take the global-memory loop.
+constexpr int kEigLdsMax = 128 * 1024 / 8;
+__host__ __device__ constexpr int64_t orth_blocked_doubles(int64_t J) {
+  return J + 32 + (int64_t)kOB * ((J + 15) & ~int64_t(15)) + (int64_t)orth_ksplit((int)J) * kOC * kOB;
+}
 
 __device__ __forceinline__ void orth_blocked(double* __restrict__ Z, int J, int R, int first,
                                              const double* __restrict__ lam, double otol, double* sh) {
@@ -885,10 +945,10 @@ constexpr int kOrthCapBatched = 4096;
 __host__ __device__ inline int orth_cap_batched(int64_t Jmax) {
   return (int)(Jmax * Jmax < kOrthCapBatched ? Jmax * Jmax : kOrthCapBatched);
 }
+inline bool orth_blocked_fits(int64_t J) { return orth_blocked_doubles(J) <= kEigLdsMax; }
 inline size_t orth_lds_bytes(int64_t J) {
-  const int64_t Jp = (J + 15) & ~int64_t(15);
-  const int64_t blocked = 16 + kOB * Jp + (int64_t)orth_ksplit((int)J) * kOC * kOB;
-  return sizeof(double) * ((size_t)J + 16 + (size_t)std::max<int64_t>(std::min<int64_t>(J * J, kOrthCap), blocked));
+  const int64_t copy = J + 16 + std::min<int64_t>(J * J, kOrthCap);
+  return sizeof(double) * (size_t)std::max<int64_t>(copy, orth_blocked_fits(J) ? orth_blocked_doubles(J) : 0);
 }
 
 // The vectors are copied to LDS when R * J fits in `cap` doubles (the rounds
@@ -922,9 +982,9 @@ __device__ __forceinline__ void orth_body(double* __restrict__ Zt, int J, const 
 __global__ __launch_bounds__(kEigThreads) void eig_orth_kernel(double* __restrict__ Zt, int J,
                                                                const double* __restrict__ lam,
                                                                const int64_t* __restrict__ Rp,
-                                                               const double* __restrict__ scal) {
+                                                               const double* __restrict__ scal, int blocked) {
   extern __shared__ double sh[];
-  orth_body(Zt, J, lam, Rp, scal, sh, (int)std::min<int64_t>((int64_t)J * J, kOrthCap), true);
+  orth_body(Zt, J, lam, Rp, scal, sh, (int)std::min<int64_t>((int64_t)J * J, kOrthCap), blocked != 0);
 }
 
 // ---------------------------------------------------------------- 6. back-transformation + signs
@@ -1356,6 +1416,7 @@ hipError_t launch_eig_truncate(const double* S, int J, double thr, const double*
                            k, V, P, sc);
         hipLaunchKernelGGL(eig_tri_big_update, dim3(grid), dim3(kBigThreads), sizeof(double) * 2 * (size_t)J, stream,
                            w.A, J, k, V, P, sc, w.d, w.e, w.tau);
+        LAUNCH_OK();
       }
       src = w.A;
       k0 = nbig;
@@ -1375,6 +1436,7 @@ hipError_t launch_eig_truncate(const double* S, int J, double thr, const double*
       else if (Jl <= 192) { next = 128; TRI_LAUNCH(8, 6, 12); }
       else { next = 192; TRI_LAUNCH(4, 13, 13); }  // Jl <= kRegMaxJ
 #undef TRI_LAUNCH
+      LAUNCH_OK();
       if (next == 0) break;
       src = w.A;
       k0 += Jl - next;
@@ -1383,16 +1445,20 @@ hipError_t launch_eig_truncate(const double* S, int J, double thr, const double*
   const size_t shb = sizeof(double) * (2 * (size_t)J + 4);
   hipLaunchKernelGGL(eig_bisect_kernel, dim3(ceil_div(J, 256 / kBisLanes)), dim3(256), shb, stream, w.d, w.e, J,
                      lam, w.scal);
+  LAUNCH_OK();
   hipLaunchKernelGGL(eig_truncate_kernel, dim3(1), dim3(64), sizeof(double) * (size_t)J, stream, lam, J, thr, nx2,
                      trace_ref, R, disc);
+  LAUNCH_OK();
   {
     const int nvw = invit_vectors_per_group(J);
     const size_t shi = sizeof(double) * kInvitArrays * (size_t)J * nvw;
     hipLaunchKernelGGL(eig_invit_kernel, dim3(ceil_div(J, nvw)), dim3(64), shi, stream, w.d, w.e, J, lam, R,
                        w.scal, w.Zt, nvw);
+    LAUNCH_OK();
   }
   hipLaunchKernelGGL(eig_orth_kernel, dim3(1), dim3(kEigThreads), orth_lds_bytes(J), stream, w.Zt, J, lam, R,
-                     w.scal);
+                     w.scal, orth_blocked_fits(J) ? 1 : 0);
+  LAUNCH_OK();
   const int q = (int)ceil_div(J, 64);
   if (q <= 1) launch_back<1>(w, J, R, U, stream);
   else if (q <= 2) launch_back<2>(w, J, R, U, stream);

@@ -80,7 +80,7 @@ def _gram_of(rng, J, K, decay):
     return A @ A.T
 
 
-@pytest.mark.parametrize("J", [1, 2, 3, 11, 16, 33, 50, 64, 100, 200, 256, 300, 513, 672])
+@pytest.mark.parametrize("J", [1, 2, 3, 11, 16, 33, 50, 64, 100, 200, 208, 209, 256, 300, 513, 672, 800, 1024])
 def test_eig_truncate_parity(tk, orc, J):
     rng = np.random.default_rng(J)
     S = _gram_of(rng, J, J + 5, 0.8)
