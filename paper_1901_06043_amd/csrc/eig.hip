@@ -803,10 +803,11 @@ __device__ __forceinline__ void orth_loop(double* __restrict__ Z, int J, int R, 
 // vector-by-vector loop.
 constexpr int kOB = 16;  // vectors per block
 constexpr int kOC = 64;  // preceding vectors per chunk
-__host__ __device__ constexpr int orth_ksplit(int J) { return J <= 720 ? 4 : 2; }
-// LDS of the blocked form (doubles); it runs only while this stays within the
-// 128 KB a workgroup may use (J <= 840), larger J take the global-memory loop.
-constexpr int kEigLdsMax = 128 * 1024 / 8;
+__host__ __device__ constexpr int orth_ksplit(int J) { return J <= 960 ? 4 : 2; }
+// LDS of the blocked form (doubles); it runs while this stays within the
+// 160 KB a gfx950 workgroup may use (every J up to 1024), otherwise the
+// global-memory loop does.
+constexpr int kEigLdsMax = 160 * 1024 / 8;
 __host__ __device__ constexpr int64_t orth_blocked_doubles(int64_t J) {
   return J + 32 + (int64_t)kOB * ((J + 15) & ~int64_t(15)) + (int64_t)orth_ksplit((int)J) * kOC * kOB;
 }
