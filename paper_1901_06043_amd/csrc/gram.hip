@@ -27,7 +27,7 @@ namespace tk {
 namespace {
 
 constexpr int kKC = 16;         // unfolding columns per LDS chunk
-constexpr int kLds = kKC + 1;   // LDS row stride (doubles)
+constexpr int kLds = kKC + 2;   // LDS row stride (doubles)
 
 // ---------------------------------------------------------------- whole triangle per workgroup
 // The flattened block list (row-major over bi <= bj) is cut into 8 contiguous

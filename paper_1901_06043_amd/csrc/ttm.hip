@@ -31,7 +31,23 @@ namespace {
 constexpr int kTK = 64;     // output rows per wave (4 MFMA blocks)
 constexpr int kWaves = 4;   // waves per workgroup; each owns 16 columns
 constexpr int kJB = 64;     // reduction rows per LDS block of M (4 chunks of 16)
-constexpr int kMS = kJB + 1;
+// LDS layout of M blocks: row stride and position of reduction index jj.
+// FP64: stride (columns) + 1.  FP32 (one bank per value): a stride of 4 modulo
+// 64, and within each 16-index chunk the two 2-bit fields of jj are swapped
+// for L = 1, so that the A-operand read of lane (i, q) at step s, chunk t
+// lands on bank 4 i + q (+ const) in both layouts: 64 distinct banks.
+template <typename CT>
+struct MLds {
+  static constexpr bool kF32 = sizeof(CT) == 4;
+  static constexpr int S = kF32 ? kJB + 4 : kJB + 1;  // tile kernel (kJB columns)
+  // resident kernel: jp (a multiple of 16) columns
+  static __host__ __device__ __forceinline__ int ld(int jp) { return kF32 ? ((jp + 63) & ~63) + 4 : jp + 1; }
+  template <bool UNIT_L>
+  static __device__ __forceinline__ int pos(int jj) {
+    if constexpr (kF32 && UNIT_L) return (jj & ~15) | ((jj & 3) << 2) | ((jj >> 2) & 3);
+    return jj;
+  }
+};
 
 template <typename T>
 __device__ __forceinline__ void store_as(T* p, double v) {
@@ -68,7 +84,8 @@ __device__ __forceinline__ void ttm_tile(const TI* __restrict__ Y, int J, uint32
                                          const double* __restrict__ M, int64_t msk, int64_t msj, int K,
                                          TO* __restrict__ Z, int64_t ct, int rt) {
   using A = Acc<CT>;
-  __shared__ CT sM[kTK * kMS];  // M block: 64 output rows x 64 reduction rows
+  using ML = MLds<CT>;
+  __shared__ CT sM[kTK * ML::S];  // M block: 64 output rows x 64 reduction rows
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t c0 = (ct * kWaves + wave) * 16;  // this wave's first column
   const int k0 = rt * kTK;
@@ -117,7 +134,8 @@ __device__ __forceinline__ void ttm_tile(const TI* __restrict__ Y, int J, uint32
     for (int e = tid; e < 16 * RB * kJB; e += 256) {
       const int kk = e / kJB, jj = e - kk * kJB;
       const int k = k0 + kk, j = jb + jj;
-      sM[kk * kMS + jj] = (k < K && j < J) ? (CT)M[(int64_t)k * msk + (int64_t)j * msj] : (CT)0;
+      sM[kk * ML::S + ML::template pos<UNIT_L>(jj)] =
+          (k < K && j < J) ? (CT)M[(int64_t)k * msk + (int64_t)j * msj] : (CT)0;
     }
     __syncthreads();
 #pragma unroll
@@ -129,7 +147,7 @@ __device__ __forceinline__ void ttm_tile(const TI* __restrict__ Y, int J, uint32
         const CT y = (!kConv || (cok && jb + jj < J)) ? yv : (CT)0;
 #pragma unroll
         for (int b = 0; b < RB; ++b) {
-          acc[b] = A::mfma(sM[(16 * b + i) * kMS + jj], y, acc[b]);
+          acc[b] = A::mfma(sM[(16 * b + i) * ML::S + ML::template pos<UNIT_L>(jj)], y, acc[b]);
         }
       }
   }
@@ -266,12 +284,13 @@ __global__ __launch_bounds__(64 * kResWaves) void ttm_resident_kernel(const TI* 
   extern __shared__ unsigned char smem[];
   const int nj = (J + 15) / 16;
   const int jp = 16 * nj;        // reduction rows padded to whole MFMA blocks (zeros)
-  const int ldm = jp + 1;
+  using ML = MLds<CT>;
+  const int ldm = ML::ld(jp);
   CT* sM = reinterpret_cast<CT*>(smem);  // [16 RB][ldm]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   for (int e = tid; e < 16 * RB * jp; e += 64 * kResWaves) {
     const int k = e / jp, j = e - k * jp;
-    sM[k * ldm + j] = (k < K && j < J) ? (CT)M[(int64_t)k * msk + (int64_t)j * msj] : (CT)0;
+    sM[k * ldm + ML::template pos<UNIT_L>(j)] = (k < K && j < J) ? (CT)M[(int64_t)k * msk + (int64_t)j * msj] : (CT)0;
   }
   __syncthreads();
   const int q = lane >> 4, i = lane & 15;
@@ -298,7 +317,8 @@ __global__ __launch_bounds__(64 * kResWaves) void ttm_resident_kernel(const TI* 
       for (int s2 = 0; s2 < 4; ++s2) {
         const int jj = 16 * jb + (UNIT_L ? 4 * q + s2 : 4 * s2 + q);
 #pragma unroll
-        for (int b = 0; b < RB; ++b) acc[b] = A::mfma(sM[(16 * b + i) * ldm + jj], y[s2], acc[b]);
+        for (int b = 0; b < RB; ++b)
+          acc[b] = A::mfma(sM[(16 * b + i) * ldm + ML::template pos<UNIT_L>(jj)], y[s2], acc[b]);
       }
     };
     if (nj < kDepth) {
@@ -374,7 +394,7 @@ template <typename TI, typename TO, typename CT>
 hipError_t launch_ttm_ct(const TI* Y, int J, uint64_t L, uint64_t cols, const double* M, int64_t msk, int64_t msj,
                          int K, TO* Z, hipStream_t stream) {
   const int rbr = (int)ceil_div(K, 16);
-  const size_t lds = sizeof(CT) * (size_t)(16 * rbr) * (size_t)(16 * ceil_div(J, 16) + 1);
+  const size_t lds = sizeof(CT) * (size_t)(16 * rbr) * (size_t)MLds<CT>::ld((int)(16 * ceil_div(J, 16)));
   if (K <= 64 && lds <= (size_t)kResidentLds) {
     const int64_t nct = ceil_div((int64_t)cols, 16 * kResWaves);
     const int64_t grid = std::min<int64_t>(nct, 2 * 256);
