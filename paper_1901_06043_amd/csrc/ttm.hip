@@ -19,7 +19,6 @@
 // the workgroup's four waves and follows the same assignment.  Four 16-row
 // chunks of Y are loaded before they are consumed, keeping enough bytes in
 // flight per CU.
-#include <type_traits>
 
 #include "common.hpp"
 #include "kernels.hpp"
@@ -75,11 +74,91 @@ struct Acc<float> {
   static __device__ __forceinline__ int row(int q, int v) { return 4 * q + v; }
 };
 
+// Raw operand data of one 16-row block for one lane: 4 reduction rows of its
+// column.  VW = 4 (L = 1, J % 4 == 0, Y 16-byte aligned): the 4 consecutive
+// rows are one 16-byte load (two for doubles); VW = 2 (L = 1, J even): two
+// loads of a pair of rows each.
+template <typename TI>
+struct Raw4 {
+  TI v[4];
+};
+
+// Issues the loads of block jb without any condition: the row and column are
+// clamped into the tensor, and use4() masks what lies outside.  (A load under
+// a condition, or converted right after it, would have to complete at once.)
+template <typename TI, bool UNIT_L, int VW>
+__device__ __forceinline__ void issue4(const TI* __restrict__ Y, int64_t cbase, int J, uint32_t L, int jb, int q,
+                                       Raw4<TI>& r) {
+  if constexpr (VW == 4) {
+    const int j = min(16 * jb + 4 * q, J - 4);
+    const TI* src = Y + cbase + j;
+    if constexpr (sizeof(TI) == 4) {
+      const float4 f = *reinterpret_cast<const float4*>(src);
+      r.v[0] = f.x;
+      r.v[1] = f.y;
+      r.v[2] = f.z;
+      r.v[3] = f.w;
+    } else {
+      const double2 a = *reinterpret_cast<const double2*>(src);
+      const double2 b = *reinterpret_cast<const double2*>(src + 2);
+      r.v[0] = a.x;
+      r.v[1] = a.y;
+      r.v[2] = b.x;
+      r.v[3] = b.y;
+    }
+  } else if constexpr (VW == 2) {
+    // two pairs of rows, each clamped on its own (J even: a pair never straddles J)
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const TI* src = Y + cbase + min(16 * jb + 4 * q + 2 * h, J - 2);
+      if constexpr (sizeof(TI) == 4) {
+        const float2 f = *reinterpret_cast<const float2*>(src);
+        r.v[2 * h] = f.x;
+        r.v[2 * h + 1] = f.y;
+      } else {
+        const double2 f = *reinterpret_cast<const double2*>(src);
+        r.v[2 * h] = f.x;
+        r.v[2 * h + 1] = f.y;
+      }
+    }
+  } else {
+#pragma unroll
+    for (int s2 = 0; s2 < 4; ++s2) {
+      const int j = min(16 * jb + (UNIT_L ? 4 * q + s2 : 4 * s2 + q), J - 1);
+      r.v[s2] = Y[cbase + (UNIT_L ? (int64_t)j : (int64_t)L * j)];
+    }
+  }
+}
+
+// Vector width of the Y loads for L = 1: 4 rows per 16-byte access (two for
+// doubles) when J % 4 == 0, pairs of rows when J is even, else single rows;
+// Y must be aligned to the access.
+template <typename TI>
+int y_vector_width(const TI* Y, int J, uint64_t L) {
+  const uintptr_t a = reinterpret_cast<uintptr_t>(Y);
+  if (L != 1) return 1;
+  if (J % 4 == 0 && a % 16 == 0) return 4;
+  if (J % 2 == 0 && a % (2 * sizeof(TI)) == 0) return 2;
+  return 1;
+}
+
+// Converts block jb's raw data to the product type, zero outside the tensor.
+template <typename TI, typename CT, bool UNIT_L>
+__device__ __forceinline__ void use4(const Raw4<TI>& r, bool cok, int J, int jb, int q, CT (&y)[4]) {
+#pragma unroll
+  for (int s2 = 0; s2 < 4; ++s2) {
+    const int j = 16 * jb + (UNIT_L ? 4 * q + s2 : 4 * s2 + q);
+    const CT x = (CT)r.v[s2];
+    y[s2] = (cok && j < J) ? x : (CT)0;
+  }
+}
+
 // CT: arithmetic type of the products (double: FP64 MFMA; float: FP32 MFMA).
 // RB: 16-row output blocks per wave (1..4), chosen from K at launch.
+// VW: vector width of the Y loads (as in issue4).
 // One workgroup tile: output rows [64 rt, 64 rt + 16 RB) and columns
 // [64 ct, 64 ct + 64) (16 per wave).
-template <typename TI, typename TO, typename CT, bool UNIT_L, int RB>
+template <typename TI, typename TO, typename CT, bool UNIT_L, int RB, int VW>
 __device__ __forceinline__ void ttm_tile(const TI* __restrict__ Y, int J, uint32_t L, uint32_t cols,
                                          const double* __restrict__ M, int64_t msk, int64_t msj, int K,
                                          TO* __restrict__ Z, int64_t ct, int rt) {
@@ -111,24 +190,11 @@ __device__ __forceinline__ void ttm_tile(const TI* __restrict__ Y, int J, uint32
 
   for (int jb = 0; jb < J; jb += kJB) {
     // Y operands of the four 16-row chunks of this block (row of (chunk t, step s)
-    // is jb + 16 t + 4 q + s for L = 1 and jb + 16 t + 4 s + q otherwise).
-    // When the products take another type than the tensor, the loads are
-    // unconditional (row clamped) and masked and converted where they are
-    // used, so that no conversion waits for a load right after it is issued.
-    constexpr bool kConv = !std::is_same<TI, CT>::value;
-    TI yr[4][4];
+    // is jb + 16 t + 4 q + s for L = 1 and jb + 16 t + 4 s + q otherwise),
+    // loaded without condition and masked where they are used (issue4, use4)
+    Raw4<TI> raw[4];
 #pragma unroll
-    for (int t = 0; t < 4; ++t)
-#pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        const int j = jb + 16 * t + (UNIT_L ? 4 * q + s : 4 * s + q);
-        if constexpr (kConv) {
-          const int jc = min(j, J - 1);
-          yr[t][s] = Y[cbase + (UNIT_L ? (int64_t)jc : (int64_t)L * jc)];
-        } else {
-          yr[t][s] = (cok && j < J) ? Y[cbase + (UNIT_L ? (int64_t)j : (int64_t)L * j)] : (TI)0;
-        }
-      }
+    for (int t = 0; t < 4; ++t) issue4<TI, UNIT_L, VW>(Y, cbase, J, L, jb / 16 + t, q, raw[t]);
     // M block into LDS: sM[k][j] = M(k0 + k, jb + j)
     __syncthreads();
     for (int e = tid; e < 16 * RB * kJB; e += 256) {
@@ -139,17 +205,17 @@ __device__ __forceinline__ void ttm_tile(const TI* __restrict__ Y, int J, uint32
     }
     __syncthreads();
 #pragma unroll
-    for (int t = 0; t < 4; ++t)
+    for (int t = 0; t < 4; ++t) {
+      CT y[4];
+      use4<TI, CT, UNIT_L>(raw[t], cok, J, jb / 16 + t, q, y);
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
         const int jj = 16 * t + (UNIT_L ? 4 * q + s : 4 * s + q);
-        const CT yv = (CT)yr[t][s];
-        const CT y = (!kConv || (cok && jb + jj < J)) ? yv : (CT)0;
 #pragma unroll
-        for (int b = 0; b < RB; ++b) {
-          acc[b] = A::mfma(sM[(16 * b + i) * ML::S + ML::template pos<UNIT_L>(jj)], y, acc[b]);
-        }
+        for (int b = 0; b < RB; ++b)
+          acc[b] = A::mfma(sM[(16 * b + i) * ML::S + ML::template pos<UNIT_L>(jj)], y[s], acc[b]);
       }
+    }
   }
 
   // output row k0 + 16 b + A::row(l >> 4, v), output column c0 + (l & 15)
@@ -174,13 +240,13 @@ __device__ __forceinline__ void ttm_tile(const TI* __restrict__ Y, int J, uint32
     }
 }
 
-template <typename TI, typename TO, typename CT, bool UNIT_L, int RB>
+template <typename TI, typename TO, typename CT, bool UNIT_L, int RB, int VW>
 __global__ __launch_bounds__(256) void ttm_kernel(const TI* __restrict__ Y, int J, uint32_t L, uint32_t cols,
                                                   const double* __restrict__ M, int64_t msk, int64_t msj, int K,
                                                   TO* __restrict__ Z, int nrt, int64_t total) {
   const int64_t item = xcd_remap(blockIdx.x, gridDim.x, total);
   if (item < 0) return;
-  ttm_tile<TI, TO, CT, UNIT_L, RB>(Y, J, L, cols, M, msk, msj, K, Z, item / nrt, (int)(item % nrt));
+  ttm_tile<TI, TO, CT, UNIT_L, RB, VW>(Y, J, L, cols, M, msk, msj, K, Z, item / nrt, (int)(item % nrt));
 }
 
 // Batched form: item i covers column tiles [ct0, ct1) of tensor t (planned
@@ -205,7 +271,7 @@ __global__ __launch_bounds__(256) void ttm_batch_kernel(TtmBatch b) {
   const double* U = b.U + (int64_t)t * b.Jmax * b.Jmax;
   for (int64_t ct = d[1]; ct < ct1; ++ct)
     for (int rt = 0; rt * kTK < K; ++rt)
-      ttm_tile<TI, TO, CT, UNIT_L, 4>(Y, J, (uint32_t)L, (uint32_t)cols, U, J, 1, K, Z, ct, rt);
+      ttm_tile<TI, TO, CT, UNIT_L, 4, 1>(Y, J, (uint32_t)L, (uint32_t)cols, U, J, 1, K, Z, ct, rt);
 }
 
 // Resident-M variant for K <= 64 with M (K_pad x J) small enough for LDS:
@@ -216,57 +282,6 @@ __global__ __launch_bounds__(256) void ttm_batch_kernel(TtmBatch b) {
 constexpr int kResidentLds = 128 * 1024;
 constexpr int kResWaves = 8;
 
-// Raw operand data of one 16-row block for one lane: 4 reduction rows of its
-// column.  VEC (L = 1, J % 4 == 0, Y 16-byte aligned): the 4 consecutive rows
-// are one 16-byte load (two for doubles).
-template <typename TI>
-struct Raw4 {
-  TI v[4];
-};
-
-// Issues the loads of block jb without any condition: the row and column are
-// clamped into the tensor, and use4() masks what lies outside.  (A load under
-// a condition, or converted right after it, would have to complete at once.)
-template <typename TI, bool UNIT_L, bool VEC>
-__device__ __forceinline__ void issue4(const TI* __restrict__ Y, int64_t cbase, int J, uint32_t L, int jb, int q,
-                                       Raw4<TI>& r) {
-  if constexpr (VEC) {
-    const int j = min(16 * jb + 4 * q, J - 4);
-    const TI* src = Y + cbase + j;
-    if constexpr (sizeof(TI) == 4) {
-      const float4 f = *reinterpret_cast<const float4*>(src);
-      r.v[0] = f.x;
-      r.v[1] = f.y;
-      r.v[2] = f.z;
-      r.v[3] = f.w;
-    } else {
-      const double2 a = *reinterpret_cast<const double2*>(src);
-      const double2 b = *reinterpret_cast<const double2*>(src + 2);
-      r.v[0] = a.x;
-      r.v[1] = a.y;
-      r.v[2] = b.x;
-      r.v[3] = b.y;
-    }
-  } else {
-#pragma unroll
-    for (int s2 = 0; s2 < 4; ++s2) {
-      const int j = min(16 * jb + (UNIT_L ? 4 * q + s2 : 4 * s2 + q), J - 1);
-      r.v[s2] = Y[cbase + (UNIT_L ? (int64_t)j : (int64_t)L * j)];
-    }
-  }
-}
-
-// Converts block jb's raw data to the product type, zero outside the tensor.
-template <typename TI, typename CT, bool UNIT_L>
-__device__ __forceinline__ void use4(const Raw4<TI>& r, bool cok, int J, int jb, int q, CT (&y)[4]) {
-#pragma unroll
-  for (int s2 = 0; s2 < 4; ++s2) {
-    const int j = 16 * jb + (UNIT_L ? 4 * q + s2 : 4 * s2 + q);
-    const CT x = (CT)r.v[s2];
-    y[s2] = (cok && j < J) ? x : (CT)0;
-  }
-}
-
 // TTM with the whole factor resident in LDS (K <= 64): each wave computes
 // 16 output columns at a time, Z[0:K, cols] = M Y[:, cols], with the factor
 // rows as the MFMA A operand (from LDS) and the tensor columns as the B
@@ -275,7 +290,7 @@ __device__ __forceinline__ void use4(const Raw4<TI>& r, bool cok, int J, int jb,
 // buffer keeps its registers (no moves that would wait for a load).
 constexpr int kDepth = 3;
 
-template <typename TI, typename TO, typename CT, bool UNIT_L, int RB, bool VEC>
+template <typename TI, typename TO, typename CT, bool UNIT_L, int RB, int VW>
 __global__ __launch_bounds__(64 * kResWaves) void ttm_resident_kernel(const TI* __restrict__ Y, int J, uint32_t L,
                                                                       uint32_t cols, const double* __restrict__ M,
                                                                       int64_t msk, int64_t msj, int K,
@@ -325,7 +340,7 @@ __global__ __launch_bounds__(64 * kResWaves) void ttm_resident_kernel(const TI* 
       // fewer blocks than buffers: issue them all, then use them
 #pragma unroll
       for (int u = 0; u < kDepth - 1; ++u)
-        if (u < nj) issue4<TI, UNIT_L, VEC>(Y, cbase, J, L, u, q, raw[u]);
+        if (u < nj) issue4<TI, UNIT_L, VW>(Y, cbase, J, L, u, q, raw[u]);
 #pragma unroll
       for (int u = 0; u < kDepth - 1; ++u)
         if (u < nj) {
@@ -335,7 +350,7 @@ __global__ __launch_bounds__(64 * kResWaves) void ttm_resident_kernel(const TI* 
         }
     } else {
 #pragma unroll
-      for (int u = 0; u < kDepth; ++u) issue4<TI, UNIT_L, VEC>(Y, cbase, J, L, u, q, raw[u]);
+      for (int u = 0; u < kDepth; ++u) issue4<TI, UNIT_L, VW>(Y, cbase, J, L, u, q, raw[u]);
       // main loop: whole groups of kDepth blocks whose refills all lie inside
       // the tensor; every path issues the same loads in the same order, so each
       // use waits only for its own block
@@ -345,7 +360,7 @@ __global__ __launch_bounds__(64 * kResWaves) void ttm_resident_kernel(const TI* 
         for (int u = 0; u < kDepth; ++u) {
           CT y[4];
           use4<TI, CT, UNIT_L>(raw[u], cok, J, jb0 + u, q, y);
-          issue4<TI, UNIT_L, VEC>(Y, cbase, J, L, jb0 + u + kDepth, q, raw[u]);
+          issue4<TI, UNIT_L, VW>(Y, cbase, J, L, jb0 + u + kDepth, q, raw[u]);
           mma(jb0 + u, y);
         }
       }
@@ -355,7 +370,7 @@ __global__ __launch_bounds__(64 * kResWaves) void ttm_resident_kernel(const TI* 
         if (jb0 + u < nj) {  // uniform
           CT y[4];
           use4<TI, CT, UNIT_L>(raw[u], cok, J, jb0 + u, q, y);
-          if (jb0 + u + kDepth < nj) issue4<TI, UNIT_L, VEC>(Y, cbase, J, L, jb0 + u + kDepth, q, raw[u]);
+          if (jb0 + u + kDepth < nj) issue4<TI, UNIT_L, VW>(Y, cbase, J, L, jb0 + u + kDepth, q, raw[u]);
           mma(jb0 + u, y);
         }
       }
@@ -401,22 +416,27 @@ hipError_t launch_ttm_ct(const TI* Y, int J, uint64_t L, uint64_t cols, const do
 #define TR_LAUNCH(U, RBV, V)                                                                                   \
   hipLaunchKernelGGL((ttm_resident_kernel<TI, TO, CT, U, RBV, V>), dim3(grid), dim3(64 * kResWaves), lds,       \
                      stream, Y, J, (uint32_t)L, (uint32_t)cols, M, msk, msj, K, Z, nct)
-    const bool vec = (L == 1) && (J % 4 == 0) && (reinterpret_cast<uintptr_t>(Y) % 16 == 0);
-    if (vec) {
-      if (rbr == 1) TR_LAUNCH(true, 1, true);
-      else if (rbr == 2) TR_LAUNCH(true, 2, true);
-      else if (rbr == 3) TR_LAUNCH(true, 3, true);
-      else TR_LAUNCH(true, 4, true);
+    const int vw = y_vector_width(Y, J, L);
+    if (vw == 4) {
+      if (rbr == 1) TR_LAUNCH(true, 1, 4);
+      else if (rbr == 2) TR_LAUNCH(true, 2, 4);
+      else if (rbr == 3) TR_LAUNCH(true, 3, 4);
+      else TR_LAUNCH(true, 4, 4);
+    } else if (vw == 2) {
+      if (rbr == 1) TR_LAUNCH(true, 1, 2);
+      else if (rbr == 2) TR_LAUNCH(true, 2, 2);
+      else if (rbr == 3) TR_LAUNCH(true, 3, 2);
+      else TR_LAUNCH(true, 4, 2);
     } else if (L == 1) {
-      if (rbr == 1) TR_LAUNCH(true, 1, false);
-      else if (rbr == 2) TR_LAUNCH(true, 2, false);
-      else if (rbr == 3) TR_LAUNCH(true, 3, false);
-      else TR_LAUNCH(true, 4, false);
+      if (rbr == 1) TR_LAUNCH(true, 1, 1);
+      else if (rbr == 2) TR_LAUNCH(true, 2, 1);
+      else if (rbr == 3) TR_LAUNCH(true, 3, 1);
+      else TR_LAUNCH(true, 4, 1);
     } else {
-      if (rbr == 1) TR_LAUNCH(false, 1, false);
-      else if (rbr == 2) TR_LAUNCH(false, 2, false);
-      else if (rbr == 3) TR_LAUNCH(false, 3, false);
-      else TR_LAUNCH(false, 4, false);
+      if (rbr == 1) TR_LAUNCH(false, 1, 1);
+      else if (rbr == 2) TR_LAUNCH(false, 2, 1);
+      else if (rbr == 3) TR_LAUNCH(false, 3, 1);
+      else TR_LAUNCH(false, 4, 1);
     }
 #undef TR_LAUNCH
     return hipGetLastError();
@@ -426,19 +446,30 @@ hipError_t launch_ttm_ct(const TI* Y, int J, uint64_t L, uint64_t cols, const do
   const int64_t total = nct * nrt;
   const int64_t grid = ceil_div(total, kXcds) * kXcds;
   const int rb = (K >= kTK) ? 4 : (int)ceil_div(K, 16);
-#define TTM_LAUNCH(U, RBV)                                                                                   \
-  hipLaunchKernelGGL((ttm_kernel<TI, TO, CT, U, RBV>), dim3(grid), dim3(64 * kWaves), 0, stream, Y, J,        \
+#define TTM_LAUNCH(U, RBV, V)                                                                                \
+  hipLaunchKernelGGL((ttm_kernel<TI, TO, CT, U, RBV, V>), dim3(grid), dim3(64 * kWaves), 0, stream, Y, J,     \
                      (uint32_t)L, (uint32_t)cols, M, msk, msj, K, Z, nrt, total)
-  if (L == 1) {
-    if (rb == 1) TTM_LAUNCH(true, 1);
-    else if (rb == 2) TTM_LAUNCH(true, 2);
-    else if (rb == 3) TTM_LAUNCH(true, 3);
-    else TTM_LAUNCH(true, 4);
+  const int vw = y_vector_width(Y, J, L);
+  if (vw == 4) {
+    if (rb == 1) TTM_LAUNCH(true, 1, 4);
+    else if (rb == 2) TTM_LAUNCH(true, 2, 4);
+    else if (rb == 3) TTM_LAUNCH(true, 3, 4);
+    else TTM_LAUNCH(true, 4, 4);
+  } else if (vw == 2) {
+    if (rb == 1) TTM_LAUNCH(true, 1, 2);
+    else if (rb == 2) TTM_LAUNCH(true, 2, 2);
+    else if (rb == 3) TTM_LAUNCH(true, 3, 2);
+    else TTM_LAUNCH(true, 4, 2);
+  } else if (L == 1) {
+    if (rb == 1) TTM_LAUNCH(true, 1, 1);
+    else if (rb == 2) TTM_LAUNCH(true, 2, 1);
+    else if (rb == 3) TTM_LAUNCH(true, 3, 1);
+    else TTM_LAUNCH(true, 4, 1);
   } else {
-    if (rb == 1) TTM_LAUNCH(false, 1);
-    else if (rb == 2) TTM_LAUNCH(false, 2);
-    else if (rb == 3) TTM_LAUNCH(false, 3);
-    else TTM_LAUNCH(false, 4);
+    if (rb == 1) TTM_LAUNCH(false, 1, 1);
+    else if (rb == 2) TTM_LAUNCH(false, 2, 1);
+    else if (rb == 3) TTM_LAUNCH(false, 3, 1);
+    else TTM_LAUNCH(false, 4, 1);
   }
 #undef TTM_LAUNCH
   return hipGetLastError();

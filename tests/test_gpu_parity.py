@@ -138,6 +138,12 @@ TTM_CASES = [
     ([64, 64, 64], 2, 8),
     ([9, 5, 1, 3], 2, 4),
     ([100], 0, 130),
+    # L = 1 with J = 2 mod 4 (paired-row loads) and odd J (single rows), for
+    # the resident (K <= 64) and tiled kernels, with ragged last blocks
+    ([102, 30], 0, 40),
+    ([102, 30], 0, 70),
+    ([101, 30], 0, 70),
+    ([626, 9], 0, 130),
 ]
 
 
@@ -155,6 +161,22 @@ def test_ttm_parity(tk, orc, dims, n, K, ydt, zdt):
         Aref, _ = orc.ttm(np.abs(X.astype(np.float64)), dims, n, np.abs(M))
         tol = (1e-12 if zdt == np.float64 else 1e-6) * Aref + 1e-300
         assert np.all(np.abs(Z.cpu().numpy().reshape(-1).astype(np.float64) - Zref) <= tol)
+
+
+@pytest.mark.parametrize("dims,n,K", TTM_CASES)
+@pytest.mark.parametrize("ydt", [np.float64, np.float32])
+def test_ttm_fp32_products_parity(tk, orc, dims, n, K, ydt):
+    # products in FP32 (FP32 MFMA), accumulation in FP32: |error| <= J u32 |M||Y|
+    rng = np.random.default_rng(3 * K + n)
+    X = rng.standard_normal(int(np.prod(dims))).astype(ydt)
+    M = rng.standard_normal((K, dims[n]))
+    t_y = torch.float64 if ydt == np.float64 else torch.float32
+    Z = tk.ttm(to_dev(X, dims, t_y), n, torch.from_numpy(M).cuda(), dims=dims, out_dtype=torch.float32,
+               fp32_products=True)
+    Zref, _ = orc.ttm(X.astype(np.float64), dims, n, M)
+    Aref, _ = orc.ttm(np.abs(X.astype(np.float64)), dims, n, np.abs(M))
+    tol = (dims[n] + 2) * 2.0 ** -23 * Aref + 1e-30
+    assert np.all(np.abs(Z.cpu().numpy().reshape(-1).astype(np.float64) - Zref) <= tol)
 
 
 def _check_sthosvd(tk, orc, X, dims, eps, order, dtype=torch.float64):
