@@ -30,21 +30,35 @@ namespace {
 constexpr int kTK = 64;     // output rows per wave (4 MFMA blocks)
 constexpr int kWaves = 4;   // waves per workgroup; each owns 16 columns
 constexpr int kJB = 64;     // reduction rows per LDS block of M (4 chunks of 16)
-// LDS layout of M blocks: row stride and position of reduction index jj.
-// FP64: stride (columns) + 1.  FP32 (one bank per value): a stride of 4 modulo
-// 64, and within each 16-index chunk the two 2-bit fields of jj are swapped
-// for L = 1, so that the A-operand read of lane (i, q) at step s, chunk t
-// lands on bank 4 i + q (+ const) in both layouts: 64 distinct banks.
+// LDS layout of M blocks (row-major, padded rows).  Lane (i, q) reads the
+// A operands of its 4 MFMA steps, reduction rows 16 t + 4 q + s (s < 4), as
+// one vector of 4 consecutive values.  The row stride is 4 modulo 64 floats
+// (2 modulo 32 doubles), so that the 16 lanes i of a vector read cover 64
+// distinct banks.
 template <typename CT>
 struct MLds {
   static constexpr bool kF32 = sizeof(CT) == 4;
-  static constexpr int S = kF32 ? kJB + 4 : kJB + 1;  // tile kernel (kJB columns)
+  static constexpr int S = kF32 ? kJB + 4 : kJB + 2;  // tile kernel (kJB columns)
   // resident kernel: jp (a multiple of 16) columns
-  static __host__ __device__ __forceinline__ int ld(int jp) { return kF32 ? ((jp + 63) & ~63) + 4 : jp + 1; }
-  template <bool UNIT_L>
-  static __device__ __forceinline__ int pos(int jj) {
-    if constexpr (kF32 && UNIT_L) return (jj & ~15) | ((jj & 3) << 2) | ((jj >> 2) & 3);
-    return jj;
+  static __host__ __device__ __forceinline__ int ld(int jp) {
+    return kF32 ? ((jp + 63) & ~63) + 4 : ((jp + 31) & ~31) + 2;
+  }
+  // the 4 values at p (16-byte aligned)
+  static __device__ __forceinline__ void read4(const CT* p, CT (&a)[4]) {
+    if constexpr (kF32) {
+      const float4 v = *reinterpret_cast<const float4*>(p);
+      a[0] = v.x;
+      a[1] = v.y;
+      a[2] = v.z;
+      a[3] = v.w;
+    } else {
+      const double2 u = *reinterpret_cast<const double2*>(p);
+      const double2 w = *reinterpret_cast<const double2*>(p + 2);
+      a[0] = u.x;
+      a[1] = u.y;
+      a[2] = w.x;
+      a[3] = w.y;
+    }
   }
 };
 
@@ -124,7 +138,7 @@ __device__ __forceinline__ void issue4(const TI* __restrict__ Y, int64_t cbase, 
   } else {
 #pragma unroll
     for (int s2 = 0; s2 < 4; ++s2) {
-      const int j = min(16 * jb + (UNIT_L ? 4 * q + s2 : 4 * s2 + q), J - 1);
+      const int j = min(16 * jb + 4 * q + s2, J - 1);
       r.v[s2] = Y[cbase + (UNIT_L ? (int64_t)j : (int64_t)L * j)];
     }
   }
@@ -147,7 +161,7 @@ template <typename TI, typename CT, bool UNIT_L>
 __device__ __forceinline__ void use4(const Raw4<TI>& r, bool cok, int J, int jb, int q, CT (&y)[4]) {
 #pragma unroll
   for (int s2 = 0; s2 < 4; ++s2) {
-    const int j = 16 * jb + (UNIT_L ? 4 * q + s2 : 4 * s2 + q);
+    const int j = 16 * jb + 4 * q + s2;
     const CT x = (CT)r.v[s2];
     y[s2] = (cok && j < J) ? x : (CT)0;
   }
@@ -164,7 +178,7 @@ __device__ __forceinline__ void ttm_tile(const TI* __restrict__ Y, int J, uint32
                                          TO* __restrict__ Z, int64_t ct, int rt) {
   using A = Acc<CT>;
   using ML = MLds<CT>;
-  __shared__ CT sM[kTK * ML::S];  // M block: 64 output rows x 64 reduction rows
+  __shared__ __align__(16) CT sM[kTK * ML::S];  // M block: 64 output rows x 64 reduction rows
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t c0 = (ct * kWaves + wave) * 16;  // this wave's first column
   const int k0 = rt * kTK;
@@ -189,9 +203,9 @@ __device__ __forceinline__ void ttm_tile(const TI* __restrict__ Y, int J, uint32
   for (int b = 0; b < RB; ++b) acc[b] = typename A::type{0, 0, 0, 0};
 
   for (int jb = 0; jb < J; jb += kJB) {
-    // Y operands of the four 16-row chunks of this block (row of (chunk t, step s)
-    // is jb + 16 t + 4 q + s for L = 1 and jb + 16 t + 4 s + q otherwise),
-    // loaded without condition and masked where they are used (issue4, use4)
+    // Y operands of the four 16-row chunks of this block (row of (chunk t,
+    // step s): jb + 16 t + 4 q + s), loaded without condition and masked where
+    // they are used (issue4, use4)
     Raw4<TI> raw[4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) issue4<TI, UNIT_L, VW>(Y, cbase, J, L, jb / 16 + t, q, raw[t]);
@@ -200,8 +214,7 @@ __device__ __forceinline__ void ttm_tile(const TI* __restrict__ Y, int J, uint32
     for (int e = tid; e < 16 * RB * kJB; e += 256) {
       const int kk = e / kJB, jj = e - kk * kJB;
       const int k = k0 + kk, j = jb + jj;
-      sM[kk * ML::S + ML::template pos<UNIT_L>(jj)] =
-          (k < K && j < J) ? (CT)M[(int64_t)k * msk + (int64_t)j * msj] : (CT)0;
+      sM[kk * ML::S + jj] = (k < K && j < J) ? (CT)M[(int64_t)k * msk + (int64_t)j * msj] : (CT)0;
     }
     __syncthreads();
 #pragma unroll
@@ -209,11 +222,11 @@ __device__ __forceinline__ void ttm_tile(const TI* __restrict__ Y, int J, uint32
       CT y[4];
       use4<TI, CT, UNIT_L>(raw[t], cok, J, jb / 16 + t, q, y);
 #pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        const int jj = 16 * t + (UNIT_L ? 4 * q + s : 4 * s + q);
+      for (int b = 0; b < RB; ++b) {
+        CT a4[4];
+        ML::read4(&sM[(16 * b + i) * ML::S + 16 * t + 4 * q], a4);
 #pragma unroll
-        for (int b = 0; b < RB; ++b)
-          acc[b] = A::mfma(sM[(16 * b + i) * ML::S + ML::template pos<UNIT_L>(jj)], y[s], acc[b]);
+        for (int s = 0; s < 4; ++s) acc[b] = A::mfma(a4[s], y[s], acc[b]);
       }
     }
   }
@@ -296,7 +309,7 @@ __global__ __launch_bounds__(64 * kResWaves) void ttm_resident_kernel(const TI* 
                                                                       int64_t msk, int64_t msj, int K,
                                                                       TO* __restrict__ Z, int64_t nct) {
   using A = Acc<CT>;
-  extern __shared__ unsigned char smem[];
+  extern __shared__ __align__(16) unsigned char smem[];
   const int nj = (J + 15) / 16;
   const int jp = 16 * nj;        // reduction rows padded to whole MFMA blocks (zeros)
   using ML = MLds<CT>;
@@ -305,7 +318,7 @@ __global__ __launch_bounds__(64 * kResWaves) void ttm_resident_kernel(const TI* 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   for (int e = tid; e < 16 * RB * jp; e += 64 * kResWaves) {
     const int k = e / jp, j = e - k * jp;
-    sM[k * ldm + ML::template pos<UNIT_L>(j)] = (k < K && j < J) ? (CT)M[(int64_t)k * msk + (int64_t)j * msj] : (CT)0;
+    sM[k * ldm + j] = (k < K && j < J) ? (CT)M[(int64_t)k * msk + (int64_t)j * msj] : (CT)0;
   }
   __syncthreads();
   const int q = lane >> 4, i = lane & 15;
@@ -325,15 +338,15 @@ __global__ __launch_bounds__(64 * kResWaves) void ttm_resident_kernel(const TI* 
     typename A::type acc[RB];
 #pragma unroll
     for (int b = 0; b < RB; ++b) acc[b] = typename A::type{0, 0, 0, 0};
-    // reduction row of (block jb, step s) for this lane: 16 jb + (UNIT_L ? 4q + s : 4s + q)
+    // reduction row of (block jb, step s) for this lane: 16 jb + 4 q + s
     Raw4<TI> raw[kDepth];
     auto mma = [&](int jb, const CT (&y)[4]) {
 #pragma unroll
-      for (int s2 = 0; s2 < 4; ++s2) {
-        const int jj = 16 * jb + (UNIT_L ? 4 * q + s2 : 4 * s2 + q);
+      for (int b = 0; b < RB; ++b) {
+        CT a4[4];
+        ML::read4(&sM[(16 * b + i) * ldm + 16 * jb + 4 * q], a4);
 #pragma unroll
-        for (int b = 0; b < RB; ++b)
-          acc[b] = A::mfma(sM[(16 * b + i) * ldm + ML::template pos<UNIT_L>(jj)], y[s2], acc[b]);
+        for (int s2 = 0; s2 < 4; ++s2) acc[b] = A::mfma(a4[s2], y[s2], acc[b]);
       }
     };
     if (nj < kDepth) {
