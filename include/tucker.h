@@ -96,7 +96,8 @@ typedef struct tucker_t tucker_t; /* opaque result handle */
  *              ranks; release it with tucker_free.
  * Errors: EINVAL for bad arguments or non-finite ||X||^2; ENOMEM; EHIP;
  *         ENOCONV if the eigensolver exceeded its iteration cap.
- * Synchronises `stream` once per mode to read back the rank R_n. */
+ * Waits once per mode for the rank R_n, which is read back while that mode's
+ * eigenvectors are being formed, and synchronises `stream` before returning. */
 tucker_status tucker_sthosvd(const void* data, tucker_dtype dtype, const int64_t* dims, int N,
                              double eps, const int* mode_order, tucker_gram_prec prec,
                              hipStream_t stream, tucker_t** out);

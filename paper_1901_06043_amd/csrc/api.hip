@@ -424,6 +424,12 @@ tucker_status tucker_sthosvd(const void* data, tucker_dtype dtype, const int64_t
 
   Events evs;
   HIP_TRY(evs.create(5 * N));
+  hipEvent_t rank_ready = nullptr;
+  HIP_TRY(hipEventCreateWithFlags(&rank_ready, hipEventDisableTiming));
+  struct EventGuard {
+    hipEvent_t e;
+    ~EventGuard() { (void)hipEventDestroy(e); }
+  } rank_ready_guard{rank_ready};
 
   int64_t cur[TUCKER_MAX_MODES];
   std::memcpy(cur, dims, sizeof(int64_t) * N);
@@ -455,14 +461,18 @@ tucker_status tucker_sthosvd(const void* data, tucker_dtype dtype, const int64_t
       if ((st = run_gram(Y, ydt, cur, N, n, pp, Sbuf.as<double>(), sqp, stream, ev[4]))) return st;
       if (pp != TUCKER_GRAM_FP64) HIP_TRY(tk::launch_gram_guard(Sbuf.as<double>(), (int)J, sqp, d_flag + step, stream));
       HIP_TRY(hipEventRecord(ev[1], stream));
-      HIP_TRY(tk::launch_eig_truncate(Sbuf.as<double>(), (int)J, thr_mul, d_nx2, nullptr, w, t->lam[n],
-                                      t->U[n], t->dranks + n, d_disc + n, stream));
-      HIP_TRY(hipEventRecord(ev[2], stream));
+      HIP_TRY(tk::launch_eig_values(Sbuf.as<double>(), (int)J, thr_mul, d_nx2, nullptr, w, t->lam[n],
+                                    t->dranks + n, d_disc + n, stream));
+      // the rank (and flag, norm) go to the host while the eigenvectors are formed,
+      // so that the next launches are enqueued before the GPU runs out of work
       HIP_TRY(hipMemcpyAsync(h_R, t->dranks + n, sizeof(int64_t), hipMemcpyDeviceToHost, stream));
       if (pp != TUCKER_GRAM_FP64)
         HIP_TRY(hipMemcpyAsync(h_flag, d_flag + step, sizeof(double), hipMemcpyDeviceToHost, stream));
       if (step == 0) HIP_TRY(hipMemcpyAsync(h_nx2, d_nx2, sizeof(double), hipMemcpyDeviceToHost, stream));
-      HIP_TRY(hipStreamSynchronize(stream));
+      HIP_TRY(hipEventRecord(rank_ready, stream));
+      HIP_TRY(tk::launch_eig_vectors((int)J, w, t->lam[n], t->dranks + n, t->U[n], stream));
+      HIP_TRY(hipEventRecord(ev[2], stream));
+      HIP_TRY(hipEventSynchronize(rank_ready));
       if (pp == TUCKER_GRAM_FP64 || h_flag[0] == 0.0) break;
       t->prec_used[n] = TUCKER_GRAM_FP64;
     }

@@ -1397,9 +1397,8 @@ void eig_work_carve(double* base, int64_t J, EigWork& w) {
   w.scal = w.tau + J;
 }
 
-hipError_t launch_eig_truncate(const double* S, int J, double thr, const double* nx2, const double* trace_ref,
-                               const EigWork& w, double* lam, double* U, int64_t* R, double* disc,
-                               hipStream_t stream) {
+hipError_t launch_eig_values(const double* S, int J, double thr, const double* nx2, const double* trace_ref,
+                             const EigWork& w, double* lam, int64_t* R, double* disc, hipStream_t stream) {
   {
     const double* src = S;
     int ld = J, k0 = 0;
@@ -1449,7 +1448,11 @@ hipError_t launch_eig_truncate(const double* S, int J, double thr, const double*
   LAUNCH_OK();
   hipLaunchKernelGGL(eig_truncate_kernel, dim3(1), dim3(64), sizeof(double) * (size_t)J, stream, lam, J, thr, nx2,
                      trace_ref, R, disc);
-  LAUNCH_OK();
+  return hipGetLastError();
+}
+
+hipError_t launch_eig_vectors(int J, const EigWork& w, const double* lam, const int64_t* R, double* U,
+                              hipStream_t stream) {
   {
     const int nvw = invit_vectors_per_group(J);
     const size_t shi = sizeof(double) * kInvitArrays * (size_t)J * nvw;
@@ -1468,6 +1471,13 @@ hipError_t launch_eig_truncate(const double* S, int J, double thr, const double*
   else if (q <= 11) launch_back<11>(w, J, R, U, stream);
   else launch_back<16>(w, J, R, U, stream);
   return hipGetLastError();
+}
+
+hipError_t launch_eig_truncate(const double* S, int J, double thr, const double* nx2, const double* trace_ref,
+                               const EigWork& w, double* lam, double* U, int64_t* R, double* disc,
+                               hipStream_t stream) {
+  const hipError_t e = launch_eig_values(S, J, thr, nx2, trace_ref, w, lam, R, disc, stream);
+  return e != hipSuccess ? e : launch_eig_vectors(J, w, lam, R, U, stream);
 }
 
 hipError_t launch_eig_truncate_batched(const EigBatch& b, double thr_mul, hipStream_t stream) {

@@ -92,6 +92,14 @@ void eig_work_carve(double* base, int64_t J, EigWork& w);
 hipError_t launch_eig_truncate(const double* S, int J, double thr, const double* nx2, const double* trace_ref,
                                const EigWork& w, double* lam, double* U, int64_t* R, double* disc,
                                hipStream_t stream);
+// The same in two parts, so that R can be read back while the eigenvectors
+// are being formed: the eigenvalues and the truncation (lam, R, disc; steps
+// 1-3), then the leading R eigenvectors (U; steps 4-6), which only read w,
+// lam and R.
+hipError_t launch_eig_values(const double* S, int J, double thr, const double* nx2, const double* trace_ref,
+                             const EigWork& w, double* lam, int64_t* R, double* disc, hipStream_t stream);
+hipError_t launch_eig_vectors(int J, const EigWork& w, const double* lam, const int64_t* R, double* U,
+                              hipStream_t stream);
 
 // ---------------------------------------------------------------- batched form
 // `count` independent matrices; matrix m has size J[m] (device; 0 = none),
