@@ -14,8 +14,8 @@
 //     from registers, with look-ahead (the owner of the next row publishes it
 //     and its reflector scalars during the update).  Larger matrices first
 //     take steps of two launches each over row blocks in global memory.
-//  2. All eigenvalues of T by Sturm-count multisection: one wave per
-//     eigenvalue tests 64 interior points at once; many workgroups.
+//  2. All eigenvalues of T by Sturm-count multisection: one workgroup per
+//     eigenvalue tests 256 interior points at once; many workgroups.
 //  3. Truncation: tail sums of the clamped eigenvalues from the smallest upward.
 //  4. Leading R eigenvectors of T by two steps of inverse iteration
 //     (tridiagonal LU with partial pivoting, factors in LDS), one thread per
@@ -507,10 +507,10 @@ __device__ __forceinline__ int sturm_count(const double* sd, const double* se2, 
   return cnt;
 }
 
-// 256 threads, LANES per eigenvalue (LANES interior points per round): the
-// single-matrix form takes a wave per eigenvalue (fewer, latency-bound rounds),
-// the batched form 32 lanes (less work in total, throughput-bound).
-constexpr int kBisLanes = 64;
+// 256 threads, LANES per eigenvalue (LANES interior points per round), used
+// by the batched form with 32 lanes (less work in total, throughput-bound);
+// the single-matrix form takes a whole workgroup per eigenvalue (fewer,
+// latency-bound rounds; eig_bisect_wide_kernel).
 constexpr int kBisLanesBatched = 32;
 template <int LANES>
 __device__ __forceinline__ void bisect_body(const double* __restrict__ d, const double* __restrict__ e, int J,
@@ -544,10 +544,45 @@ __device__ __forceinline__ void bisect_body(const double* __restrict__ d, const 
   if (q == 0) lam[J - 1 - a] = 0.5 * (lo + hi);
 }
 
-__global__ __launch_bounds__(256) void eig_bisect_kernel(const double* __restrict__ d, const double* __restrict__ e,
-                                                         int J, double* __restrict__ lam,
-                                                         double* __restrict__ scal) {
-  bisect_body<kBisLanes>(d, e, J, lam, scal, blockIdx.x);
+// Single-matrix form with a whole workgroup per eigenvalue: its 256 threads
+// test 256 interior points per round (257 subintervals instead of 65, so
+// about 7 rounds instead of 9 reach the tolerance); the waves' ballots are
+// combined through LDS.  Every thread holds the same interval (the same
+// fixed-order data), so the loop is uniform over the workgroup.
+__global__ __launch_bounds__(256) void eig_bisect_wide_kernel(const double* __restrict__ d,
+                                                              const double* __restrict__ e, int J,
+                                                              double* __restrict__ lam, double* __restrict__ scal) {
+  extern __shared__ double sh[];
+  double* sd = sh;            // J
+  double* se2 = sh + J;       // J
+  double* sred = sh + 2 * J;  // 4
+  __shared__ uint64_t sbal[4];
+  const TriBounds b = tri_bounds(d, e, J, sd, se2, sred);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int a = blockIdx.x;  // ascending index
+  if (a == 0 && tid == 0) {
+    scal[0] = b.tnorm;
+    scal[1] = b.pivmin;
+  }
+  double lo = b.glo, hi = b.ghi;
+  for (int it = 0; it < 64 && (hi - lo) > b.atol; ++it) {
+    const double h = (hi - lo) / 257.0;
+    const double sig = lo + h * (tid + 1);
+    const int cnt = sturm_count(sd, se2, J, sig, b.pivmin);
+    const uint64_t bal = __ballot(cnt > a);
+    if (lane == 0) sbal[wave] = bal;
+    __syncthreads();
+    int f = 256;  // first point with more than a eigenvalues below it
+#pragma unroll
+    for (int w = 3; w >= 0; --w)
+      if (sbal[w]) f = 64 * w + __ffsll((long long)sbal[w]) - 1;
+    __syncthreads();  // every thread has read sbal before the next round
+    const double nlo = (f == 0) ? lo : lo + h * f;
+    const double nhi = (f == 256) ? hi : lo + h * (f + 1);
+    lo = nlo;
+    hi = nhi;
+  }
+  if (tid == 0) lam[J - 1 - a] = 0.5 * (lo + hi);
 }
 
 // ---------------------------------------------------------------- 3. truncation
@@ -1443,8 +1478,7 @@ hipError_t launch_eig_values(const double* S, int J, double thr, const double* n
     }
   }
   const size_t shb = sizeof(double) * (2 * (size_t)J + 4);
-  hipLaunchKernelGGL(eig_bisect_kernel, dim3(ceil_div(J, 256 / kBisLanes)), dim3(256), shb, stream, w.d, w.e, J,
-                     lam, w.scal);
+  hipLaunchKernelGGL(eig_bisect_wide_kernel, dim3(J), dim3(256), shb, stream, w.d, w.e, J, lam, w.scal);
   LAUNCH_OK();
   hipLaunchKernelGGL(eig_truncate_kernel, dim3(1), dim3(64), sizeof(double) * (size_t)J, stream, lam, J, thr, nx2,
                      trace_ref, R, disc);
