@@ -115,7 +115,7 @@ __device__ __forceinline__ void put(typename Cfg<PREC>::elem* s, int plane_strid
 // PAIR: rows are the 128-row tiles of a pair (NR = 128 or 256, a power of two),
 // so the loader's (row, column) of each value follows from the thread index
 // with shifts instead of per-value index registers.
-template <typename T, int PREC, int ROWS, int NBW, bool SHARED_A, bool UNIT_L, bool PAIR>
+template <typename T, int PREC, int ROWS, int NBW, bool SHARED_A, bool UNIT_L, bool PAIR, bool UNC = false>
 struct GramItem {
   using C = Cfg<PREC>;
   using E_t = typename C::elem;
@@ -151,10 +151,11 @@ struct GramItem {
   // tensor (none when chv is false); store() zeroes the others.  kUncond: the
   // loads are issued without any condition (row and column clamped into the
   // tensor), since a load under a condition makes the waits before the next
-  // loads conservative and undoes the two-chunk lead of the loads.  That is
-  // measured faster for the FP32 pair kernel only (which then also spills far
-  // less); the other kernels keep loads under the bounds condition.
-  static constexpr bool kUncond = (PREC == 1 && PAIR);
+  // loads conservative and undoes the two-chunk lead of the loads.  It is
+  // chosen at launch where it measured faster: the FP32 pair kernel (which
+  // then also spills far less) and the BF16X3 pair kernel for more than two
+  // row tiles; the other kernels keep loads under the bounds condition.
+  static constexpr bool kUncond = UNC;
   __device__ __forceinline__ uint32_t load(T (&rv)[E], int64_t ch, bool chv) const {
     uint32_t vm = 0;
 #pragma unroll
@@ -311,10 +312,10 @@ struct BodyArgs {
   double* sqo;
 };
 
-template <typename T, int PREC, int ROWS, int NBW, bool SHARED_A, bool UNIT_L, bool PAIR>
+template <typename T, int PREC, int ROWS, int NBW, bool SHARED_A, bool UNIT_L, bool PAIR, bool UNC = false>
 __device__ __forceinline__ void gram_body(const BodyArgs& g, bool diag, int ra, int rb, int NR, int nbl,
                                           typename Cfg<PREC>::elem* sY, double* sred) {
-  using W = GramItem<T, PREC, ROWS, NBW, SHARED_A, UNIT_L, PAIR>;
+  using W = GramItem<T, PREC, ROWS, NBW, SHARED_A, UNIT_L, PAIR, UNC>;
   constexpr int E = W::E, KC = W::KC, LR = W::LR;
   W w;
   const int tid = threadIdx.x, lane = tid & 63;
@@ -475,7 +476,8 @@ __global__ __launch_bounds__(kNT) void gram_mp_tri_kernel(MPParams g) {
 }
 
 // Pair mode: J > 128, items (split, tile pair) placed split-major on XCDs.
-template <typename T, int PREC, bool UNIT_L>
+// UNC: unconditional loads (GramItem::kUncond).
+template <typename T, int PREC, bool UNIT_L, bool UNC>
 __global__ __launch_bounds__(kNT) void gram_mp_pair_kernel(MPParams g) {
   using C = Cfg<PREC>;
   __shared__ typename C::elem sY[2 * C::PLANES * 256 * C::LR];
@@ -489,9 +491,9 @@ __global__ __launch_bounds__(kNT) void gram_mp_pair_kernel(MPParams g) {
   const BodyArgs a{g.Y, g.J, g.L, g.K, split, g.nsplit, (g.nchunks - split + g.nsplit - 1) / g.nsplit,
                    g.part + item * (int64_t)g.nblk * 256, g.sq ? g.sq + item : nullptr};
   if (ta == tb)
-    gram_body<T, PREC, 256, 5, false, UNIT_L, true>(a, true, 128 * ta, 128 * ta, 128, 8, sY, sred);
+    gram_body<T, PREC, 256, 5, false, UNIT_L, true, UNC>(a, true, 128 * ta, 128 * ta, 128, 8, sY, sred);
   else
-    gram_body<T, PREC, 256, 8, true, UNIT_L, true>(a, false, 128 * ta, 128 * tb, 256, 8, sY, sred);
+    gram_body<T, PREC, 256, 8, true, UNIT_L, true, UNC>(a, false, 128 * ta, 128 * tb, 256, 8, sY, sred);
 }
 
 // Sum the partial blocks of all splits in a fixed order; write both triangles.
@@ -625,8 +627,21 @@ void launch_main(const MPParams& g, bool tri, bool unit, int64_t grid, hipStream
     else TRI_L(5);
 #undef TRI_L
   } else {
-    if (unit) hipLaunchKernelGGL((gram_mp_pair_kernel<T, PREC, true>), dim3(grid), dim3(kNT), 0, s, g);
-    else hipLaunchKernelGGL((gram_mp_pair_kernel<T, PREC, false>), dim3(grid), dim3(kNT), 0, s, g);
+#define PAIR_L(UNC)                                                                                              \
+  do {                                                                                                           \
+    if (unit) hipLaunchKernelGGL((gram_mp_pair_kernel<T, PREC, true, UNC>), dim3(grid), dim3(kNT), 0, s, g);     \
+    else hipLaunchKernelGGL((gram_mp_pair_kernel<T, PREC, false, UNC>), dim3(grid), dim3(kNT), 0, s, g);         \
+  } while (0)
+    // unconditional loads where they measured faster (GramItem::kUncond)
+    if constexpr (PREC == 1) {
+      PAIR_L(true);
+    } else if constexpr (PREC == 2) {
+      if (g.ntiles > 2) PAIR_L(true);
+      else PAIR_L(false);
+    } else {
+      PAIR_L(false);
+    }
+#undef PAIR_L
   }
 }
 

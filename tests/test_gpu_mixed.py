@@ -49,6 +49,7 @@ MP_SHAPES = [
     ([1, 7, 1, 5], [0, 1, 2, 3]),
     ([256, 65], [0, 1]),
     ([128, 300], [0, 1]),
+    ([520, 40], [0]),  # L = 1 pair mode with five row tiles, the last one ragged
     ([5], [0]),
 ]
 
