@@ -103,6 +103,51 @@ hipError_t dev_alloc(void** out, size_t bytes, hipStream_t s) {
       return hipSuccess;
     }
   }
+  // Make room first: when the device has less than the request (plus 1 GiB)
+  // free, an idle block of this stream of any larger size is reused, else
+  // idle cached blocks of this device go back to HIP, largest first, until the
+  // request would fit.  (Failing allocations, and returning every cached
+  // block, are much slower than freeing one or two large blocks.)
+  {
+    size_t fr = 0, tot = 0;
+    const size_t want = bytes + (size_t(1) << 30);
+    if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
+      (void)hipGetLastError();  // no figure: hipMalloc decides below
+    } else if (fr < want) {
+      std::vector<void*> drop;
+      {
+        std::lock_guard<std::mutex> lk(g_cache_mu);
+        // a larger idle block of this stream is taken whole rather than freed
+        // (fresh device memory is expensive to map)
+        int best = -1;
+        for (int i = 0; i < (int)g_cache_free.size(); ++i) {
+          const CachedBlock& b = g_cache_free[i];
+          if (b.dev != dev || b.stream != s || b.bytes < bytes) continue;
+          if (best < 0 || b.bytes < g_cache_free[best].bytes) best = i;
+        }
+        if (best >= 0) {
+          *out = g_cache_free[best].p;
+          g_cache_live.push_back({*out, g_cache_free[best].bytes});
+          g_cache_free.erase(g_cache_free.begin() + best);
+          return hipSuccess;
+        }
+        size_t got = 0;
+        while (fr + got < want) {
+          int big = -1;
+          for (int i = 0; i < (int)g_cache_free.size(); ++i)
+            if (g_cache_free[i].dev == dev && (big < 0 || g_cache_free[i].bytes > g_cache_free[big].bytes)) big = i;
+          if (big < 0) break;
+          got += g_cache_free[big].bytes;
+          drop.push_back(g_cache_free[big].p);
+          g_cache_free.erase(g_cache_free.begin() + big);
+        }
+      }
+      if (!drop.empty()) {
+        (void)hipDeviceSynchronize();  // the blocks may still be read by work in flight
+        for (void* p : drop) (void)hipFree(p);
+      }
+    }
+  }
   e = hipMalloc(out, bytes);
   if (e == hipErrorOutOfMemory) {
     // give idle cached blocks of this device back and retry once
