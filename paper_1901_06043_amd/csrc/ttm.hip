@@ -28,7 +28,14 @@ namespace tk {
 namespace {
 
 constexpr int kTK = 64;     // output rows per wave (4 MFMA blocks)
-constexpr int kWaves = 4;   // waves per workgroup; each owns 16 columns
+constexpr int kWaves = 4;   // waves per workgroup; each owns 16 CG columns
+// column groups of 16 per wave in ttm_kernel: two with FP32 products and
+// L = 1, else one (FP64 accumulators and operands would halve the occupancy,
+// and L > 1 measured slower with two); the batched form uses one
+template <typename CT, bool UNIT_L>
+constexpr int tile_cg() {
+  return (sizeof(CT) == 4 && UNIT_L) ? 2 : 1;
+}
 constexpr int kJB = 64;     // reduction rows per LDS block of M (4 chunks of 16)
 // LDS layout of M blocks (row-major, padded rows).  Lane (i, q) reads the
 // A operands of its 4 MFMA steps, reduction rows 16 t + 4 q + s (s < 4), as
@@ -170,9 +177,11 @@ __device__ __forceinline__ void use4(const Raw4<TI>& r, bool cok, int J, int jb,
 // CT: arithmetic type of the products (double: FP64 MFMA; float: FP32 MFMA).
 // RB: 16-row output blocks per wave (1..4), chosen from K at launch.
 // VW: vector width of the Y loads (as in issue4).
+// CG: column groups of 16 per wave; the A operand read from LDS serves all
+// of them, and the M block staged per workgroup is shared by 64 CG columns.
 // One workgroup tile: output rows [64 rt, 64 rt + 16 RB) and columns
-// [64 ct, 64 ct + 64) (16 per wave).
-template <typename TI, typename TO, typename CT, bool UNIT_L, int RB, int VW>
+// [64 CG ct, 64 CG (ct + 1)) (16 CG per wave).
+template <typename TI, typename TO, typename CT, bool UNIT_L, int RB, int VW, int CG>
 __device__ __forceinline__ void ttm_tile(const TI* __restrict__ Y, int J, uint32_t L, uint32_t cols,
                                          const double* __restrict__ M, int64_t msk, int64_t msj, int K,
                                          TO* __restrict__ Z, int64_t ct, int rt) {
@@ -180,35 +189,43 @@ __device__ __forceinline__ void ttm_tile(const TI* __restrict__ Y, int J, uint32
   using ML = MLds<CT>;
   __shared__ __align__(16) CT sM[kTK * ML::S];  // M block: 64 output rows x 64 reduction rows
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int64_t c0 = (ct * kWaves + wave) * 16;  // this wave's first column
+  const int64_t c0 = (ct * kWaves + wave) * 16 * CG;  // this wave's first column
   const int k0 = rt * kTK;
   const int q = lane >> 4, i = lane & 15;
   const int64_t JL = (int64_t)J * L;
 
-  // the column this lane reads (B operand: column c0 + i; clamped into the
-  // tensor for the addresses, masked where it lies beyond)
-  const int64_t c = c0 + i;
-  const bool cok = c < (int64_t)cols;
-  const int64_t ca = cok ? c : (int64_t)cols - 1;
-  int64_t cbase;
-  if constexpr (UNIT_L) {
-    cbase = (int64_t)J * ca;
-  } else {
-    const uint32_t cc = (uint32_t)ca;
-    const uint32_t r = cc / L, l = cc - r * L;
-    cbase = (int64_t)l + JL * r;
-  }
-  typename A::type acc[RB];
+  // the columns this lane reads (B operands: columns c0 + 16 g + i; clamped
+  // into the tensor for the addresses, masked where they lie beyond)
+  bool cok[CG];
+  int64_t cbase[CG];
 #pragma unroll
-  for (int b = 0; b < RB; ++b) acc[b] = typename A::type{0, 0, 0, 0};
+  for (int g = 0; g < CG; ++g) {
+    const int64_t c = c0 + 16 * g + i;
+    cok[g] = c < (int64_t)cols;
+    const int64_t ca = cok[g] ? c : (int64_t)cols - 1;
+    if constexpr (UNIT_L) {
+      cbase[g] = (int64_t)J * ca;
+    } else {
+      const uint32_t cc = (uint32_t)ca;
+      const uint32_t r = cc / L, l = cc - r * L;
+      cbase[g] = (int64_t)l + JL * r;
+    }
+  }
+  typename A::type acc[CG][RB];
+#pragma unroll
+  for (int g = 0; g < CG; ++g)
+#pragma unroll
+    for (int b = 0; b < RB; ++b) acc[g][b] = typename A::type{0, 0, 0, 0};
 
   for (int jb = 0; jb < J; jb += kJB) {
     // Y operands of the four 16-row chunks of this block (row of (chunk t,
     // step s): jb + 16 t + 4 q + s), loaded without condition and masked where
     // they are used (issue4, use4)
-    Raw4<TI> raw[4];
+    Raw4<TI> raw[CG][4];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) issue4<TI, UNIT_L, VW>(Y, cbase, J, L, jb / 16 + t, q, raw[t]);
+    for (int g = 0; g < CG; ++g)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) issue4<TI, UNIT_L, VW>(Y, cbase[g], J, L, jb / 16 + t, q, raw[g][t]);
     // M block into LDS: sM[k][j] = M(k0 + k, jb + j)
     __syncthreads();
     for (int e = tid; e < 16 * RB * kJB; e += 256) {
@@ -219,38 +236,45 @@ __device__ __forceinline__ void ttm_tile(const TI* __restrict__ Y, int J, uint32
     __syncthreads();
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-      CT y[4];
-      use4<TI, CT, UNIT_L>(raw[t], cok, J, jb / 16 + t, q, y);
+      CT y[CG][4];
+#pragma unroll
+      for (int g = 0; g < CG; ++g) use4<TI, CT, UNIT_L>(raw[g][t], cok[g], J, jb / 16 + t, q, y[g]);
 #pragma unroll
       for (int b = 0; b < RB; ++b) {
         CT a4[4];
-        ML::read4(&sM[(16 * b + i) * ML::S + 16 * t + 4 * q], a4);
+        ML::read4(&sM[(16 * b + i) * ML::S + 16 * t + 4 * q], a4);  // shared by the column groups
 #pragma unroll
-        for (int s = 0; s < 4; ++s) acc[b] = A::mfma(a4[s], y[s], acc[b]);
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+          for (int g = 0; g < CG; ++g) acc[g][b] = A::mfma(a4[s], y[g][s], acc[g][b]);
       }
     }
   }
 
-  // output row k0 + 16 b + A::row(l >> 4, v), output column c0 + (l & 15)
-  if (!cok) return;
-  int64_t zb;
-  int64_t kstride;
-  if constexpr (UNIT_L) {
-    zb = (int64_t)K * c;
-    kstride = 1;
-  } else {
-    const uint32_t cc = (uint32_t)c;
-    const uint32_t r = cc / L, l = cc - r * L;
-    zb = (int64_t)l + (int64_t)L * K * r;
-    kstride = L;
-  }
+  // output row k0 + 16 b + A::row(l >> 4, v), output column c0 + 16 g + (l & 15)
 #pragma unroll
-  for (int b = 0; b < RB; ++b)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int k = k0 + 16 * b + A::row(q, v);
-      if (k < K) store_as(&Z[zb + kstride * k], (double)acc[b][v]);
+  for (int g = 0; g < CG; ++g) {
+    if (!cok[g]) continue;
+    const int64_t c = c0 + 16 * g + i;
+    int64_t zb;
+    int64_t kstride;
+    if constexpr (UNIT_L) {
+      zb = (int64_t)K * c;
+      kstride = 1;
+    } else {
+      const uint32_t cc = (uint32_t)c;
+      const uint32_t r = cc / L, l = cc - r * L;
+      zb = (int64_t)l + (int64_t)L * K * r;
+      kstride = L;
     }
+#pragma unroll
+    for (int b = 0; b < RB; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int k = k0 + 16 * b + A::row(q, v);
+        if (k < K) store_as(&Z[zb + kstride * k], (double)acc[g][b][v]);
+      }
+  }
 }
 
 template <typename TI, typename TO, typename CT, bool UNIT_L, int RB, int VW>
@@ -259,7 +283,8 @@ __global__ __launch_bounds__(256) void ttm_kernel(const TI* __restrict__ Y, int 
                                                   TO* __restrict__ Z, int nrt, int64_t total) {
   const int64_t item = xcd_remap(blockIdx.x, gridDim.x, total);
   if (item < 0) return;
-  ttm_tile<TI, TO, CT, UNIT_L, RB, VW>(Y, J, L, cols, M, msk, msj, K, Z, item / nrt, (int)(item % nrt));
+  ttm_tile<TI, TO, CT, UNIT_L, RB, VW, tile_cg<CT, UNIT_L>()>(Y, J, L, cols, M, msk, msj, K, Z, item / nrt,
+                                                            (int)(item % nrt));
 }
 
 // Batched form: item i covers column tiles [ct0, ct1) of tensor t (planned
@@ -284,7 +309,7 @@ __global__ __launch_bounds__(256) void ttm_batch_kernel(TtmBatch b) {
   const double* U = b.U + (int64_t)t * b.Jmax * b.Jmax;
   for (int64_t ct = d[1]; ct < ct1; ++ct)
     for (int rt = 0; rt * kTK < K; ++rt)
-      ttm_tile<TI, TO, CT, UNIT_L, 4, 1>(Y, J, (uint32_t)L, (uint32_t)cols, U, J, 1, K, Z, ct, rt);
+      ttm_tile<TI, TO, CT, UNIT_L, 4, 1, 1>(Y, J, (uint32_t)L, (uint32_t)cols, U, J, 1, K, Z, ct, rt);
 }
 
 // Resident-M variant for K <= 64 with M (K_pad x J) small enough for LDS:
@@ -455,7 +480,8 @@ hipError_t launch_ttm_ct(const TI* Y, int J, uint64_t L, uint64_t cols, const do
     return hipGetLastError();
   }
   const int nrt = (int)ceil_div(K, kTK);
-  const int64_t nct = ceil_div((int64_t)cols, 16 * kWaves);
+  const int cg = (L == 1) ? tile_cg<CT, true>() : tile_cg<CT, false>();
+  const int64_t nct = ceil_div((int64_t)cols, 16 * kWaves * cg);
   const int64_t total = nct * nrt;
   const int64_t grid = ceil_div(total, kXcds) * kXcds;
   const int rb = (K >= kTK) ? 4 : (int)ceil_div(K, 16);
