@@ -40,6 +40,8 @@ GRAM_SHAPES = [
     ([1, 7, 1, 5], [0, 1, 2, 3]),
     ([256, 65], [0, 1]),
     ([33, 2, 70], [0, 2]),
+    ([232, 40], [0, 1]),   # 120 triangle blocks: the largest per-wave block count
+    ([7, 232, 3], [1]),
     ([5], [0]),
 ]
 
