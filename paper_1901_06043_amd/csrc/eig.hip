@@ -12,8 +12,10 @@
 //     registers (each matrix row on 16 lanes of a wave), in phases of shrinking
 //     register layouts; the matrix-vector products and the rank-2 updates run
 //     from registers, with look-ahead (the owner of the next row publishes it
-//     and its reflector scalars during the update).  Larger matrices first
-//     take steps of two launches each over row blocks in global memory.
+//     and its reflector scalars during the update).  The phases of at most
+//     128 rows share one launch and hand the trailing block on through LDS.
+//     Larger matrices first take steps of two launches each over row blocks
+//     in global memory.
 //  2. All eigenvalues of T by Sturm-count multisection: one workgroup per
 //     eigenvalue tests 256 interior points at once; many workgroups.
 //  3. Truncation: tail sums of the clamped eigenvalues from the smallest upward.
@@ -183,10 +185,13 @@ __device__ __forceinline__ void publish_row(int kk, int J, int wave, int rs, int
   }
 }
 
-// Phase of the reduction: the matrix block S[k0.., k0..] (leading dimension
-// ld) of size J is reduced for at most `nsteps` steps; if rows remain, the
-// trailing block is written to A (leading dimension ld, same global indices)
-// for the next, smaller, phase.  d, e, tau and H use global indices.
+// Phase of the reduction: the J x J block at S (leading dimension lds) is
+// reduced for at most `nsteps` steps; if rows remain, the trailing block
+// (rows and columns >= nsteps) is written to Aout (leading dimension lda,
+// indices relative to that block) for the next, smaller, phase, which may
+// read it in place.  d, e, tau and H (leading dimension ldh) start at the
+// block's first row.  Waves numbered NW and above hold no rows: they only
+// take part in the barriers.
 // Look-ahead: during the update of step k the wave owning row k + 1 (in its
 // first live group) writes that row to LDS as soon as it is updated and
 // computes the scalars of step k + 1 from its registers, so a step starts
@@ -194,16 +199,23 @@ __device__ __forceinline__ void publish_row(int kk, int J, int wave, int rs, int
 // wave.  Columns and scalars are double-buffered by the parity of k: one
 // barrier after the matrix-vector product and one at the end of each step.
 template <int NW, int NG, int NC>
-__device__ __forceinline__ void tridiag_reg_body(const double* __restrict__ S, int ld, int k0, int J, int nsteps,
-                                                 double* __restrict__ A, double* __restrict__ H,
-                                                 double* __restrict__ d, double* __restrict__ e,
-                                                 double* __restrict__ tau) {
+__device__ __forceinline__ void tridiag_reg_body(const double* S, int lds, int J, int nsteps, double* Aout, int lda,
+                                                 double* __restrict__ H, int ldh, double* __restrict__ d,
+                                                 double* __restrict__ e, double* __restrict__ tau) {
   __shared__ double sxb[2][16 * NC];  // column k of the current matrix (by parity of k)
   __shared__ double ssc[2][4];        // beta, tau, scale of step k (by parity of k)
   __shared__ double sp[16 * NC];      // p = tau A v
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int c = lane & 15, rs = lane >> 4;
+  if (wave >= NW) {  // uniform: one barrier after the first row, two per step
+    lds_barrier();
+    for (int k = 0; k + 2 < J && k < nsteps; ++k) {
+      lds_barrier();
+      lds_barrier();
+    }
+    return;
+  }
 
   double a[NG][NC];
 #pragma unroll
@@ -211,13 +223,9 @@ __device__ __forceinline__ void tridiag_reg_body(const double* __restrict__ S, i
 #pragma unroll
     for (int cc = 0; cc < NC; ++cc) {
       const int i = 4 * (NW * g + wave) + rs, j = c + 16 * cc;
-      a[g][cc] = (i < J && j < J) ? S[(int64_t)(k0 + i) * ld + (k0 + j)] : 0.0;
+      a[g][cc] = (i < J && j < J) ? S[(int64_t)i * lds + j] : 0.0;
     }
   for (int j = tid; j < 16 * NC; j += 64 * NW) sp[j] = 0.0;
-  d += k0;
-  e += k0;
-  tau += k0;
-  H += (int64_t)k0 * ld + k0;
   publish_row<NW, NG, NC>(0, J, wave, rs, c, a, sxb[0], ssc[0]);
   lds_barrier();
 
@@ -233,7 +241,7 @@ __device__ __forceinline__ void tridiag_reg_body(const double* __restrict__ S, i
       tau[k] = tk;
     }
     if (wave == 0)
-      for (int j = k + 2 + lane; j < J; j += 64) H[(int64_t)k * ld + j] = sx[j] * scale;
+      for (int j = k + 2 + lane; j < J; j += 64) H[(int64_t)k * ldh + j] = sx[j] * scale;
     // (tau = 0 needs no special case: p, w and the update vanish).  LDS reads
     // are unconditional (then selected) so that they are issued together.
     double vj[NC];
@@ -319,7 +327,7 @@ __device__ __forceinline__ void tridiag_reg_body(const double* __restrict__ S, i
 #pragma unroll
       for (int cc = 0; cc < NC; ++cc) {
         const int j = c + 16 * cc;
-        if (j >= k && j < J) A[(int64_t)(k0 + i) * ld + (k0 + j)] = a[g][cc];
+        if (j >= k && j < J) Aout[(int64_t)(i - k) * lda + (j - k)] = a[g][cc];
       }
     }
     return;
@@ -343,12 +351,54 @@ __device__ __forceinline__ void tridiag_reg_body(const double* __restrict__ S, i
   }
 }
 
+// One phase on the trailing block of S (leading dimension ld) that starts at
+// row and column k0; the block left after `nsteps` steps goes to A (same
+// global indices).
 template <int NW, int NG, int NC>
-__global__ __launch_bounds__(64 * NW) void eig_tridiag_reg_kernel(const double* __restrict__ S, int ld, int k0,
-                                                                  int J, int nsteps, double* __restrict__ A,
-                                                                  double* __restrict__ H, double* __restrict__ d,
-                                                                  double* __restrict__ e, double* __restrict__ tau) {
-  tridiag_reg_body<NW, NG, NC>(S, ld, k0, J, nsteps, A, H, d, e, tau);
+__global__ __launch_bounds__(64 * NW) void eig_tridiag_reg_kernel(const double* S, int ld, int k0, int J, int nsteps,
+                                                                  double* A, double* __restrict__ H,
+                                                                  double* __restrict__ d, double* __restrict__ e,
+                                                                  double* __restrict__ tau) {
+  const int kt = min(k0 + nsteps, ld - 1);  // origin of the block handed on (only written if rows remain)
+  tridiag_reg_body<NW, NG, NC>(S + (int64_t)k0 * ld + k0, ld, J, nsteps, A + (int64_t)kt * ld + kt, ld,
+                               H + (int64_t)k0 * ld + k0, ld, d + k0, e + k0, tau + k0);
+}
+
+// The phases of at most 128 rows in one workgroup of 16 waves: each phase
+// hands its trailing block to the next through LDS (kTailHand doubles,
+// dynamic) instead of global memory and a new launch.  Phases with fewer
+// waves leave the others to wait at the barriers.
+constexpr int kTailRows = 128;
+constexpr int kTailHand = 96 * 96;
+__global__ __launch_bounds__(1024) void eig_tridiag_tail_kernel(const double* S, int ld, int k0, int J,
+                                                                double* __restrict__ H, double* __restrict__ d,
+                                                                double* __restrict__ e, double* __restrict__ tau) {
+  extern __shared__ double hand[];
+  const double* src = S + (int64_t)k0 * ld + k0;
+  int lsrc = ld, Jl = J - k0;
+  H += (int64_t)k0 * ld + k0;
+  d += k0;
+  e += k0;
+  tau += k0;
+  // one phase that stops when `next` rows are left, handing them on through LDS
+#define TAIL_PHASE(NW, NG, NC, next)                                                            \
+  if (Jl > (next)) {                                                                            \
+    const int ns = Jl - (next);                                                                 \
+    tridiag_reg_body<NW, NG, NC>(src, lsrc, Jl, ns, hand, (next), H, ld, d, e, tau);            \
+    __syncthreads();                                                                            \
+    src = hand;                                                                                 \
+    lsrc = (next);                                                                              \
+    Jl = (next);                                                                                \
+    H += (int64_t)ns * ld + ns;                                                                 \
+    d += ns;                                                                                    \
+    e += ns;                                                                                    \
+    tau += ns;                                                                                  \
+  }
+  TAIL_PHASE(16, 2, 8, 96)
+  TAIL_PHASE(16, 2, 6, 64)
+  TAIL_PHASE(16, 1, 4, 32)
+#undef TAIL_PHASE
+  tridiag_reg_body<8, 1, 2>(src, lsrc, Jl, Jl, hand, 32, H, ld, d, e, tau);
 }
 
 // ---------------------------------------------------------------- 1b. tridiagonalisation steps, J > 208
@@ -1373,8 +1423,10 @@ __global__ __launch_bounds__(64 * NW) void eig_tridiag_reg_batched(EigBatch b, i
   const int Jl = min(J, hi);
   const int k0 = J - Jl;
   const double* src = (J <= hi) ? b.S + o2 : b.A + o2;
-  tridiag_reg_body<NW, NG, NC>(src, J, k0, Jl, lo > 0 ? Jl - lo : Jl, b.A + o2, b.A + o2, b.d + o1, b.e + o1,
-                               b.tau + o1);
+  const int ns = lo > 0 ? Jl - lo : Jl;
+  const int kt = min(k0 + ns, J - 1);  // origin of the block handed on (only written if rows remain)
+  tridiag_reg_body<NW, NG, NC>(src + (int64_t)k0 * J + k0, J, Jl, ns, b.A + o2 + (int64_t)kt * J + kt, J,
+                               b.A + o2 + (int64_t)k0 * J + k0, J, b.d + o1 + k0, b.e + o1 + k0, b.tau + o1 + k0);
 }
 
 __global__ __launch_bounds__(256) void eig_bisect_batched(EigBatch b) {
@@ -1464,11 +1516,11 @@ hipError_t launch_eig_values(const double* S, int J, double thr, const double* n
 #define TRI_LAUNCH(NW, NG, NC)                                                                                    \
   hipLaunchKernelGGL((eig_tridiag_reg_kernel<NW, NG, NC>), dim3(1), dim3(64 * NW), 0, stream, src, ld, k0, Jl, \
                      Jl - next, w.A, w.A, w.d, w.e, w.tau)
-      if (Jl <= 32) { next = 0; TRI_LAUNCH(8, 1, 2); }
-      else if (Jl <= 64) { next = 32; TRI_LAUNCH(16, 1, 4); }
-      else if (Jl <= 96) { next = 64; TRI_LAUNCH(16, 2, 6); }
-      else if (Jl <= 128) { next = 96; TRI_LAUNCH(16, 2, 8); }
-      else if (Jl <= 192) { next = 128; TRI_LAUNCH(8, 6, 12); }
+      if (Jl <= kTailRows) {
+        next = 0;
+        hipLaunchKernelGGL(eig_tridiag_tail_kernel, dim3(1), dim3(1024), sizeof(double) * kTailHand, stream, src, ld,
+                           k0, J, w.A, w.d, w.e, w.tau);
+      } else if (Jl <= 192) { next = 128; TRI_LAUNCH(8, 6, 12); }
       else { next = 192; TRI_LAUNCH(4, 13, 13); }  // Jl <= kRegMaxJ
 #undef TRI_LAUNCH
       LAUNCH_OK();
