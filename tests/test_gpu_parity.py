@@ -82,7 +82,10 @@ def _gram_of(rng, J, K, decay):
     return A @ A.T
 
 
-@pytest.mark.parametrize("J", [1, 2, 3, 11, 16, 33, 50, 64, 100, 200, 208, 209, 256, 300, 513, 672, 800, 1024])
+# sizes on both sides of every register-phase boundary of the
+# tridiagonalisation (32, 64, 96, 128, 192, 208) and the global-memory steps beyond
+@pytest.mark.parametrize("J", [1, 2, 3, 11, 16, 32, 33, 50, 64, 65, 96, 97, 100, 128, 129, 192, 193, 200, 208, 209,
+                               256, 300, 513, 672, 800, 1024])
 def test_eig_truncate_parity(tk, orc, J):
     rng = np.random.default_rng(J)
     S = _gram_of(rng, J, J + 5, 0.8)
