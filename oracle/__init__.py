@@ -17,9 +17,9 @@ bytes.  Factors are column-major ``I_n x R_n`` (stored as numpy arrays of shape
 Parity: every function here is pinned by ``tests/test_oracle_*.py`` against the
 paper's printed worked example, closed-form identities (Theorem 1, Corollary 1,
 the norm identity of Sec. 3), textbook special cases (Eckart-Young via an SVD)
-and brute force on tiny inputs.  Absolute factor/core values on general inputs
-have no printed value in the paper; they are pinned only through those
-identities ("parity unpinned" for absolute values, as stated in the design doc).
+and brute force on tiny inputs.  Absolute factor and core values on general
+inputs have no printed value in the paper; they are pinned through those
+identities, the SVD special case and brute force.
 """
 from __future__ import annotations
 
