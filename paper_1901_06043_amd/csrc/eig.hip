@@ -558,10 +558,12 @@ __device__ __forceinline__ int sturm_count(const double* sd, const double* se2, 
 }
 
 // 256 threads, LANES per eigenvalue (LANES interior points per round), used
-// by the batched form with 32 lanes (less work in total, throughput-bound);
-// the single-matrix form takes a whole workgroup per eigenvalue (fewer,
+// by the batched form with 4 lanes: a batch holds thousands of eigenvalues,
+// so the total number of Sturm counts (LANES x rounds: 4 x ~23 against
+// 32 x ~11) decides, not the length of one eigenvalue's chain of rounds.
+// The single-matrix form takes a whole workgroup per eigenvalue (fewer,
 // latency-bound rounds; eig_bisect_wide_kernel).
-constexpr int kBisLanesBatched = 32;
+constexpr int kBisLanesBatched = 4;
 template <int LANES>
 __device__ __forceinline__ void bisect_body(const double* __restrict__ d, const double* __restrict__ e, int J,
                                             double* __restrict__ lam, double* __restrict__ scal, int bx) {
