@@ -23,6 +23,7 @@ F32, F64 = 0, 1
 GRAM_FP64, GRAM_FP32, GRAM_BF16X3, GRAM_BF16X6 = 0, 1, 2, 3
 _PREC = {"fp64": GRAM_FP64, "fp32": GRAM_FP32, "bf16x3": GRAM_BF16X3, "bf16x6": GRAM_BF16X6}
 PREC_NAMES = {v: k for k, v in _PREC.items()}
+PREC_CODES = dict(_PREC)
 STATUS = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EHIP", 4: "ENOCONV", 5: "EUNSUPPORTED"}
 MAX_MODES = 16
 
@@ -164,9 +165,10 @@ class Tucker:
     owned by the C handle; tensors returned here are views kept alive by this
     object)."""
 
-    def __init__(self, handle: int, stream: int):
+    def __init__(self, handle: int, stream: int, requested_precision: str = "fp64"):
         self._h = handle
         self._stream = stream
+        self.requested_precision = requested_precision
         L = lib()
         self.N = L.tucker_ndims(handle)
         d = (ctypes.c_int64 * self.N)()
@@ -262,7 +264,7 @@ def sthosvd(x, eps: float, mode_order=None, prec: str = "fp64", dims=None, strea
     _check(lib().tucker_sthosvd(x.data_ptr(), _dtype_code(x), _i64(dims), len(dims), float(eps),
                                 _i32(mode_order) if mode_order is not None else None, _PREC[prec], s,
                                 ctypes.byref(h)))
-    return Tucker(h.value, s)
+    return Tucker(h.value, s, prec)
 
 
 def reconstruct_order(ranks, out_sizes):

@@ -3,7 +3,9 @@
 * FP64 Grams: every tensor of the batch gets the oracle's ranks (ties within
   rounding accepted, as for the single-tensor path) and a relative error within
   1e-10 of the oracle's, and the same ranks as the single-tensor GPU call.
-* Reduced forms: relative error within 1.05 eps for every tensor.
+* Reduced forms: relative error within 1.05 eps for every tensor, and the
+  oracle's ranks except at threshold ties within Weyl's bound of the form's
+  Gram error.
 * A run captured in a HIP graph and replayed gives the eager run's results.
 """
 import numpy as np
@@ -79,21 +81,59 @@ def test_batched_fp64_matches_oracle_and_single(tk, orc, batch48):
     b.free()
 
 
+# Per-entry bounds of the reduced Grams relative to sqrt(S_aa S_bb) (derived in
+# tests/test_gpu_mixed.py); the spectral norm of the error is at most the bound
+# times trace(S), since ||E||_2 <= ||E||_F <= bound * sqrt(sum S_aa S_bb).
+U32 = 2.0 ** -24
+BOUND = {"fp32": (32 + 8) * U32, "bf16x3": (768 + 8) * U32 + 3.1 * 2.0 ** -16, "bf16x6": (192 + 14) * U32}
+
+
+def weyl_ok(lam, R, thr, e2):
+    """R is a rank the truncation rule may select from some Gram within
+    spectral distance e2 of the Gram with eigenvalues lam: each eigenvalue
+    moves by at most e2 (Weyl), so the tail at r moves by at most (J - r) e2."""
+    lam = np.clip(np.asarray(lam), 0.0, None)
+    J = lam.size
+    tail = np.concatenate([np.cumsum(lam[::-1])[::-1], [0.0]])
+    fits = tail[R] <= thr + (J - R) * e2
+    minimal = R == 1 or tail[R - 1] > thr - (J - R + 1) * e2
+    return bool(fits and minimal)
+
+
 @pytest.mark.parametrize("prec", ["fp32", "bf16x6", "bf16x3"])
-def test_batched_reduced_error_target(tk, batch48, prec):
+def test_batched_reduced_error_target(tk, orc, batch48, prec):
+    """Reduced Grams in the batching form: every tensor within 1.05 eps, and
+    every tensor's ranks equal to the FP64 oracle's, except at a threshold tie:
+    the first mode (in processing order) where they differ must lie within
+    Weyl's bound of the form's Gram error (bound * trace S) around the oracle's
+    eigenvalues of that mode; later modes of such a tensor work on a different
+    partial core and are reported, not compared."""
     eps = 1e-3 if prec != "bf16x3" else 1e-2
+    order = [0, 1, 2]
     xs = [to_dev(X, d) for X, d in batch48]
     b = tk.Batch(xs, eps, prec=prec, dims=[d for _, d in batch48])
     b.run()
+    ranks = b.ranks()
     worst = 0.0
-    for i in range(len(xs)):
+    ties = []
+    for i, (X, d) in enumerate(batch48):
         t = b.item(i)
         assert t.core_dtype == tk.F32
         e = relerr(t, xs[i])
         worst = max(worst, e / eps)
         assert e <= 1.05 * eps, (i, e)
         t.free()
-    print(f"{prec}: worst relerr / eps = {worst:.4f}", flush=True)
+        ref = orc.sthosvd(X.astype(np.float64), d, eps, order)
+        thr = eps * eps * ref.norm2 / 3
+        for n in order:
+            if ranks[i][n] == ref.ranks[n]:
+                continue
+            lam = ref.eigenvalues[n]
+            e2 = BOUND[prec] * float(np.sum(np.clip(lam, 0.0, None))) + 64 * np.finfo(float).eps * float(lam[0])
+            assert weyl_ok(lam, ranks[i][n], thr, e2), (i, n, ranks[i], ref.ranks)
+            ties.append((i, n, ranks[i], ref.ranks))
+            break
+    print(f"{prec}: worst relerr / eps = {worst:.4f}; threshold ties {ties}", flush=True)
     b.free()
 
 

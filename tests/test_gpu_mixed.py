@@ -51,6 +51,9 @@ MP_SHAPES = [
     ([128, 300], [0, 1]),
     ([520, 40], [0]),  # L = 1 pair mode with five row tiles, the last one ragged
     ([5], [0]),
+    ([672, 600], [0]),  # the 672x672x33x626 workload's mode sizes: six and five row tiles
+    ([9, 672, 3], [1]),
+    ([7, 5, 626], [2]),
 ]
 
 
@@ -159,20 +162,69 @@ def _mixed_report(tk, orc, X, dims, eps, order, prec):
     return t, ref, e, angles, dk, e2
 
 
-def _first_mode_rank_ok(t, ref, eps, n0, e2):
-    """Weyl's bound: every eigenvalue of the first mode's reduced-precision Gram
-    is within ||E||_2 of the exact one, so its tail at rank R is within
-    (J - R) ||E||_2 of the oracle's.  Accept exactly the ranks that some Gram
-    within that distance would select."""
-    N = len(t.ranks)
-    thr = eps * eps * ref.norm2 / N
-    lam = np.clip(ref.eigenvalues[n0], 0.0, None)
-    J = len(lam)
+def accepted_ranks(lam, thr, E, slack):
+    """Ranks that the truncation rule may select from a Gram S + E, given the
+    exact eigenvalues `lam` of S (descending) and the error matrix E.
+
+    By Lidskii's theorem (Ky Fan's principle for sums of eigenvalues), the sum
+    of the k smallest eigenvalues of S + E differs from that of S by at most
+    the sum of the k largest singular values of E.  So the computed tail at
+    rank r lies within kf[J - r] of the exact tail[r] (plus `slack` for the
+    FP64 eigensolver and summation rounding), and r is selectable iff
+    tail[r] <= thr + kf[J - r] + slack (it may fit) and, for r > 1,
+    tail[r - 1] > thr - kf[J - r + 1] - slack (r - 1 may not fit)."""
+    lam = np.clip(np.asarray(lam, dtype=np.float64), 0.0, None)
+    J = lam.size
     tail = np.concatenate([np.cumsum(lam[::-1])[::-1], [0.0]])
-    R = t.ranks[n0]
-    fits = tail[R] <= thr + (J - R) * e2
-    minimal = R == 1 or tail[R - 1] > thr - (J - R + 1) * e2
-    return bool(fits and minimal)
+    sv = np.linalg.svd(E, compute_uv=False)
+    kf = np.concatenate([[0.0], np.cumsum(sv)])  # kf[k] = sum of the k largest singular values
+    ok = set()
+    for r in range(1, J + 1):
+        fits = tail[r] <= thr + kf[J - r] + slack
+        minimal = r == 1 or tail[r - 1] > thr - kf[J - r + 1] - slack
+        if fits and minimal:
+            ok.add(r)
+    return ok
+
+
+def composed_rank_check(tk, orc, X, dims, eps, order, prec, t_ranks):
+    """Run the reduced-form mode loop from the single-step C ABI calls
+    (tucker_gram, tucker_eig_truncate, tucker_ttm: the kernels tucker_sthosvd
+    runs), and check every mode's rank against the oracle's exact eigenvalues
+    of the GPU's own partial core at that step, accepting exactly the ranks
+    that a Gram within the measured error of the exact one may select
+    (accepted_ranks).  Also checks the Gram error against the form's per-entry
+    bound and that the composed loop reproduces tucker_sthosvd's ranks.
+    Returns the per-mode (rank, accepted set, ||E||_2 / trace)."""
+    N = len(dims)
+    y = to_dev(X, dims)
+    cur = list(dims)
+    thr = None
+    out = []
+    for n in order:
+        S, nrm = tk.gram(y, n, prec=prec, dims=cur, with_norm=True)
+        if thr is None:
+            thr = (eps * eps / N) * float(nrm.item())
+        Y64 = y.double().cpu().numpy().reshape(-1)
+        Sref = orc.gram(Y64, cur, n)
+        lam_ref, _ = orc.eig(Sref)
+        E = S.cpu().numpy() - Sref
+        tr = float(np.trace(Sref))
+        d = np.sqrt(np.outer(np.diag(Sref), np.diag(Sref))) + 1e-300
+        assert (np.abs(E) / d).max() <= BOUND[prec], (n, (np.abs(E) / d).max())
+        lam, U, R, _ = tk.eig_truncate(S, thr)
+        J = cur[n]
+        ok = accepted_ranks(lam_ref, thr, E, 64 * J * np.finfo(float).eps * tr)
+        assert R in ok, (n, R, sorted(ok))
+        out.append((n, R, sorted(ok), float(np.linalg.norm(E, 2)) / max(tr, 1e-300)))
+        y = tk.ttm(y, n, U.t(), dims=cur, out_dtype=torch.float32, fp32_products=True)
+        cur[n] = R
+    ranks = [0] * N
+    for n, R, _, _ in out:
+        ranks[n] = R
+    assert ranks == list(t_ranks), (ranks, t_ranks)
+    print(f"  composed per-mode (mode, rank, accepted, |E|_2/tr): {out}", flush=True)
+    return out
 
 
 SIM = [((40, 36, 32, 11, 6), [0, 1, 2, 3, 4]), ((40, 36, 32, 11, 6), [4, 3, 0, 1, 2])]
@@ -183,40 +235,41 @@ SIM = [((40, 36, 32, 11, 6), [0, 1, 2, 3, 4]), ((40, 36, 32, 11, 6), [4, 3, 0, 1
 @pytest.mark.parametrize("shape,order", SIM)
 def test_sthosvd_reduced_matches_oracle(tk, orc, prec, eps, shape, order):
     """FP32-MFMA and BF16X6 Grams on a combustion-shaped float32 tensor:
-    relative error within 1.05 eps; at eps >= 1e-3 the oracle's ranks exactly
-    and a first-mode subspace within the Davis-Kahan bound of the Gram's
-    measured error; at 1e-4 (where eigenvalues next to the threshold differ by
-    less than the Gram's error on this small tensor) a first-mode rank within
-    Weyl's bound of that error; later ranks are reported."""
+    relative error within 1.05 eps; every mode's rank accepted against the
+    oracle's exact eigenvalues of the GPU's own partial core with that mode's
+    measured Gram error (composed_rank_check); at eps >= 1e-3 also the FP64
+    oracle's ranks exactly and a first-mode subspace within the Davis-Kahan
+    bound of the Gram's measured error."""
     X, dims, _ = synthetic.combustion(shape, nbumps=16, seed=31)
     t, ref, e, angles, dk, e2 = _mixed_report(tk, orc, X, dims, eps, order, prec)
     assert e <= 1.05 * eps
+    composed_rank_check(tk, orc, X, dims, eps, order, prec, t.ranks)
     if eps >= 1e-3:
         assert t.ranks == ref.ranks
         assert angles[order[0]] <= max(dk, 1e-6)
-    else:
-        assert _first_mode_rank_ok(t, ref, eps, order[0], e2), (t.ranks, ref.ranks)
 
 
 @pytest.mark.parametrize("eps", [1e-2, 1e-3])
 def test_sthosvd_bf16x3_error_target(tk, orc, eps):
     """BF16X3 meets the 1.05 eps target at eps >= 1e-3 on this tensor; its Gram
     under-estimates (the dropped b1 c1' term), so its ranks are never above the
-    oracle's.  Below that the bias exceeds the budget (reported by the
-    benchmark, not asserted)."""
+    oracle's; every mode's rank is accepted by the per-mode check.  Below that
+    the bias exceeds the budget (reported by the benchmark, not asserted)."""
     X, dims, _ = synthetic.combustion(SIM[0][0], nbumps=16, seed=31)
     t, ref, e, angles, dk, e2 = _mixed_report(tk, orc, X, dims, eps, SIM[0][1], "bf16x3")
     assert e <= 1.05 * eps
     assert all(r <= q for r, q in zip(t.ranks, ref.ranks))
+    composed_rank_check(tk, orc, X, dims, eps, SIM[0][1], "bf16x3", t.ranks)
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16x6"])
 def test_sthosvd_reduced_fourier(tk, orc, prec):
-    """Fourier-field tensor (2 space, 33 variables, time) in mode order 3,2,0,1."""
+    """Fourier-field tensor (2 space, 33 variables, time) in mode order 3,2,0,1:
+    1.05 eps and the per-mode rank check on every mode."""
     X, dims = synthetic.fourier_fields((96, 80, 33, 40), nmodes=64, seed=41)
     t, ref, e, angles, dk, e2 = _mixed_report(tk, orc, X, dims, 1e-4, [3, 2, 0, 1], prec)
     assert e <= 1.05e-4
-    assert _first_mode_rank_ok(t, ref, 1e-4, 3, e2), (t.ranks, ref.ranks)
+    composed_rank_check(tk, orc, X, dims, 1e-4, [3, 2, 0, 1], prec, t.ranks)
 
 
 def test_reconstruct_fp32_core(tk, orc):

@@ -43,6 +43,12 @@ GRAM_SHAPES = [
     ([232, 40], [0, 1]),   # 120 triangle blocks: the largest per-wave block count
     ([7, 232, 3], [1]),
     ([5], [0]),
+    # the mode sizes of the 672x672x33x626 workload in the tile-pair kernel:
+    # J = 672 with L = 1 (six 128-row tiles, 21 pairs, the last tile ragged),
+    # J = 672 with L > 1, and J = 626 as the last mode (L > 1, no block above it)
+    ([672, 1500], [0]),
+    ([9, 672, 4], [1]),
+    ([7, 5, 626], [2]),
 ]
 
 
