@@ -133,11 +133,24 @@ tucker_status tucker_timings(const tucker_t* t, double* ms_out);
 tucker_status tucker_gram_precision(const tucker_t* t, tucker_gram_prec* prec_out);
 void tucker_free(tucker_t* t);
 
+/* A handle from a given Tucker model (core G, factors U_n), e.g. one
+ * compressed elsewhere and moved to this machine for reconstruction (Sec. 8).
+ *   core     device, prod(ranks) values of core_dtype, natural descending.
+ *   dims     host, N original sizes I_n >= 1.  ranks: host, N values, 1 <= R_n <= I_n.
+ *   factors  host array of N device pointers; U_n is I_n x R_n column-major FP64.
+ * Everything is copied into handle-owned memory (synchronises `stream`); the
+ * handle has no eigenvalues (count 0), zero norm and discarded energies, and
+ * its Gram precision entries read FP64.  Errors: EINVAL, ENOMEM, EHIP. */
+tucker_status tucker_create(const void* core, tucker_dtype core_dtype, const int64_t* dims, const int64_t* ranks,
+                            int N, const double* const* factors, hipStream_t stream, tucker_t** out);
+
 /* ------------------------------------------------------------------------
  * Reconstruction (Sec. 8): X^[begin:end) = G x_0 U_0[b_0:e_0,:] ... x_{N-1} U_{N-1}[b:e,:]
  * ------------------------------------------------------------------------ */
 
-/* begin/end  host, N each; half-open index ranges 0 <= begin_n < end_n <= I_n;
+/* Index ranges are the RANGE operators with step 1 of tucker_reconstruct_ops
+ * (post-processing attached with tucker_set_postprocess is applied).
+ * begin/end  host, N each; half-open index ranges 0 <= begin_n < end_n <= I_n;
  *            NULL means the full range.
  * order      host, N ints, permutation giving the order of the mode products;
  *            NULL = the flop-minimising order of tucker_reconstruct_order.
@@ -146,7 +159,9 @@ void tucker_free(tucker_t* t);
  * Products are FP64 MFMA, except that an FP32 core (reduced-precision
  * compression) reconstructed into FP32 output uses FP32 MFMA products.
  * Scratch for intermediate results is taken from the device's stream-ordered
- * pool and released before return (stream order). */
+ * pool and released before return (stream order).  The call may use any
+ * stream: tucker_free then orders the release of the handle's memory after
+ * the work enqueued here. */
 tucker_status tucker_reconstruct(const tucker_t* t, const int64_t* begin, const int64_t* end,
                                  const int* order, void* out, tucker_dtype out_dtype,
                                  hipStream_t stream);
@@ -157,6 +172,124 @@ tucker_status tucker_reconstruct(const tucker_t* t, const int64_t* begin, const 
  * ranks, out_sizes: host, N each, >= 1.  order_out: host, N ints.  Host only. */
 tucker_status tucker_reconstruct_order(int N, const int64_t* ranks, const int64_t* out_sizes,
                                        int* order_out);
+
+/* ------------------------------------------------------------------------
+ * Reconstruction through per-mode linear operators (Sec. 8): the result is
+ *   Z = G x_0 (C_0^T U_0) x_1 (C_1^T U_1) ... x_{N-1} (C_{N-1}^T U_{N-1}),
+ * i.e. the operator C_n^T (K_n x I_n) applied along every mode of X^.  The
+ * paper's examples: down-sampling a mode by averaging neighbouring indices,
+ * selecting one variable or one time step, and all-ones operators for a
+ * summary statistic (the mean of one variable over space and time).
+ * ------------------------------------------------------------------------ */
+typedef enum {
+  TUCKER_OP_IDENTITY = 0, /* every row (K_n = I_n) */
+  TUCKER_OP_RANGE = 1,    /* rows begin, begin+step, ... below end: K_n = ceil((end-begin)/step) */
+  TUCKER_OP_AVERAGE = 2,  /* down-sampling by averaging: output k is the mean of rows
+                             [begin + k*step, min(begin + (k+1)*step, end)); K_n = ceil((end-begin)/step) */
+  TUCKER_OP_SUM = 3,      /* one output, the sum of rows [begin, end): K_n = 1 */
+  TUCKER_OP_MEAN = 4,     /* one output, their mean: K_n = 1 */
+  TUCKER_OP_MATRIX = 5    /* a given operator: `matrix` (device, FP64) holds C_n^T, `rows` x I_n, row-major */
+} tucker_op_kind;
+
+typedef struct {
+  int kind;             /* tucker_op_kind */
+  int64_t begin, end;   /* RANGE, AVERAGE, SUM, MEAN: 0 <= begin < end <= I_n */
+  int64_t step;         /* RANGE: stride >= 1; AVERAGE: window width >= 1 */
+  int64_t rows;         /* MATRIX: K_n >= 1 */
+  const double* matrix; /* MATRIX: device pointer; read during the call */
+} tucker_op;
+
+/* Order rules for the mode products of a reconstruction (Sec. 8).
+ *   FLOPS : mode i precedes mode j when K_i R_i R_j + K_i R_j K_j < R_i R_j K_j + R_i K_i K_j
+ *           (tucker_reconstruct_order);
+ *   MEMORY: smallest temporary footprint: the intermediate after a product grows
+ *           by K_i / R_i, so modes are taken by increasing K_i / R_i, i.e. mode i
+ *           precedes mode j when R_i / K_i > R_j / K_j (ties: lower mode first).
+ *           The paper prints this comparison with the opposite sign; its own
+ *           measurements (the order 43120 using the least memory on both SP
+ *           scenarios) follow the rule as stated here. */
+typedef enum { TUCKER_ORDER_FLOPS = 0, TUCKER_ORDER_MEMORY = 1 } tucker_order_rule;
+
+/* K_n of an operator applied to a mode of size I (host only); EINVAL for an
+ * invalid operator. */
+tucker_status tucker_op_size(const tucker_op* op, int64_t I, int64_t* K);
+
+/* Order of the mode products for ranks R and output sizes K under `rule`
+ * (host only; ranks, out_sizes >= 1; order_out: N ints). */
+tucker_status tucker_reconstruct_order_rule(int N, const int64_t* ranks, const int64_t* out_sizes,
+                                            tucker_order_rule rule, int* order_out);
+
+/* Z as above.
+ *   ops        host, N operators (NULL = identity on every mode).
+ *   order      host, N ints, a permutation (the order of the mode products);
+ *              NULL = by `rule`.
+ *   out        device, caller-allocated, prod(K_n) values of out_dtype,
+ *              natural descending.
+ * The mode-n factor C_n^T U_n is formed on the device (FP64) first; then the
+ * mode products run as in tucker_reconstruct.  Post-processing stored with
+ * tucker_set_postprocess is applied (see there).
+ * Errors: EINVAL (handle, operators, order, dtype, out), ENOMEM, EHIP. */
+tucker_status tucker_reconstruct_ops(const tucker_t* t, const tucker_op* ops, const int* order,
+                                     tucker_order_rule rule, void* out, tucker_dtype out_dtype,
+                                     hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Pre- and post-processing by hyperslice (Sec. 3.5).  A hyperslice of mode n
+ * is the set of elements with one fixed index i_n (for a variable mode: all
+ * values of one variable).  Statistics are gathered per hyperslice, one
+ * affine map per hyperslice shifts and/or scales its values before
+ * compression, and the stored vectors undo the map after reconstruction.
+ * ------------------------------------------------------------------------ */
+#define TUCKER_NSTATS 6
+typedef enum {
+  TUCKER_STAT_MEAN = 0,
+  TUCKER_STAT_STD = 1,   /* standard deviation, dividing by the element count */
+  TUCKER_STAT_MIN = 2,
+  TUCKER_STAT_MAX = 3,
+  TUCKER_STAT_NORM1 = 4, /* sum of |x| */
+  TUCKER_STAT_NORM2 = 5  /* sqrt(sum of x^2) */
+} tucker_stat;
+
+/* Statistics of the I_n hyperslices of mode n of X (device, natural
+ * descending, `dtype`): stats (device) receives TUCKER_NSTATS x I_n doubles,
+ * stats[s * I_n + i] for statistic s of slice i.  Accumulated in FP64 in a
+ * fixed order (two passes over X: the mean first).  Asynchronous. */
+tucker_status tucker_slice_stats(const void* X, tucker_dtype dtype, const int64_t* dims, int N, int n,
+                                 double* stats, hipStream_t stream);
+
+/* The two pre-processing methods of Sec. 3.5, from the statistics above:
+ *   STANDARDIZE: shift = mean, scale = standard deviation;
+ *   MAX        : shift = 0,    scale = max |x|.
+ * A zero scale (a constant slice) becomes 1.  stats, shift, scale: device,
+ * J values each for shift and scale.  Asynchronous. */
+typedef enum { TUCKER_SCALE_STANDARDIZE = 0, TUCKER_SCALE_MAX = 1 } tucker_scale_method;
+tucker_status tucker_scaling_vectors(const double* stats, int64_t J, tucker_scale_method method, double* shift,
+                                     double* scale, hipStream_t stream);
+
+/* Y = (X - shift_i) / scale_i on every element of hyperslice i of mode n
+ * (inverse == 0), or Y = X * scale_i + shift_i with one rounding (inverse != 0),
+ * computed in FP64 and rounded once to ydtype.  X and Y: device, natural
+ * descending; Y may be X when the dtypes agree (in place).  shift, scale:
+ * device, I_n values; scale entries must be non-zero.  Asynchronous. */
+tucker_status tucker_slice_transform(const void* X, tucker_dtype xdtype, const int64_t* dims, int N, int n,
+                                     const double* shift, const double* scale, int inverse, void* Y,
+                                     tucker_dtype ydtype, hipStream_t stream);
+
+/* Statistics, vectors and forward map in one call: Y = the pre-processed X
+ * (Y may be X), shift and scale (device, I_n values each) receive the vectors
+ * to store with the compressed tensor.  Asynchronous. */
+tucker_status tucker_preprocess(const void* X, tucker_dtype xdtype, const int64_t* dims, int N, int n,
+                                tucker_scale_method method, void* Y, tucker_dtype ydtype, double* shift,
+                                double* scale, hipStream_t stream);
+
+/* Attach the pre-processing of mode n to a handle (copies I_n values of
+ * shift and scale, device pointers; shift may be NULL for a pure scaling).
+ * Every later reconstruction returns data in the original units: the scale is
+ * folded into the mode-n factor (C_n^T diag(scale) U_n) and the shift adds the
+ * separable term (C_n^T shift) x prod_{m != n} (C_m^T 1).  Synchronises
+ * `stream`. */
+tucker_status tucker_set_postprocess(tucker_t* t, int n, const double* shift, const double* scale,
+                                     hipStream_t stream);
 
 /* ------------------------------------------------------------------------
  * Batching form (not in the paper): many independent tensors of the same

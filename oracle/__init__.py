@@ -67,6 +67,12 @@ def _load():
         lib.oracle_sign_fix.argtypes = [P, i64, i64]
         lib.oracle_ttm.restype = i32
         lib.oracle_ttm.argtypes = [P, P, i32, i32, P, i64, i64, i64, P, i32]
+        lib.oracle_tail.restype = d
+        lib.oracle_tail.argtypes = [P, i32, i32]
+        lib.oracle_slice_stats.restype = i32
+        lib.oracle_slice_stats.argtypes = [P, P, i32, i32, P]
+        lib.oracle_slice_transform.restype = i32
+        lib.oracle_slice_transform.argtypes = [P, P, i32, i32, P, P, i32, P]
         _lib = lib
     return _lib
 
@@ -171,20 +177,35 @@ class Tucker:
     order: list = field(default_factory=list)
 
 
-def sthosvd(X, dims, eps: float, order=None, max_sweeps: int = 60) -> Tucker:
+def tail(lam, R: int) -> float:
+    """Energy discarded by keeping the R leading eigenvectors: the sum of the
+    clamped eigenvalues lam[R:], accumulated from the smallest (Corollary 1)."""
+    lam = _f64(lam)
+    return float(_load().oracle_tail(_ptr(lam), lam.size, int(R)))
+
+
+def sthosvd(X, dims, eps: float, order=None, max_sweeps: int = 60, ranks=None) -> Tucker:
     """ST-HOSVD of paper Alg. 1, step by step, in FP64.
 
     Y <- X; for each n in ``order``: S <- Y_(n) Y_(n)^T; (lam, V) <- eig(S)
     (descending); R_n <- smallest R whose discarded tail is <= eps^2 ||X||^2 / N
     (eq. Un); U_n <- V(:, 1:R_n) (sign convention: largest |entry| positive);
     Y <- Y x_n U_n^T.  Returns G = Y and the factors.
+
+    ``ranks`` (the fixed-rank variant the paper mentions in Sec. 9.4.1: the
+    user gives the core size and the error follows): R_n <- min(ranks[n], J_n)
+    instead of the eq. Un rule; eps is then ignored.
     """
     dims = [int(v) for v in dims]
     N = len(dims)
     if N < 1 or any(v < 1 for v in dims):
         raise ValueError("dims must be positive")
-    if not (eps >= 0.0) or not np.isfinite(eps):
+    if ranks is None and (not (eps >= 0.0) or not np.isfinite(eps)):
         raise ValueError("eps must be finite and >= 0")
+    if ranks is not None:
+        ranks = [int(v) for v in ranks]
+        if len(ranks) != N or any(v < 1 for v in ranks):
+            raise ValueError("ranks must be N values >= 1")
     order = list(range(N)) if order is None else [int(v) for v in order]
     if sorted(order) != list(range(N)):
         raise ValueError("order must be a permutation of 0..N-1")
@@ -194,7 +215,7 @@ def sthosvd(X, dims, eps: float, order=None, max_sweeps: int = 60) -> Tucker:
     nx2 = norm2(Y)
     if not np.isfinite(nx2):
         raise ValueError("non-finite data")
-    thr = eps * eps * nx2 / N
+    thr = eps * eps * nx2 / N if ranks is None else 0.0
     cur = list(dims)
     U = [None] * N
     R = [0] * N
@@ -203,7 +224,11 @@ def sthosvd(X, dims, eps: float, order=None, max_sweeps: int = 60) -> Tucker:
     for n in order:
         S = gram(Y, cur, n)
         lam, V = eig(S, max_sweeps)
-        Rn, dn = truncate(lam, thr)
+        if ranks is None:
+            Rn, dn = truncate(lam, thr)
+        else:
+            Rn = min(ranks[n], cur[n])
+            dn = tail(lam, Rn)
         Un = sign_fix(V[:, :Rn])
         Y, cur = ttm(Y, cur, n, Un.T)
         U[n], R[n], lams[n], disc[n] = Un, Rn, lam, dn
@@ -259,3 +284,127 @@ def relerr(X, t: Tucker) -> float:
     if nx == 0.0:
         return 0.0
     return float(np.sqrt(norm2(X - Xh)) / nx)
+
+
+# ---------------------------------------------------------------------------
+# Pre- and post-processing (paper Sec. 3.5)
+# ---------------------------------------------------------------------------
+
+STAT_NAMES = ["mean", "std", "min", "max", "norm1", "norm2"]
+
+
+def slice_stats(Y, dims, n: int) -> np.ndarray:
+    """Statistics of every hyperslice of mode n: a (6, J_n) array with rows
+    mean, standard deviation (divided by the count), minimum, maximum, 1-norm
+    and 2-norm (paper Sec. 3.5)."""
+    Y = _f64(Y)
+    d = _dims(dims)
+    J = int(d[n])
+    out = np.empty(6 * J, dtype=np.float64)
+    if _load().oracle_slice_stats(_ptr(Y), _ptr(d), d.size, n, _ptr(out)) != 0:
+        raise ValueError("bad shape")
+    return out.reshape(6, J)
+
+
+def scaling_vectors(stats: np.ndarray, method: str):
+    """(shift, scale) of the two pre-processing methods of paper Sec. 3.5:
+    "standardize" shifts by the mean and scales by the standard deviation;
+    "max" scales by the largest absolute value (no shift).  A zero scale (a
+    constant or all-zero slice) is replaced by 1, so the map stays invertible."""
+    stats = np.asarray(stats, dtype=np.float64)
+    if method == "standardize":
+        shift = stats[0].copy()
+        scale = stats[1].copy()
+    elif method == "max":
+        shift = np.zeros(stats.shape[1])
+        scale = np.maximum(np.abs(stats[2]), np.abs(stats[3]))
+    else:
+        raise ValueError("method is 'standardize' or 'max'")
+    scale[scale == 0.0] = 1.0
+    return shift, scale
+
+
+def slice_transform(Y, dims, n: int, shift, scale, inverse: bool = False) -> np.ndarray:
+    """Per-hyperslice affine map along mode n: (Y - shift_i) / scale_i, or
+    with ``inverse`` Y * scale_i + shift_i (one rounding)."""
+    Y = _f64(Y)
+    d = _dims(dims)
+    sh, sc = _f64(shift), _f64(scale)
+    if sh.size != int(d[n]) or sc.size != int(d[n]):
+        raise ValueError("shift and scale need J_n values")
+    Z = np.empty_like(Y)
+    if _load().oracle_slice_transform(_ptr(Y), _ptr(d), d.size, n, _ptr(sh), _ptr(sc), int(bool(inverse)),
+                                      _ptr(Z)) != 0:
+        raise ValueError("bad shape")
+    return Z
+
+
+# ---------------------------------------------------------------------------
+# Reconstruction through per-mode linear operators (paper Sec. 8)
+# ---------------------------------------------------------------------------
+
+def operator_matrix(op, I: int) -> np.ndarray:
+    """The K x I matrix C^T of one mode's operator (paper Sec. 8: the mode-n
+    factor U_n is replaced by C_n^T U_n).  ``op`` is None (identity) or a
+    tuple:
+      ("range", begin, end, step)   rows begin, begin+step, ... below end;
+      ("average", begin, end, w)    row k = the mean of rows [begin+k*w,
+                                    min(begin+(k+1)*w, end)) (down-sampling by
+                                    averaging; the paper's example takes w=2);
+      ("sum", begin, end)           one row: the sum of rows [begin, end);
+      ("mean", begin, end)          one row: their mean;
+      ("matrix", Ct)                a given K x I matrix.
+    """
+    if op is None:
+        return np.eye(I)
+    kind = op[0]
+    if kind == "matrix":
+        Ct = np.asarray(op[1], dtype=np.float64)
+        if Ct.ndim != 2 or Ct.shape[1] != I:
+            raise ValueError("matrix operator must be K x I")
+        return Ct
+    b, e = int(op[1]), int(op[2])
+    if not (0 <= b < e <= I):
+        raise ValueError("bad range")
+    if kind == "range":
+        step = int(op[3])
+        rows = list(range(b, e, step))
+        Ct = np.zeros((len(rows), I))
+        for k, i in enumerate(rows):
+            Ct[k, i] = 1.0
+        return Ct
+    if kind == "average":
+        w = int(op[3])
+        K = -(-(e - b) // w)
+        Ct = np.zeros((K, I))
+        for k in range(K):
+            lo, hi = b + k * w, min(b + (k + 1) * w, e)
+            Ct[k, lo:hi] = 1.0 / (hi - lo)
+        return Ct
+    if kind in ("sum", "mean"):
+        Ct = np.zeros((1, I))
+        Ct[0, b:e] = 1.0 if kind == "sum" else 1.0 / (e - b)
+        return Ct
+    raise ValueError(f"unknown operator {kind}")
+
+
+def reconstruct_ops(t: Tucker, ops=None, order=None, post=None):
+    """Z = X^ x_0 C_0^T x_1 ... x_{N-1} C_{N-1}^T (paper Sec. 8), written out
+    plainly: the full reconstruction X^ = G x_n U_n (one TTM per mode in
+    ``order``), then, if ``post`` = (m, shift, scale) is given, the inverse of
+    the mode-m pre-processing X^ <- X^ * scale + shift (paper Sec. 3.5), then
+    the operators as mode products in increasing mode order.  (Any order of
+    the mode products gives the same result, up to rounding.)"""
+    N = len(t.dims)
+    ops = [None] * N if ops is None else list(ops)
+    Xh, cur = reconstruct(t, order=order)
+    if post is not None:
+        m, shift, scale = post
+        Xh = slice_transform(Xh, cur, m, shift, scale, inverse=True)
+    Z = Xh
+    for n in range(N):
+        if ops[n] is None:
+            continue
+        Ct = operator_matrix(ops[n], t.dims[n])
+        Z, cur = ttm(Z, cur, n, Ct)
+    return Z, cur

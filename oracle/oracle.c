@@ -236,3 +236,68 @@ int oracle_ttm(const double* Y, const int64_t* dims, int N, int n, const double*
       }
   return 0;
 }
+
+int oracle_slice_stats(const double* Y, const int64_t* dims, int N, int n, double* stats) {
+  /* paper Sec. 3.5: statistics of every hyperslice of mode n.  Slice i holds
+   * the elements Y[l + L*i + L*J*r] (l < L, r < Rt).  Two plain passes: the
+   * sum, extremes and norms first, then the squared deviations from the
+   * mean.  The standard deviation divides by the element count. */
+  if (check_shape(dims, N, n) || !Y || !stats) return -1;
+  int64_t L, Rt;
+  left_right(dims, N, n, &L, &Rt);
+  const int64_t J = dims[n];
+  const double cnt = (double)(L * Rt);
+  for (int64_t i = 0; i < J; ++i) {
+    double sum = 0.0, mn = INFINITY, mx = -INFINITY, n1 = 0.0, n2 = 0.0;
+    for (int64_t r = 0; r < Rt; ++r)
+      for (int64_t l = 0; l < L; ++l) {
+        const double v = Y[l + L * i + L * J * r];
+        sum += v;
+        if (v < mn) mn = v;
+        if (v > mx) mx = v;
+        n1 += fabs(v);
+        n2 += v * v;
+      }
+    const double mean = sum / cnt;
+    double m2 = 0.0;
+    for (int64_t r = 0; r < Rt; ++r)
+      for (int64_t l = 0; l < L; ++l) {
+        const double d = Y[l + L * i + L * J * r] - mean;
+        m2 += d * d;
+      }
+    stats[0 * J + i] = mean;
+    stats[1 * J + i] = sqrt(m2 / cnt);
+    stats[2 * J + i] = mn;
+    stats[3 * J + i] = mx;
+    stats[4 * J + i] = n1;
+    stats[5 * J + i] = sqrt(n2);
+  }
+  return 0;
+}
+
+int oracle_slice_transform(const double* Y, const int64_t* dims, int N, int n, const double* shift,
+                           const double* scale, int inverse, double* Z) {
+  /* paper Sec. 3.5: one affine map per hyperslice of mode n.  Forward:
+   * Z = (Y - shift_i) / scale_i; inverse: Z = Y * scale_i + shift_i with a
+   * single rounding (fused multiply-add). */
+  if (check_shape(dims, N, n) || !Y || !Z || !shift || !scale) return -1;
+  int64_t L, Rt;
+  left_right(dims, N, n, &L, &Rt);
+  const int64_t J = dims[n];
+  for (int64_t r = 0; r < Rt; ++r)
+    for (int64_t i = 0; i < J; ++i)
+      for (int64_t l = 0; l < L; ++l) {
+        const int64_t e = l + L * i + L * J * r;
+        Z[e] = inverse ? fma(Y[e], scale[i], shift[i]) : (Y[e] - shift[i]) / scale[i];
+      }
+  return 0;
+}
+
+double oracle_tail(const double* lam, int J, int R) {
+  /* sum of the clamped eigenvalues lam[R..J) (0-based), accumulated from the
+   * smallest upward, as in oracle_truncate: the energy a rank-R truncation
+   * of the mode discards (paper Corollary 1). */
+  double t = 0.0;
+  for (int i = J - 1; i >= R; --i) t += (lam[i] > 0.0 ? lam[i] : 0.0);
+  return t;
+}

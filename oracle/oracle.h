@@ -58,6 +58,21 @@ void oracle_sign_fix(double* U, int64_t I, int64_t R);
 int oracle_ttm(const double* Y, const int64_t* dims, int N, int n, const double* M,
                int64_t K, int64_t msk, int64_t msj, double* Z, int nthreads);
 
+/* Sum of max(lam_i, 0) for i = R..J-1, accumulated from the last (smallest)
+ * value upward: the energy discarded by keeping R leading eigenvectors. */
+double oracle_tail(const double* lam, int J, int R);
+
+/* Hyperslice statistics of mode n (paper Sec. 3.5): for every index i of
+ * mode n, over the prod_{k!=n} J_k elements of that slice, stats[s*J_n + i]
+ * holds s = 0 mean, 1 standard deviation (divided by the count), 2 minimum,
+ * 3 maximum, 4 1-norm, 5 2-norm. */
+int oracle_slice_stats(const double* Y, const int64_t* dims, int N, int n, double* stats);
+
+/* Per-hyperslice affine map along mode n (paper Sec. 3.5): inverse == 0 gives
+ * Z = (Y - shift_i) / scale_i, inverse != 0 gives Z = fma(Y, scale_i, shift_i). */
+int oracle_slice_transform(const double* Y, const int64_t* dims, int N, int n, const double* shift,
+                           const double* scale, int inverse, double* Z);
+
 #ifdef __cplusplus
 }
 #endif

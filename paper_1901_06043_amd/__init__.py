@@ -16,6 +16,8 @@ import ctypes
 import os
 from dataclasses import dataclass
 
+import numpy as np
+
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libtuckerhip.so")
 
@@ -34,7 +36,20 @@ EXPORTS = [
     "tucker_eig_truncate", "tucker_ttm", "tucker_last_error", "tucker_version",
     "tucker_batch_create", "tucker_batch_run", "tucker_sthosvd_batched", "tucker_batch_ranks",
     "tucker_batch_norm2", "tucker_batch_item", "tucker_batch_tiles", "tucker_batch_free",
+    "tucker_op_size", "tucker_reconstruct_order_rule", "tucker_reconstruct_ops", "tucker_slice_stats",
+    "tucker_scaling_vectors", "tucker_slice_transform", "tucker_preprocess", "tucker_set_postprocess",
+    "tucker_create",
 ]
+
+OP_KINDS = {"identity": 0, "range": 1, "average": 2, "sum": 3, "mean": 4, "matrix": 5}
+ORDER_RULES = {"flops": 0, "memory": 1}
+SCALE_METHODS = {"standardize": 0, "max": 1}
+STAT_NAMES = ["mean", "std", "min", "max", "norm1", "norm2"]
+
+
+class _Op(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("begin", ctypes.c_int64), ("end", ctypes.c_int64),
+                ("step", ctypes.c_int64), ("rows", ctypes.c_int64), ("matrix", ctypes.c_void_p)]
 
 _lib = None
 
@@ -82,6 +97,15 @@ def lib():
             "tucker_batch_item": (i32, [P, i32, PP]),
             "tucker_batch_tiles": (i32, [P, P, P]),
             "tucker_batch_free": (None, [P]),
+            "tucker_op_size": (i32, [P, i64, P]),
+            "tucker_reconstruct_order_rule": (i32, [i32, P, P, i32, P]),
+            "tucker_reconstruct_ops": (i32, [P, P, P, i32, P, i32, P]),
+            "tucker_slice_stats": (i32, [P, i32, P, i32, i32, P, P]),
+            "tucker_scaling_vectors": (i32, [P, i64, i32, P, P, P]),
+            "tucker_slice_transform": (i32, [P, i32, P, i32, i32, P, P, i32, P, i32, P]),
+            "tucker_preprocess": (i32, [P, i32, P, i32, i32, i32, P, i32, P, P, P]),
+            "tucker_set_postprocess": (i32, [P, i32, P, P, P]),
+            "tucker_create": (i32, [P, i32, P, P, i32, P, P, PP]),
             "tucker_last_error": (ctypes.c_char_p, []),
             "tucker_version": (ctypes.c_char_p, []),
         }
@@ -244,6 +268,31 @@ class Tucker:
                                         out.data_ptr(), code, _stream(stream)))
         return out
 
+    def reconstruct_ops(self, ops=None, order=None, rule="flops", out_dtype=None, out=None, stream=None):
+        """Z = G x_n (C_n^T U_n) for per-mode operators (paper Sec. 8); ``ops`` is
+        a list of N entries: None, ("range", b, e, step), ("average", b, e, w),
+        ("sum", b, e), ("mean", b, e) or ("matrix", Ct) with Ct a K x I_n float64
+        GPU tensor.  Returns a torch tensor of shape K[::-1]."""
+        import torch
+        self._alive()
+        arr, keep = _ops_array(ops, self.N)
+        K = [op_size(None if ops is None else ops[n], self.dims[n]) for n in range(self.N)]
+        if out is None:
+            if out_dtype is None:
+                out_dtype = torch.float64 if self.core_dtype == F64 else torch.float32
+            out = torch.empty(list(reversed(K)), dtype=out_dtype, device="cuda")
+        _check(lib().tucker_reconstruct_ops(self._h, arr, _i32(order) if order is not None else None,
+                                            ORDER_RULES[rule], out.data_ptr(), _dtype_code(out), _stream(stream)))
+        del keep
+        return out
+
+    def set_postprocess(self, n: int, shift, scale, stream=None):
+        """Attach the mode-n pre-processing vectors (paper Sec. 3.5) so that every
+        reconstruction returns data in the original units; shift may be None."""
+        self._alive()
+        _check(lib().tucker_set_postprocess(self._h, int(n), None if shift is None else _f64_dev(shift).data_ptr(),
+                                            _f64_dev(scale).data_ptr(), _stream(stream)))
+
     def free(self):
         if self._h:
             lib().tucker_free(self._h)
@@ -256,6 +305,108 @@ class Tucker:
             pass
 
 
+def _f64_dev(v):
+    import torch
+    if not (v.is_cuda and v.dtype == torch.float64 and v.is_contiguous()):
+        raise ValueError("expected a contiguous float64 GPU tensor")
+    return v
+
+
+def _ops_array(ops, N):
+    """ctypes array of N tucker_op from the Python operator specs (and the
+    tensors that must stay alive during the call)."""
+    if ops is None:
+        return None, []
+    if len(ops) != N:
+        raise ValueError(f"need {N} operators")
+    arr = (_Op * N)()
+    keep = []
+    for n, op in enumerate(ops):
+        if op is None:
+            arr[n] = _Op(0, 0, 0, 1, 0, None)
+            continue
+        kind = op[0]
+        if kind in ("range", "average"):
+            arr[n] = _Op(OP_KINDS[kind], int(op[1]), int(op[2]), int(op[3]), 0, None)
+        elif kind in ("sum", "mean"):
+            arr[n] = _Op(OP_KINDS[kind], int(op[1]), int(op[2]), 1, 0, None)
+        elif kind == "matrix":
+            Ct = _f64_dev(op[1])
+            keep.append(Ct)
+            arr[n] = _Op(OP_KINDS[kind], 0, 0, 1, int(Ct.shape[0]), Ct.data_ptr())
+        else:
+            raise ValueError(f"unknown operator {kind}")
+    return arr, keep
+
+
+def op_size(op, I: int) -> int:
+    """K of an operator spec on a mode of size I (host rule of the library)."""
+    arr, keep = _ops_array([op], 1)
+    if arr is None:
+        return int(I)
+    K = ctypes.c_int64(0)
+    _check(lib().tucker_op_size(ctypes.byref(arr[0]), int(I), ctypes.byref(K)))
+    return K.value
+
+
+def reconstruct_order_rule(ranks, out_sizes, rule="flops"):
+    N = len(ranks)
+    o = (ctypes.c_int * N)()
+    _check(lib().tucker_reconstruct_order_rule(N, _i64(ranks), _i64(out_sizes), ORDER_RULES[rule], o))
+    return list(o)
+
+
+def slice_stats(x, n: int, dims=None, stream=None):
+    """Statistics of the hyperslices of mode n (paper Sec. 3.5): a (6, I_n) float64
+    GPU tensor with rows mean, std, min, max, 1-norm, 2-norm."""
+    import torch
+    dims = _dims_of(x, dims)
+    st = torch.empty((6, dims[n]), dtype=torch.float64, device=x.device)
+    _check(lib().tucker_slice_stats(x.data_ptr(), _dtype_code(x), _i64(dims), len(dims), int(n), st.data_ptr(),
+                                    _stream(stream)))
+    return st
+
+
+def scaling_vectors(stats, method: str, stream=None):
+    """(shift, scale) of "standardize" or "max" from slice statistics."""
+    import torch
+    stats = _f64_dev(stats)
+    J = stats.shape[1]
+    shift = torch.empty(J, dtype=torch.float64, device=stats.device)
+    scale = torch.empty(J, dtype=torch.float64, device=stats.device)
+    _check(lib().tucker_scaling_vectors(stats.data_ptr(), J, SCALE_METHODS[method], shift.data_ptr(),
+                                        scale.data_ptr(), _stream(stream)))
+    return shift, scale
+
+
+def slice_transform(x, n: int, shift, scale, inverse: bool = False, out=None, out_dtype=None, dims=None,
+                    stream=None):
+    """(x - shift_i) / scale_i along mode n (or the inverse x * scale_i + shift_i);
+    ``out`` may be ``x`` (in place)."""
+    import torch
+    dims = _dims_of(x, dims)
+    if out is None:
+        out = torch.empty(x.shape, dtype=out_dtype or x.dtype, device=x.device)
+    _check(lib().tucker_slice_transform(x.data_ptr(), _dtype_code(x), _i64(dims), len(dims), int(n),
+                                        _f64_dev(shift).data_ptr(), _f64_dev(scale).data_ptr(), int(bool(inverse)),
+                                        out.data_ptr(), _dtype_code(out), _stream(stream)))
+    return out
+
+
+def preprocess(x, n: int, method: str, out=None, dims=None, stream=None):
+    """Statistics + vectors + forward map in one call: returns (y, shift, scale)."""
+    import torch
+    dims = _dims_of(x, dims)
+    if out is None:
+        out = torch.empty_like(x)
+    shift = torch.empty(dims[n], dtype=torch.float64, device=x.device)
+    scale = torch.empty(dims[n], dtype=torch.float64, device=x.device)
+    _check(lib().tucker_preprocess(x.data_ptr(), _dtype_code(x), _i64(dims), len(dims), int(n),
+                                   SCALE_METHODS[method], out.data_ptr(), _dtype_code(out), shift.data_ptr(),
+                                   scale.data_ptr(), _stream(stream)))
+    return out, shift, scale
+
+
 def sthosvd(x, eps: float, mode_order=None, prec: str = "fp64", dims=None, stream=None) -> Tucker:
     """ST-HOSVD of a GPU tensor (paper Alg. 1) -> Tucker handle."""
     dims = _dims_of(x, dims)
@@ -265,6 +416,25 @@ def sthosvd(x, eps: float, mode_order=None, prec: str = "fp64", dims=None, strea
                                 _i32(mode_order) if mode_order is not None else None, _PREC[prec], s,
                                 ctypes.byref(h)))
     return Tucker(h.value, s, prec)
+
+
+def from_model(core, factors, dims=None, stream=None) -> Tucker:
+    """A handle from a given Tucker model: ``core`` a GPU tensor of shape
+    ranks[::-1] (float32 or float64), ``factors`` the N float64 GPU matrices
+    U_n (I_n x R_n, any strides; copied column-major)."""
+    import torch
+    N = len(factors)
+    ranks = [int(U.shape[1]) for U in factors]
+    dims = [int(U.shape[0]) for U in factors] if dims is None else list(dims)
+    if not core.is_contiguous() or core.numel() != int(np.prod(ranks)):
+        raise ValueError("core must be contiguous with prod(ranks) elements")
+    cols = [U.to(torch.float64).t().contiguous() for U in factors]  # (R, I) C-order == I x R column-major
+    ptrs = (ctypes.c_void_p * N)(*[c.data_ptr() for c in cols])
+    h = ctypes.c_void_p(0)
+    s = _stream(stream)
+    _check(lib().tucker_create(core.data_ptr(), _dtype_code(core), _i64(dims), _i64(ranks), N, ptrs, s,
+                               ctypes.byref(h)))
+    return Tucker(h.value, s, "fp64")
 
 
 def reconstruct_order(ranks, out_sizes):

@@ -353,6 +353,15 @@ struct tucker_t {
   int64_t* dranks = nullptr;
   hipStream_t stream = nullptr;
   std::vector<void*> owned;
+  // post-processing of one mode (tucker_set_postprocess): shift may be null
+  int post_mode = -1;
+  double* post_shift = nullptr;  // post_shift_buf while a shift is attached
+  double* post_shift_buf = nullptr;
+  double* post_scale = nullptr;
+  // events recorded on other streams after work that reads the handle
+  // (reconstructions); tucker_free orders the release after them
+  mutable std::mutex foreign_mu;
+  mutable std::vector<hipEvent_t> foreign;
 
   hipError_t alloc(void** p, size_t bytes);
   void release();
@@ -365,6 +374,16 @@ hipError_t tucker_t::alloc(void** p, size_t bytes) {
 }
 
 void tucker_t::release() {
+  {
+    // blocks go back to the cache of `stream`; work on other streams that
+    // still reads them must finish first
+    std::lock_guard<std::mutex> lk(foreign_mu);
+    for (hipEvent_t e : foreign) {
+      (void)hipStreamWaitEvent(stream, e, 0);
+      (void)hipEventDestroy(e);
+    }
+    foreign.clear();
+  }
   for (void* p : owned) dev_free(p, stream);
   owned.clear();
 }
@@ -569,6 +588,43 @@ tucker_status tucker_sthosvd(const void* data, tucker_dtype dtype, const int64_t
   return TUCKER_OK;
 }
 
+tucker_status tucker_create(const void* core, tucker_dtype core_dtype, const int64_t* dims, const int64_t* ranks,
+                            int N, const double* const* factors, hipStream_t stream, tucker_t** out) {
+  if (!out) return fail(TUCKER_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!core || !ranks || !factors) return fail(TUCKER_EINVAL, "NULL argument");
+  if (core_dtype != TUCKER_F32 && core_dtype != TUCKER_F64) return fail(TUCKER_EINVAL, "bad dtype");
+  tucker_status st = validate_dims(dims, N);
+  if (st) return st;
+  for (int k = 0; k < N; ++k) {
+    if (ranks[k] < 1 || ranks[k] > dims[k])
+      return fail(TUCKER_EINVAL, "rank %lld of mode %d outside 1..%lld", (long long)ranks[k], k, (long long)dims[k]);
+    if (!factors[k]) return fail(TUCKER_EINVAL, "factor %d is NULL", k);
+  }
+  if ((st = ensure_device())) return st;
+  HandleGuard g(new tucker_t);
+  tucker_t* t = g.t;
+  t->N = N;
+  t->stream = stream;
+  t->core_dtype = core_dtype;
+  int64_t ce = 1;
+  for (int k = 0; k < N; ++k) {
+    t->dims[k] = dims[k];
+    t->ranks[k] = ranks[k];
+    t->order[k] = k;
+    t->prec_used[k] = TUCKER_GRAM_FP64;
+    ce *= ranks[k];
+    HIP_TRY(t->alloc((void**)&t->U[k], sizeof(double) * dims[k] * ranks[k]));
+    HIP_TRY(hipMemcpyAsync(t->U[k], factors[k], sizeof(double) * dims[k] * ranks[k], hipMemcpyDeviceToDevice,
+                           stream));
+  }
+  HIP_TRY(t->alloc(&t->core, dtype_size(core_dtype) * ce));
+  HIP_TRY(hipMemcpyAsync(t->core, core, dtype_size(core_dtype) * ce, hipMemcpyDeviceToDevice, stream));
+  HIP_TRY(hipStreamSynchronize(stream));
+  *out = g.take();
+  return TUCKER_OK;
+}
+
 int tucker_ndims(const tucker_t* t) { return t ? t->N : 0; }
 
 tucker_status tucker_dims(const tucker_t* t, int64_t* o) {
@@ -632,29 +688,96 @@ void tucker_free(tucker_t* t) {
   delete t;
 }
 
-tucker_status tucker_reconstruct(const tucker_t* t, const int64_t* begin, const int64_t* end, const int* order,
-                                 void* out, tucker_dtype out_dtype, hipStream_t stream) {
+tucker_status tucker_op_size(const tucker_op* op, int64_t I, int64_t* K) {
+  if (!op || !K) return fail(TUCKER_EINVAL, "NULL argument");
+  if (I < 1) return fail(TUCKER_EINVAL, "mode size %lld < 1", (long long)I);
+  const bool ranged = op->kind >= TUCKER_OP_RANGE && op->kind <= TUCKER_OP_MEAN;
+  if (ranged && !(op->begin >= 0 && op->begin < op->end && op->end <= I))
+    return fail(TUCKER_EINVAL, "operator range [%lld, %lld) invalid for size %lld", (long long)op->begin,
+                (long long)op->end, (long long)I);
+  switch (op->kind) {
+    case TUCKER_OP_IDENTITY: *K = I; return TUCKER_OK;
+    case TUCKER_OP_RANGE:
+    case TUCKER_OP_AVERAGE:
+      if (op->step < 1) return fail(TUCKER_EINVAL, "operator step %lld < 1", (long long)op->step);
+      *K = (op->end - op->begin + op->step - 1) / op->step;
+      return TUCKER_OK;
+    case TUCKER_OP_SUM:
+    case TUCKER_OP_MEAN: *K = 1; return TUCKER_OK;
+    case TUCKER_OP_MATRIX:
+      if (op->rows < 1 || !op->matrix) return fail(TUCKER_EINVAL, "matrix operator needs rows >= 1 and a matrix");
+      *K = op->rows;
+      return TUCKER_OK;
+    default: return fail(TUCKER_EINVAL, "unknown operator kind %d", op->kind);
+  }
+}
+
+tucker_status tucker_reconstruct_order_rule(int N, const int64_t* ranks, const int64_t* out_sizes,
+                                            tucker_order_rule rule, int* order_out) {
+  if (rule == TUCKER_ORDER_FLOPS) return tucker_reconstruct_order(N, ranks, out_sizes, order_out);
+  if (rule != TUCKER_ORDER_MEMORY) return fail(TUCKER_EINVAL, "unknown order rule %d", (int)rule);
+  if (!ranks || !out_sizes || !order_out) return fail(TUCKER_EINVAL, "NULL argument");
+  if (N < 1 || N > TUCKER_MAX_MODES) return fail(TUCKER_EINVAL, "N=%d outside 1..%d", N, TUCKER_MAX_MODES);
+  for (int k = 0; k < N; ++k)
+    if (ranks[k] < 1 || out_sizes[k] < 1) return fail(TUCKER_EINVAL, "sizes must be >= 1");
+  std::vector<int> ord(N);
+  std::iota(ord.begin(), ord.end(), 0);
+  // i before j iff K_i / R_i < K_j / R_j, i.e. K_i R_j < K_j R_i (exact, 128-bit)
+  std::stable_sort(ord.begin(), ord.end(), [&](int i, int j) {
+    return (__int128)out_sizes[i] * ranks[j] < (__int128)out_sizes[j] * ranks[i];
+  });
+  for (int k = 0; k < N; ++k) order_out[k] = ord[k];
+  return TUCKER_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Shared by tucker_reconstruct and tucker_reconstruct_ops: the mode products
+// G x_n W_n with W_n = C_n^T diag(s) U_n (s: the post-processing scale of its
+// mode), then the separable shift term of the post-processing.
+tucker_status reconstruct_impl(const tucker_t* t, const tucker_op* ops, const int* order, tucker_order_rule rule,
+                               void* out, tucker_dtype out_dtype, hipStream_t stream) {
   if (!t) return fail(TUCKER_EINVAL, "handle is NULL");
   if (!out) return fail(TUCKER_EINVAL, "out is NULL");
   if (out_dtype != TUCKER_F32 && out_dtype != TUCKER_F64) return fail(TUCKER_EINVAL, "bad dtype");
   const int N = t->N;
-  int64_t b[TUCKER_MAX_MODES], e[TUCKER_MAX_MODES], K[TUCKER_MAX_MODES];
+  tucker_op op[TUCKER_MAX_MODES];
+  int64_t K[TUCKER_MAX_MODES];
+  tucker_status st;
   for (int k = 0; k < N; ++k) {
-    b[k] = begin ? begin[k] : 0;
-    e[k] = end ? end[k] : t->dims[k];
-    if (b[k] < 0 || e[k] > t->dims[k] || b[k] >= e[k])
-      return fail(TUCKER_EINVAL, "mode %d range [%lld, %lld) invalid for size %lld", k, (long long)b[k],
-                  (long long)e[k], (long long)t->dims[k]);
-    K[k] = e[k] - b[k];
+    op[k] = ops ? ops[k] : tucker_op{TUCKER_OP_IDENTITY, 0, 0, 1, 0, nullptr};
+    if ((st = tucker_op_size(&op[k], t->dims[k], &K[k]))) return fail(st, "mode %d: %s", k, g_err.c_str());
   }
   int ord[TUCKER_MAX_MODES];
-  tucker_status st;
   if (order) {
     if ((st = validate_order(order, N, ord))) return st;
-  } else if ((st = tucker_reconstruct_order(N, t->ranks, K, ord))) {
+  } else if ((st = tucker_reconstruct_order_rule(N, t->ranks, K, rule, ord))) {
     return st;
   }
   if ((st = ensure_device())) return st;
+  // factors: a row slice of U_n read in place where possible, else W_n formed on the device
+  const double* M[TUCKER_MAX_MODES];
+  int64_t msk[TUCKER_MAX_MODES], msj[TUCKER_MAX_MODES];
+  TmpBuf wbuf[TUCKER_MAX_MODES];
+  for (int k = 0; k < N; ++k) {
+    const bool post = (k == t->post_mode);
+    const bool slice =
+        !post && (op[k].kind == TUCKER_OP_IDENTITY || (op[k].kind == TUCKER_OP_RANGE && op[k].step == 1));
+    if (slice) {
+      M[k] = t->U[k] + (op[k].kind == TUCKER_OP_RANGE ? op[k].begin : 0);
+      msk[k] = 1;
+      msj[k] = t->dims[k];
+      continue;
+    }
+    HIP_TRY(wbuf[k].alloc(sizeof(double) * K[k] * t->ranks[k], stream));
+    HIP_TRY(tk::launch_op_factor(op[k].kind, op[k].begin, op[k].end, op[k].step, op[k].matrix, t->dims[k], K[k],
+                                 t->ranks[k], t->U[k], post ? t->post_scale : nullptr, wbuf[k].as<double>(), stream));
+    M[k] = wbuf[k].as<double>();
+    msk[k] = t->ranks[k];
+    msj[k] = 1;
+  }
   int64_t cur[TUCKER_MAX_MODES];
   std::memcpy(cur, t->ranks, sizeof(int64_t) * N);
   const void* Y = t->core;
@@ -675,9 +798,7 @@ tucker_status tucker_reconstruct(const tucker_t* t, const int64_t* begin, const 
       HIP_TRY(nb.alloc(dtype_size(zdt) * next, stream));
       Z = nb.p;
     }
-    // M(k, j) = U_n[b_n + k, j]  (U_n is I_n x R_n column-major)
-    const double* M = t->U[n] + b[n];
-    if ((st = run_ttm(Y, ydt, cur, N, n, M, K[n], 1, t->dims[n], Z, zdt, f32p, stream))) return st;
+    if ((st = run_ttm(Y, ydt, cur, N, n, M[n], K[n], msk[n], msj[n], Z, zdt, f32p, stream))) return st;
     a.release();
     if (!last) {
       a.p = nb.p;
@@ -688,6 +809,178 @@ tucker_status tucker_reconstruct(const tucker_t* t, const int64_t* begin, const 
     }
     cur[n] = K[n];
   }
+  if (t->post_mode >= 0 && t->post_shift) {
+    // + (C_p^T shift) x prod_{m != p} (C_m^T 1): one vector per mode, then a
+    // two-factor broadcast over the output (modes below q / from q on)
+    int64_t Imax = 1, voff[TUCKER_MAX_MODES], vtot = 0;
+    for (int k = 0; k < N; ++k) {
+      Imax = std::max(Imax, t->dims[k]);
+      voff[k] = vtot;
+      vtot += K[k];
+    }
+    TmpBuf ones, vec;
+    HIP_TRY(ones.alloc(sizeof(double) * Imax, stream));
+    HIP_TRY(vec.alloc(sizeof(double) * vtot, stream));
+    HIP_TRY(tk::launch_fill(ones.as<double>(), (uint64_t)Imax, 1.0, stream));
+    for (int k = 0; k < N; ++k) {
+      const double* src = (k == t->post_mode) ? t->post_shift : ones.as<double>();
+      HIP_TRY(tk::launch_op_factor(op[k].kind, op[k].begin, op[k].end, op[k].step, op[k].matrix, t->dims[k], K[k], 1,
+                                   src, nullptr, vec.as<double>() + voff[k], stream));
+    }
+    tk::OuterGeo g{};
+    for (int k = 0; k < N; ++k) {
+      g.K[k] = K[k];
+      g.voff[k] = voff[k];
+    }
+    int q = 0;
+    uint64_t inner = 1;
+    while (q < N && inner < 256) inner *= (uint64_t)K[q++];
+    uint64_t outer = 1;
+    for (int k = q; k < N; ++k) outer *= (uint64_t)K[k];
+    TmpBuf ci, co;
+    HIP_TRY(ci.alloc(sizeof(double) * inner, stream));
+    HIP_TRY(co.alloc(sizeof(double) * outer, stream));
+    HIP_TRY(tk::launch_outer_coef(vec.as<double>(), g, 0, q, inner, ci.as<double>(), stream));
+    HIP_TRY(tk::launch_outer_coef(vec.as<double>(), g, q, N, outer, co.as<double>(), stream));
+    if (out_dtype == TUCKER_F64)
+      HIP_TRY(tk::launch_add_outer(static_cast<double*>(out), inner, outer, ci.as<double>(), co.as<double>(), stream));
+    else
+      HIP_TRY(tk::launch_add_outer(static_cast<float*>(out), inner, outer, ci.as<double>(), co.as<double>(), stream));
+  }
+  if (stream != t->stream) {
+    // the handle's memory is read on a stream other than its own: tucker_free
+    // makes the owning stream wait for this point before reusing it
+    hipEvent_t e = nullptr;
+    HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    HIP_TRY(hipEventRecord(e, stream));
+    std::lock_guard<std::mutex> lk(t->foreign_mu);
+    t->foreign.push_back(e);
+  }
+  return TUCKER_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+tucker_status tucker_reconstruct(const tucker_t* t, const int64_t* begin, const int64_t* end, const int* order,
+                                 void* out, tucker_dtype out_dtype, hipStream_t stream) {
+  if (!t) return fail(TUCKER_EINVAL, "handle is NULL");
+  tucker_op op[TUCKER_MAX_MODES];
+  for (int k = 0; k < t->N; ++k) {
+    const int64_t b = begin ? begin[k] : 0, e = end ? end[k] : t->dims[k];
+    if (b < 0 || e > t->dims[k] || b >= e)
+      return fail(TUCKER_EINVAL, "mode %d range [%lld, %lld) invalid for size %lld", k, (long long)b, (long long)e,
+                  (long long)t->dims[k]);
+    op[k] = tucker_op{TUCKER_OP_RANGE, b, e, 1, 0, nullptr};
+  }
+  return reconstruct_impl(t, op, order, TUCKER_ORDER_FLOPS, out, out_dtype, stream);
+}
+
+tucker_status tucker_reconstruct_ops(const tucker_t* t, const tucker_op* ops, const int* order,
+                                     tucker_order_rule rule, void* out, tucker_dtype out_dtype, hipStream_t stream) {
+  if (rule != TUCKER_ORDER_FLOPS && rule != TUCKER_ORDER_MEMORY)
+    return fail(TUCKER_EINVAL, "unknown order rule %d", (int)rule);
+  return reconstruct_impl(t, ops, order, rule, out, out_dtype, stream);
+}
+
+// ---------------------------------------------------------------- pre/post-processing
+tucker_status tucker_slice_stats(const void* X, tucker_dtype dtype, const int64_t* dims, int N, int n, double* stats,
+                                 hipStream_t stream) {
+  if (!X || !stats) return fail(TUCKER_EINVAL, "NULL pointer");
+  if (dtype != TUCKER_F32 && dtype != TUCKER_F64) return fail(TUCKER_EINVAL, "bad dtype");
+  tucker_status st = validate_dims(dims, N);
+  if (st) return st;
+  if (n < 0 || n >= N) return fail(TUCKER_EINVAL, "mode %d outside 0..%d", n, N - 1);
+  if ((st = ensure_device())) return st;
+  int64_t L, Rt;
+  left_right(dims, N, n, L, Rt);
+  TmpBuf work;
+  HIP_TRY(work.alloc(sizeof(double) * tk::slice_stats_work_doubles(L, dims[n], Rt), stream));
+  if (dtype == TUCKER_F64)
+    HIP_TRY(tk::launch_slice_stats(static_cast<const double*>(X), L, dims[n], Rt, true, work.as<double>(), stats,
+                                   stream));
+  else
+    HIP_TRY(tk::launch_slice_stats(static_cast<const float*>(X), L, dims[n], Rt, true, work.as<double>(), stats,
+                                   stream));
+  return TUCKER_OK;
+}
+
+tucker_status tucker_scaling_vectors(const double* stats, int64_t J, tucker_scale_method method, double* shift,
+                                     double* scale, hipStream_t stream) {
+  if (!stats || !shift || !scale) return fail(TUCKER_EINVAL, "NULL pointer");
+  if (J < 1) return fail(TUCKER_EINVAL, "J=%lld < 1", (long long)J);
+  if (method != TUCKER_SCALE_STANDARDIZE && method != TUCKER_SCALE_MAX)
+    return fail(TUCKER_EINVAL, "unknown scaling method %d", (int)method);
+  tucker_status st;
+  if ((st = ensure_device())) return st;
+  HIP_TRY(tk::launch_scaling_vectors(stats, (uint64_t)J, (int)method, shift, scale, stream));
+  return TUCKER_OK;
+}
+
+tucker_status tucker_slice_transform(const void* X, tucker_dtype xdtype, const int64_t* dims, int N, int n,
+                                     const double* shift, const double* scale, int inverse, void* Y,
+                                     tucker_dtype ydtype, hipStream_t stream) {
+  if (!X || !Y || !shift || !scale) return fail(TUCKER_EINVAL, "NULL pointer");
+  if ((xdtype != TUCKER_F32 && xdtype != TUCKER_F64) || (ydtype != TUCKER_F32 && ydtype != TUCKER_F64))
+    return fail(TUCKER_EINVAL, "bad dtype");
+  tucker_status st = validate_dims(dims, N);
+  if (st) return st;
+  if (n < 0 || n >= N) return fail(TUCKER_EINVAL, "mode %d outside 0..%d", n, N - 1);
+  if (X == Y && xdtype != ydtype) return fail(TUCKER_EINVAL, "in-place transform needs equal dtypes");
+  if ((st = ensure_device())) return st;
+  int64_t L, Rt;
+  left_right(dims, N, n, L, Rt);
+  const uint64_t total = (uint64_t)(L * dims[n] * Rt);
+  const bool inv = inverse != 0;
+  if (xdtype == TUCKER_F32 && ydtype == TUCKER_F32)
+    HIP_TRY(tk::launch_slice_transform(static_cast<const float*>(X), static_cast<float*>(Y), total, L, dims[n], shift,
+                                       scale, inv, stream));
+  else if (xdtype == TUCKER_F32)
+    HIP_TRY(tk::launch_slice_transform(static_cast<const float*>(X), static_cast<double*>(Y), total, L, dims[n], shift,
+                                       scale, inv, stream));
+  else if (ydtype == TUCKER_F32)
+    HIP_TRY(tk::launch_slice_transform(static_cast<const double*>(X), static_cast<float*>(Y), total, L, dims[n],
+                                       shift, scale, inv, stream));
+  else
+    HIP_TRY(tk::launch_slice_transform(static_cast<const double*>(X), static_cast<double*>(Y), total, L, dims[n],
+                                       shift, scale, inv, stream));
+  return TUCKER_OK;
+}
+
+tucker_status tucker_preprocess(const void* X, tucker_dtype xdtype, const int64_t* dims, int N, int n,
+                                tucker_scale_method method, void* Y, tucker_dtype ydtype, double* shift,
+                                double* scale, hipStream_t stream) {
+  if (!shift || !scale) return fail(TUCKER_EINVAL, "NULL pointer");
+  tucker_status st = validate_dims(dims, N);
+  if (st) return st;
+  if (n < 0 || n >= N) return fail(TUCKER_EINVAL, "mode %d outside 0..%d", n, N - 1);
+  if ((st = ensure_device())) return st;
+  TmpBuf stats;
+  HIP_TRY(stats.alloc(sizeof(double) * TUCKER_NSTATS * dims[n], stream));
+  if ((st = tucker_slice_stats(X, xdtype, dims, N, n, stats.as<double>(), stream))) return st;
+  if ((st = tucker_scaling_vectors(stats.as<double>(), dims[n], method, shift, scale, stream))) return st;
+  return tucker_slice_transform(X, xdtype, dims, N, n, shift, scale, 0, Y, ydtype, stream);
+}
+
+tucker_status tucker_set_postprocess(tucker_t* t, int n, const double* shift, const double* scale,
+                                     hipStream_t stream) {
+  if (!t || !scale) return fail(TUCKER_EINVAL, "NULL argument");
+  if (n < 0 || n >= t->N) return fail(TUCKER_EINVAL, "mode %d outside 0..%d", n, t->N - 1);
+  tucker_status st;
+  if ((st = ensure_device())) return st;
+  if (t->post_mode >= 0 && t->post_mode != n)
+    return fail(TUCKER_EINVAL, "post-processing is already attached to mode %d", t->post_mode);
+  const size_t bytes = sizeof(double) * t->dims[n];
+  // the vectors may still be being written on `stream`
+  HIP_TRY(hipStreamSynchronize(stream));
+  if (!t->post_scale) HIP_TRY(t->alloc((void**)&t->post_scale, bytes));
+  if (shift && !t->post_shift_buf) HIP_TRY(t->alloc((void**)&t->post_shift_buf, bytes));
+  HIP_TRY(hipMemcpyAsync(t->post_scale, scale, bytes, hipMemcpyDeviceToDevice, t->stream));
+  if (shift) HIP_TRY(hipMemcpyAsync(t->post_shift_buf, shift, bytes, hipMemcpyDeviceToDevice, t->stream));
+  HIP_TRY(hipStreamSynchronize(t->stream));
+  t->post_shift = shift ? t->post_shift_buf : nullptr;
+  t->post_mode = n;
   return TUCKER_OK;
 }
 

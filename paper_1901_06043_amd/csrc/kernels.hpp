@@ -164,4 +164,39 @@ struct TtmBatch {
 template <typename TI, typename TO>
 hipError_t launch_ttm_batched(const TtmBatch& b, bool fp32_products, bool unit_l, hipStream_t stream);
 
+// ---------------------------------------------------------------- hyperslices (slice.hip)
+// Statistics of the J slices of mode n (geometry L, J, Rt): stats[s*J + a]
+// for s = mean, std, min, max, 1-norm, 2-norm; the standard deviation (second
+// pass) only if both_passes.  work: slice_stats_work_doubles doubles.
+int64_t slice_stats_work_doubles(uint64_t L, uint64_t J, uint64_t Rt);
+template <typename T>
+hipError_t launch_slice_stats(const T* Y, uint64_t L, uint64_t J, uint64_t Rt, bool both_passes, double* work,
+                              double* stats, hipStream_t s);
+// shift/scale from stats: method 0 standardization, 1 max rescaling (a zero scale becomes 1).
+hipError_t launch_scaling_vectors(const double* stats, uint64_t J, int method, double* shift, double* scale,
+                                  hipStream_t s);
+// rscale[a] = 2^-e with max|x| of slice a in [2^(e-1), 2^e) (from the min/max rows of stats).
+hipError_t launch_slice_pow2(const double* stats, uint64_t J, double* rscale, hipStream_t s);
+// Y = (X - shift_a) / scale_a, or fma(X, scale_a, shift_a) if inverse; X == Y allowed.
+template <typename TI, typename TO>
+hipError_t launch_slice_transform(const TI* X, TO* Y, uint64_t total, uint64_t L, uint64_t J, const double* shift,
+                                  const double* scale, bool inverse, hipStream_t s);
+// W = C^T diag(scl) U (K x R row-major) for a reconstruction operator (kind as
+// tucker_op_kind; Ct the dense K x I operator for kind 5); scl may be null.
+hipError_t launch_op_factor(int kind, int64_t begin, int64_t end, int64_t step, const double* Ct, int64_t I, int64_t K,
+                            int64_t R, const double* U, const double* scl, double* W, hipStream_t s);
+hipError_t launch_fill(double* p, uint64_t n, double v, hipStream_t s);
+// coef[e] = prod_{m in [lo,hi)} vec[voff[m] + e_m] over the natural-descending
+// multi-index e of sizes K[lo..hi).
+struct OuterGeo {
+  int64_t K[16];
+  int64_t voff[16];
+};
+hipError_t launch_outer_coef(const double* vec, const OuterGeo& g, int lo, int hi, uint64_t count, double* coef,
+                             hipStream_t s);
+// out[o*inner + i] += co[o] * ci[i].
+template <typename TO>
+hipError_t launch_add_outer(TO* out, uint64_t inner, uint64_t outer, const double* ci, const double* co,
+                            hipStream_t s);
+
 }  // namespace tk

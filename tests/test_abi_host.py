@@ -162,3 +162,87 @@ def test_batch_create_rejects_bad_arguments_without_gpu(tk):
     assert h.value is None
     L.tucker_batch_free(None)
 
+
+
+def _peak_memory(order, R, K):
+    """Largest input + output of one mode product in a reconstruction chain."""
+    cur, peak = list(R), 0
+    for n in order:
+        before = int(np.prod(cur))
+        cur[n] = K[n]
+        peak = max(peak, before + int(np.prod(cur)))
+    return peak
+
+
+def test_memory_order_reproduces_paper_table(tk):
+    """Sec. 9 partial reconstruction (tab:partial): order 43120 uses the least
+    memory for both SP compression scenarios.  The memory rule (increasing
+    K_i / R_i) gives it and attains the brute-force minimum of the peak
+    (input + output of a step) over all 5! orders; the comparison as printed in
+    Sec. 8 (increasing R_i / K_i) would start with the expanding modes."""
+    g = _read_recon()
+    K = [int(v) for v in g["out"]]
+    for core in ("core_high", "core_low"):
+        R = [int(v) for v in g[core]]
+        order = tk.reconstruct_order_rule(R, K, "memory")
+        assert order == [int(v) for v in g["best_order"]]
+        best = min(_peak_memory(o, R, K) for o in itertools.permutations(range(5)))
+        assert _peak_memory(order, R, K) == best
+        printed = sorted(range(5), key=lambda i: R[i] / K[i])
+        assert _peak_memory(printed, R, K) > 10 * best
+    assert tk.reconstruct_order_rule([30, 38, 35, 6, 11], K, "flops") == tk.reconstruct_order([30, 38, 35, 6, 11], K)
+
+
+@pytest.mark.parametrize("seed", range(20))
+def test_memory_order_is_optimal_random(tk, seed):
+    rng = np.random.default_rng(100 + seed)
+    N = int(rng.integers(1, 6))
+    R = [int(v) for v in rng.integers(1, 40, N)]
+    K = [int(v) for v in rng.integers(1, 60, N)]
+    order = tk.reconstruct_order_rule(R, K, "memory")
+    assert sorted(order) == list(range(N))
+    assert _peak_memory(order, R, K) == min(_peak_memory(o, R, K) for o in itertools.permutations(range(N)))
+
+
+def test_operator_sizes_and_validation(tk):
+    assert tk.op_size(None, 17) == 17
+    assert tk.op_size(("range", 0, 17, 1), 17) == 17
+    assert tk.op_size(("range", 2, 17, 5), 17) == 3       # rows 2, 7, 12
+    assert tk.op_size(("average", 1, 9, 2), 9) == 4       # pairs (1,2) ... (7,8)
+    assert tk.op_size(("average", 0, 9, 2), 9) == 5      # the last window holds one row
+    assert tk.op_size(("sum", 3, 4), 9) == 1
+    assert tk.op_size(("mean", 0, 9), 9) == 1
+    for bad in (("range", 0, 18, 1), ("range", 5, 5, 1), ("range", 0, 9, 0), ("average", -1, 4, 2),
+                ("average", 0, 4, 0), ("sum", 4, 3)):
+        with pytest.raises(tk.TuckerError):
+            tk.op_size(bad, 17)
+    L = tk.lib()
+    op = tk._Op(5, 0, 0, 1, 0, None)  # matrix operator without a matrix
+    K = ctypes.c_int64(0)
+    assert L.tucker_op_size(ctypes.byref(op), 9, ctypes.byref(K)) == 1
+    op = tk._Op(9, 0, 1, 1, 0, None)
+    assert L.tucker_op_size(ctypes.byref(op), 9, ctypes.byref(K)) == 1
+    o = (ctypes.c_int * 2)()
+    assert L.tucker_reconstruct_order_rule(2, tk._i64([2, 3]), tk._i64([4, 5]), 7, o) == 1
+
+
+def test_pre_post_entry_points_reject_bad_arguments(tk):
+    L = tk.lib()
+    dummy = ctypes.c_void_p(16)  # never dereferenced: validation precedes device work
+    dims = tk._i64([4, 5, 6])
+    assert L.tucker_slice_stats(None, 1, dims, 3, 0, dummy, None) == 1
+    assert L.tucker_slice_stats(dummy, 1, dims, 3, 3, dummy, None) == 1
+    assert L.tucker_slice_stats(dummy, 2, dims, 3, 0, dummy, None) == 1
+    assert L.tucker_scaling_vectors(dummy, 0, 0, dummy, dummy, None) == 1
+    assert L.tucker_scaling_vectors(dummy, 4, 2, dummy, dummy, None) == 1
+    assert L.tucker_slice_transform(dummy, 1, dims, 3, 1, dummy, dummy, 0, None, 1, None) == 1
+    assert L.tucker_slice_transform(dummy, 1, dims, 3, 1, dummy, dummy, 0, dummy, 0, None) == 1  # in place, f64->f32
+    assert L.tucker_preprocess(dummy, 1, dims, 3, 1, 0, dummy, 1, None, dummy, None) == 1
+    assert L.tucker_set_postprocess(None, 0, dummy, dummy, None) == 1
+    assert L.tucker_reconstruct_ops(None, None, None, 0, dummy, 1, None) == 1
+    h = ctypes.c_void_p(0)
+    fac = (ctypes.c_void_p * 3)(16, 16, 16)
+    assert L.tucker_create(dummy, 1, dims, tk._i64([2, 6, 2]), 3, fac, None, ctypes.byref(h)) == 1  # rank > size
+    assert L.tucker_create(dummy, 1, dims, tk._i64([2, 0, 2]), 3, fac, None, ctypes.byref(h)) == 1
+    assert L.tucker_create(None, 1, dims, tk._i64([2, 2, 2]), 3, fac, None, ctypes.byref(h)) == 1
+    assert h.value is None
