@@ -62,16 +62,54 @@ typedef enum { TUCKER_F32 = 0, TUCKER_F64 = 1 } tucker_dtype;
  *            term makes the Gram a slight under-estimate (relative ~1e-6).
  *   BF16X6 : three pieces b0, b1, b2 and the six products b2*b0' + b0*b2' +
  *            b1*b1' + b1*b0' + b0*b1' + b0*b0'.
- * Range guard: for the reduced forms every Gram is checked on the device; if an
- * entry is not finite or its trace differs from the FP64 sum of squares of the
- * working tensor by more than 1e-3 relative (FP32 overflow or underflow), the
- * Gram of that mode is recomputed in FP64 (see tucker_gram_precision). */
+ *   AUTO   : the cheapest form whose predicted error of the truncation's tail
+ *            sums, delta * ||X||^2, is at most 1% of the slack of a 1.05 eps
+ *            target, (1.05^2 - 1) eps^2 ||X||^2 / N; delta = 2^-16/3 for
+ *            BF16X3 (its bias) and 2^-23 for FP32 (the FP32 rounding of the
+ *            working tensor and the accumulation); else FP64.  FP64 data and
+ *            the fixed-rank form (no error target) always take FP64.  So FP32
+ *            is chosen for eps >= 0.0108 sqrt(N), BF16X3 for eps >= 0.0705
+ *            sqrt(N).  tucker_gram_precision reports the choice.
+ * Range handling (per-slice scaling): every reduced Gram is checked on the
+ * device.  If an entry is not finite, its trace differs from the FP64 sum of
+ * squares of the working tensor by more than 1e-3 relative, or a diagonal
+ * entry's mean square lies outside [2^-100, 2^100] (squares near the FP32
+ * underflow or overflow range), the Gram of that mode is redone on a copy of
+ * the working tensor in which every hyperslice of mode n (every row of the
+ * unfolding) is divided by a power of two near its largest magnitude, and S
+ * is multiplied back exactly (tucker_gram_scaled reports it); if that check
+ * fails as well, the Gram is recomputed in FP64 (tucker_gram_precision). */
 typedef enum {
   TUCKER_GRAM_FP64 = 0,
   TUCKER_GRAM_FP32 = 1,
   TUCKER_GRAM_BF16X3 = 2,
-  TUCKER_GRAM_BF16X6 = 3
+  TUCKER_GRAM_BF16X6 = 3,
+  TUCKER_GRAM_AUTO = 4
 } tucker_gram_prec;
+
+/* Device memory allocator hook.  By default the library takes device memory
+ * from its own stream-ordered caching pool (hipMalloc when nothing cached
+ * fits).  With an allocator set, every block (handles, batch plans, scratch)
+ * comes from alloc(bytes, ctx, stream), where `stream` is the stream the
+ * block will be used on, and goes back through free(ptr, ctx, stream) in
+ * stream order: the allocator may hand the block to later work on that
+ * stream without synchronisation, as a caching allocator like PyTorch's
+ * does.  alloc returns NULL when it cannot satisfy the request (the call then
+ * fails with TUCKER_ENOMEM).  A block is returned to the allocator that
+ * produced it, even after the setting changes.  The callbacks are called
+ * from the calling thread, never concurrently for one call. */
+typedef struct {
+  void* (*alloc)(size_t bytes, void* ctx, hipStream_t stream);
+  void (*free)(void* ptr, void* ctx, hipStream_t stream);
+  void* ctx;
+} tucker_allocator;
+
+/* Set (a) or clear (NULL: the built-in pool) the allocator for all later
+ * allocations of the library in this process.  EINVAL if a callback is NULL. */
+tucker_status tucker_set_allocator(const tucker_allocator* a);
+/* Return the built-in pool's idle blocks of the current device to HIP
+ * (synchronises the device first: work in flight may still read them). */
+tucker_status tucker_empty_cache(void);
 
 typedef struct tucker_t tucker_t; /* opaque result handle */
 
@@ -90,17 +128,42 @@ typedef struct tucker_t tucker_t; /* opaque result handle */
  *   prec       Gram arithmetic (see tucker_gram_prec).  TUCKER_GRAM_FP64 keeps
  *              the working tensor in FP64 (FP64 MFMA products throughout);
  *              the reduced forms need dtype == TUCKER_F32 and keep the working
- *              tensor and the core in FP32.
+ *              tensor and the core in FP32; AUTO chooses.
  *   stream     HIP stream for all work (0 = default stream).
  *   out        receives a new handle owning core, factors, eigenvalues and
  *              ranks; release it with tucker_free.
- * Errors: EINVAL for bad arguments or non-finite ||X||^2; ENOMEM; EHIP;
- *         ENOCONV if the eigensolver exceeded its iteration cap.
+ * Errors: EINVAL for bad arguments or non-finite ||X||^2; ENOMEM (predicted
+ *         before the launches, see tucker_sthosvd_memory, or from a failed
+ *         allocation); EHIP; ENOCONV if the eigensolver exceeded its
+ *         iteration cap; EUNSUPPORTED for a mode above 1024.
  * Waits once per mode for the rank R_n, which is read back while that mode's
  * eigenvectors are being formed, and synchronises `stream` before returning. */
 tucker_status tucker_sthosvd(const void* data, tucker_dtype dtype, const int64_t* dims, int N,
                              double eps, const int* mode_order, tucker_gram_prec prec,
                              hipStream_t stream, tucker_t** out);
+
+/* Fixed-rank ST-HOSVD (Sec. 9.4.1: the user gives the core size and the error
+ * follows): as tucker_sthosvd with R_n = min(ranks[n], J_n) in place of the
+ * eq. Un rule.  ranks: host, N values >= 1.  tucker_discarded reports the
+ * discarded energy per mode (their sum is ||X - X^||^2).  With FP64 Grams
+ * the whole compression is enqueued without a host round trip and `stream`
+ * is synchronised once at the end; reduced forms read the range check back
+ * per mode.  AUTO takes FP64 here (there is no error target). */
+tucker_status tucker_sthosvd_ranks(const void* data, tucker_dtype dtype, const int64_t* dims, int N,
+                                   const int64_t* ranks, const int* mode_order, tucker_gram_prec prec,
+                                   hipStream_t stream, tucker_t** out);
+
+/* Predicted device memory of a compression (host only; the input tensor
+ * is not counted): the handle's factors and eigenvalues, the Gram and
+ * eigensolver workspaces, and the largest pair of working tensors with the
+ * scratch of one step.  ranks: host, N values, or NULL for an upper bound
+ * (no truncation).  prec: FP64 or a reduced form.  tucker_sthosvd and
+ * tucker_sthosvd_ranks compare this prediction (the whole run for given
+ * ranks, else the first step, then each next working tensor once its rank is
+ * known) with the free device memory plus the pool's idle blocks, and return
+ * TUCKER_ENOMEM before launching work that would not fit. */
+tucker_status tucker_sthosvd_memory(tucker_dtype dtype, const int64_t* dims, int N, const int64_t* ranks,
+                                    const int* mode_order, tucker_gram_prec prec, size_t* bytes);
 
 /* Handle accessors.  Pointers returned are owned by the handle and valid until
  * tucker_free.  All of them are cheap and do not synchronise. */
@@ -129,8 +192,11 @@ tucker_status tucker_discarded(const tucker_t* t, double* disc_out);
  * main Gram kernel alone. */
 tucker_status tucker_timings(const tucker_t* t, double* ms_out);
 /* host out[N]: per mode, the Gram arithmetic actually used: the requested
- * one, or TUCKER_GRAM_FP64 where the range guard recomputed it. */
+ * one (AUTO resolved), or TUCKER_GRAM_FP64 where the range handling fell back
+ * to it. */
 tucker_status tucker_gram_precision(const tucker_t* t, tucker_gram_prec* prec_out);
+/* host out[N]: per mode, 1 if its Gram ran on the per-slice scaled copy. */
+tucker_status tucker_gram_scaled(const tucker_t* t, int* scaled_out);
 void tucker_free(tucker_t* t);
 
 /* A handle from a given Tucker model (core G, factors U_n), e.g. one
@@ -308,7 +374,8 @@ typedef struct tucker_batch tucker_batch;
 /*   count      number of tensors, >= 1.
  *   data       host array of `count` device pointers (natural descending, `dtype`).
  *   dims       host, count x N sizes (tensor t's sizes at dims + t*N), each 1..128.
- *   eps, mode_order, prec: as for tucker_sthosvd (the order is shared).
+ *   eps, mode_order, prec: as for tucker_sthosvd (the order is shared; AUTO
+ *              is resolved once for the batch).
  *   stream     used for the plan's uploads and its tuning runs; synchronised.
  * Errors: EINVAL (arguments), EUNSUPPORTED (a size above 128), ENOMEM, EHIP. */
 tucker_status tucker_batch_create(int count, const void* const* data, tucker_dtype dtype,
@@ -330,6 +397,13 @@ tucker_status tucker_batch_norm2(tucker_batch* b, double* norm2_out);
 /* Tensor i of the last run as a standalone handle (copies of its core,
  * factors and eigenvalues); release with tucker_free. */
 tucker_status tucker_batch_item(tucker_batch* b, int i, tucker_t** out);
+/* host out[count]: per tensor of the last run, bit 0 (1) if its data holds a
+ * non-finite value (its results are then meaningless), bit 1 (2) if a
+ * reduced-precision Gram of it failed the range check and was recomputed in
+ * FP64 on the device (the batched form's range handling: checked per tensor
+ * and step against the FP64 sum of squares of its working tensor, as in
+ * tucker_gram_prec).  Synchronises as tucker_batch_ranks. */
+tucker_status tucker_batch_status(tucker_batch* b, int* status_out);
 /* The chosen tiles: Gram chunks per work item, TTM 64-column tiles per item. */
 tucker_status tucker_batch_tiles(const tucker_batch* b, int* gram_chunks, int* ttm_tiles);
 /* Synchronises the last run's stream, then releases everything. */

@@ -22,8 +22,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libtuckerhip.so")
 
 F32, F64 = 0, 1
-GRAM_FP64, GRAM_FP32, GRAM_BF16X3, GRAM_BF16X6 = 0, 1, 2, 3
-_PREC = {"fp64": GRAM_FP64, "fp32": GRAM_FP32, "bf16x3": GRAM_BF16X3, "bf16x6": GRAM_BF16X6}
+GRAM_FP64, GRAM_FP32, GRAM_BF16X3, GRAM_BF16X6, GRAM_AUTO = 0, 1, 2, 3, 4
+_PREC = {"fp64": GRAM_FP64, "fp32": GRAM_FP32, "bf16x3": GRAM_BF16X3, "bf16x6": GRAM_BF16X6, "auto": GRAM_AUTO}
 PREC_NAMES = {v: k for k, v in _PREC.items()}
 PREC_CODES = dict(_PREC)
 STATUS = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EHIP", 4: "ENOCONV", 5: "EUNSUPPORTED"}
@@ -38,7 +38,8 @@ EXPORTS = [
     "tucker_batch_norm2", "tucker_batch_item", "tucker_batch_tiles", "tucker_batch_free",
     "tucker_op_size", "tucker_reconstruct_order_rule", "tucker_reconstruct_ops", "tucker_slice_stats",
     "tucker_scaling_vectors", "tucker_slice_transform", "tucker_preprocess", "tucker_set_postprocess",
-    "tucker_create",
+    "tucker_create", "tucker_sthosvd_ranks", "tucker_sthosvd_memory", "tucker_set_allocator", "tucker_gram_scaled",
+    "tucker_batch_status", "tucker_empty_cache",
 ]
 
 OP_KINDS = {"identity": 0, "range": 1, "average": 2, "sum": 3, "mean": 4, "matrix": 5}
@@ -106,6 +107,12 @@ def lib():
             "tucker_preprocess": (i32, [P, i32, P, i32, i32, i32, P, i32, P, P, P]),
             "tucker_set_postprocess": (i32, [P, i32, P, P, P]),
             "tucker_create": (i32, [P, i32, P, P, i32, P, P, PP]),
+            "tucker_sthosvd_ranks": (i32, [P, i32, P, i32, P, P, i32, P, PP]),
+            "tucker_sthosvd_memory": (i32, [i32, P, i32, P, P, i32, P]),
+            "tucker_set_allocator": (i32, [P]),
+            "tucker_gram_scaled": (i32, [P, P]),
+            "tucker_batch_status": (i32, [P, P]),
+            "tucker_empty_cache": (i32, []),
             "tucker_last_error": (ctypes.c_char_p, []),
             "tucker_version": (ctypes.c_char_p, []),
         }
@@ -213,8 +220,12 @@ class Tucker:
         self.timings = [Timing(ms[4 * n], ms[4 * n + 1], ms[4 * n + 2], ms[4 * n + 3]) for n in range(self.N)]
         gp = (ctypes.c_int * self.N)()
         _check(L.tucker_gram_precision(handle, gp))
-        # per mode: the Gram arithmetic used ("fp64" where the range guard redid it)
+        # per mode: the Gram arithmetic used ("fp64" where the range handling fell back to it)
         self.gram_precision = [PREC_NAMES[v] for v in gp]
+        sc = (ctypes.c_int * self.N)()
+        _check(L.tucker_gram_scaled(handle, sc))
+        # per mode: True if the Gram ran on the per-slice scaled copy
+        self.gram_scaled = [bool(v) for v in sc]
 
     def _alive(self):
         if not self._h:
@@ -437,6 +448,65 @@ def from_model(core, factors, dims=None, stream=None) -> Tucker:
     return Tucker(h.value, s, "fp64")
 
 
+def sthosvd_ranks(x, ranks, mode_order=None, prec: str = "fp64", dims=None, stream=None) -> Tucker:
+    """Fixed-rank ST-HOSVD: R_n = min(ranks[n], J_n) (the core size is given)."""
+    dims = _dims_of(x, dims)
+    h = ctypes.c_void_p(0)
+    s = _stream(stream)
+    _check(lib().tucker_sthosvd_ranks(x.data_ptr(), _dtype_code(x), _i64(dims), len(dims), _i64(ranks),
+                                      _i32(mode_order) if mode_order is not None else None, _PREC[prec], s,
+                                      ctypes.byref(h)))
+    return Tucker(h.value, s, prec)
+
+
+def sthosvd_memory(dims, dtype: int = F64, ranks=None, mode_order=None, prec: str = "fp64") -> int:
+    """Predicted device bytes of a compression (ranks None = no truncation bound)."""
+    b = ctypes.c_size_t(0)
+    _check(lib().tucker_sthosvd_memory(int(dtype), _i64(dims), len(dims), _i64(ranks) if ranks is not None else None,
+                                       _i32(mode_order) if mode_order is not None else None, _PREC[prec],
+                                       ctypes.byref(b)))
+    return b.value
+
+
+class _Allocator(ctypes.Structure):
+    _fields_ = [("alloc", ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)),
+                ("free", ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)),
+                ("ctx", ctypes.c_void_p)]
+
+
+_torch_alloc = None
+
+
+def use_torch_allocator(enable: bool = True):
+    """Route every device allocation of the library through PyTorch's caching
+    allocator (tucker_set_allocator with ctypes callbacks), so that PyTorch
+    provides the memory; enable=False restores the library's own pool."""
+    global _torch_alloc
+    if not enable:
+        _check(lib().tucker_set_allocator(None))
+        _torch_alloc = None
+        return
+    import torch
+
+    def _alloc(nbytes, ctx, stream):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), torch.cuda.current_device(), stream or 0)
+        except Exception:
+            return None
+
+    def _free(ptr, ctx, stream):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    a = _Allocator(_Allocator._fields_[0][1](_alloc), _Allocator._fields_[1][1](_free), None)
+    _check(lib().tucker_set_allocator(ctypes.byref(a)))
+    _torch_alloc = a  # the callbacks must outlive their use
+
+
+def empty_cache():
+    """Return the library pool's idle device blocks to HIP."""
+    _check(lib().tucker_empty_cache())
+
+
 def reconstruct_order(ranks, out_sizes):
     """Flop-minimising Multi-TTM order (host rule of Sec. 8)."""
     N = len(ranks)
@@ -536,6 +606,12 @@ class Batch:
         h = ctypes.c_void_p(0)
         _check(lib().tucker_batch_item(self._h, int(i), ctypes.byref(h)))
         return Tucker(h.value, 0)
+
+    def status(self):
+        """Per tensor: 1 non-finite data, 2 a Gram recomputed in FP64 (bits)."""
+        out = (ctypes.c_int * self.count)()
+        _check(lib().tucker_batch_status(self._h, out))
+        return list(out)
 
     def tiles(self):
         g, t = ctypes.c_int(0), ctypes.c_int(0)

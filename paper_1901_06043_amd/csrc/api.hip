@@ -73,9 +73,17 @@ struct CachedBlock {
   hipStream_t stream;
   int dev;
 };
+struct LiveBlock {
+  void* p;
+  size_t bytes;
+  bool external;         // from a caller-supplied allocator (returned to it, not cached)
+  tucker_allocator ext;  // that allocator
+};
 std::mutex g_cache_mu;
-std::vector<CachedBlock> g_cache_free;                 // idle blocks
-std::vector<std::pair<void*, size_t>> g_cache_live;    // blocks in use and their sizes
+std::vector<CachedBlock> g_cache_free;  // idle blocks
+std::vector<LiveBlock> g_cache_live;    // blocks in use
+bool g_ext_set = false;                 // tucker_set_allocator
+tucker_allocator g_ext{};
 
 size_t round_bytes(size_t b) {
   b = std::max<size_t>(b, 256);
@@ -88,6 +96,21 @@ hipError_t dev_alloc(void** out, size_t bytes, hipStream_t s) {
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return e;
   bytes = round_bytes(bytes);
+  tucker_allocator ext{};
+  bool use_ext = false;
+  {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    use_ext = g_ext_set;
+    ext = g_ext;
+  }
+  if (use_ext) {
+    void* p = ext.alloc(bytes, ext.ctx, s);
+    if (!p) return hipErrorOutOfMemory;
+    *out = p;
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    g_cache_live.push_back({p, bytes, true, ext});
+    return hipSuccess;
+  }
   {
     std::lock_guard<std::mutex> lk(g_cache_mu);
     int best = -1;
@@ -98,7 +121,7 @@ hipError_t dev_alloc(void** out, size_t bytes, hipStream_t s) {
     }
     if (best >= 0) {
       *out = g_cache_free[best].p;
-      g_cache_live.push_back({*out, g_cache_free[best].bytes});
+      g_cache_live.push_back({*out, g_cache_free[best].bytes, false, {}});
       g_cache_free.erase(g_cache_free.begin() + best);
       return hipSuccess;
     }
@@ -127,7 +150,7 @@ hipError_t dev_alloc(void** out, size_t bytes, hipStream_t s) {
         }
         if (best >= 0) {
           *out = g_cache_free[best].p;
-          g_cache_live.push_back({*out, g_cache_free[best].bytes});
+          g_cache_live.push_back({*out, g_cache_free[best].bytes, false, {}});
           g_cache_free.erase(g_cache_free.begin() + best);
           return hipSuccess;
         }
@@ -169,9 +192,30 @@ hipError_t dev_alloc(void** out, size_t bytes, hipStream_t s) {
   }
   if (e == hipSuccess) {
     std::lock_guard<std::mutex> lk(g_cache_mu);
-    g_cache_live.push_back({*out, bytes});
+    g_cache_live.push_back({*out, bytes, false, {}});
   }
   return e;
+}
+
+// Bytes the built-in pool can hand out on this device without a failed
+// allocation: free device memory plus idle cached blocks.  SIZE_MAX when a
+// caller-supplied allocator is set (its capacity is not known here).
+size_t dev_available() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  size_t idle = 0;
+  {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    if (g_ext_set) return SIZE_MAX;
+    for (const CachedBlock& b : g_cache_free)
+      if (b.dev == dev) idle += b.bytes;
+  }
+  size_t fr = 0, tot = 0;
+  if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
+    (void)hipGetLastError();
+    return SIZE_MAX;
+  }
+  return fr + idle;
 }
 
 // Return a block to the cache; it may be reused by later work on stream s.
@@ -179,14 +223,21 @@ void dev_free(void* p, hipStream_t s) {
   if (!p) return;
   int dev = 0;
   (void)hipGetDevice(&dev);
-  std::lock_guard<std::mutex> lk(g_cache_mu);
-  for (size_t i = 0; i < g_cache_live.size(); ++i)
-    if (g_cache_live[i].first == p) {
-      g_cache_free.push_back({p, g_cache_live[i].second, s, dev});
-      g_cache_live[i] = g_cache_live.back();
-      g_cache_live.pop_back();
-      return;
-    }
+  tucker_allocator ext{};
+  bool external = false;
+  {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    for (size_t i = 0; i < g_cache_live.size(); ++i)
+      if (g_cache_live[i].p == p) {
+        external = g_cache_live[i].external;
+        ext = g_cache_live[i].ext;
+        if (!external) g_cache_free.push_back({p, g_cache_live[i].bytes, s, dev});
+        g_cache_live[i] = g_cache_live.back();
+        g_cache_live.pop_back();
+        break;
+      }
+  }
+  if (external) ext.free(p, ext.ctx, s);  // outside the lock: the callback may allocate
 }
 
 // Temporary device buffer returned to the cache (stream-ordered) on scope exit.
@@ -344,6 +395,7 @@ struct tucker_t {
   double norm2 = 0.0;
   tucker_dtype core_dtype = TUCKER_F64;
   tucker_gram_prec prec_used[TUCKER_MAX_MODES] = {TUCKER_GRAM_FP64};
+  int scaled[TUCKER_MAX_MODES] = {0};  // per mode: 1 if its Gram ran with per-slice scaling
   void* core = nullptr;
   double* U[TUCKER_MAX_MODES] = {nullptr};
   double* lam[TUCKER_MAX_MODES] = {nullptr};
@@ -444,25 +496,123 @@ tucker_status tucker_reconstruct_order(int N, const int64_t* ranks, const int64_
   return TUCKER_OK;
 }
 
-tucker_status tucker_sthosvd(const void* data, tucker_dtype dtype, const int64_t* dims, int N, double eps,
-                             const int* mode_order, tucker_gram_prec prec, hipStream_t stream, tucker_t** out) {
+}  // extern "C"
+
+namespace {
+
+// Predicted unit roundoff-level error of a reduced Gram, relative to ||Y||^2
+// (the selection rule of TUCKER_GRAM_AUTO): FP32 and BF16X6 carry the FP32
+// rounding of the working tensor and of the accumulation, 2^-23; BF16X3 its
+// systematic under-estimate, 2^-16 / 3 of the trace (the dropped product).
+constexpr double kAutoErrFp32 = 0x1p-23;
+constexpr double kAutoErrBf16x3 = 0x1p-16 / 3.0;
+
+tucker_gram_prec resolve_auto(tucker_dtype dtype, int N, double eps, bool fixed) {
+  if (dtype != TUCKER_F32 || fixed) return TUCKER_GRAM_FP64;
+  // slack of the 1.05 eps target in the truncation rule, relative to ||X||^2
+  const double slack = (1.05 * 1.05 - 1.0) * eps * eps / N;
+  if (kAutoErrBf16x3 <= 0.01 * slack) return TUCKER_GRAM_BF16X3;
+  if (kAutoErrFp32 <= 0.01 * slack) return TUCKER_GRAM_FP32;
+  return TUCKER_GRAM_FP64;
+}
+
+// Scratch of one Gram of mode n (split-K partials and sums of squares).
+int64_t gram_scratch_doubles(const int64_t* dims, int N, int n, tucker_gram_prec prec) {
+  int64_t L, Rt;
+  left_right(dims, N, n, L, Rt);
+  const int64_t J = dims[n], K = L * Rt;
+  tk::GramPlan p;
+  if (J <= tk::kStreamMaxJ) p = tk::plan_gram_stream((int)J, (uint64_t)K, (int)prec);
+  else if (prec == TUCKER_GRAM_FP64 && J <= tk::kTriMaxJ) p = tk::plan_gram_f64((int)J, (uint64_t)L, (uint64_t)K);
+  else p = tk::plan_gram_mp((int)J, (uint64_t)K, (int)prec);
+  return p.part_elems + p.sq_elems;
+}
+
+// Device memory of one compression (the input excluded), following the
+// allocations of sthosvd_impl: the handle's factors, eigenvalues and
+// scalars, the Gram and eigensolver workspaces, and per step the current and
+// next working tensors plus that step's Gram scratch (and, for the reduced
+// forms, what the per-slice scaled pass needs).  `ranks` = NULL takes R_n =
+// J_n at every step (an upper bound when the ranks are not known).
+size_t predict_bytes(tucker_dtype dtype, const int64_t* dims, int N, const int64_t* ranks, const int* order,
+                     tucker_gram_prec prec) {
+  const bool reduced = (prec != TUCKER_GRAM_FP64);
+  const size_t wsz = reduced ? 4 : 8;
+  int64_t maxJ = 0;
+  for (int k = 0; k < N; ++k) maxJ = std::max(maxJ, dims[k]);
+  size_t fixed = round_bytes(sizeof(double) * (2 + 3 * TUCKER_MAX_MODES)) + round_bytes(8 * TUCKER_MAX_MODES) +
+                 round_bytes(sizeof(double) * maxJ * maxJ) +
+                 round_bytes(sizeof(double) * tk::eig_work_doubles(maxJ));
+  for (int k = 0; k < N; ++k)
+    fixed += round_bytes(sizeof(double) * dims[k] * dims[k]) + round_bytes(sizeof(double) * dims[k]);
+  int64_t cur[TUCKER_MAX_MODES];
+  std::memcpy(cur, dims, sizeof(int64_t) * N);
+  size_t peak = 0;
+  for (int s = 0; s < N; ++s) {
+    const int n = order[s];
+    int64_t total = 1;
+    for (int k = 0; k < N; ++k) total *= cur[k];
+    const int64_t J = cur[n];
+    const int64_t R = ranks ? std::min<int64_t>(ranks[n], J) : J;
+    const size_t ycur = (s == 0) ? 0 : round_bytes(wsz * total);
+    const size_t ynext = round_bytes(wsz * (total / J * R));
+    size_t gram = round_bytes(sizeof(double) * gram_scratch_doubles(cur, N, n, prec));
+    if (reduced) {
+      int64_t L, Rt;
+      left_right(cur, N, n, L, Rt);
+      gram += round_bytes(4 * total) + round_bytes(sizeof(double) * tk::slice_stats_work_doubles(L, J, Rt)) +
+              3 * round_bytes(sizeof(double) * TUCKER_NSTATS * J);
+    }
+    // the Gram scratch is released before the next working tensor is allocated
+    peak = std::max(peak, ycur + std::max(gram, ynext));
+    cur[n] = R;
+  }
+  (void)dtype;
+  return fixed + peak;
+}
+
+tucker_status fits(size_t bytes, const char* what) {
+  const size_t avail = dev_available();
+  if (bytes > avail)
+    return fail(TUCKER_ENOMEM, "%s needs %.3f GB of device memory; %.3f GB are available", what, bytes / 1e9,
+                avail / 1e9);
+  return TUCKER_OK;
+}
+
+// ST-HOSVD (Alg. 1) with the eq. Un rank rule, or with given ranks.
+tucker_status sthosvd_impl(const void* data, tucker_dtype dtype, const int64_t* dims, int N, double eps,
+                           const int64_t* fixed_ranks, const int* mode_order, tucker_gram_prec prec,
+                           hipStream_t stream, tucker_t** out) {
   if (!out) return fail(TUCKER_EINVAL, "out is NULL");
   *out = nullptr;
   if (!data) return fail(TUCKER_EINVAL, "data is NULL");
   if (dtype != TUCKER_F32 && dtype != TUCKER_F64) return fail(TUCKER_EINVAL, "bad dtype");
-  if (prec < TUCKER_GRAM_FP64 || prec > TUCKER_GRAM_BF16X6) return fail(TUCKER_EINVAL, "bad Gram precision");
-  if (prec != TUCKER_GRAM_FP64 && dtype != TUCKER_F32)
+  if (prec < TUCKER_GRAM_FP64 || prec > TUCKER_GRAM_AUTO) return fail(TUCKER_EINVAL, "bad Gram precision");
+  if (prec != TUCKER_GRAM_FP64 && prec != TUCKER_GRAM_AUTO && dtype != TUCKER_F32)
     return fail(TUCKER_EINVAL, "reduced-precision Gram needs FP32 data");
-  if (!(eps >= 0.0) || !std::isfinite(eps)) return fail(TUCKER_EINVAL, "eps must be finite and >= 0");
+  if (!fixed_ranks && (!(eps >= 0.0) || !std::isfinite(eps)))
+    return fail(TUCKER_EINVAL, "eps must be finite and >= 0");
   tucker_status st = validate_dims(dims, N);
   if (st) return st;
+  if (fixed_ranks)
+    for (int k = 0; k < N; ++k)
+      if (fixed_ranks[k] < 1) return fail(TUCKER_EINVAL, "ranks[%d]=%lld < 1", k, (long long)fixed_ranks[k]);
   int order[TUCKER_MAX_MODES];
   if ((st = validate_order(mode_order, N, order))) return st;
   for (int k = 0; k < N; ++k)
     if (dims[k] > kMaxEigJ)
       return fail(TUCKER_EUNSUPPORTED, "mode %d has size %lld; the eigensolver supports up to %lld", k,
                   (long long)dims[k], (long long)kMaxEigJ);
+  if (prec == TUCKER_GRAM_AUTO) prec = resolve_auto(dtype, N, eps, fixed_ranks != nullptr);
   if ((st = ensure_device())) return st;
+  // memory: the whole run when the ranks are given, else what the first step needs
+  {
+    int64_t first[TUCKER_MAX_MODES];
+    for (int k = 0; k < N; ++k) first[k] = (k == order[0]) ? dims[k] : 1;
+    const size_t need = fixed_ranks ? predict_bytes(dtype, dims, N, fixed_ranks, order, prec)
+                                    : predict_bytes(dtype, dims, N, first, order, prec);
+    if ((st = fits(need, "the compression"))) return st;
+  }
 
   HandleGuard g(new tucker_t);
   tucker_t* t = g.t;
@@ -479,6 +629,8 @@ tucker_status tucker_sthosvd(const void* data, tucker_dtype dtype, const int64_t
   double* d_sq = t->scalars + 2 + TUCKER_MAX_MODES;
   double* d_flag = t->scalars + 2 + 2 * TUCKER_MAX_MODES;
   const bool reduced = (prec != TUCKER_GRAM_FP64);
+  // with given ranks in FP64 nothing depends on a read-back: one synchronisation at the end
+  const bool async = fixed_ranks && !reduced;
 
   void* hp = nullptr;
   if ((st = pinned(&hp))) return st;
@@ -505,11 +657,12 @@ tucker_status tucker_sthosvd(const void* data, tucker_dtype dtype, const int64_t
   TmpBuf Sbuf, ewbuf;
   HIP_TRY(Sbuf.alloc(sizeof(double) * maxJ * maxJ, stream));
   HIP_TRY(ewbuf.alloc(sizeof(double) * tk::eig_work_doubles(maxJ), stream));
-  const double thr_mul = eps * eps / N;
+  const double thr_mul = fixed_ranks ? 0.0 : eps * eps / N;
 
   for (int step = 0; step < N; ++step) {
     const int n = order[step];
     const int64_t J = cur[n];
+    const int fixed = fixed_ranks ? (int)std::min<int64_t>(fixed_ranks[n], J) : 0;
     hipEvent_t* ev = evs.ev + 5 * step;
     HIP_TRY(t->alloc((void**)&t->U[n], sizeof(double) * J * J));
     HIP_TRY(t->alloc((void**)&t->lam[n], sizeof(double) * J));
@@ -517,32 +670,74 @@ tucker_status tucker_sthosvd(const void* data, tucker_dtype dtype, const int64_t
     tk::EigWork w;
     tk::eig_work_carve(ewbuf.as<double>(), J, w);
     t->prec_used[n] = prec;
+    int64_t L, Rt;
+    left_right(cur, N, n, L, Rt);
     double* sqp = (step == 0) ? d_nx2 : (reduced ? d_sq + step : nullptr);
-    // Gram (+ range guard) and eigensolve; a second pass in FP64 if the guard fired
-    for (int pass = 0; pass < 2; ++pass) {
-      const tucker_gram_prec pp = (pass == 0) ? prec : TUCKER_GRAM_FP64;
+    // Gram (+ range guard) and eigensolve.  Reduced forms: if the guard fires,
+    // a second pass with per-slice power-of-two scaling, and FP64 if that
+    // fires too.
+    for (int pass = 0; pass < 3; ++pass) {
+      if (pass > 0 && !reduced) break;
+      const tucker_gram_prec pp = (pass < 2) ? prec : TUCKER_GRAM_FP64;
       HIP_TRY(hipEventRecord(ev[0], stream));
-      if ((st = run_gram(Y, ydt, cur, N, n, pp, Sbuf.as<double>(), sqp, stream, ev[4]))) return st;
-      if (pp != TUCKER_GRAM_FP64) HIP_TRY(tk::launch_gram_guard(Sbuf.as<double>(), (int)J, sqp, d_flag + step, stream));
-      HIP_TRY(hipEventRecord(ev[1], stream));
-      HIP_TRY(tk::launch_eig_values(Sbuf.as<double>(), (int)J, thr_mul, d_nx2, nullptr, w, t->lam[n],
-                                    t->dranks + n, d_disc + n, stream));
-      // the rank (and flag, norm) go to the host while the eigenvectors are formed,
-      // so that the next launches are enqueued before the GPU runs out of work
-      HIP_TRY(hipMemcpyAsync(h_R, t->dranks + n, sizeof(int64_t), hipMemcpyDeviceToHost, stream));
+      TmpBuf stats, pscale, zero, scaled;
+      if (pass == 1) {
+        // each slice of mode n divided by a power of two near its largest
+        // magnitude (exact), the Gram of that copy, S multiplied back
+        HIP_TRY(stats.alloc(sizeof(double) * TUCKER_NSTATS * J, stream));
+        HIP_TRY(pscale.alloc(sizeof(double) * J, stream));
+        HIP_TRY(zero.alloc(sizeof(double) * J, stream));
+        TmpBuf work;
+        HIP_TRY(work.alloc(sizeof(double) * tk::slice_stats_work_doubles(L, J, Rt), stream));
+        if (ydt == TUCKER_F64)
+          HIP_TRY(tk::launch_slice_stats(static_cast<const double*>(Y), L, J, Rt, false, work.as<double>(),
+                                         stats.as<double>(), stream));
+        else
+          HIP_TRY(tk::launch_slice_stats(static_cast<const float*>(Y), L, J, Rt, false, work.as<double>(),
+                                         stats.as<double>(), stream));
+        HIP_TRY(tk::launch_slice_pow2(stats.as<double>(), J, pscale.as<double>(), stream));
+        HIP_TRY(tk::launch_fill(zero.as<double>(), J, 0.0, stream));
+        const uint64_t total = (uint64_t)(L * J * Rt);
+        HIP_TRY(scaled.alloc(sizeof(float) * total, stream));
+        if (ydt == TUCKER_F64)
+          HIP_TRY(tk::launch_slice_transform(static_cast<const double*>(Y), scaled.as<float>(), total, L, J,
+                                             zero.as<double>(), pscale.as<double>(), false, stream));
+        else
+          HIP_TRY(tk::launch_slice_transform(static_cast<const float*>(Y), scaled.as<float>(), total, L, J,
+                                             zero.as<double>(), pscale.as<double>(), false, stream));
+        // the FP64 sum of squares of the unscaled tensor is already known (pass 0)
+        if ((st = run_gram(scaled.p, TUCKER_F32, cur, N, n, pp, Sbuf.as<double>(), nullptr, stream, ev[4]))) return st;
+        HIP_TRY(tk::launch_gram_unscale(Sbuf.as<double>(), J, pscale.as<double>(), stream));
+      } else {
+        if ((st = run_gram(Y, ydt, cur, N, n, pp, Sbuf.as<double>(), sqp, stream, ev[4]))) return st;
+      }
       if (pp != TUCKER_GRAM_FP64)
-        HIP_TRY(hipMemcpyAsync(h_flag, d_flag + step, sizeof(double), hipMemcpyDeviceToHost, stream));
-      if (step == 0) HIP_TRY(hipMemcpyAsync(h_nx2, d_nx2, sizeof(double), hipMemcpyDeviceToHost, stream));
-      HIP_TRY(hipEventRecord(rank_ready, stream));
+        HIP_TRY(tk::launch_gram_guard(Sbuf.as<double>(), (int)J, pass == 1 ? 0.0 : (double)(L * Rt),
+                                      sqp ? sqp : d_sq + step, d_flag + step, stream));
+      HIP_TRY(hipEventRecord(ev[1], stream));
+      HIP_TRY(tk::launch_eig_values(Sbuf.as<double>(), (int)J, thr_mul, fixed_ranks ? nullptr : d_nx2, fixed, w,
+                                    t->lam[n], t->dranks + n, d_disc + n, stream));
+      if (!async) {
+        // the rank (and flag, norm) go to the host while the eigenvectors are
+        // formed, so that the next launches are enqueued before the GPU runs
+        // out of work
+        HIP_TRY(hipMemcpyAsync(h_R, t->dranks + n, sizeof(int64_t), hipMemcpyDeviceToHost, stream));
+        if (pp != TUCKER_GRAM_FP64)
+          HIP_TRY(hipMemcpyAsync(h_flag, d_flag + step, sizeof(double), hipMemcpyDeviceToHost, stream));
+        if (step == 0) HIP_TRY(hipMemcpyAsync(h_nx2, d_nx2, sizeof(double), hipMemcpyDeviceToHost, stream));
+        HIP_TRY(hipEventRecord(rank_ready, stream));
+      }
       HIP_TRY(tk::launch_eig_vectors((int)J, w, t->lam[n], t->dranks + n, t->U[n], stream));
       HIP_TRY(hipEventRecord(ev[2], stream));
+      if (async) break;
       HIP_TRY(hipEventSynchronize(rank_ready));
       if (pp == TUCKER_GRAM_FP64 || h_flag[0] == 0.0) break;
-      t->prec_used[n] = TUCKER_GRAM_FP64;
+      if (pass == 0) t->scaled[n] = 1;
+      else t->prec_used[n] = TUCKER_GRAM_FP64;
     }
-    const int64_t R = h_R[0];
+    const int64_t R = async ? fixed : h_R[0];
     if (R < 1 || R > J) return fail(TUCKER_ENOCONV, "eigensolver returned rank %lld for J=%lld", (long long)R, (long long)J);
-    if (step == 0) {
+    if (step == 0 && !async) {
       // non-finite data shows up as a non-finite norm
       const double nx2 = h_nx2[0];  // read back with the rank
       if (!std::isfinite(nx2)) return fail(TUCKER_EINVAL, "data contains non-finite values (||X||^2 = %g)", nx2);
@@ -553,6 +748,7 @@ tucker_status tucker_sthosvd(const void* data, tucker_dtype dtype, const int64_t
     int64_t total = 1;
     for (int k = 0; k < N; ++k) total *= cur[k];
     const int64_t next_elems = total / J * R;
+    if (!async && (st = fits(round_bytes(dtype_size(wdt) * next_elems), "the next working tensor"))) return st;
     TmpBuf nbuf;
     HIP_TRY(nbuf.alloc(dtype_size(wdt) * next_elems, stream));
     if ((st = run_ttm(Y, ydt, cur, N, n, t->U[n], R, J, 1, nbuf.p, wdt, reduced, stream))) return st;
@@ -570,7 +766,13 @@ tucker_status tucker_sthosvd(const void* data, tucker_dtype dtype, const int64_t
   t->owned.push_back(ybuf.p);
   ybuf.p = nullptr;
   HIP_TRY(hipMemcpyAsync(t->disc, d_disc, sizeof(double) * N, hipMemcpyDeviceToHost, stream));
+  if (async) HIP_TRY(hipMemcpyAsync(h_nx2, d_nx2, sizeof(double), hipMemcpyDeviceToHost, stream));
   HIP_TRY(hipStreamSynchronize(stream));
+  if (async) {
+    const double nx2 = h_nx2[0];
+    if (!std::isfinite(nx2)) return fail(TUCKER_EINVAL, "data contains non-finite values (||X||^2 = %g)", nx2);
+    t->norm2 = nx2;
+  }
   for (int step = 0; step < N; ++step) {
     const int n = order[step];
     float a = 0, b = 0, c = 0, k = 0;
@@ -585,6 +787,74 @@ tucker_status tucker_sthosvd(const void* data, tucker_dtype dtype, const int64_t
     t->ms[4 * n + 3] = k;
   }
   *out = g.take();
+  return TUCKER_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+tucker_status tucker_sthosvd(const void* data, tucker_dtype dtype, const int64_t* dims, int N, double eps,
+                             const int* mode_order, tucker_gram_prec prec, hipStream_t stream, tucker_t** out) {
+  return sthosvd_impl(data, dtype, dims, N, eps, nullptr, mode_order, prec, stream, out);
+}
+
+tucker_status tucker_sthosvd_ranks(const void* data, tucker_dtype dtype, const int64_t* dims, int N,
+                                   const int64_t* ranks, const int* mode_order, tucker_gram_prec prec,
+                                   hipStream_t stream, tucker_t** out) {
+  if (!ranks) {
+    if (out) *out = nullptr;
+    return fail(TUCKER_EINVAL, "ranks is NULL");
+  }
+  return sthosvd_impl(data, dtype, dims, N, 0.0, ranks, mode_order, prec, stream, out);
+}
+
+tucker_status tucker_sthosvd_memory(tucker_dtype dtype, const int64_t* dims, int N, const int64_t* ranks,
+                                    const int* mode_order, tucker_gram_prec prec, size_t* bytes) {
+  if (!bytes) return fail(TUCKER_EINVAL, "bytes is NULL");
+  if (dtype != TUCKER_F32 && dtype != TUCKER_F64) return fail(TUCKER_EINVAL, "bad dtype");
+  if (prec < TUCKER_GRAM_FP64 || prec > TUCKER_GRAM_BF16X6) return fail(TUCKER_EINVAL, "bad Gram precision");
+  tucker_status st = validate_dims(dims, N);
+  if (st) return st;
+  if (ranks)
+    for (int k = 0; k < N; ++k)
+      if (ranks[k] < 1) return fail(TUCKER_EINVAL, "ranks[%d] < 1", k);
+  int order[TUCKER_MAX_MODES];
+  if ((st = validate_order(mode_order, N, order))) return st;
+  *bytes = predict_bytes(dtype, dims, N, ranks, order, prec);
+  return TUCKER_OK;
+}
+
+tucker_status tucker_set_allocator(const tucker_allocator* a) {
+  if (a && (!a->alloc || !a->free)) return fail(TUCKER_EINVAL, "allocator needs alloc and free");
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  g_ext_set = (a != nullptr);
+  g_ext = a ? *a : tucker_allocator{};
+  return TUCKER_OK;
+}
+
+tucker_status tucker_empty_cache(void) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(TUCKER_EHIP, "no HIP device");
+  std::vector<void*> drop;
+  {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    for (int i = (int)g_cache_free.size() - 1; i >= 0; --i)
+      if (g_cache_free[i].dev == dev) {
+        drop.push_back(g_cache_free[i].p);
+        g_cache_free.erase(g_cache_free.begin() + i);
+      }
+  }
+  if (!drop.empty()) {
+    HIP_TRY(hipDeviceSynchronize());  // idle blocks may still be read by work in flight
+    for (void* p : drop) HIP_TRY(hipFree(p));
+  }
+  return TUCKER_OK;
+}
+
+tucker_status tucker_gram_scaled(const tucker_t* t, int* o) {
+  if (!t || !o) return fail(TUCKER_EINVAL, "NULL argument");
+  std::memcpy(o, t->scaled, sizeof(int) * t->N);
   return TUCKER_OK;
 }
 
@@ -1009,7 +1279,7 @@ tucker_status tucker_eig_truncate(const double* S, int64_t J, double thr, double
   HIP_TRY(wb.alloc(sizeof(double) * tk::eig_work_doubles(J), stream));
   tk::EigWork w;
   tk::eig_work_carve(wb.as<double>(), J, w);
-  HIP_TRY(tk::launch_eig_truncate(S, (int)J, thr, nullptr, nullptr, w, lam, U, R, disc, stream));
+  HIP_TRY(tk::launch_eig_truncate(S, (int)J, thr, nullptr, 0, w, lam, U, R, disc, stream));
   return TUCKER_OK;
 }
 
@@ -1038,6 +1308,11 @@ namespace {
 __global__ void batch_reset_cur_kernel(const int64_t* __restrict__ dims0, int64_t* __restrict__ cur, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) cur[i] = dims0[i];
+}
+
+__global__ void batch_zero_int_kernel(int* __restrict__ p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
 }
 
 __global__ void batch_set_rank_kernel(const int64_t* __restrict__ R, int count, int N, int n,
@@ -1083,6 +1358,9 @@ struct tucker_batch {
   int tn[TUCKER_MAX_MODES] = {0};
   double *part = nullptr, *sq = nullptr, *S = nullptr, *A = nullptr, *Zt = nullptr, *dd = nullptr, *ee = nullptr,
          *tau = nullptr, *scal = nullptr, *nx2 = nullptr;
+  double* sqs = nullptr;  // per step s >= 1 and tensor: FP64 sum of squares of the working tensor
+  int* gflag = nullptr;   // per tensor: the last reduced Gram was flagged by the range guard
+  int* status = nullptr;  // per tensor: 1 non-finite data, 2 a Gram recomputed in FP64
   double* U[TUCKER_MAX_MODES] = {nullptr};
   double* lam[TUCKER_MAX_MODES] = {nullptr};
   int64_t* R[TUCKER_MAX_MODES] = {nullptr};
@@ -1091,6 +1369,7 @@ struct tucker_batch {
   std::vector<int64_t> hR;     // count x N
   std::vector<double> hnorm2;  // count
   std::vector<double> hdisc;   // count x N
+  std::vector<int> hstatus;    // count
 
   hipError_t alloc(void** p, size_t bytes) {
     hipError_t e = dev_alloc(p, bytes, alloc_stream);
@@ -1174,10 +1453,26 @@ tucker_status batch_enqueue_gram(tucker_batch* b, int s, hipStream_t stream) {
   g.part = b->part;
   g.sq = b->sq;
   g.S = b->S;
-  g.nx2 = (s == 0) ? b->nx2 : nullptr;
+  // per-tensor FP64 sums of squares: ||X_t||^2 at the first step, the working
+  // tensor's later (the range guard compares the trace with them)
+  g.nx2 = (s == 0) ? b->nx2 : b->sqs + (size_t)s * b->count;
+  g.flag = nullptr;
+  g.chunk_mul = 1;
   const tucker_dtype ydt = (s == 0) ? b->in_dt : b->wdt;
   if (ydt == TUCKER_F64) HIP_TRY(tk::launch_gram_batched<double>(g, (int)b->prec, n == 0, stream));
   else HIP_TRY(tk::launch_gram_batched<float>(g, (int)b->prec, n == 0, stream));
+  if (b->prec != TUCKER_GRAM_FP64) {
+    // range guard per tensor, then the flagged tensors' Grams again in FP64
+    // (launched unconditionally; items of other tensors return at once, so a
+    // captured run stays valid whatever the data)
+    HIP_TRY(tk::launch_gram_guard_batched(g, b->gflag, b->status, stream));
+    tk::GramBatch g2 = g;
+    g2.flag = b->gflag;
+    g2.chunk_mul = 2;  // the plan's 32-column chunks in FP64's 16-column chunks
+    g2.nx2 = nullptr;
+    g2.sq = nullptr;
+    HIP_TRY(tk::launch_gram_batched<float>(g2, (int)TUCKER_GRAM_FP64, n == 0, stream));
+  }
   return TUCKER_OK;
 }
 
@@ -1232,6 +1527,8 @@ tucker_status batch_enqueue_eig(tucker_batch* b, int s, hipStream_t stream) {
 tucker_status batch_enqueue_all(tucker_batch* b, hipStream_t stream) {
   const int64_t nc = (int64_t)b->count * b->N;
   hipLaunchKernelGGL(batch_reset_cur_kernel, dim3(ceil_div(nc, 256)), dim3(256), 0, stream, b->dims0, b->cur, nc);
+  hipLaunchKernelGGL(batch_zero_int_kernel, dim3(ceil_div(b->count, 256)), dim3(256), 0, stream, b->status,
+                     (int64_t)b->count);
   HIP_TRY(hipGetLastError());
   tucker_status st;
   for (int s = 0; s < b->N; ++s) {
@@ -1291,12 +1588,13 @@ tucker_status tucker_batch_create(int count, const void* const* data, tucker_dty
   if (count < 1) return fail(TUCKER_EINVAL, "count=%d < 1", count);
   if (!data || !dims) return fail(TUCKER_EINVAL, "NULL argument");
   if (dtype != TUCKER_F32 && dtype != TUCKER_F64) return fail(TUCKER_EINVAL, "bad dtype");
-  if (prec < TUCKER_GRAM_FP64 || prec > TUCKER_GRAM_BF16X6) return fail(TUCKER_EINVAL, "bad Gram precision");
-  if (prec != TUCKER_GRAM_FP64 && dtype != TUCKER_F32)
+  if (prec < TUCKER_GRAM_FP64 || prec > TUCKER_GRAM_AUTO) return fail(TUCKER_EINVAL, "bad Gram precision");
+  if (prec != TUCKER_GRAM_FP64 && prec != TUCKER_GRAM_AUTO && dtype != TUCKER_F32)
     return fail(TUCKER_EINVAL, "reduced-precision Gram needs FP32 data");
   if (!(eps >= 0.0) || !std::isfinite(eps)) return fail(TUCKER_EINVAL, "eps must be finite and >= 0");
   tucker_status st;
   if (N < 1 || N > TUCKER_MAX_MODES) return fail(TUCKER_EINVAL, "N=%d outside 1..%d", N, TUCKER_MAX_MODES);
+  if (prec == TUCKER_GRAM_AUTO) prec = resolve_auto(dtype, N, eps, false);
   for (int t = 0; t < count; ++t) {
     if (!data[t]) return fail(TUCKER_EINVAL, "data[%d] is NULL", t);
     if ((st = validate_dims(dims + (size_t)t * N, N))) return st;
@@ -1371,6 +1669,9 @@ tucker_status tucker_batch_create(int count, const void* const* data, tucker_dty
   HIP_TRY(b->alloc((void**)&b->tau, sizeof(double) * Jall * count));
   HIP_TRY(b->alloc((void**)&b->scal, sizeof(double) * 8 * count));
   HIP_TRY(b->alloc((void**)&b->nx2, sizeof(double) * count));
+  HIP_TRY(b->alloc((void**)&b->sqs, sizeof(double) * count * N));
+  HIP_TRY(b->alloc((void**)&b->gflag, sizeof(int) * count));
+  HIP_TRY(b->alloc((void**)&b->status, sizeof(int) * count));
   for (int s = 0; s < N; ++s) {
     const int n = order[s];
     const size_t Jn = (size_t)b->Jmax[s];
@@ -1505,6 +1806,8 @@ tucker_status batch_sync(tucker_batch* b) {
     }
   }
   HIP_TRY(hipMemcpy(b->hnorm2.data(), b->nx2, sizeof(double) * C, hipMemcpyDeviceToHost));
+  b->hstatus.assign(C, 0);
+  HIP_TRY(hipMemcpy(b->hstatus.data(), b->status, sizeof(int) * C, hipMemcpyDeviceToHost));
   return TUCKER_OK;
 }
 
@@ -1525,6 +1828,14 @@ tucker_status tucker_batch_norm2(tucker_batch* b, double* norm2_out) {
   tucker_status st = batch_sync(b);
   if (st) return st;
   std::memcpy(norm2_out, b->hnorm2.data(), sizeof(double) * b->count);
+  return TUCKER_OK;
+}
+
+tucker_status tucker_batch_status(tucker_batch* b, int* status_out) {
+  if (!b || !status_out) return fail(TUCKER_EINVAL, "NULL argument");
+  tucker_status st = batch_sync(b);
+  if (st) return st;
+  std::memcpy(status_out, b->hstatus.data(), sizeof(int) * b->count);
   return TUCKER_OK;
 }
 

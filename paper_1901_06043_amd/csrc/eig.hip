@@ -640,45 +640,27 @@ __global__ __launch_bounds__(256) void eig_bisect_wide_kernel(const double* __re
 // ---------------------------------------------------------------- 3. truncation
 // The threshold is thr, or thr * (*nx2) when nx2 is non-null (so that
 // eps^2 ||X||^2 / N is formed on the device without a host round trip).
-// Tail sums: by default sum_{i>=R} max(lam_i, 0), accumulated from the
-// smallest eigenvalue upward (eq. Un).  With trace_ref (device, the FP64 sum
-// of squares of the unfolded tensor, which equals trace S) the tail is
-// trace_ref - sum_{i<R} max(lam_i, 0) instead: used when S itself carries
-// reduced-precision error, since the leading eigenvalues are then far better
-// determined than the small ones, and a Gram that under-estimates (BF16X3)
-// can only make this tail larger, i.e. keep more.  R = J discards nothing.
+// Tail sums: sum_{i>=R} max(lam_i, 0), accumulated from the smallest
+// eigenvalue upward (eq. Un); R = J discards nothing.  fixed > 0 selects the
+// fixed-rank variant instead: R = min(fixed, J), and disc is its tail.
 __device__ __forceinline__ void truncate_body(const double* __restrict__ lam, int J, double thr,
-                                              const double* __restrict__ nx2, const double* __restrict__ trace_ref,
+                                              const double* __restrict__ nx2, int fixed,
                                               int64_t* __restrict__ Rout, double* __restrict__ disc) {
   if (nx2 != nullptr) thr *= *nx2;
+  const int Rf = (fixed > 0) ? min(fixed, J) : 0;
   int R = J;
   double tailR = 0.0;
-  // (the loops run over all entries without an early exit, so that the loads
-  // can be issued ahead; the tails are monotone in r)
-  if (trace_ref == nullptr) {
-    // smallest R in 1..J with sum_{i>=R} max(lam_i, 0) <= thr (lam descending)
-    double tail = 0.0;
-    bool ok = true;
+  // smallest R in 1..J with sum_{i>=R} max(lam_i, 0) <= thr (lam descending),
+  // or R = Rf; the loop runs over all entries without an early exit, so that
+  // the loads can be issued ahead (the tails are monotone in r)
+  double tail = 0.0;
+  bool ok = true;
 #pragma unroll 8
-    for (int r = J - 1; r >= 1; --r) {
-      tail += fmax(lam[r], 0.0);
-      ok = ok && (tail <= thr);
-      R = ok ? r : R;
-      tailR = ok ? tail : tailR;
-    }
-  } else {
-    const double tr = *trace_ref;
-    double head = 0.0;
-    bool found = false;
-#pragma unroll 8
-    for (int r = 1; r < J; ++r) {
-      head += fmax(lam[r - 1], 0.0);
-      const double tail = fmax(tr - head, 0.0);
-      const bool take = !found && (tail <= thr);
-      R = take ? r : R;
-      tailR = take ? tail : tailR;
-      found = found || take;
-    }
+  for (int r = J - 1; r >= 1; --r) {
+    tail += fmax(lam[r], 0.0);
+    ok = ok && (Rf > 0 ? r >= Rf : tail <= thr);
+    R = ok ? r : R;
+    tailR = ok ? tail : tailR;
   }
   *Rout = R;
   *disc = tailR;
@@ -687,13 +669,13 @@ __device__ __forceinline__ void truncate_body(const double* __restrict__ lam, in
 // One workgroup of 64 threads: the eigenvalues are staged in LDS (dynamic,
 // J doubles), then thread 0 runs the sequential tail sums over LDS.
 __global__ void eig_truncate_kernel(const double* __restrict__ lam, int J, double thr,
-                                    const double* __restrict__ nx2, const double* __restrict__ trace_ref,
-                                    int64_t* __restrict__ Rout, double* __restrict__ disc) {
+                                    const double* __restrict__ nx2, int fixed, int64_t* __restrict__ Rout,
+                                    double* __restrict__ disc) {
   extern __shared__ double sl[];
   for (int i = threadIdx.x; i < J; i += blockDim.x) sl[i] = lam[i];
   __syncthreads();
   if (threadIdx.x != 0) return;
-  truncate_body(sl, J, thr, nx2, trace_ref, Rout, disc);
+  truncate_body(sl, J, thr, nx2, fixed, Rout, disc);
 }
 
 // ---------------------------------------------------------------- 4. inverse iteration
@@ -1444,7 +1426,7 @@ __global__ void eig_truncate_batched(EigBatch b, double thr_mul) {
   if (m >= b.count) return;
   const int J = b.J[m];
   if (J <= 0) return;
-  truncate_body(b.lam + (int64_t)m * b.Jmax, J, thr_mul, b.nx2 ? b.nx2 + m : nullptr, nullptr, b.R + m,
+  truncate_body(b.lam + (int64_t)m * b.Jmax, J, thr_mul, b.nx2 ? b.nx2 + m : nullptr, 0, b.R + m,
                 b.disc + m);
 }
 
@@ -1486,8 +1468,8 @@ void eig_work_carve(double* base, int64_t J, EigWork& w) {
   w.scal = w.tau + J;
 }
 
-hipError_t launch_eig_values(const double* S, int J, double thr, const double* nx2, const double* trace_ref,
-                             const EigWork& w, double* lam, int64_t* R, double* disc, hipStream_t stream) {
+hipError_t launch_eig_values(const double* S, int J, double thr, const double* nx2, int fixed, const EigWork& w,
+                             double* lam, int64_t* R, double* disc, hipStream_t stream) {
   {
     const double* src = S;
     int ld = J, k0 = 0;
@@ -1535,7 +1517,7 @@ hipError_t launch_eig_values(const double* S, int J, double thr, const double* n
   hipLaunchKernelGGL(eig_bisect_wide_kernel, dim3(J), dim3(256), shb, stream, w.d, w.e, J, lam, w.scal);
   LAUNCH_OK();
   hipLaunchKernelGGL(eig_truncate_kernel, dim3(1), dim3(64), sizeof(double) * (size_t)J, stream, lam, J, thr, nx2,
-                     trace_ref, R, disc);
+                     fixed, R, disc);
   return hipGetLastError();
 }
 
@@ -1561,10 +1543,9 @@ hipError_t launch_eig_vectors(int J, const EigWork& w, const double* lam, const 
   return hipGetLastError();
 }
 
-hipError_t launch_eig_truncate(const double* S, int J, double thr, const double* nx2, const double* trace_ref,
-                               const EigWork& w, double* lam, double* U, int64_t* R, double* disc,
-                               hipStream_t stream) {
-  const hipError_t e = launch_eig_values(S, J, thr, nx2, trace_ref, w, lam, R, disc, stream);
+hipError_t launch_eig_truncate(const double* S, int J, double thr, const double* nx2, int fixed, const EigWork& w,
+                               double* lam, double* U, int64_t* R, double* disc, hipStream_t stream) {
+  const hipError_t e = launch_eig_values(S, J, thr, nx2, fixed, w, lam, R, disc, stream);
   return e != hipSuccess ? e : launch_eig_vectors(J, w, lam, R, U, stream);
 }
 

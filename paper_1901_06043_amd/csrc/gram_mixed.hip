@@ -552,6 +552,7 @@ __global__ __launch_bounds__(kNT) void gram_batch_kernel(GramBatch b, int item0)
   const int it = item0 + blockIdx.x;
   const int64_t* d = b.items + 4 * (int64_t)it;
   const int t = (int)d[0];
+  if (b.flag != nullptr && b.flag[t] == 0) return;
   const int J = b.J[t];
   uint64_t L = 1, Rt = 1;
   for (int k = 0; k < b.N; ++k) {
@@ -561,7 +562,7 @@ __global__ __launch_bounds__(kNT) void gram_batch_kernel(GramBatch b, int item0)
   }
   const uint64_t K = L * Rt;
   const int64_t nch = (int64_t)((K + C::KC - 1) / C::KC);
-  const int64_t cb = d[1], ce = min(d[2], nch);
+  const int64_t cb = d[1] * b.chunk_mul, ce = min(d[2] * b.chunk_mul, nch);
   const BodyArgs a{b.Y[t], J, (uint32_t)L, (uint32_t)K, cb, 1, ce > cb ? ce - cb : 0, b.part + d[3],
                    b.sq ? b.sq + it : nullptr};
   const int NR = (J + 15) & ~15;
@@ -574,6 +575,7 @@ __global__ __launch_bounds__(256) void gram_batch_reduce_kernel(GramBatch b) {
   const int t = blockIdx.y;
   const int J = b.J[t];
   if (J <= 0) return;
+  if (b.flag != nullptr && b.flag[t] == 0) return;
   const int nb = (J + 15) / 16, nblk = nb * (nb + 1) / 2;
   const int idx = blockIdx.x * 256 + threadIdx.x;
   const int i0 = b.ifirst[2 * t], i1 = b.ifirst[2 * t + 1];
@@ -735,9 +737,10 @@ template hipError_t launch_gram_batched<float>(const GramBatch&, int, bool, hipS
 template hipError_t launch_gram_batched<double>(const GramBatch&, int, bool, hipStream_t);
 
 // Range guard of a reduced-precision Gram: flag = 1 and S zeroed if an entry
-// is not finite or trace(S) differs from the FP64 sum of squares by more
-// than 1e-3 relative; flag = 0 otherwise.  One workgroup.
-__global__ __launch_bounds__(256) void gram_guard_kernel(double* __restrict__ S, int J,
+// is not finite, trace(S) differs from the FP64 sum of squares by more than
+// 1e-3 relative, or (K > 0) a diagonal entry's mean square S_aa / K lies
+// outside [2^-100, 2^100]; flag = 0 otherwise.  One workgroup.
+__global__ __launch_bounds__(256) void gram_guard_kernel(double* __restrict__ S, int J, double K,
                                                          const double* __restrict__ sq, double* __restrict__ flag) {
   __shared__ double str[256];
   __shared__ int sbad[256];
@@ -747,7 +750,12 @@ __global__ __launch_bounds__(256) void gram_guard_kernel(double* __restrict__ S,
   for (int64_t e = tid; e < JJ; e += 256)
     if (!isfinite(S[e])) bad = 1;
   double tr = 0.0;
-  for (int a = tid; a < J; a += 256) tr += S[(int64_t)a * J + a];
+  const double lo = (K > 0.0) ? 0x1p-100 * K : 0.0, hi = (K > 0.0) ? 0x1p100 * K : INFINITY;
+  for (int a = tid; a < J; a += 256) {
+    const double d = S[(int64_t)a * J + a];
+    tr += d;
+    if (!(d >= lo && d <= hi)) bad = 1;
+  }
   str[tid] = tr;
   sbad[tid] = bad;
   __syncthreads();
@@ -765,8 +773,57 @@ __global__ __launch_bounds__(256) void gram_guard_kernel(double* __restrict__ S,
   if (tid == 0) *flag = fire ? 1.0 : 0.0;
 }
 
-hipError_t launch_gram_guard(double* S, int J, const double* sq, double* flag, hipStream_t stream) {
-  hipLaunchKernelGGL(gram_guard_kernel, dim3(1), dim3(256), 0, stream, S, J, sq, flag);
+// One workgroup per tensor of a batch, the checks of gram_guard_kernel.
+__global__ __launch_bounds__(256) void gram_guard_batched_kernel(GramBatch b, int* __restrict__ flag,
+                                                                 int* __restrict__ status) {
+  __shared__ double str[256];
+  __shared__ int sbad[256];
+  const int t = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int J = b.J[t];
+  if (J <= 0) return;
+  double K = 1.0;
+  for (int k = 0; k < b.N; ++k)
+    if (k != b.n) K *= (double)b.cur[(int64_t)t * b.N + k];
+  double* __restrict__ S = b.S + (int64_t)t * b.Jmax * b.Jmax;
+  const int64_t JJ = (int64_t)J * J;
+  int bad = 0;
+  for (int64_t e = tid; e < JJ; e += 256)
+    if (!isfinite(S[e])) bad = 1;
+  double tr = 0.0;
+  const double lo = 0x1p-100 * K, hi = 0x1p100 * K;
+  for (int a = tid; a < J; a += 256) {
+    const double d = S[(int64_t)a * J + a];
+    tr += d;
+    if (!(d >= lo && d <= hi)) bad = 1;
+  }
+  str[tid] = tr;
+  sbad[tid] = bad;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (tid < w) {
+      str[tid] += str[tid + w];
+      sbad[tid] |= sbad[tid + w];
+    }
+    __syncthreads();
+  }
+  const double ref = b.nx2[t];
+  const bool fire = sbad[0] != 0 || !(fabs(str[0] - ref) <= 1e-3 * ref);
+  if (fire)
+    for (int64_t e = tid; e < JJ; e += 256) S[e] = 0.0;
+  if (tid == 0) {
+    flag[t] = fire ? 1 : 0;
+    status[t] |= (isfinite(ref) ? 0 : 1) | (fire ? 2 : 0);
+  }
+}
+
+hipError_t launch_gram_guard_batched(const GramBatch& b, int* flag, int* status, hipStream_t stream) {
+  hipLaunchKernelGGL(gram_guard_batched_kernel, dim3(b.count), dim3(256), 0, stream, b, flag, status);
+  return hipGetLastError();
+}
+
+hipError_t launch_gram_guard(double* S, int J, double K, const double* sq, double* flag, hipStream_t stream) {
+  hipLaunchKernelGGL(gram_guard_kernel, dim3(1), dim3(256), 0, stream, S, J, K, sq, flag);
   return hipGetLastError();
 }
 

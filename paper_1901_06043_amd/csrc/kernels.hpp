@@ -60,10 +60,13 @@ template <typename T>
 hipError_t launch_gram_stream(const T* Y, int J, uint64_t L, uint64_t K, int prec, const GramPlan& p, double* part,
                               double* sq, double* S, double* norm2, hipStream_t stream, hipEvent_t after_main);
 
-// Range guard of a reduced-precision Gram (one workgroup): if S has a
-// non-finite entry or |trace(S) - *sq| > 1e-3 *sq, zero S and set *flag = 1,
-// else *flag = 0.
-hipError_t launch_gram_guard(double* S, int J, const double* sq, double* flag, hipStream_t stream);
+// Range guard of a reduced-precision Gram over K columns (one workgroup): if
+// S has a non-finite entry, |trace(S) - *sq| > 1e-3 *sq, or (K > 0) a diagonal
+// entry with S_aa / K outside [2^-100, 2^100] (squares near the FP32
+// underflow or overflow range, or an all-zero row, which cannot be told apart
+// from one; K = 0 skips this check, for a Gram computed on scaled slices),
+// zero S and set *flag = 1, else *flag = 0.
+hipError_t launch_gram_guard(double* S, int J, double K, const double* sq, double* flag, hipStream_t stream);
 
 __global__ void sum_fixed_kernel(const double* __restrict__ x, int64_t n, double* __restrict__ out);
 
@@ -86,18 +89,16 @@ struct EigWork {
 int64_t eig_work_doubles(int64_t J);
 void eig_work_carve(double* base, int64_t J, EigWork& w);
 // S (J x J, device) -> lam (desc), U (J x J, first R columns), R, disc.
-// Threshold: thr, or thr * (*nx2) if nx2 (device) is non-null.  trace_ref
-// (device, may be null): tail sums taken as *trace_ref minus the leading
-// eigenvalues (for Grams computed in reduced precision).
-hipError_t launch_eig_truncate(const double* S, int J, double thr, const double* nx2, const double* trace_ref,
-                               const EigWork& w, double* lam, double* U, int64_t* R, double* disc,
-                               hipStream_t stream);
+// Threshold: thr, or thr * (*nx2) if nx2 (device) is non-null; fixed > 0
+// takes R = min(fixed, J) instead of the threshold rule.
+hipError_t launch_eig_truncate(const double* S, int J, double thr, const double* nx2, int fixed, const EigWork& w,
+                               double* lam, double* U, int64_t* R, double* disc, hipStream_t stream);
 // The same in two parts, so that R can be read back while the eigenvectors
 // are being formed: the eigenvalues and the truncation (lam, R, disc; steps
 // 1-3), then the leading R eigenvectors (U; steps 4-6), which only read w,
 // lam and R.
-hipError_t launch_eig_values(const double* S, int J, double thr, const double* nx2, const double* trace_ref,
-                             const EigWork& w, double* lam, int64_t* R, double* disc, hipStream_t stream);
+hipError_t launch_eig_values(const double* S, int J, double thr, const double* nx2, int fixed, const EigWork& w,
+                             double* lam, int64_t* R, double* disc, hipStream_t stream);
 hipError_t launch_eig_vectors(int J, const EigWork& w, const double* lam, const int64_t* R, double* U,
                               hipStream_t stream);
 
@@ -143,9 +144,20 @@ struct GramBatch {
   double* sq;  // per item (needed when nx2 is set)
   double* S;
   double* nx2;
+  // recomputation of flagged Grams: only tensors t with flag[t] != 0 are
+  // processed (null: all), and the items' chunk ranges are in units of
+  // chunk_mul chunks of this arithmetic (a plan made for 32-column chunks
+  // run with FP64's 16-column chunks has chunk_mul = 2)
+  const int* flag;
+  int chunk_mul;
 };
 template <typename T>
 hipError_t launch_gram_batched(const GramBatch& b, int prec, bool unit_l, hipStream_t stream);
+// Batched range guard of reduced Grams: for tensor t (J[t], K[t] columns from
+// the current sizes), flag[t] = 1 and S_t zeroed under the conditions of
+// launch_gram_guard (sq: per-tensor FP64 sums of squares), else 0; status[t]
+// accumulates 1 for a non-finite sum of squares and 2 for a flagged Gram.
+hipError_t launch_gram_guard_batched(const GramBatch& b, int* flag, int* status, hipStream_t stream);
 
 // Batched mode-n product Z_t = Y_t x_n U_t^T with K = R[t] output rows.
 // items: 3 int64 per work item (tensor, first column tile, end column tile),
@@ -175,8 +187,10 @@ hipError_t launch_slice_stats(const T* Y, uint64_t L, uint64_t J, uint64_t Rt, b
 // shift/scale from stats: method 0 standardization, 1 max rescaling (a zero scale becomes 1).
 hipError_t launch_scaling_vectors(const double* stats, uint64_t J, int method, double* shift, double* scale,
                                   hipStream_t s);
-// rscale[a] = 2^-e with max|x| of slice a in [2^(e-1), 2^e) (from the min/max rows of stats).
-hipError_t launch_slice_pow2(const double* stats, uint64_t J, double* rscale, hipStream_t s);
+// pscale[a] = 2^e with max|x| of slice a in [2^(e-1), 2^e) (from the min/max rows of stats).
+hipError_t launch_slice_pow2(const double* stats, uint64_t J, double* pscale, hipStream_t s);
+// S_ab *= pscale_a * pscale_b (J x J).
+hipError_t launch_gram_unscale(double* S, int64_t J, const double* pscale, hipStream_t s);
 // Y = (X - shift_a) / scale_a, or fma(X, scale_a, shift_a) if inverse; X == Y allowed.
 template <typename TI, typename TO>
 hipError_t launch_slice_transform(const TI* X, TO* Y, uint64_t total, uint64_t L, uint64_t J, const double* shift,

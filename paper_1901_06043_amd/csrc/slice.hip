@@ -265,17 +265,27 @@ __global__ __launch_bounds__(kST) void scaling_vectors_kernel(const double* __re
   scale[a] = (sc == 0.0) ? 1.0 : sc;
 }
 
-// Power-of-two scale per slice for the reduced-precision Gram: rscale[a] =
-// 2^-e with max|x| of the slice in [2^(e-1), 2^e), so that every scaled value
-// has magnitude below 1 and the largest at least 1/2 (1 for an all-zero slice).
+// Power-of-two divisor per slice for the reduced-precision Gram: pscale[a] =
+// 2^e with max|x| of the slice in [2^(e-1), 2^e), so that every scaled value
+// x / 2^e has magnitude below 1 and the largest at least 1/2 (1 for an
+// all-zero or non-finite slice).  Division by a power of two is exact.
 __global__ __launch_bounds__(kST) void slice_pow2_kernel(const double* __restrict__ stats, uint64_t J,
-                                                         double* __restrict__ rscale) {
+                                                         double* __restrict__ pscale) {
   const uint64_t a = (uint64_t)blockIdx.x * kST + threadIdx.x;
   if (a >= J) return;
   const double mx = fmax(fabs(stats[2 * J + a]), fabs(stats[3 * J + a]));
   int e = 0;
   if (mx > 0.0 && isfinite(mx)) (void)frexp(mx, &e);
-  rscale[a] = ldexp(1.0, -e);
+  pscale[a] = ldexp(1.0, e);
+}
+
+// S_ab *= pscale_a pscale_b (exact: powers of two), undoing the per-slice scaling.
+__global__ __launch_bounds__(kST) void gram_unscale_kernel(double* __restrict__ S, int64_t J,
+                                                           const double* __restrict__ pscale) {
+  const int64_t e = (int64_t)blockIdx.x * kST + threadIdx.x;
+  if (e >= J * J) return;
+  const int64_t a = e / J, b = e - a * J;
+  S[e] = S[e] * (pscale[a] * pscale[b]);
 }
 
 template <typename TI, typename TO, bool INV>
@@ -477,8 +487,13 @@ hipError_t launch_scaling_vectors(const double* stats, uint64_t J, int method, d
   return hipGetLastError();
 }
 
-hipError_t launch_slice_pow2(const double* stats, uint64_t J, double* rscale, hipStream_t s) {
-  hipLaunchKernelGGL(slice_pow2_kernel, dim3((unsigned)ceil_div(J, kST)), dim3(kST), 0, s, stats, J, rscale);
+hipError_t launch_slice_pow2(const double* stats, uint64_t J, double* pscale, hipStream_t s) {
+  hipLaunchKernelGGL(slice_pow2_kernel, dim3((unsigned)ceil_div(J, kST)), dim3(kST), 0, s, stats, J, pscale);
+  return hipGetLastError();
+}
+
+hipError_t launch_gram_unscale(double* S, int64_t J, const double* pscale, hipStream_t s) {
+  hipLaunchKernelGGL(gram_unscale_kernel, dim3((unsigned)ceil_div(J * J, kST)), dim3(kST), 0, s, S, J, pscale);
   return hipGetLastError();
 }
 

@@ -110,21 +110,62 @@ def test_ttm_fp32_products(tk, orc, dims, n, K):
 
 
 @pytest.mark.parametrize("scale,prec", [(1e20, "fp32"), (1e-25, "fp32"), (1e20, "bf16x3"), (1e-25, "bf16x6")])
-def test_range_guard_recomputes_in_fp64(tk, orc, scale, prec):
+def test_range_handling_scales_slices(tk, orc, scale, prec):
     """FP32 squares overflow above ~1.8e19 and vanish below ~1e-23: the guard
-    sees the trace or a non-finite entry disagree with the FP64 sum of squares
-    and redoes the Gram in FP64; the result equals the FP64 path's."""
+    sees the trace, a non-finite entry or a diagonal outside the safe range,
+    and the Gram is redone in the same reduced form on the per-slice scaled
+    copy (powers of two), so the result equals the FP64 oracle's ranks."""
     X, dims = synthetic.random_tucker([30, 20, 10], [4, 3, 2], 1e-3, seed=21)
     X = (X * scale).astype(np.float32)
     t = tk.sthosvd(to_dev(X, dims), 1e-2, prec=prec, dims=dims)
     ref = orc.sthosvd(X.astype(np.float64), dims, 1e-2)
-    assert t.gram_precision[0] == "fp64"
+    assert t.gram_precision[0] == prec and t.gram_scaled[0]
     assert t.ranks == ref.ranks
     assert t.norm2 == pytest.approx(ref.norm2, rel=1e-11)
-    # in range: no recomputation
+    # in range: no second pass
     Xn = (X.astype(np.float64) / scale).astype(np.float32)
     t2 = tk.sthosvd(to_dev(Xn, dims), 1e-2, prec=prec, dims=dims)
-    assert t2.gram_precision == [prec] * 3
+    assert t2.gram_precision == [prec] * 3 and not any(t2.gram_scaled)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x6"])
+def test_per_slice_scaling_small_magnitudes(tk, orc, prec):
+    """Slices of mode 0 with magnitudes 1e-24 .. 1e-22: their squares lie below
+    the FP32 normal range, so the plain reduced Gram loses them; the guard sees
+    the diagonal out of range and the scaled pass computes the Gram to the
+    form's accuracy, so every eigenvalue is within Weyl's bound
+    ||E||_2 <= bound * trace S of the oracle's."""
+    rng = np.random.default_rng(3)
+    dims = [12, 40, 30]
+    X = rng.standard_normal(int(np.prod(dims))).reshape(30, 40, 12)
+    X *= (10.0 ** rng.uniform(-24, -22, 12))[None, None, :]
+    X = X.astype(np.float32).reshape(-1)
+    t = tk.sthosvd(to_dev(X, dims), 1e-2, prec=prec, dims=dims)
+    assert t.gram_scaled[0] and t.gram_precision[0] == prec
+    lam = t.eigenvalues(0).cpu().numpy()
+    lref, _ = orc.eig(orc.gram(X.astype(np.float64), dims, 0))
+    tr = float(np.sum(lref))
+    assert np.abs(lam - lref).max() <= (BOUND[prec] + 64 * 2.0 ** -52) * tr
+
+
+@pytest.mark.parametrize("eps,want", [(1e-3, "fp64"), (3e-2, "fp32"), (0.2, "bf16x3")])
+def test_auto_precision_rule(tk, orc, eps, want):
+    """AUTO takes the cheapest form whose predicted error (2^-16/3 of ||X||^2
+    for BF16X3, 2^-23 for FP32) is within 1% of the slack of the 1.05 eps
+    target, (1.05^2 - 1) eps^2 ||X||^2 / N (N = 3: FP32 from eps = 0.0187,
+    BF16X3 from 0.122), and FP64 otherwise; FP64 data always takes FP64."""
+    X, dims = synthetic.random_tucker([40, 30, 20], [6, 5, 4], 1e-2, seed=5, dtype=np.float32)
+    t = tk.sthosvd(to_dev(X, dims), eps, prec="auto", dims=dims)
+    assert t.gram_precision == [want] * 3
+    assert t.core_dtype == (tk.F64 if want == "fp64" else tk.F32)
+    ref = orc.sthosvd(X.astype(np.float64), dims, eps)
+    xh = t.reconstruct(out_dtype=torch.float64)
+    x64 = to_dev(X, dims).double()
+    e = float(torch.linalg.vector_norm((x64 - xh).reshape(-1)) / torch.linalg.vector_norm(x64.reshape(-1)))
+    assert e <= 1.05 * eps
+    assert t.ranks == ref.ranks
+    t64 = tk.sthosvd(to_dev(X, dims, torch.float64), eps, prec="auto", dims=dims)
+    assert t64.gram_precision == ["fp64"] * 3
 
 
 def _principal_sin(Ua, Ub):

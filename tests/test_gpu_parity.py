@@ -289,3 +289,50 @@ def test_sthosvd_decaying_full_size(tk, orc, eps):
     """The 200x200x200x16 float64 workload at full size (the benchmark's)."""
     X, dims = synthetic.decaying_200()
     _check_sthosvd(tk, orc, X, dims, eps, [0, 1, 2, 3])
+
+
+@pytest.mark.parametrize("case", [
+    ([40, 30, 20], [5, 4, 3], [0, 1, 2], [40, 30, 20]),
+    ([40, 30, 20], [5, 4, 3], [2, 0, 1], [3, 9, 2]),
+    ([64, 64, 64], [8, 8, 8], [1, 2, 0], [8, 8, 8]),
+    ([17, 1, 9, 6], [3, 1, 2, 2], [3, 0, 2, 1], [50, 1, 4, 50]),
+    ([300, 20], [10, 8], [0, 1], [7, 7]),
+])
+def test_sthosvd_fixed_ranks_parity(tk, orc, case):
+    """Fixed-rank ST-HOSVD (the core size is given): ranks min(R_n, J_n), the
+    oracle's relative error within 1e-10, Corollary 1 on the GPU side,
+    orthonormal factors and the oracle's eigenvalues."""
+    dims, true_ranks, order, ranks = case
+    X, dims = synthetic.random_tucker(dims, true_ranks, 1e-3, seed=sum(dims) + 3)
+    print(f"fixed ranks dims={dims} ranks={ranks} order={order}", flush=True)
+    t = tk.sthosvd_ranks(to_dev(X, dims), ranks, mode_order=order, dims=dims)
+    ref = orc.sthosvd(X, dims, 0.0, order, ranks=ranks)
+    assert t.ranks == ref.ranks
+    x = to_dev(X, dims)
+    xh = t.reconstruct()
+    e_gpu = float(torch.linalg.vector_norm((x - xh).reshape(-1)) / torch.linalg.vector_norm(x.reshape(-1)))
+    assert abs(e_gpu - orc.relerr(X, ref)) <= 1e-10
+    assert abs(e_gpu ** 2 * t.norm2 - sum(t.discarded)) <= 1e-10 * t.norm2
+    np.testing.assert_allclose(t.discarded, ref.discarded, rtol=1e-9, atol=1e-12 * ref.norm2)
+    for n in range(len(dims)):
+        U = t.factor(n).cpu().numpy()
+        assert np.abs(U.T @ U - np.eye(t.ranks[n])).max() <= 1e-12
+        np.testing.assert_allclose(t.eigenvalues(n).cpu().numpy(), ref.eigenvalues[n],
+                                   atol=1e-12 * ref.eigenvalues[n][0])
+
+
+def test_sthosvd_fixed_ranks_float32_and_reduced(tk, orc):
+    X, dims = synthetic.random_tucker([60, 40, 30], [6, 5, 4], 1e-3, seed=77, dtype=np.float32)
+    ref = orc.sthosvd(X.astype(np.float64), dims, 0.0, ranks=[6, 5, 4])
+    t = tk.sthosvd_ranks(to_dev(X, dims, torch.float32), [6, 5, 4], dims=dims)
+    assert t.ranks == [6, 5, 4] and t.core_dtype == tk.F64
+    assert abs(np.sqrt(sum(t.discarded) / t.norm2) - orc.relerr(X.astype(np.float64), ref)) <= 1e-10
+    t32 = tk.sthosvd_ranks(to_dev(X, dims, torch.float32), [6, 5, 4], prec="fp32", dims=dims)
+    assert t32.ranks == [6, 5, 4] and t32.core_dtype == tk.F32
+    xh = t32.reconstruct(out_dtype=torch.float64)
+    x64 = to_dev(X, dims, torch.float64)
+    e = float(torch.linalg.vector_norm((x64 - xh).reshape(-1)) / torch.linalg.vector_norm(x64.reshape(-1)))
+    assert abs(e - orc.relerr(X.astype(np.float64), ref)) <= 1e-5
+    # AUTO has no error target here and takes FP64
+    ta = tk.sthosvd_ranks(to_dev(X, dims, torch.float32), [6, 5, 4], prec="auto", dims=dims)
+    assert ta.gram_precision == ["fp64"] * 3
