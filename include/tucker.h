@@ -153,6 +153,22 @@ tucker_status tucker_sthosvd_ranks(const void* data, tucker_dtype dtype, const i
                                    const int64_t* ranks, const int* mode_order, tucker_gram_prec prec,
                                    hipStream_t stream, tucker_t** out);
 
+/* Mode order by predicted cost (host only).  The cost model of Sec. 7: the
+ * step that processes mode n does (J_n^2 + 2 R_n J_n) K flops (its Gram, with
+ * the symmetric count, and its mode product), K the product of the other
+ * current sizes; the eigensolve's (10/3) I_n^3 does not depend on the order.
+ *   ranks   host, N values (given or estimated core sizes, capped at I_n):
+ *           the order of least total flops, found exactly by dynamic
+ *           programming over the sets of processed modes (2^N N steps); ties
+ *           keep the first minimum found.  NULL (ranks unknown, the eps
+ *           rule): increasing I_n, ties by mode index, which is the optimum
+ *           when every mode shrinks by the same factor (later steps work on
+ *           smaller tensors, so the larger modes go last).
+ *   order_out host, N ints; flops_out host, the predicted flops (0 when ranks
+ *           is NULL), may be NULL. */
+tucker_status tucker_sthosvd_order(int N, const int64_t* dims, const int64_t* ranks, int* order_out,
+                                   double* flops_out);
+
 /* Predicted device memory of a compression (host only; the input tensor
  * is not counted): the handle's factors and eigenvalues, the Gram and
  * eigensolver workspaces, and the largest pair of working tensors with the

@@ -12,8 +12,10 @@ dims (I_0, ..., I_{N-1}); ``dims`` below are always in the paper's order.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
+import weakref
 from dataclasses import dataclass
 
 import numpy as np
@@ -40,6 +42,7 @@ EXPORTS = [
     "tucker_scaling_vectors", "tucker_slice_transform", "tucker_preprocess", "tucker_set_postprocess",
     "tucker_create", "tucker_sthosvd_ranks", "tucker_sthosvd_memory", "tucker_set_allocator", "tucker_gram_scaled",
     "tucker_batch_status", "tucker_empty_cache",
+    "tucker_sthosvd_order",
 ]
 
 OP_KINDS = {"identity": 0, "range": 1, "average": 2, "sum": 3, "mean": 4, "matrix": 5}
@@ -113,6 +116,7 @@ def lib():
             "tucker_gram_scaled": (i32, [P, P]),
             "tucker_batch_status": (i32, [P, P]),
             "tucker_empty_cache": (i32, []),
+            "tucker_sthosvd_order": (i32, [i32, P, P, P, P]),
             "tucker_last_error": (ctypes.c_char_p, []),
             "tucker_version": (ctypes.c_char_p, []),
         }
@@ -200,6 +204,7 @@ class Tucker:
         self._h = handle
         self._stream = stream
         self.requested_precision = requested_precision
+        _live.add(self)
         L = lib()
         self.N = L.tucker_ndims(handle)
         d = (ctypes.c_int64 * self.N)()
@@ -459,6 +464,17 @@ def sthosvd_ranks(x, ranks, mode_order=None, prec: str = "fp64", dims=None, stre
     return Tucker(h.value, s, prec)
 
 
+def sthosvd_order(dims, ranks=None):
+    """(mode order, predicted flops) by the Sec. 7 cost model; ranks None:
+    increasing mode size."""
+    N = len(dims)
+    o = (ctypes.c_int * N)()
+    f = ctypes.c_double(0.0)
+    _check(lib().tucker_sthosvd_order(N, _i64(dims), _i64(ranks) if ranks is not None else None, o,
+                                      ctypes.byref(f)))
+    return list(o), f.value
+
+
 def sthosvd_memory(dims, dtype: int = F64, ranks=None, mode_order=None, prec: str = "fp64") -> int:
     """Predicted device bytes of a compression (ranks None = no truncation bound)."""
     b = ctypes.c_size_t(0)
@@ -475,31 +491,61 @@ class _Allocator(ctypes.Structure):
 
 
 _torch_alloc = None
+# bytes the library holds from PyTorch's allocator: live, peak since the last
+# reset_allocator_stats(), and the number of alloc callbacks
+allocator_stats = {"live": 0, "peak": 0, "calls": 0}
+_torch_blocks = {}
+
+
+def reset_allocator_stats():
+    allocator_stats["peak"] = allocator_stats["live"]
+    allocator_stats["calls"] = 0
 
 
 def use_torch_allocator(enable: bool = True):
     """Route every device allocation of the library through PyTorch's caching
     allocator (tucker_set_allocator with ctypes callbacks), so that PyTorch
-    provides the memory; enable=False restores the library's own pool."""
+    provides the memory; enable=False restores the library's own pool (blocks
+    taken from PyTorch go back to it when released)."""
     global _torch_alloc
     if not enable:
         _check(lib().tucker_set_allocator(None))
-        _torch_alloc = None
         return
     import torch
 
     def _alloc(nbytes, ctx, stream):
         try:
-            return torch.cuda.caching_allocator_alloc(int(nbytes), torch.cuda.current_device(), stream or 0)
+            p = torch.cuda.caching_allocator_alloc(int(nbytes), torch.cuda.current_device(), stream or 0)
         except Exception:
             return None
+        _torch_blocks[p] = int(nbytes)
+        allocator_stats["live"] += int(nbytes)
+        allocator_stats["peak"] = max(allocator_stats["peak"], allocator_stats["live"])
+        allocator_stats["calls"] += 1
+        return p
 
     def _free(ptr, ctx, stream):
+        allocator_stats["live"] -= _torch_blocks.pop(ptr, 0)
         torch.cuda.caching_allocator_delete(ptr)
 
     a = _Allocator(_Allocator._fields_[0][1](_alloc), _Allocator._fields_[1][1](_free), None)
     _check(lib().tucker_set_allocator(ctypes.byref(a)))
-    _torch_alloc = a  # the callbacks must outlive their use
+    _torch_alloc = a  # the callbacks must outlive every block they produced
+
+
+# Handles and plans still alive when the interpreter exits are released while
+# Python still runs: their memory may belong to PyTorch's allocator, whose
+# release goes through a Python callback.
+_live = weakref.WeakSet()
+
+
+@atexit.register
+def _release_live():
+    for obj in list(_live):
+        try:
+            obj.free()
+        except Exception:
+            pass
 
 
 def empty_cache():
@@ -588,6 +634,7 @@ class Batch:
                                          _i32(mode_order) if mode_order is not None else None, _PREC[prec],
                                          _stream(stream), ctypes.byref(h)))
         self._h = h.value
+        _live.add(self)
 
     def run(self, stream=None):
         _check(lib().tucker_batch_run(self._h, _stream(stream)))

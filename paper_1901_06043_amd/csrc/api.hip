@@ -833,6 +833,62 @@ tucker_status tucker_set_allocator(const tucker_allocator* a) {
   return TUCKER_OK;
 }
 
+tucker_status tucker_sthosvd_order(int N, const int64_t* dims, const int64_t* ranks, int* order_out,
+                                   double* flops_out) {
+  if (!dims || !order_out) return fail(TUCKER_EINVAL, "NULL argument");
+  tucker_status st = validate_dims(dims, N);
+  if (st) return st;
+  if (ranks)
+    for (int k = 0; k < N; ++k)
+      if (ranks[k] < 1) return fail(TUCKER_EINVAL, "ranks[%d] < 1", k);
+  if (!ranks) {
+    // unknown ranks: increasing size (ties: lower mode first)
+    std::vector<int> ord(N);
+    std::iota(ord.begin(), ord.end(), 0);
+    std::stable_sort(ord.begin(), ord.end(), [&](int i, int j) { return dims[i] < dims[j]; });
+    for (int k = 0; k < N; ++k) order_out[k] = ord[k];
+    if (flops_out) *flops_out = 0.0;
+    return TUCKER_OK;
+  }
+  // exact minimum over orders of the flop model, by dynamic programming over
+  // the set of processed modes: processing mode n after the set P costs
+  // (J_n^2 + 2 R_n J_n) K with J_n = I_n and K = prod_{m in P} R_m prod_{m not in P, m != n} I_m
+  // (the eigensolve, (10/3) I_n^3, does not depend on the order)
+  const int64_t nset = int64_t(1) << N;
+  std::vector<double> best(nset, INFINITY);
+  std::vector<int8_t> last(nset, -1);
+  best[0] = 0.0;
+  double R[TUCKER_MAX_MODES];
+  for (int k = 0; k < N; ++k) R[k] = (double)std::min(ranks[k], dims[k]);
+  for (int64_t P = 0; P < nset; ++P) {
+    if (!std::isfinite(best[P])) continue;
+    double prodP = 1.0, prodQ = 1.0;  // over processed (ranks) and unprocessed (sizes) modes
+    for (int m = 0; m < N; ++m) {
+      if (P >> m & 1) prodP *= R[m];
+      else prodQ *= (double)dims[m];
+    }
+    for (int n = 0; n < N; ++n) {
+      if (P >> n & 1) continue;
+      const double I = (double)dims[n];
+      const double K = prodP * (prodQ / I);
+      const double c = best[P] + (I * I + 2.0 * R[n] * I) * K;
+      const int64_t Q = P | (int64_t(1) << n);
+      if (c < best[Q]) {
+        best[Q] = c;
+        last[Q] = (int8_t)n;
+      }
+    }
+  }
+  int64_t P = nset - 1;
+  for (int k = N - 1; k >= 0; --k) {
+    const int n = last[P];
+    order_out[k] = n;
+    P &= ~(int64_t(1) << n);
+  }
+  if (flops_out) *flops_out = best[nset - 1];
+  return TUCKER_OK;
+}
+
 tucker_status tucker_empty_cache(void) {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return fail(TUCKER_EHIP, "no HIP device");

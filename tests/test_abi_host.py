@@ -246,3 +246,39 @@ def test_pre_post_entry_points_reject_bad_arguments(tk):
     assert L.tucker_create(dummy, 1, dims, tk._i64([2, 0, 2]), 3, fac, None, ctypes.byref(h)) == 1
     assert L.tucker_create(None, 1, dims, tk._i64([2, 2, 2]), 3, fac, None, ctypes.byref(h)) == 1
     assert h.value is None
+
+
+def _sthosvd_flops(order, I, R):
+    cur, f = list(I), 0
+    for n in order:
+        K = int(np.prod(cur)) // cur[n]
+        f += (cur[n] ** 2 + 2 * min(R[n], I[n]) * cur[n]) * K
+        cur[n] = min(R[n], I[n])
+    return f
+
+
+@pytest.mark.parametrize("seed", range(25))
+def test_sthosvd_order_is_optimal(tk, seed):
+    """The dynamic program of tucker_sthosvd_order reaches the brute-force
+    minimum of the cost model over all N! orders."""
+    rng = np.random.default_rng(500 + seed)
+    N = int(rng.integers(1, 7))
+    I = [int(v) for v in rng.integers(1, 700, N)]
+    R = [int(v) for v in rng.integers(1, 700, N)]
+    order, fl = tk.sthosvd_order(I, R)
+    assert sorted(order) == list(range(N))
+    best = min(_sthosvd_flops(o, I, R) for o in itertools.permutations(range(N)))
+    assert _sthosvd_flops(order, I, R) == best
+    assert fl == pytest.approx(best, rel=1e-12)
+
+
+def test_sthosvd_order_unknown_ranks_and_large_share(tk):
+    assert tk.sthosvd_order([672, 672, 33, 626])[0] == [2, 3, 0, 1]
+    assert tk.sthosvd_order([5, 5, 2])[0] == [2, 0, 1]
+    # the 672x672x33x626 workload with its eps = 1e-4 ranks: the model's best
+    # order against the given 3,2,0,1
+    I, R = [672, 672, 33, 626], [447, 336, 33, 469]
+    order, fl = tk.sthosvd_order(I, R)
+    assert _sthosvd_flops(order, I, R) <= _sthosvd_flops([3, 2, 0, 1], I, R)
+    with pytest.raises(tk.TuckerError):
+        tk.sthosvd_order([4, 0, 3])
