@@ -449,6 +449,18 @@ tucker_status tucker_gram(const void* Y, tucker_dtype dtype, const int64_t* dims
 tucker_status tucker_eig_truncate(const double* S, int64_t J, double thr, double* lam, double* U,
                                   int64_t* R, double* disc, hipStream_t stream);
 
+/* tucker_eig_truncate without any allocation, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, kernels and results as
+ * tucker_eig_truncate; the eigensolver's workspace is a static device array
+ * of the library sized for J <= 1024 (16.8 MB per device, held until the
+ * process ends), so J above 1024 is rejected with EINVAL.  The first call on
+ * a device looks up the array's device address.  Every call on a device uses
+ * that device's one workspace: calls that overlap on one device (different
+ * streams, or host threads) race and must be serialised by the caller. */
+tucker_status tucker_eig_truncate_noalloc(const double* S, int64_t J, double thr, double* lam, double* U,
+                                          int64_t* R, double* disc, hipStream_t stream);
+
 /* Mode product Z = Y x_n M (Sec. 2.2.3, Algorithm 3), M a K x J_n FP64
  * matrix with element (k,j) at M[k*msk + j*msj]; Z has the sizes of Y with
  * mode n replaced by K, in `zdtype`.  Y in `ydtype`.  fp32_products != 0

@@ -41,7 +41,7 @@ EXPORTS = [
     "tucker_op_size", "tucker_reconstruct_order_rule", "tucker_reconstruct_ops", "tucker_slice_stats",
     "tucker_scaling_vectors", "tucker_slice_transform", "tucker_preprocess", "tucker_set_postprocess",
     "tucker_create", "tucker_sthosvd_ranks", "tucker_sthosvd_memory", "tucker_set_allocator", "tucker_gram_scaled",
-    "tucker_batch_status", "tucker_empty_cache",
+    "tucker_batch_status", "tucker_empty_cache", "tucker_eig_truncate_noalloc",
     "tucker_sthosvd_order",
 ]
 
@@ -117,6 +117,7 @@ def lib():
             "tucker_batch_status": (i32, [P, P]),
             "tucker_empty_cache": (i32, []),
             "tucker_sthosvd_order": (i32, [i32, P, P, P, P]),
+            "tucker_eig_truncate_noalloc": (i32, [P, i64, d, P, P, P, P, P]),
             "tucker_last_error": (ctypes.c_char_p, []),
             "tucker_version": (ctypes.c_char_p, []),
         }
@@ -588,6 +589,15 @@ def eig_truncate(S, thr: float, stream=None):
     r = int(R.item())
     # column-major J x J buffer: row k of Ubuf is column k of U
     return lam, Ubuf[:r].t(), r, float(disc.item())
+
+
+def eig_truncate_noalloc(S, thr: float, lam, Ubuf, R, disc, stream=None):
+    """tucker_eig_truncate_noalloc on caller-provided outputs (lam: J float64,
+    Ubuf: J x J float64 whose row k receives eigenvector k, R: one int64,
+    disc: one float64, all GPU tensors); the library allocates nothing."""
+    J = S.shape[0]
+    _check(lib().tucker_eig_truncate_noalloc(S.data_ptr(), J, float(thr), lam.data_ptr(), Ubuf.data_ptr(),
+                                             R.data_ptr(), disc.data_ptr(), _stream(stream)))
 
 
 def ttm(y, n: int, M, dims=None, out_dtype=None, fp32_products: bool = False, stream=None):

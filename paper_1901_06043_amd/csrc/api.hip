@@ -1324,6 +1324,58 @@ tucker_status tucker_gram(const void* Y, tucker_dtype dtype, const int64_t* dims
   return run_gram(Y, dtype, dims, N, n, prec, S, norm2, stream);
 }
 
+}  // extern "C"
+
+namespace {
+
+// Workspace of tucker_eig_truncate_noalloc: the eigensolver's workspace for
+// the largest supported J (2 J^2 + 3 J + 8 doubles at J = 1024, 16.8 MB),
+// one copy per device for the life of the process.  Host code never uses the
+// array's name as an address: the device address comes from
+// hipGetSymbolAddress, once per device, with that device current.
+constexpr int64_t kNoAllocMaxJ = kMaxEigJ;
+constexpr int64_t kNoAllocDoubles = 2 * kNoAllocMaxJ * kNoAllocMaxJ + 3 * kNoAllocMaxJ + 8;
+static __device__ __align__(256) double scratch[kNoAllocDoubles];
+
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[64];
+
+tucker_status scratch_address(double** out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return fail(TUCKER_EUNSUPPORTED, "device index %d out of range", dev);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(TUCKER_EHIP, "hipGetSymbolAddress returned no address for the static workspace");
+    g_scratch_ptr[dev] = static_cast<double*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return TUCKER_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+tucker_status tucker_eig_truncate_noalloc(const double* S, int64_t J, double thr, double* lam, double* U,
+                                          int64_t* R, double* disc, hipStream_t stream) {
+  if (!S || !lam || !U || !R || !disc) return fail(TUCKER_EINVAL, "NULL pointer");
+  if (J < 1 || J > kNoAllocMaxJ)
+    return fail(TUCKER_EINVAL, "J=%lld outside 1..%lld (the static workspace holds the eigensolver of J <= %lld)",
+                (long long)J, (long long)kNoAllocMaxJ, (long long)kNoAllocMaxJ);
+  if (!(thr >= 0.0) || !std::isfinite(thr)) return fail(TUCKER_EINVAL, "thr must be finite and >= 0");
+  tucker_status st;
+  if ((st = ensure_device())) return st;
+  double* ws = nullptr;
+  if ((st = scratch_address(&ws))) return st;
+  tk::EigWork w;
+  tk::eig_work_carve(ws, J, w);
+  HIP_TRY(tk::launch_eig_truncate(S, (int)J, thr, nullptr, 0, w, lam, U, R, disc, stream));
+  return TUCKER_OK;
+}
+
 tucker_status tucker_eig_truncate(const double* S, int64_t J, double thr, double* lam, double* U, int64_t* R,
                                   double* disc, hipStream_t stream) {
   if (!S || !lam || !U || !R || !disc) return fail(TUCKER_EINVAL, "NULL pointer");
