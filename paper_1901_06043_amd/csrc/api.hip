@@ -347,6 +347,19 @@ tucker_status run_gram(const void* Y, tucker_dtype dt, const int64_t* dims, int 
                                   sq.as<double>(), S, norm2, s, after_main));
     return TUCKER_OK;
   }
+  const int es = (dt == TUCKER_F64) ? 8 : 4;
+  if (prec == TUCKER_GRAM_FP64 && tk::gram_dma_eligible((int)J, (uint64_t)L, es, Y)) {
+    // larger modes, FP64: tile pairs staged by direct global-to-LDS loads
+    tk::GramPlan p = tk::plan_gram_dma((int)J, (uint64_t)L, (uint64_t)K, es);
+    HIP_TRY(part.alloc(sizeof(double) * p.part_elems, s));
+    if (dt == TUCKER_F64)
+      HIP_TRY(tk::launch_gram_dma(static_cast<const double*>(Y), (int)J, L, K, p, part.as<double>(), S, norm2, s,
+                                  after_main));
+    else
+      HIP_TRY(tk::launch_gram_dma(static_cast<const float*>(Y), (int)J, L, K, p, part.as<double>(), S, norm2, s,
+                                  after_main));
+    return TUCKER_OK;
+  }
   tk::GramPlan p = tk::plan_gram_mp((int)J, (uint64_t)K, (int)prec);
   HIP_TRY(part.alloc(sizeof(double) * p.part_elems, s));
   HIP_TRY(sq.alloc(sizeof(double) * p.sq_elems, s));
@@ -525,7 +538,14 @@ int64_t gram_scratch_doubles(const int64_t* dims, int N, int n, tucker_gram_prec
   if (J <= tk::kStreamMaxJ) p = tk::plan_gram_stream((int)J, (uint64_t)K, (int)prec);
   else if (prec == TUCKER_GRAM_FP64 && J <= tk::kTriMaxJ) p = tk::plan_gram_f64((int)J, (uint64_t)L, (uint64_t)K);
   else p = tk::plan_gram_mp((int)J, (uint64_t)K, (int)prec);
-  return p.part_elems + p.sq_elems;
+  int64_t need = p.part_elems + p.sq_elems;
+  if (prec == TUCKER_GRAM_FP64 && J > tk::kTriMaxJ) {
+    // the tile-pair kernel with direct LDS loads, for either input type
+    for (int es : {4, 8})
+      if (tk::gram_dma_eligible((int)J, (uint64_t)L, es, nullptr))
+        need = std::max(need, tk::plan_gram_dma((int)J, (uint64_t)L, (uint64_t)K, es).part_elems);
+  }
+  return need;
 }
 
 // Device memory of one compression (the input excluded), following the

@@ -715,6 +715,13 @@ hipError_t launch_gram_mp(const T* Y, int J, uint64_t L, uint64_t K, int prec, c
   return hipGetLastError();
 }
 
+void launch_gram_pair_reduce(const double* part, int ntiles, int npairs, int64_t nsplit, int J, double* S,
+                             hipStream_t stream) {
+  const int64_t nel = (int64_t)npairs * 64 * 256;
+  hipLaunchKernelGGL(gram_mp_reduce_kernel, dim3(ceil_div(nel, 256)), dim3(256), 0, stream, part, 0, ntiles, npairs,
+                     64, nsplit, J, S);
+}
+
 template <typename T>
 hipError_t launch_gram_batched(const GramBatch& b, int prec, bool unit_l, hipStream_t stream) {
   if (b.Jmax > 128 || b.nitems <= 0) return hipErrorInvalidValue;

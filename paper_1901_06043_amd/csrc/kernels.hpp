@@ -35,6 +35,21 @@ struct GramPlan {
   int64_t sq_elems;    // doubles of sum-of-squares workspace
 };
 
+// FP64 Gram for J > 128 with direct global-to-LDS staging (gram_dma.hip):
+// float or double input, unit stride (L = 1) or row segments (L >= 64 or L a
+// multiple of the chunk width 128 / sizeof(T)), 16-byte aligned base and
+// column (L = 1) or row stride.  Partial blocks in the tile-pair layout of
+// launch_gram_pair_reduce; norm2 (may be null) receives trace(S).
+bool gram_dma_eligible(int J, uint64_t L, int elem_size, const void* Y);
+GramPlan plan_gram_dma(int J, uint64_t L, uint64_t K, int elem_size);
+template <typename T>
+hipError_t launch_gram_dma(const T* Y, int J, uint64_t L, uint64_t K, const GramPlan& p, double* part, double* S,
+                           double* norm2, hipStream_t stream, hipEvent_t after_main);
+// Sums the partial 128 x 128 tile-pair blocks of nsplit splits into S (both
+// triangles), in a fixed order.
+void launch_gram_pair_reduce(const double* part, int ntiles, int npairs, int64_t nsplit, int J, double* S,
+                             hipStream_t stream);
+
 // FP64 Gram with the whole triangle per workgroup, J <= kTriMaxJ.
 constexpr int kTriMaxJ = 240;
 GramPlan plan_gram_f64(int J, uint64_t L, uint64_t K);

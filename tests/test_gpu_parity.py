@@ -49,6 +49,19 @@ GRAM_SHAPES = [
     ([672, 1500], [0]),
     ([9, 672, 4], [1]),
     ([7, 5, 626], [2]),
+    # FP64 Grams of J > 240: unit stride with even J (direct LDS loads) and a
+    # ragged 44-row last tile; odd J and J = 999 over L = 301 columns (strides
+    # not 16-byte aligned: register-staged tile pairs); L = 64 (direct loads,
+    # five slabs); L = 447 (odd: register-staged); the last mode with
+    # L = 1000; fewer columns than one chunk; L = 80 (a ragged chunk for float
+    # input)
+    ([300, 2000], [0]),
+    ([301, 999], [0, 1]),
+    ([64, 260, 5], [1]),
+    ([447, 300, 3], [1]),
+    ([1000, 250], [1]),
+    ([300, 7], [0]),
+    ([80, 384], [1]),
 ]
 
 
@@ -67,6 +80,30 @@ def test_gram_parity(tk, orc, dims, modes, dtype):
         d = np.sqrt(np.outer(np.diag(Sref), np.diag(Sref)))
         err = np.abs(S.cpu().numpy() - Sref)
         assert np.all(err <= 1e-11 * d + 1e-300), (err / (d + 1e-300)).max()
+        assert float(nrm.item()) == pytest.approx(orc.norm2(X.astype(np.float64)), rel=1e-11)
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_gram_unaligned_base(tk, orc, dtype):
+    """A tensor that starts one element past a 16-byte boundary: the FP64
+    Gram of a large mode cannot use 16-byte direct loads and takes the
+    register-staged tile-pair kernel."""
+    dims = [260, 300]
+    rng = np.random.default_rng(7)
+    X = rng.standard_normal(int(np.prod(dims))).astype(dtype)
+    tdt = torch.float64 if dtype == np.float64 else torch.float32
+    buf = torch.empty(X.size + 4, dtype=tdt, device="cuda")
+    x = buf[1:1 + X.size]
+    x.copy_(torch.from_numpy(X))
+    assert x.data_ptr() % 16 != 0
+    x = x.view(dims[::-1])
+    for n in (0, 1):
+        print(f"gram unaligned dims={dims} n={n} dtype={dtype.__name__}", flush=True)
+        S, nrm = tk.gram(x, n, dims=dims, with_norm=True)
+        torch.cuda.synchronize()
+        Sref = orc.gram(X.astype(np.float64), dims, n)
+        d = np.sqrt(np.outer(np.diag(Sref), np.diag(Sref)))
+        assert np.all(np.abs(S.cpu().numpy() - Sref) <= 1e-11 * d)
         assert float(nrm.item()) == pytest.approx(orc.norm2(X.astype(np.float64)), rel=1e-11)
 
 
