@@ -88,6 +88,16 @@ __global__ void sum_fixed_kernel(const double* __restrict__ x, int64_t n, double
 // ---------------------------------------------------------------- TTM
 // Z_(n) = M Y_(n);  M is K x J with element (k,j) at M[k*msk + j*msj].
 // fp32_products: FP32 MFMA products (M and Y rounded to FP32), else FP64.
+// FP64 mode product for more than 64 output rows with direct global-to-LDS
+// staging (ttm_dma.hip): M with contiguous rows (msj = 1) or columns
+// (msk = 1) and even stride, 16-byte aligned M and Y; L = 1 needs double Y
+// and even J, L > 1 needs L a multiple of 16 / sizeof(TI); float Y only with
+// contiguous rows of M and double output.  launch_ttm uses it when eligible.
+bool ttm_dma_eligible(int J, uint64_t L, uint64_t cols, int K, int64_t msk, int64_t msj, int ysize, int zsize,
+                      const void* Y, const void* M);
+template <typename TY, typename TZ>
+hipError_t launch_ttm_dma(const TY* Y, int J, uint64_t L, uint64_t cols, const double* M, int64_t msk, int64_t msj,
+                          int K, TZ* Z, hipStream_t stream);
 template <typename TI, typename TO>
 hipError_t launch_ttm(const TI* Y, int J, uint64_t L, uint64_t cols, const double* M, int64_t msk, int64_t msj,
                       int K, TO* Z, bool fp32_products, hipStream_t stream);

@@ -528,6 +528,10 @@ template <typename TI, typename TO>
 hipError_t launch_ttm(const TI* Y, int J, uint64_t L, uint64_t cols, const double* M, int64_t msk, int64_t msj,
                       int K, TO* Z, bool fp32_products, hipStream_t stream) {
   if (fp32_products) return launch_ttm_ct<TI, TO, float>(Y, J, L, cols, M, msk, msj, K, Z, stream);
+  // more than 64 output rows with 16-byte aligned operands: the tiled kernel
+  // with direct global-to-LDS staging (ttm_dma.hip)
+  if (ttm_dma_eligible(J, L, cols, K, msk, msj, (int)sizeof(TI), (int)sizeof(TO), Y, M))
+    return launch_ttm_dma(Y, J, L, cols, M, msk, msj, K, Z, stream);
   return launch_ttm_ct<TI, TO, double>(Y, J, L, cols, M, msk, msj, K, Z, stream);
 }
 

@@ -192,6 +192,14 @@ TTM_CASES = [
     ([102, 30], 0, 70),
     ([101, 30], 0, 70),
     ([626, 9], 0, 130),
+    # more than 64 output rows with direct LDS staging: L > 1 (L = 6: double
+    # input only; L = 8 and 12: both; 128-column tiles crossing slabs of L),
+    # the last mode (L = 200), ragged J and ragged row tiles (K = 130, 150)
+    ([6, 100, 50], 1, 70),
+    ([8, 90, 40], 1, 130),
+    ([12, 40, 70], 1, 150),
+    ([20, 10, 96], 2, 100),
+    ([300, 50], 0, 260),
 ]
 
 
