@@ -46,35 +46,46 @@ struct TtmDmaParams {
 
 // ORI 0 (L > 1): A = M (row form MF = 0, column form MF = 1), B = Y (column
 // form).  ORI 1 (L = 1): A = Y (row form), B = M.
-template <typename TY, int ORI, int MF>
+// WY: bytes per lane of the Y loads, 16, or 4 where Y's rows or columns are
+// only 8-byte aligned (odd L or J); M is always loaded in 16-byte units.
+template <typename TY, int ORI, int MF, int WY>
 struct Cfg {
   using IM = TImg<MF == 0 ? 0 : 1, 8>;
   using IY = TImg<ORI == 0 ? 1 : 0, sizeof(TY)>;
   static constexpr int MB = IM::BYTES, YB = IY::BYTES;
   static constexpr int BUF = MB + YB;  // one chunk: M image then Y image
-  static constexpr int NIM = MB / 1024, NIY = YB / 1024;  // load instructions per image
+  static constexpr int NIM = MB / 1024, NIY = YB / (64 * WY);  // load instructions per image
+  static_assert(WY == 16 || sizeof(TY) == 8, "4-byte loads for double input only");
 };
 
 // Per-lane state of the loads of one item (tile at output row k0, column
 // c0).  The wave issues instructions jj = w, w + 4, ... of each image; a
-// lane's load address is a fixed per-lane part plus a per-instruction part
-// common to the wave: in the column form the lane's rows are the same for all
-// of the wave's instructions (the swizzle of j = w + 4 n depends on w only),
-// in the row form they move by 8 rows per instruction.
-template <typename TY, int ORI, int MF>
+// lane's load address is a per-lane part fixed for the item plus a
+// per-instruction part common to the wave:
+//   16-byte loads: in the column form the lane's rows are the same for all of
+//     the wave's instructions (the swizzle of j = w + 4 n depends on w only),
+//     in the row form they move by 8 rows per instruction;
+//   4-byte loads (256 bytes per instruction; Y only): column form, j = n and
+//     the lane's rows alternate between two sets with the swizzle of j (bit 1
+//     of n); row form, 2 rows per instruction (8 more per n) and the lane's j
+//     alternate between two values with the row pair's swizzle (bit 0 of n).
+template <typename TY, int ORI, int MF, int WY>
 struct Loader {
-  const char* mlane;  // M(k0 + mrow0, 0)
-  const char* ylane;  // Y(0, c0 + yrow0)
-  int64_t mjstride;   // M bytes per reduction index j
-  int64_t yjstride;   // Y bytes per j
+  const char* mlane;   // M(k0 + mrow0, 0)
+  const char* ylane;   // Y(0, c0 + yrow0) (16-byte loads, 4-byte row form)
+  const char* ycol0;   // 4-byte column form: Y(0, c0 + yr0) with the lane's byte,
+  const char* ycol1;   // and for the other swizzle pattern
+  int64_t mjstride;    // M bytes per reduction index j
+  int64_t yjstride;    // Y bytes per j
   int64_t c0;
   int k0, mrow0, yrow0;
+  int yr0, yr1, yj0, yj1;  // 4-byte loads: rows (column form) or j (row form) per pattern
 };
 
-template <typename TY, int ORI, int MF>
-__device__ __forceinline__ void loader_init(Loader<TY, ORI, MF>& ld, const TtmDmaParams& g, int k0, int64_t c0,
+template <typename TY, int ORI, int MF, int WY>
+__device__ __forceinline__ void loader_init(Loader<TY, ORI, MF, WY>& ld, const TtmDmaParams& g, int k0, int64_t c0,
                                             int wave, int lane) {
-  using C = Cfg<TY, ORI, MF>;
+  using C = Cfg<TY, ORI, MF, WY>;
   ld.k0 = k0;
   ld.c0 = c0;
   int r, j;
@@ -82,26 +93,41 @@ __device__ __forceinline__ void loader_init(Loader<TY, ORI, MF>& ld, const TtmDm
   ld.mrow0 = r;
   ld.mlane = g.M + (int64_t)(k0 + r) * g.msk * 8;
   ld.mjstride = g.msj * 8;
-  C::IY::unit_of(wave, lane, r, j);
-  ld.yrow0 = r;
-  if constexpr (ORI == 0) {
-    // column c of the unfolding sits at l + L J m (clamped into the tensor;
-    // lanes past the end issue nothing)
-    const int64_t c = min(c0 + r, g.cols - 1);
+  ld.yjstride = (ORI == 0) ? g.L * (int64_t)sizeof(TY) : (int64_t)sizeof(TY);
+  // column c of the unfolding sits at l + L J m (clamped into the tensor;
+  // lanes past the end issue nothing)
+  auto colbase = [&](int rr) {
+    const int64_t c = min(c0 + rr, g.cols - 1);
     const int64_t m = c / g.L, l = c - m * g.L;
-    ld.ylane = g.Y + (l + g.L * (int64_t)g.J * m) * (int64_t)sizeof(TY);
-    ld.yjstride = g.L * (int64_t)sizeof(TY);
+    return g.Y + (l + g.L * (int64_t)g.J * m) * (int64_t)sizeof(TY);
+  };
+  if constexpr (WY == 16) {
+    C::IY::unit_of(wave, lane, r, j);
+    ld.yrow0 = r;
+    if constexpr (ORI == 0) ld.ylane = colbase(r);
+    else ld.ylane = g.Y + min(c0 + r, g.cols - 1) * g.J * (int64_t)sizeof(TY);
+  } else if constexpr (ORI == 0) {
+    // column form, 1024 bytes per j: instruction w + 4 n covers quarter w of j = n
+    const int u = 16 * wave + (lane >> 2);
+    ld.yr0 = 2 * u + ((lane & 3) >> 1);
+    ld.yr1 = 2 * (u ^ 8) + ((lane & 3) >> 1);
+    ld.ycol0 = colbase(ld.yr0) + (lane & 1) * 4;
+    ld.ycol1 = colbase(ld.yr1) + (lane & 1) * 4;
   } else {
-    ld.ylane = g.Y + min(c0 + r, g.cols - 1) * g.J * (int64_t)sizeof(TY);
-    ld.yjstride = (int64_t)sizeof(TY);
+    // row form, 2 rows of 128 bytes per instruction: rows 2 w + 8 n + (lane >> 5)
+    ld.yrow0 = 2 * wave + (lane >> 5);
+    ld.ylane = g.Y + min(c0 + ld.yrow0, g.cols - 1) * g.J * (int64_t)sizeof(TY) + (lane & 1) * 4;
+    const int pu = (lane & 31) >> 2;
+    ld.yj0 = 2 * (pu ^ wave) + ((lane & 3) >> 1);
+    ld.yj1 = 2 * (pu ^ wave ^ 4) + ((lane & 3) >> 1);
   }
 }
 
 // Loads chunk t (reduction indices 16 t ..) into buf: M image, then Y image.
-template <typename TY, int ORI, int MF>
-__device__ __forceinline__ void issue_chunk(const Loader<TY, ORI, MF>& ld, const TtmDmaParams& g, int t, char* buf,
+template <typename TY, int ORI, int MF, int WY>
+__device__ __forceinline__ void issue_chunk(const Loader<TY, ORI, MF, WY>& ld, const TtmDmaParams& g, int t, char* buf,
                                             int wave, int lane) {
-  using C = Cfg<TY, ORI, MF>;
+  using C = Cfg<TY, ORI, MF, WY>;
   const int j0 = kJC * t;
 #pragma unroll
   for (int n = 0; n < C::NIM / kTDW; ++n) {
@@ -116,33 +142,81 @@ __device__ __forceinline__ void issue_chunk(const Loader<TY, ORI, MF>& ld, const
       __builtin_amdgcn_global_load_lds(static_cast<const void*>(src), (lds_void*)(buf + jj * 1024), 16, 0, 0);
     }
   }
+  if constexpr (WY == 16) {
 #pragma unroll
-  for (int n = 0; n < C::NIY / kTDW; ++n) {
-    const int jj = wave + kTDW * n;
-    int r, j;
-    C::IY::unit_of(jj, lane, r, j);
-    if (ld.c0 + r < g.cols && j0 + j < g.J) {
-      const int64_t row_off = (ORI == 1) ? (int64_t)(r - ld.yrow0) * g.J * (int64_t)sizeof(TY) : 0;
-      const char* src = ld.ylane + row_off + (int64_t)(j0 + j) * ld.yjstride;
-      __builtin_amdgcn_global_load_lds(static_cast<const void*>(src), (lds_void*)(buf + C::MB + jj * 1024), 16, 0,
-                                       0);
+    for (int n = 0; n < C::NIY / kTDW; ++n) {
+      const int jj = wave + kTDW * n;
+      int r, j;
+      C::IY::unit_of(jj, lane, r, j);
+      if (ld.c0 + r < g.cols && j0 + j < g.J) {
+        const int64_t row_off = (ORI == 1) ? (int64_t)(r - ld.yrow0) * g.J * (int64_t)sizeof(TY) : 0;
+        const char* src = ld.ylane + row_off + (int64_t)(j0 + j) * ld.yjstride;
+        __builtin_amdgcn_global_load_lds(static_cast<const void*>(src), (lds_void*)(buf + C::MB + jj * 1024), 16,
+                                         0, 0);
+      }
+    }
+  } else {
+    // 4-byte loads, 16 instructions per wave, rolled in pairs (the lane
+    // pattern is selected per instruction)
+#pragma unroll 2
+    for (int n = 0; n < C::NIY / kTDW; ++n) {
+      const int jj = wave + kTDW * n;
+      if constexpr (ORI == 0) {
+        const bool p = (n >> 1) & 1;
+        if (ld.c0 + (p ? ld.yr1 : ld.yr0) < g.cols && j0 + n < g.J) {
+          const char* src = (p ? ld.ycol1 : ld.ycol0) + (int64_t)(j0 + n) * ld.yjstride;
+          __builtin_amdgcn_global_load_lds(static_cast<const void*>(src), (lds_void*)(buf + C::MB + jj * 256), 4, 0,
+                                           0);
+        }
+      } else {
+        const int yj = (n & 1) ? ld.yj1 : ld.yj0;
+        if (ld.c0 + ld.yrow0 + 8 * n < g.cols && j0 + yj < g.J) {
+          const char* src = ld.ylane + (int64_t)(8 * n) * g.J * (int64_t)sizeof(TY) + (int64_t)(j0 + yj) * 8;
+          __builtin_amdgcn_global_load_lds(static_cast<const void*>(src), (lds_void*)(buf + C::MB + jj * 256), 4, 0,
+                                           0);
+        }
+      }
     }
   }
 }
 
-// Zeros the units of indices j >= J in both images of the last chunk (none
-// of them is loaded).  Called once the wave's own loads have landed.
-template <typename TY, int ORI, int MF>
-__device__ __forceinline__ void fill_chunk(const TtmDmaParams& g, int t, char* buf, int tid) {
-  using C = Cfg<TY, ORI, MF>;
+// Zeros the elements of indices j >= J in both images of the last chunk.
+// Each wave clears the slots of its own load instructions (loaded or not),
+// once its loads have landed, so that no load of another wave can land on a
+// cleared element afterwards.
+template <typename TY, int ORI, int MF, int WY>
+__device__ __forceinline__ void fill_chunk(const Loader<TY, ORI, MF, WY>& ld, const TtmDmaParams& g, int t,
+                                           char* buf, int wave, int lane) {
+  using C = Cfg<TY, ORI, MF, WY>;
   const int j0 = kJC * t;
   if (j0 + kJC <= g.J) return;
-  for (int u = tid; u < C::BUF / 16; u += kTDNT) {
-    const int P = u * 16;
+  (void)ld;
+  // M: 16-byte units of two doubles; the row form's two elements have j, j + 1
+#pragma unroll
+  for (int n = 0; n < C::NIM / kTDW; ++n) {
+    const int jj = wave + kTDW * n;
     int r, j;
-    if (P < C::MB) C::IM::unit_of(P >> 10, (P & 1023) >> 4, r, j);
-    else C::IY::unit_of((P - C::MB) >> 10, ((P - C::MB) & 1023) >> 4, r, j);
-    if (j0 + j >= g.J) *reinterpret_cast<uint4*>(buf + P) = uint4{0u, 0u, 0u, 0u};
+    C::IM::unit_of(jj, lane, r, j);
+    double* e = reinterpret_cast<double*>(buf + jj * 1024 + lane * 16);
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+      if (j0 + j + (MF == 0 ? h : 0) >= g.J) e[h] = 0.0;
+  }
+  constexpr int ES = sizeof(TY);
+#pragma unroll
+  for (int n = 0; n < C::NIY / kTDW; ++n) {
+    const int jj = wave + kTDW * n;
+    if constexpr (WY == 16) {
+      int r, j;
+      C::IY::unit_of(jj, lane, r, j);
+      TY* e = reinterpret_cast<TY*>(buf + C::MB + jj * 1024 + lane * 16);
+#pragma unroll
+      for (int h = 0; h < 16 / ES; ++h)
+        if (j0 + j + (ORI == 1 ? h : 0) >= g.J) e[h] = (TY)0;
+    } else {
+      const int jl = (ORI == 0) ? n : ((n & 1) ? ld.yj1 : ld.yj0);
+      if (j0 + jl >= g.J) *reinterpret_cast<uint32_t*>(buf + C::MB + jj * 256 + lane * 4) = 0u;
+    }
   }
 }
 
@@ -203,11 +277,11 @@ __device__ __forceinline__ void compute_chunk(const char* abuf, const char* bbuf
   }
 }
 
-template <unsigned MK, typename TY, int ORI, int MF>
-__device__ __forceinline__ void chunk_loop(const Loader<TY, ORI, MF>& ld, const TtmDmaParams& g, char* buf0,
+template <unsigned MK, typename TY, int ORI, int MF, int WY>
+__device__ __forceinline__ void chunk_loop(const Loader<TY, ORI, MF, WY>& ld, const TtmDmaParams& g, char* buf0,
                                            char* buf1, const int (&oa)[4], int da, const int (&ob)[4], int db,
                                            d4 (&acc)[4][4], int wave, int lane, int tid) {
-  using C = Cfg<TY, ORI, MF>;
+  using C = Cfg<TY, ORI, MF, WY>;
   // A and B operand images: forms, element types and offsets in a buffer
   constexpr int FM = (MF == 0) ? 0 : 1, FY = (ORI == 0) ? 1 : 0;
   constexpr int FA = (ORI == 0) ? FM : FY, FB = (ORI == 0) ? FY : FM;
@@ -217,20 +291,20 @@ __device__ __forceinline__ void chunk_loop(const Loader<TY, ORI, MF>& ld, const 
   const int nch = (g.J + kJC - 1) / kJC;
   issue_chunk(ld, g, 0, buf0, wave, lane);
   __builtin_amdgcn_s_waitcnt(0);
-  fill_chunk<TY, ORI, MF>(g, 0, buf0, tid);
+  fill_chunk(ld, g, 0, buf0, wave, lane);
   __syncthreads();
   for (int t = 0;; t += 2) {
     if (t + 1 < nch) issue_chunk(ld, g, t + 1, buf1, wave, lane);
     compute_chunk<MK, FA, TA, FB, TB>(buf0 + AOFF, buf0 + BOFF, oa, da, ob, db, acc);
     if (t + 1 >= nch) break;
     __builtin_amdgcn_s_waitcnt(0);
-    fill_chunk<TY, ORI, MF>(g, t + 1, buf1, tid);
+    fill_chunk(ld, g, t + 1, buf1, wave, lane);
     __syncthreads();
     if (t + 2 < nch) issue_chunk(ld, g, t + 2, buf0, wave, lane);
     compute_chunk<MK, FA, TA, FB, TB>(buf1 + AOFF, buf1 + BOFF, oa, da, ob, db, acc);
     if (t + 2 >= nch) break;
     __builtin_amdgcn_s_waitcnt(0);
-    fill_chunk<TY, ORI, MF>(g, t + 2, buf0, tid);
+    fill_chunk(ld, g, t + 2, buf0, wave, lane);
     __syncthreads();
   }
 }
@@ -281,8 +355,8 @@ __device__ __forceinline__ void store_tile(const TtmDmaParams& g, const d4 (&acc
 // The whole item for one block mask class: accumulators zeroed, all chunks,
 // then the stores (one copy per class, so that no accumulator is merged
 // across classes).
-template <unsigned MK, typename TY, typename TZ, int ORI, int MF>
-__device__ __forceinline__ void tile_body(const Loader<TY, ORI, MF>& ld, const TtmDmaParams& g, char* buf0,
+template <unsigned MK, typename TY, typename TZ, int ORI, int MF, int WY>
+__device__ __forceinline__ void tile_body(const Loader<TY, ORI, MF, WY>& ld, const TtmDmaParams& g, char* buf0,
                                           char* buf1, const int (&oa)[4], int da, const int (&ob)[4], int db,
                                           int wave, int lane, int tid, int k0, int64_t c0l, int a0, int b0) {
   d4 acc[4][4];
@@ -294,9 +368,9 @@ __device__ __forceinline__ void tile_body(const Loader<TY, ORI, MF>& ld, const T
   store_tile<MK, TZ, ORI>(g, acc, k0, c0l, a0, b0, lane & 15, lane >> 4);
 }
 
-template <typename TY, typename TZ, int ORI, int MF>
+template <typename TY, typename TZ, int ORI, int MF, int WY>
 __global__ __launch_bounds__(kTDNT, 2) void ttm_dma_kernel(TtmDmaParams g) {
-  using C = Cfg<TY, ORI, MF>;
+  using C = Cfg<TY, ORI, MF, WY>;
   __shared__ __attribute__((aligned(16))) char buf0[C::BUF];
   __shared__ __attribute__((aligned(16))) char buf1[C::BUF];
   const int64_t item = xcd_remap(blockIdx.x, gridDim.x, g.total);
@@ -308,7 +382,7 @@ __global__ __launch_bounds__(kTDNT, 2) void ttm_dma_kernel(TtmDmaParams g) {
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int i = lane & 15, q = lane >> 4;
 
-  Loader<TY, ORI, MF> ld;
+  Loader<TY, ORI, MF, WY> ld;
   loader_init(ld, g, k0, c0l, wave, lane);
 
   // the wave's 64 x 64 part: A blocks a0 + x, B blocks b0 + y (16 rows each)
@@ -332,7 +406,7 @@ __global__ __launch_bounds__(kTDNT, 2) void ttm_dma_kernel(TtmDmaParams g) {
     db = IB::at(i, IB::jstep(2, q)) - IB::at(i, IB::jstep(0, q));
   }
 #define TDMA_LOOP(MK) \
-  tile_body<MK, TY, TZ, ORI, MF>(ld, g, buf0, buf1, oa, da, ob, db, wave, lane, tid, k0, c0l, a0, b0)
+  tile_body<MK, TY, TZ, ORI, MF, WY>(ld, g, buf0, buf1, oa, da, ob, db, wave, lane, tid, k0, c0l, a0, b0)
   if constexpr (ORI == 0) {
     if (mask == 0xFFFFu) TDMA_LOOP(0xFFFFu);
     else if (mask == 0x0FFFu) TDMA_LOOP(0x0FFFu);
@@ -351,22 +425,29 @@ __global__ __launch_bounds__(kTDNT, 2) void ttm_dma_kernel(TtmDmaParams g) {
 
 }  // namespace
 
+// 16-byte loads of Y need its rows (L = 1: stride J) or slabs (L > 1: the
+// element offset L j) 16-byte aligned; otherwise double input takes 4-byte
+// loads.
+static bool ttm_dma_y16(int J, uint64_t L, int ysize, const void* Y) {
+  if (reinterpret_cast<uintptr_t>(Y) % 16) return false;
+  if (L == 1) return ((uint64_t)J * ysize) % 16 == 0;
+  return L % (16 / ysize) == 0;
+}
+
 bool ttm_dma_eligible(int J, uint64_t L, uint64_t cols, int K, int64_t msk, int64_t msj, int ysize, int zsize,
                       const void* Y, const void* M) {
   if (K <= 64 || J < 16 || cols == 0) return false;
-  if (reinterpret_cast<uintptr_t>(Y) % 16 || reinterpret_cast<uintptr_t>(M) % 16) return false;
+  if (reinterpret_cast<uintptr_t>(M) % 16 || reinterpret_cast<uintptr_t>(Y) % ysize) return false;
   // M: rows contiguous (msj = 1, row stride a multiple of 16 bytes) or
   // columns contiguous (msk = 1, column stride likewise)
   const bool mrow = (msj == 1 && msk % 2 == 0), mcol = (msk == 1 && msj % 2 == 0);
   if (!mrow && !mcol) return false;
-  if (L == 1) {
-    // Y rows of the image are columns c with 16 contiguous j: doubles, J even
-    return ysize == 8 && J % 2 == 0;
+  if (ysize == 4) {
+    // float input: 16-byte loads only, slabs of L > 1, the factor of a
+    // compression (rows of M contiguous) and double output
+    return L > 1 && ttm_dma_y16(J, L, ysize, Y) && mrow && zsize == 8;
   }
-  // Y columns in 16-byte units of consecutive c within a slab of L
-  if (L % (16 / ysize) != 0) return false;
-  // float input only with the factor of a compression (rows of M contiguous) and FP64 output
-  return ysize == 8 || (mrow && zsize == 8);
+  return true;
 }
 
 template <typename TY, typename TZ>
@@ -388,20 +469,27 @@ hipError_t launch_ttm_dma(const TY* Y, int J, uint64_t L, uint64_t cols, const d
   g.total = g.nkt * ceil_div((int64_t)cols, 128);
   const int64_t grid = ceil_div(g.total, kXcds) * kXcds;
   const bool mrow = (msj == 1 && msk % 2 == 0);
-#define TDMA(TYV, ORI, MF) \
-  hipLaunchKernelGGL((ttm_dma_kernel<TYV, TZ, ORI, MF>), dim3(grid), dim3(kTDNT), 0, stream, g)
+  const bool y16 = ttm_dma_y16(J, L, (int)sizeof(TY), Y);
+#define TDMA(TYV, ORI, MF, WYV) \
+  hipLaunchKernelGGL((ttm_dma_kernel<TYV, TZ, ORI, MF, WYV>), dim3(grid), dim3(kTDNT), 0, stream, g)
+#define TDMA_W(ORI, MF)               \
+  do {                                \
+    if (y16) TDMA(double, ORI, MF, 16); \
+    else TDMA(double, ORI, MF, 4);      \
+  } while (0)
   if constexpr (std::is_same<TY, float>::value) {
-    if constexpr (std::is_same<TZ, double>::value) TDMA(float, 0, 0);
+    if constexpr (std::is_same<TZ, double>::value) TDMA(float, 0, 0, 16);
     else return hipErrorInvalidValue;  // excluded by ttm_dma_eligible
   } else {
     if (L == 1) {
-      if (mrow) TDMA(double, 1, 0);
-      else TDMA(double, 1, 1);
+      if (mrow) TDMA_W(1, 0);
+      else TDMA_W(1, 1);
     } else {
-      if (mrow) TDMA(double, 0, 0);
-      else TDMA(double, 0, 1);
+      if (mrow) TDMA_W(0, 0);
+      else TDMA_W(0, 1);
     }
   }
+#undef TDMA_W
 #undef TDMA
   return hipGetLastError();
 }

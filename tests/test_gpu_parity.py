@@ -200,6 +200,9 @@ TTM_CASES = [
     ([12, 40, 70], 1, 150),
     ([20, 10, 96], 2, 100),
     ([300, 50], 0, 260),
+    # odd L or J with double input: 4-byte loads of Y
+    ([9, 45, 33], 1, 150),
+    ([99, 260], 0, 129),
 ]
 
 
@@ -233,6 +236,25 @@ def test_ttm_fp32_products_parity(tk, orc, dims, n, K, ydt):
     Aref, _ = orc.ttm(np.abs(X.astype(np.float64)), dims, n, np.abs(M))
     tol = (dims[n] + 2) * 2.0 ** -23 * Aref + 1e-30
     assert np.all(np.abs(Z.cpu().numpy().reshape(-1).astype(np.float64) - Zref) <= tol)
+
+
+@pytest.mark.parametrize("n", [0, 1])
+def test_ttm_unaligned_base(tk, orc, n):
+    """Double input starting 8 bytes past a 16-byte boundary: the tiled
+    product loads Y in 4-byte pieces."""
+    dims, K = [130, 90], 140
+    rng = np.random.default_rng(11 + n)
+    X = rng.standard_normal(int(np.prod(dims)))
+    M = rng.standard_normal((K, dims[n]))
+    buf = torch.empty(X.size + 2, dtype=torch.float64, device="cuda")
+    x = buf[1:1 + X.size]
+    x.copy_(torch.from_numpy(X))
+    assert x.data_ptr() % 16 != 0
+    print(f"ttm unaligned dims={dims} n={n}", flush=True)
+    Z = tk.ttm(x.view(dims[::-1]), n, torch.from_numpy(M).cuda(), dims=dims, out_dtype=torch.float64)
+    Zref, _ = orc.ttm(X, dims, n, M)
+    Aref, _ = orc.ttm(np.abs(X), dims, n, np.abs(M))
+    assert np.all(np.abs(Z.cpu().numpy().reshape(-1) - Zref) <= 1e-12 * Aref + 1e-300)
 
 
 def _check_sthosvd(tk, orc, X, dims, eps, order, dtype=torch.float64):
