@@ -70,8 +70,8 @@ def log(msg):
 
 
 def mode_work(dims, ranks, order):
-    """Per processed mode n (in `order`): (n, J, K, R, Gram flops J^2 K, TTM flops 2 R J K,
-    Gram bytes read per input element size, TTM elements read + written)."""
+    """Per processed mode n (in `order`): (n, J, K, R, L = product of the sizes before n, Gram
+    flops J^2 K, TTM flops 2 R J K, Gram elements read, TTM elements read + written)."""
     cur = list(dims)
     out = []
     for n in order:
@@ -80,7 +80,10 @@ def mode_work(dims, ranks, order):
             if k != n:
                 K *= v
         J, R = cur[n], ranks[n]
-        out.append({"mode": n, "J": J, "K": K, "R": R, "gram_flops": J * J * K, "ttm_flops": 2 * R * J * K,
+        L = 1
+        for v in cur[:n]:
+            L *= v
+        out.append({"mode": n, "J": J, "K": K, "R": R, "L": L, "gram_flops": J * J * K, "ttm_flops": 2 * R * J * K,
                     "gram_elems": J * K, "ttm_elems": (J + R) * K})
         cur[n] = R
     return out
@@ -416,14 +419,19 @@ def main():
     kind, n_dom, k_ms, k_flops = max(cands, key=lambda c: c[2])
     wd = next(w for w in work if w["mode"] == n_dom)
     ach = k_flops / (k_ms * 1e-3) / 1e12
+    es = 4 if n_dom == order[0] else 8  # the input (float32) feeds the first mode only
     if kind == "ttm":
-        kname = "ttm_kernel (FP64 mode product, mode %d, J=%d -> R=%d, K=%d)" % (n_dom, wd["J"], wd["R"], wd["K"])
-        tfile = "ttm_kernel_672x672x33x626_mode%d_traffic.md" % n_dom
-        abytes = wd["J"] * wd["K"] * (4 if n_dom == order[0] else 8) + wd["R"] * wd["K"] * 8
+        kname = "ttm_dma_kernel (FP64 mode product, mode %d, J=%d -> R=%d, K=%d)" % (n_dom, wd["J"], wd["R"], wd["K"])
+        tfile = "ttm_dma_kernel_672x672x33x626_mode%d_traffic.md" % n_dom
+        abytes = wd["J"] * wd["K"] * es + wd["R"] * wd["K"] * 8
     else:
-        kname = "gram_mp_pair_kernel (FP64 Gram, mode %d, J=%d, K=%d)" % (n_dom, wd["J"], wd["K"])
-        tfile = "gram_pair_kernel_672x672x33x626_mode%d_traffic.md" % n_dom
-        abytes = wd["J"] * wd["K"] * (4 if n_dom == order[0] else 8)
+        # the direct-load tile-pair kernel needs 16-byte aligned rows or columns
+        L = wd["L"]
+        dma = (wd["J"] * es % 16 == 0) if L == 1 else (L * es % 16 == 0 and (L >= 64 or L % (128 // es) == 0))
+        kern = "gram_dma_kernel" if dma else "gram_mp_pair_kernel"
+        kname = "%s (FP64 Gram, mode %d, J=%d, K=%d)" % (kern, n_dom, wd["J"], wd["K"])
+        tfile = "%s_672x672x33x626_mode%d_traffic.md" % (kern, n_dom)
+        abytes = wd["J"] * wd["K"] * es
     roofline = {"kernel": kname, "bound": "mfma", "achieved": round(ach, 3), "peak": PEAK_FP64_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(ach / PEAK_FP64_TFLOPS, 4), "traffic": profiled_traffic(tfile),
                 "avg_launch_ms": round(k_ms, 4), "algorithmic_flops_per_launch": k_flops,

@@ -548,6 +548,25 @@ int64_t gram_scratch_doubles(const int64_t* dims, int N, int n, tucker_gram_prec
   return need;
 }
 
+// Working extent of mode n after its truncation to rank R at `step`: R, or
+// R + 1 (a zero slice, from a zero column appended to U_n) when R is odd and
+// the FP64 path would otherwise meet an odd L = prod_{k<m} J_k at a later
+// mode m > n, whose rows of the unfolding would then not be 16-byte aligned
+// for the direct-load Gram and mode-product kernels.  The zero slice adds
+// nothing to any later Gram or product; the core is compacted at the end.
+int64_t working_rank(const int64_t* cur, int N, const int* order, int step, int64_t R, bool reduced) {
+  const int n = order[step];
+  if (reduced || R % 2 == 0 || R >= cur[n]) return R;
+  for (int s = step + 1; s < N; ++s) {
+    const int m = order[s];
+    if (m <= n) continue;
+    int64_t L = 1;
+    for (int k = 0; k < m; ++k) L *= (k == n) ? R : cur[k];
+    if (L > 1 && L % 2 == 1) return R + 1;
+  }
+  return R;
+}
+
 // Device memory of one compression (the input excluded), following the
 // allocations of sthosvd_impl: the handle's factors, eigenvalues and
 // scalars, the Gram and eigensolver workspaces, and per step the current and
@@ -568,12 +587,15 @@ size_t predict_bytes(tucker_dtype dtype, const int64_t* dims, int N, const int64
   int64_t cur[TUCKER_MAX_MODES];
   std::memcpy(cur, dims, sizeof(int64_t) * N);
   size_t peak = 0;
+  bool padded = false;
   for (int s = 0; s < N; ++s) {
     const int n = order[s];
     int64_t total = 1;
     for (int k = 0; k < N; ++k) total *= cur[k];
     const int64_t J = cur[n];
-    const int64_t R = ranks ? std::min<int64_t>(ranks[n], J) : J;
+    const int64_t R0 = ranks ? std::min<int64_t>(ranks[n], J) : J;
+    const int64_t R = working_rank(cur, N, order, s, R0, reduced);
+    padded = padded || (R != R0);
     const size_t ycur = (s == 0) ? 0 : round_bytes(wsz * total);
     const size_t ynext = round_bytes(wsz * (total / J * R));
     size_t gram = round_bytes(sizeof(double) * gram_scratch_doubles(cur, N, n, prec));
@@ -586,6 +608,15 @@ size_t predict_bytes(tucker_dtype dtype, const int64_t* dims, int N, const int64
     // the Gram scratch is released before the next working tensor is allocated
     peak = std::max(peak, ycur + std::max(gram, ynext));
     cur[n] = R;
+  }
+  if (padded && ranks) {
+    // the padded core and its compacted copy
+    int64_t tp = 1, tc = 1;
+    for (int k = 0; k < N; ++k) {
+      tp *= cur[k];
+      tc *= std::min<int64_t>(ranks[k], dims[k]);
+    }
+    peak = std::max(peak, round_bytes(wsz * tp) + round_bytes(wsz * tc));
   }
   (void)dtype;
   return fixed + peak;
@@ -678,6 +709,7 @@ tucker_status sthosvd_impl(const void* data, tucker_dtype dtype, const int64_t* 
   HIP_TRY(Sbuf.alloc(sizeof(double) * maxJ * maxJ, stream));
   HIP_TRY(ewbuf.alloc(sizeof(double) * tk::eig_work_doubles(maxJ), stream));
   const double thr_mul = fixed_ranks ? 0.0 : eps * eps / N;
+  bool padded = false;  // some working extent exceeds its rank (working_rank)
 
   for (int step = 0; step < N; ++step) {
     const int n = order[step];
@@ -764,14 +796,20 @@ tucker_status sthosvd_impl(const void* data, tucker_dtype dtype, const int64_t* 
       t->norm2 = nx2;
     }
     t->ranks[n] = R;
+    // working extent (R, or R + 1 with a zero column R of U_n)
+    const int64_t Rw = working_rank(cur, N, order, step, R, reduced);
+    if (Rw != R) {
+      HIP_TRY(tk::launch_fill(t->U[n] + R * J, (uint64_t)J, 0.0, stream));
+      padded = true;
+    }
     // Y <- Y x_n U_n^T: M(k, j) = U[j + k*J]
     int64_t total = 1;
     for (int k = 0; k < N; ++k) total *= cur[k];
-    const int64_t next_elems = total / J * R;
+    const int64_t next_elems = total / J * Rw;
     if (!async && (st = fits(round_bytes(dtype_size(wdt) * next_elems), "the next working tensor"))) return st;
     TmpBuf nbuf;
     HIP_TRY(nbuf.alloc(dtype_size(wdt) * next_elems, stream));
-    if ((st = run_ttm(Y, ydt, cur, N, n, t->U[n], R, J, 1, nbuf.p, wdt, reduced, stream))) return st;
+    if ((st = run_ttm(Y, ydt, cur, N, n, t->U[n], Rw, J, 1, nbuf.p, wdt, reduced, stream))) return st;
     HIP_TRY(hipEventRecord(ev[3], stream));
     ybuf.release();  // stream-ordered: after the TTM that read it
     ybuf.p = nbuf.p;
@@ -779,7 +817,25 @@ tucker_status sthosvd_impl(const void* data, tucker_dtype dtype, const int64_t* 
     nbuf.p = nullptr;
     Y = ybuf.p;
     ydt = wdt;
-    cur[n] = R;
+    cur[n] = Rw;
+  }
+  if (padded) {
+    // the core without the zero slices of padded modes
+    tk::CompactGeo geo{};
+    int64_t ctotal = 1;
+    for (int k = 0; k < N; ++k) {
+      geo.src[k] = cur[k];
+      geo.dst[k] = t->ranks[k];
+      ctotal *= t->ranks[k];
+    }
+    if (!async && (st = fits(round_bytes(sizeof(double) * ctotal), "the core"))) return st;
+    TmpBuf cbuf;
+    HIP_TRY(cbuf.alloc(sizeof(double) * ctotal, stream));
+    HIP_TRY(tk::launch_compact(ybuf.as<double>(), cbuf.as<double>(), geo, N, stream));
+    ybuf.release();
+    ybuf.p = cbuf.p;
+    ybuf.s = stream;
+    cbuf.p = nullptr;
   }
   // the last Y is the core; hand ownership to the handle
   t->core = ybuf.p;

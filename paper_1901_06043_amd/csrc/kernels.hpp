@@ -227,6 +227,13 @@ hipError_t launch_op_factor(int kind, int64_t begin, int64_t end, int64_t step, 
 hipError_t launch_fill(double* p, uint64_t n, double v, hipStream_t s);
 // coef[e] = prod_{m in [lo,hi)} vec[voff[m] + e_m] over the natural-descending
 // multi-index e of sizes K[lo..hi).
+// Copy of the leading dst[0..N) part of a tensor of sizes src[0..N) (natural
+// descending), e.g. a core whose working extents were padded.
+struct CompactGeo {
+  int64_t src[16];
+  int64_t dst[16];
+};
+hipError_t launch_compact(const double* src, double* dst, const CompactGeo& g, int N, hipStream_t s);
 struct OuterGeo {
   int64_t K[16];
   int64_t voff[16];

@@ -391,6 +391,27 @@ __global__ __launch_bounds__(kST) void fill_kernel(double* __restrict__ p, uint6
   if (i < n) p[i] = v;
 }
 
+// dst (sizes g.dst[0..N)) <- the leading part of src (sizes g.src[k] >=
+// g.dst[k]), both natural descending.  One wave per run of dst[0]
+// contiguous elements; runs r = 0 .. prod_{k>0} dst[k] - 1.
+__global__ __launch_bounds__(kST) void compact_kernel(const double* __restrict__ src, double* __restrict__ dst,
+                                                      CompactGeo g, int N, int64_t nruns) {
+  const int lane = threadIdx.x & 63;
+  const int64_t wave = ((int64_t)blockIdx.x * kST + threadIdx.x) >> 6;
+  const int64_t nwaves = ((int64_t)gridDim.x * kST) >> 6;
+  const int64_t e0 = g.dst[0];
+  for (int64_t r = wave; r < nruns; r += nwaves) {
+    int64_t rem = r, off = 0, stride = g.src[0];
+    for (int k = 1; k < N; ++k) {
+      const int64_t i = rem % g.dst[k];
+      rem /= g.dst[k];
+      off += i * stride;
+      stride *= g.src[k];
+    }
+    for (int64_t i = lane; i < e0; i += 64) dst[r * e0 + i] = src[off + i];
+  }
+}
+
 // coef[e] = prod_m v_m[e_m] over the multi-index of e in sizes K_lo..K_{hi-1}
 // (natural descending); vec holds the vectors one after another.
 __global__ __launch_bounds__(kST) void outer_coef_kernel(const double* __restrict__ vec, OuterGeo g, int lo, int hi,
@@ -520,6 +541,15 @@ hipError_t launch_op_factor(int kind, int64_t begin, int64_t end, int64_t step, 
 
 hipError_t launch_fill(double* p, uint64_t n, double v, hipStream_t s) {
   hipLaunchKernelGGL(fill_kernel, dim3((unsigned)ceil_div((int64_t)n, kST)), dim3(kST), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_compact(const double* src, double* dst, const CompactGeo& g, int N, hipStream_t s) {
+  int64_t nruns = 1;
+  for (int k = 1; k < N; ++k) nruns *= g.dst[k];
+  if (nruns <= 0 || g.dst[0] <= 0) return hipSuccess;
+  const int64_t grid = std::min<int64_t>(ceil_div(nruns, kST / 64), 8192);
+  hipLaunchKernelGGL(compact_kernel, dim3((unsigned)grid), dim3(kST), 0, s, src, dst, g, N, nruns);
   return hipGetLastError();
 }
 
