@@ -348,16 +348,22 @@ tucker_status run_gram(const void* Y, tucker_dtype dt, const int64_t* dims, int 
     return TUCKER_OK;
   }
   const int es = (dt == TUCKER_F64) ? 8 : 4;
-  if (prec == TUCKER_GRAM_FP64 && tk::gram_dma_eligible((int)J, (uint64_t)L, es, Y)) {
-    // larger modes, FP64: tile pairs staged by direct global-to-LDS loads
-    tk::GramPlan p = tk::plan_gram_dma((int)J, (uint64_t)L, (uint64_t)K, es);
+  // FP32 products: the direct-load kernel runs one workgroup per CU (its
+  // FP32 chunk sums and FP64 accumulators need more than 256 registers); it
+  // beat the register-staged kernel on unit-stride modes only
+  const int dprec = (prec == TUCKER_GRAM_FP64) ? 0 : ((prec == TUCKER_GRAM_FP32 && L == 1) ? 1 : -1);
+  if (dprec >= 0 && tk::gram_dma_eligible((int)J, (uint64_t)L, es, Y)) {
+    // larger modes, FP64 or FP32 products: tile pairs staged by direct
+    // global-to-LDS loads
+    tk::GramPlan p = tk::plan_gram_dma((int)J, (uint64_t)L, (uint64_t)K, es, dprec);
     HIP_TRY(part.alloc(sizeof(double) * p.part_elems, s));
+    if (p.sq_elems) HIP_TRY(sq.alloc(sizeof(double) * p.sq_elems, s));
     if (dt == TUCKER_F64)
-      HIP_TRY(tk::launch_gram_dma(static_cast<const double*>(Y), (int)J, L, K, p, part.as<double>(), S, norm2, s,
-                                  after_main));
+      HIP_TRY(tk::launch_gram_dma(static_cast<const double*>(Y), (int)J, L, K, dprec, p, part.as<double>(),
+                                  sq.as<double>(), S, norm2, s, after_main));
     else
-      HIP_TRY(tk::launch_gram_dma(static_cast<const float*>(Y), (int)J, L, K, p, part.as<double>(), S, norm2, s,
-                                  after_main));
+      HIP_TRY(tk::launch_gram_dma(static_cast<const float*>(Y), (int)J, L, K, dprec, p, part.as<double>(),
+                                  sq.as<double>(), S, norm2, s, after_main));
     return TUCKER_OK;
   }
   tk::GramPlan p = tk::plan_gram_mp((int)J, (uint64_t)K, (int)prec);
@@ -539,11 +545,17 @@ int64_t gram_scratch_doubles(const int64_t* dims, int N, int n, tucker_gram_prec
   else if (prec == TUCKER_GRAM_FP64 && J <= tk::kTriMaxJ) p = tk::plan_gram_f64((int)J, (uint64_t)L, (uint64_t)K);
   else p = tk::plan_gram_mp((int)J, (uint64_t)K, (int)prec);
   int64_t need = p.part_elems + p.sq_elems;
-  if (prec == TUCKER_GRAM_FP64 && J > tk::kTriMaxJ) {
-    // the tile-pair kernel with direct LDS loads, for either input type
-    for (int es : {4, 8})
-      if (tk::gram_dma_eligible((int)J, (uint64_t)L, es, nullptr))
-        need = std::max(need, tk::plan_gram_dma((int)J, (uint64_t)L, (uint64_t)K, es).part_elems);
+  if ((prec == TUCKER_GRAM_FP64 && J > tk::kTriMaxJ) || (prec == TUCKER_GRAM_FP32 && L == 1 && J > tk::kStreamMaxJ)) {
+    // the tile-pair kernel with direct LDS loads (FP64: either input type;
+    // FP32 products: float input)
+    const int dprec = (prec == TUCKER_GRAM_FP64) ? 0 : 1;
+    for (int es : {4, 8}) {
+      if (dprec == 1 && es == 8) continue;
+      if (tk::gram_dma_eligible((int)J, (uint64_t)L, es, nullptr)) {
+        const tk::GramPlan d = tk::plan_gram_dma((int)J, (uint64_t)L, (uint64_t)K, es, dprec);
+        need = std::max(need, d.part_elems + d.sq_elems);
+      }
+    }
   }
   return need;
 }

@@ -1,5 +1,7 @@
-// FP64 Gram matrix S = Y_(n) Y_(n)^T (Alg. 2; flop count Sec. 7) for mode
-// sizes above the whole-triangle kernel's range, with float or double input.
+// Gram matrix S = Y_(n) Y_(n)^T (Alg. 2; flop count Sec. 7) for mode sizes
+// above the whole-triangle kernel's range: FP64 products of float or double
+// input, or (the FP32 form) FP32 MFMA products of float input summed in FP32
+// over each 32-column chunk and in FP64 across chunks.
 //
 // Work items: a pair of 128-row tiles (ta <= tb) and a contiguous range of
 // column chunks.  Four waves per workgroup; each holds a 64 x 64 part of the
@@ -24,8 +26,9 @@
 //
 // Output: every item writes its FP64 partial blocks in the layout of the
 // tile-pair reduction (gram_mixed.hip), which sums the splits in a fixed
-// order.  ||Y||^2 is the trace of S: its diagonal entries are FP64 sums of
-// squares of the values as loaded.
+// order.  ||Y||^2 is the trace of S with FP64 products (its diagonal entries
+// are FP64 sums of squares of the values as loaded); with FP32 products the
+// diagonal items sum the squares of their tile's rows in FP64 from LDS.
 #include "common.hpp"
 #include "gram_dma.hpp"
 #include "kernels.hpp"
@@ -51,6 +54,7 @@ struct DmaParams {
   int64_t cps;     // chunks per split
   int ntiles, npairs;
   double* part;
+  double* sq;  // PREC 1: one sum of squares per item
 };
 
 __device__ __forceinline__ void decode_pair_dma(int p, int ntiles, int& ta, int& tb) {
@@ -177,8 +181,8 @@ struct Ops<T, 0> {
 #pragma unroll
     for (int t = 0; t < 4; ++t) b[t] = *reinterpret_cast<const T*>(buf + ob[t] + g * 4 * I::CB);
   }
-  __device__ __forceinline__ double A(int t, int) const { return (double)a[t]; }
-  __device__ __forceinline__ double B(int t, int) const { return (double)b[t]; }
+  __device__ __forceinline__ T A(int t, int) const { return a[t]; }
+  __device__ __forceinline__ T B(int t, int) const { return b[t]; }
 };
 
 // layout 1: one 16-byte unit per operand and group of E steps
@@ -197,20 +201,30 @@ struct Ops<T, 1> {
 #pragma unroll
     for (int t = 0; t < 4; ++t) b[t] = *reinterpret_cast<const V*>(buf + ob[t] + o);
   }
-  __device__ __forceinline__ double A(int t, int s) const { return (double)a[t][s]; }
-  __device__ __forceinline__ double B(int t, int s) const { return (double)b[t][s]; }
+  __device__ __forceinline__ T A(int t, int s) const { return a[t][s]; }
+  __device__ __forceinline__ T B(int t, int s) const { return b[t][s]; }
 };
 
 // MK: the compile-time block mask (gram_dma.hpp), or kGeneric for a mask
 // known only at run time (ragged last tiles), tested block by block.
 constexpr unsigned kGeneric = 0x10000u;
 
-template <unsigned MK, typename T, int LAY>
+// PREC 0: FP64 products and accumulation.  PREC 1 (float input): FP32 MFMA
+// products accumulated in FP32 over the chunk's 32 columns, then added to
+// the FP64 accumulators.
+template <unsigned MK, typename T, int LAY, int PREC>
 __device__ __forceinline__ void compute_chunk(const char* buf, const int (&oa)[4], const int (&ob)[4], int d,
                                               d4 (&acc)[4][4], unsigned mask) {
   using O = Ops<T, LAY>;
   O cur, nxt;
   cur.d = nxt.d = d;
+  f4 acc32[4][4];
+  if constexpr (PREC == 1) {
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+      for (int y = 0; y < 4; ++y) acc32[x][y] = f4{0.f, 0.f, 0.f, 0.f};
+  }
   cur.read(buf, oa, ob, 0);
 #pragma unroll
   for (int g = 0; g < O::NG; ++g) {
@@ -222,12 +236,52 @@ __device__ __forceinline__ void compute_chunk(const char* buf, const int (&oa)[4
 #pragma unroll
         for (int y = 0; y < 4; ++y) {
           const bool on = (MK == kGeneric) ? ((mask >> (4 * x + y)) & 1u) : ((MK >> (4 * x + y)) & 1u);
-          if (on) acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(cur.A(x, s), cur.B(y, s), acc[x][y], 0, 0, 0);
+          if (on) {
+            if constexpr (PREC == 0)
+              acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)cur.A(x, s), (double)cur.B(y, s), acc[x][y],
+                                                               0, 0, 0);
+            else
+              acc32[x][y] = __builtin_amdgcn_mfma_f32_16x16x4f32(cur.A(x, s), cur.B(y, s), acc32[x][y], 0, 0, 0);
+          }
         }
       }
     }
     if (g + 1 < O::NG) cur = nxt;
   }
+  if constexpr (PREC == 1) {
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+      for (int y = 0; y < 4; ++y) {
+        const bool on = (MK == kGeneric) ? ((mask >> (4 * x + y)) & 1u) : ((MK >> (4 * x + y)) & 1u);
+        if (on) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) acc[x][y][v] += (double)acc32[x][y][v];
+        }
+      }
+  }
+}
+
+// FP64 sum of squares of the rows of a diagonal item's tile image (float
+// input, PREC 1): rows >= J hold stale data and are skipped, columns past the
+// chunk's end were zeroed.
+template <int LAY>
+__device__ __forceinline__ double chunk_sq(const char* buf, int r0, int J, int tid) {
+  using I = Img<4, LAY>;
+  double s = 0.0;
+  for (int u = tid; u < I::TB / 16; u += kDNT) {
+    int r, c, b;
+    I::inv(16 * u, r, c, b);
+    const float4 v = *reinterpret_cast<const float4*>(buf + 16 * u);
+    const float e[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      // layout 1: the unit's elements share row r; layout 0: rows r .. r + 3
+      const int row = r0 + r + (LAY == 0 ? h : 0);
+      if (row < J) s += (double)e[h] * (double)e[h];
+    }
+  }
+  return s;
 }
 
 // The chunks of one item: chunk t sits in buffer t & 1.  The loads of chunk
@@ -235,10 +289,13 @@ __device__ __forceinline__ void compute_chunk(const char* buf, const int (&oa)[4
 // they run during chunk t's MFMAs; then the wave waits for them, zeros any
 // columns past the chunk's end and meets the others at the next barrier,
 // after which the buffer of chunk t is free for chunk t + 2.
-template <unsigned MK, typename T, int LAY>
+template <unsigned MK, typename T, int LAY, int PREC>
 __device__ __forceinline__ void chunk_loop(const DmaParams& g, int64_t split, int64_t ns, int64_t niter, char* buf0, char* buf1,
                                            int nslots, int r0a, int r0b, int wave, int lane, const int (&oa)[4],
-                                           const int (&ob)[4], int d, d4 (&acc)[4][4], unsigned mask) {
+                                           const int (&ob)[4], int d, d4 (&acc)[4][4], unsigned mask, double& sq) {
+  // PREC 1: diagonal items also sum the squares of their tile's rows
+  const bool dsq = (PREC == 1) && nslots == 1;
+  const int tid = 64 * wave + lane;
   if (niter <= 0) return;
   issue_chunk<T, LAY>(g, split, buf0, nslots, r0a, r0b, wave, lane);
   __builtin_amdgcn_s_waitcnt(0);
@@ -246,13 +303,17 @@ __device__ __forceinline__ void chunk_loop(const DmaParams& g, int64_t split, in
   __syncthreads();
   for (int64_t t = 0;; t += 2) {
     if (t + 1 < niter) issue_chunk<T, LAY>(g, split + (t + 1) * ns, buf1, nslots, r0a, r0b, wave, lane);
-    compute_chunk<MK, T, LAY>(buf0, oa, ob, d, acc, mask);
+    if constexpr (PREC == 1)
+      if (dsq) sq += chunk_sq<LAY>(buf0, r0a, g.J, tid);
+    compute_chunk<MK, T, LAY, PREC>(buf0, oa, ob, d, acc, mask);
     if (t + 1 >= niter) break;
     __builtin_amdgcn_s_waitcnt(0);
     fill_chunk<T, LAY>(g, split + (t + 1) * ns, buf1, nslots, wave, lane);
     __syncthreads();
     if (t + 2 < niter) issue_chunk<T, LAY>(g, split + (t + 2) * ns, buf0, nslots, r0a, r0b, wave, lane);
-    compute_chunk<MK, T, LAY>(buf1, oa, ob, d, acc, mask);
+    if constexpr (PREC == 1)
+      if (dsq) sq += chunk_sq<LAY>(buf1, r0a, g.J, tid);
+    compute_chunk<MK, T, LAY, PREC>(buf1, oa, ob, d, acc, mask);
     if (t + 2 >= niter) break;
     __builtin_amdgcn_s_waitcnt(0);
     fill_chunk<T, LAY>(g, split + (t + 2) * ns, buf0, nslots, wave, lane);
@@ -260,8 +321,12 @@ __device__ __forceinline__ void chunk_loop(const DmaParams& g, int64_t split, in
   }
 }
 
-template <typename T, int LAY>
-__global__ __launch_bounds__(kDNT, 2) void gram_dma_kernel(DmaParams g) {
+// FP64 products: two workgroups per CU (at most 256 registers per lane).
+// FP32 products keep FP32 chunk sums beside the FP64 accumulators, which does
+// not fit 256 registers: one workgroup (one wave per SIMD) per CU.
+template <typename T, int LAY, int PREC>
+__global__ __launch_bounds__(kDNT, PREC == 0 ? 2 : 1) void gram_dma_kernel(DmaParams g) {
+  static_assert(PREC == 0 || sizeof(T) == 4, "FP32 products read float input");
   using I = Img<sizeof(T), LAY>;
   __shared__ __attribute__((aligned(16))) char buf0[2 * I::TB];
   __shared__ __attribute__((aligned(16))) char buf1[2 * I::TB];
@@ -306,8 +371,9 @@ __global__ __launch_bounds__(kDNT, 2) void gram_dma_kernel(DmaParams g) {
   // one copy of the loop per mask class, so that the accumulators flow
   // through a single chain of MFMAs; waves without blocks still load and
   // meet the barriers
+  double sq = 0.0;
 #define DMA_LOOP(MK) \
-  chunk_loop<MK, T, LAY>(g, c0, cstep, niter, buf0, buf1, nslots, r0a, r0b, wave, lane, oa, ob, d, acc, mask)
+  chunk_loop<MK, T, LAY, PREC>(g, c0, cstep, niter, buf0, buf1, nslots, r0a, r0b, wave, lane, oa, ob, d, acc, mask, sq)
   if (mask == dma::kMaskFull) DMA_LOOP(dma::kMaskFull);
   else if (mask == dma::kMaskUpper) DMA_LOOP(dma::kMaskUpper);
   else if (mask == dma::kMaskHalf) DMA_LOOP(dma::kMaskHalf);
@@ -315,7 +381,17 @@ __global__ __launch_bounds__(kDNT, 2) void gram_dma_kernel(DmaParams g) {
   else DMA_LOOP(kGeneric);
 #undef DMA_LOOP
 
-  // partial blocks.  MFMA result: lane l, register v -> D[(l >> 4) + 4 v][l & 15]
+  if constexpr (PREC == 1) {
+    // the item's sum of squares (zero unless diagonal), in wave order
+    __shared__ double sred[kDW];
+    const double sw = wave_sum(sq);
+    if (lane == 0) sred[wave] = sw;
+    __syncthreads();
+    if (tid == 0) g.sq[item] = (sred[0] + sred[1]) + (sred[2] + sred[3]);
+  }
+
+  // partial blocks.  MFMA result, lane l, register v: FP64 D[(l >> 4) + 4 v][l & 15],
+  // FP32 D[4 (l >> 4) + v][l & 15]
   double* __restrict__ P = g.part + item * (int64_t)64 * 256;
 #pragma unroll
   for (int x = 0; x < 4; ++x) {
@@ -325,7 +401,7 @@ __global__ __launch_bounds__(kDNT, 2) void gram_dma_kernel(DmaParams g) {
         const int bi = a0 + x, bj = b0 + y;
         const int qb = diag ? dma::tri_index(bi, bj) : bi * 8 + bj;
 #pragma unroll
-        for (int v = 0; v < 4; ++v) P[(int64_t)qb * 256 + (q + 4 * v) * 16 + i] = acc[x][y][v];
+        for (int v = 0; v < 4; ++v) P[(int64_t)qb * 256 + (PREC == 0 ? q + 4 * v : 4 * q + v) * 16 + i] = acc[x][y][v];
       }
     }
   }
@@ -358,7 +434,7 @@ bool gram_dma_eligible(int J, uint64_t L, int elem_size, const void* Y) {
          reinterpret_cast<uintptr_t>(Y) % 16 == 0;
 }
 
-GramPlan plan_gram_dma(int J, uint64_t L, uint64_t K, int elem_size) {
+GramPlan plan_gram_dma(int J, uint64_t L, uint64_t K, int elem_size, int prec) {
   GramPlan p{};
   const int64_t KC = (L == 1 && elem_size == 8) ? Img<8, 0>::KC : 128 / elem_size;
   p.tile = 128;
@@ -373,14 +449,15 @@ GramPlan plan_gram_dma(int J, uint64_t L, uint64_t K, int elem_size) {
   p.cps = ceil_div(p.nchunks, nsplit);
   p.nsplit = ceil_div(p.nchunks, p.cps);
   p.part_elems = p.nsplit * p.npairs * 64 * 256;
-  p.sq_elems = 0;
+  p.sq_elems = (prec == 1) ? p.nsplit * p.npairs : 0;
   return p;
 }
 
 template <typename T>
-hipError_t launch_gram_dma(const T* Y, int J, uint64_t L, uint64_t K, const GramPlan& p, double* part, double* S,
-                           double* norm2, hipStream_t stream, hipEvent_t after_main) {
+hipError_t launch_gram_dma(const T* Y, int J, uint64_t L, uint64_t K, int prec, const GramPlan& p, double* part,
+                           double* sq, double* S, double* norm2, hipStream_t stream, hipEvent_t after_main) {
   if (!gram_dma_eligible(J, L, (int)sizeof(T), Y)) return hipErrorInvalidValue;
+  if (prec != 0 && (prec != 1 || sizeof(T) != 4 || sq == nullptr)) return hipErrorInvalidValue;
   DmaParams g{};
   g.Y = reinterpret_cast<const char*>(Y);
   g.J = J;
@@ -395,18 +472,32 @@ hipError_t launch_gram_dma(const T* Y, int J, uint64_t L, uint64_t K, const Gram
   g.npairs = p.npairs;
   g.total = p.nsplit * p.npairs;
   g.part = part;
+  g.sq = sq;
   const int64_t grid = ceil_div(g.total, kXcds) * kXcds;
-  if (L == 1) hipLaunchKernelGGL((gram_dma_kernel<T, 0>), dim3(grid), dim3(kDNT), 0, stream, g);
-  else hipLaunchKernelGGL((gram_dma_kernel<T, 1>), dim3(grid), dim3(kDNT), 0, stream, g);
+  if constexpr (sizeof(T) == 4) {
+    if (prec == 1) {
+      if (L == 1) hipLaunchKernelGGL((gram_dma_kernel<T, 0, 1>), dim3(grid), dim3(kDNT), 0, stream, g);
+      else hipLaunchKernelGGL((gram_dma_kernel<T, 1, 1>), dim3(grid), dim3(kDNT), 0, stream, g);
+    }
+  }
+  if (prec == 0) {
+    if (L == 1) hipLaunchKernelGGL((gram_dma_kernel<T, 0, 0>), dim3(grid), dim3(kDNT), 0, stream, g);
+    else hipLaunchKernelGGL((gram_dma_kernel<T, 1, 0>), dim3(grid), dim3(kDNT), 0, stream, g);
+  }
   if (after_main) (void)hipEventRecord(after_main, stream);
   launch_gram_pair_reduce(part, p.ntiles, p.npairs, p.nsplit, J, S, stream);
-  if (norm2) hipLaunchKernelGGL(gram_trace_kernel, dim3(1), dim3(256), 0, stream, S, J, norm2);
+  if (norm2) {
+    // FP64: the trace of S is the FP64 sum of squares; FP32 products: the
+    // diagonal items' FP64 sums of squares, in item order
+    if (prec == 0) hipLaunchKernelGGL(gram_trace_kernel, dim3(1), dim3(256), 0, stream, S, J, norm2);
+    else hipLaunchKernelGGL(sum_fixed_kernel, dim3(1), dim3(256), 0, stream, sq, g.total, norm2);
+  }
   return hipGetLastError();
 }
 
-template hipError_t launch_gram_dma<float>(const float*, int, uint64_t, uint64_t, const GramPlan&, double*, double*,
-                                           double*, hipStream_t, hipEvent_t);
-template hipError_t launch_gram_dma<double>(const double*, int, uint64_t, uint64_t, const GramPlan&, double*,
-                                            double*, double*, hipStream_t, hipEvent_t);
+template hipError_t launch_gram_dma<float>(const float*, int, uint64_t, uint64_t, int, const GramPlan&, double*,
+                                           double*, double*, double*, hipStream_t, hipEvent_t);
+template hipError_t launch_gram_dma<double>(const double*, int, uint64_t, uint64_t, int, const GramPlan&, double*,
+                                            double*, double*, double*, hipStream_t, hipEvent_t);
 
 }  // namespace tk

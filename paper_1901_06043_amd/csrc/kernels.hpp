@@ -41,10 +41,12 @@ struct GramPlan {
 // column (L = 1) or row stride.  Partial blocks in the tile-pair layout of
 // launch_gram_pair_reduce; norm2 (may be null) receives trace(S).
 bool gram_dma_eligible(int J, uint64_t L, int elem_size, const void* Y);
-GramPlan plan_gram_dma(int J, uint64_t L, uint64_t K, int elem_size);
+// prec 0: FP64 products; prec 1: FP32 products of float input (sq: one
+// double per item, p.sq_elems).
+GramPlan plan_gram_dma(int J, uint64_t L, uint64_t K, int elem_size, int prec);
 template <typename T>
-hipError_t launch_gram_dma(const T* Y, int J, uint64_t L, uint64_t K, const GramPlan& p, double* part, double* S,
-                           double* norm2, hipStream_t stream, hipEvent_t after_main);
+hipError_t launch_gram_dma(const T* Y, int J, uint64_t L, uint64_t K, int prec, const GramPlan& p, double* part,
+                           double* sq, double* S, double* norm2, hipStream_t stream, hipEvent_t after_main);
 // Sums the partial 128 x 128 tile-pair blocks of nsplit splits into S (both
 // triangles), in a fixed order.
 void launch_gram_pair_reduce(const double* part, int ntiles, int npairs, int64_t nsplit, int J, double* S,
