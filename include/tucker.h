@@ -135,7 +135,8 @@ typedef struct tucker_t tucker_t; /* opaque result handle */
  * Errors: EINVAL for bad arguments or non-finite ||X||^2; ENOMEM (predicted
  *         before the launches, see tucker_sthosvd_memory, or from a failed
  *         allocation); EHIP; ENOCONV if the eigensolver exceeded its
- *         iteration cap; EUNSUPPORTED for a mode above 1024.
+ *         iteration cap; EUNSUPPORTED for a mode above 2304 (the largest
+ *         matrix of the eigensolver).
  * Waits once per mode for the rank R_n, which is read back while that mode's
  * eigenvectors are being formed, and synchronises `stream` before returning. */
 tucker_status tucker_sthosvd(const void* data, tucker_dtype dtype, const int64_t* dims, int N,
@@ -445,6 +446,8 @@ tucker_status tucker_gram(const void* Y, tucker_dtype dtype, const int64_t* dims
  *        eigenvectors (sign convention as for tucker_factor); the rest is scratch;
  *   R    device, one int64: the chosen rank (1 <= R <= J);
  *   disc device, one double: sum of the discarded (clamped) eigenvalues.
+ * Errors: EINVAL for J outside 1..2304 (the largest matrix of the
+ * eigensolver), a NULL pointer or a negative or non-finite thr.
  * Does not synchronise. */
 tucker_status tucker_eig_truncate(const double* S, int64_t J, double thr, double* lam, double* U,
                                   int64_t* R, double* disc, hipStream_t stream);

@@ -308,7 +308,7 @@ void left_right(const int64_t* dims, int N, int n, int64_t& L, int64_t& Rt) {
   for (int k = n + 1; k < N; ++k) Rt *= dims[k];
 }
 
-constexpr int64_t kMaxEigJ = 1024;
+constexpr int64_t kMaxEigJ = tk::kEigMaxJ;
 
 // Gram of mode n of a tensor in (ptr, dtype) -> S (J x J FP64), optional norm.
 tucker_status run_gram(const void* Y, tucker_dtype dt, const int64_t* dims, int N, int n, tucker_gram_prec prec,
@@ -1417,11 +1417,11 @@ tucker_status tucker_gram(const void* Y, tucker_dtype dtype, const int64_t* dims
 namespace {
 
 // Workspace of tucker_eig_truncate_noalloc: the eigensolver's workspace for
-// the largest supported J (2 J^2 + 3 J + 8 doubles at J = 1024, 16.8 MB),
-// one copy per device for the life of the process.  Host code never uses the
-// array's name as an address: the device address comes from
+// J up to 1024 (2 J^2 + 3 J + 8 doubles, 16.8 MB; the allocating entry point
+// goes further), one copy per device for the life of the process.  Host code
+// never uses the array's name as an address: the device address comes from
 // hipGetSymbolAddress, once per device, with that device current.
-constexpr int64_t kNoAllocMaxJ = kMaxEigJ;
+constexpr int64_t kNoAllocMaxJ = 1024;
 constexpr int64_t kNoAllocDoubles = 2 * kNoAllocMaxJ * kNoAllocMaxJ + 3 * kNoAllocMaxJ + 8;
 static __device__ __align__(256) double scratch[kNoAllocDoubles];
 

@@ -863,37 +863,40 @@ __device__ __forceinline__ void orth_loop(double* __restrict__ Z, int J, int R, 
 
 // Blocked form, for R * J beyond the LDS copy: blocks of kOB consecutive
 // vectors.  A block is first projected, twice, against the preceding (final)
-// vectors of its window, kOC of them at a time, with FP64 MFMA products: the
+// vectors of its window, kOB of them at a time, with FP64 MFMA products: the
 // chunk's coefficients C = Z_chunk Z_blk^T (masked to each vector's window),
 // then Z_blk -= C^T Z_chunk.  Then each vector of the block is orthogonalised
 // (classical Gram-Schmidt, twice) against the block's earlier vectors of its
-// window and normalised.  The block lives in LDS; the chunks are read from
-// global memory.  In exact arithmetic this is the same projection as the
-// vector-by-vector loop.
+// window and normalised.  In exact arithmetic this is the same projection as
+// the vector-by-vector loop.  The chunks are read from global memory; the
+// block lives in LDS (zero-padded rows of Jp) while kOB rows of J fit
+// (J <= 1024), otherwise (GLB) it is updated in place in global memory, with
+// the entries past the block's R - i0 vectors or past J masked to zero.
 constexpr int kOB = 16;  // vectors per block
 constexpr int kOC = 64;  // preceding vectors per chunk
 __host__ __device__ constexpr int orth_ksplit(int J) { return J <= 960 ? 4 : 2; }
-// LDS of the blocked form (doubles); it runs while this stays within the
-// 160 KB a gfx950 workgroup may use (every J up to 1024), otherwise the
-// global-memory loop does.
+// LDS of the blocked forms (doubles); the LDS block runs while this stays
+// within the 160 KB a gfx950 workgroup may use (every J up to 1024).
 constexpr int kEigLdsMax = 160 * 1024 / 8;
-__host__ __device__ constexpr int64_t orth_blocked_doubles(int64_t J) {
-  return J + 32 + (int64_t)kOB * ((J + 15) & ~int64_t(15)) + (int64_t)orth_ksplit((int)J) * kOC * kOB;
+__host__ __device__ constexpr int64_t orth_blocked_doubles(int64_t J, bool glb = false) {
+  return J + 32 + (glb ? 0 : (int64_t)kOB * ((J + 15) & ~int64_t(15))) + (int64_t)orth_ksplit((int)J) * kOC * kOB;
 }
 
+template <bool GLB>
 __device__ __forceinline__ void orth_blocked(double* __restrict__ Z, int J, int R, int first,
                                              const double* __restrict__ lam, double otol, double* sh) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int il = lane & 15, q = lane >> 4;
   const int Jp = (J + 15) & ~15;
   const int KS = orth_ksplit(J);
+  const int ZS = GLB ? J : Jp;                        // row stride of the block
   double* hs = sh;                                    // kOB (in-block coefficients)
   double* sred = sh + J;                              // 16
   int* sjlo = reinterpret_cast<int*>(sh + J + 16);    // kOB window starts
-  double* Zb = sh + J + 32;                           // [kOB][Jp], zero-padded
-  double* sC = Zb + kOB * Jp;                         // [KS][kOC][kOB] partial coefficients
+  double* sC = sh + J + 32 + (GLB ? 0 : kOB * Jp);    // [KS][kOC][kOB] partial coefficients
   for (int i0 = first; i0 < R; i0 += kOB) {
     const int nb = min(kOB, R - i0);
+    double* Zb = GLB ? Z + (int64_t)i0 * J : sh + J + 32;  // [kOB][ZS]
     if (tid < kOB) {
       // window start: smallest j <= i with lam_j - lam_i < otol (lam descending)
       const int i = i0 + tid;
@@ -905,9 +908,11 @@ __device__ __forceinline__ void orth_blocked(double* __restrict__ Z, int J, int 
       }
       sjlo[tid] = lo;
     }
-    for (int x = tid; x < kOB * Jp; x += kEigThreads) {
-      const int t = x / Jp, r = x - t * Jp;
-      Zb[x] = (t < nb && r < J) ? Z[(int64_t)(i0 + t) * J + r] : 0.0;
+    if (!GLB) {
+      for (int x = tid; x < kOB * Jp; x += kEigThreads) {
+        const int t = x / Jp, r = x - t * Jp;
+        Zb[x] = (t < nb && r < J) ? Z[(int64_t)(i0 + t) * J + r] : 0.0;
+      }
     }
     __syncthreads();
     const int jw = sjlo[0];  // window starts grow with i
@@ -926,14 +931,18 @@ __device__ __forceinline__ void orth_blocked(double* __restrict__ Z, int J, int 
             // reduction steps in groups of 8 loads (in bounds, masked here); the
             // other waves of the SIMD cover a group's load latency
             for (int g0 = s0; g0 < s1; g0 += 8) {
-              double x[8];
+              double x[8], y[8];
 #pragma unroll
-              for (int u = 0; u < 8; ++u) x[u] = zr[min(4 * (g0 + u) + q, J - 1)];
+              for (int u = 0; u < 8; ++u) {
+                x[u] = zr[min(4 * (g0 + u) + q, J - 1)];
+                y[u] = GLB ? Zb[(int64_t)min(il, nb - 1) * J + min(4 * (g0 + u) + q, J - 1)] : 0.0;
+              }
 #pragma unroll
               for (int u = 0; u < 8; ++u) {
                 const int st = g0 + u, r = 4 * st + q;
                 const double av = (rowok && st < s1 && r < J) ? x[u] : 0.0;
-                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, Zb[il * Jp + min(r, Jp - 1)], acc, 0, 0, 0);
+                const double bv = GLB ? ((il < nb && r < J) ? y[u] : 0.0) : Zb[il * Jp + min(r, Jp - 1)];
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
               }
             }
             // D[(l >> 4) + 4v][l & 15]: chunk row 16 a + q + 4 v, block vector il
@@ -955,7 +964,15 @@ __device__ __forceinline__ void orth_blocked(double* __restrict__ Z, int J, int 
           const int r = 16 * b + il;
           d4 acc;
 #pragma unroll
-          for (int v = 0; v < 4; ++v) acc[v] = Zb[(q + 4 * v) * Jp + r];
+          for (int v = 0; v < 4; ++v) {
+            const int t = q + 4 * v;
+            if (GLB) {
+              const double zv = Zb[(int64_t)min(t, nb - 1) * J + min(r, J - 1)];  // in bounds; masked
+              acc[v] = (t < nb && r < J) ? zv : 0.0;
+            } else {
+              acc[v] = Zb[t * Jp + r];
+            }
+          }
 #pragma unroll
           for (int h = 0; h < 2; ++h) {  // two halves of 8 steps (bounds the loads in flight)
 #pragma unroll
@@ -968,7 +985,14 @@ __device__ __forceinline__ void orth_blocked(double* __restrict__ Z, int J, int 
             __builtin_amdgcn_sched_barrier(0);
           }
 #pragma unroll
-          for (int v = 0; v < 4; ++v) Zb[(q + 4 * v) * Jp + r] = acc[v];
+          for (int v = 0; v < 4; ++v) {
+            const int t = q + 4 * v;
+            if (GLB) {
+              if (t < nb && r < J) Zb[(int64_t)t * J + r] = acc[v];
+            } else {
+              Zb[t * Jp + r] = acc[v];
+            }
+          }
         }
         __syncthreads();
       }
@@ -977,19 +1001,19 @@ __device__ __forceinline__ void orth_blocked(double* __restrict__ Z, int J, int 
     for (int t = 0; t < nb; ++t) {
       const int i = i0 + t;
       if (sjlo[t] >= i) continue;  // uniform: no neighbour within otol
-      double* zt = Zb + t * Jp;
+      double* zt = Zb + (int64_t)t * ZS;
       const int u0 = max(sjlo[t], i0) - i0;
       for (int pass = 0; pass < 2 && u0 < t; ++pass) {
         for (int u = u0 + wave; u < t; u += 16) {
           double h = 0.0;
-          for (int r = lane; r < J; r += 64) h += Zb[u * Jp + r] * zt[r];
+          for (int r = lane; r < J; r += 64) h += Zb[(int64_t)u * ZS + r] * zt[r];
           h = wave_sum_fast(h);
           if (lane == 0) hs[u] = h;
         }
         __syncthreads();
         for (int r = tid; r < J; r += kEigThreads) {
           double v = zt[r];
-          for (int u = u0; u < t; ++u) v -= hs[u] * Zb[u * Jp + r];
+          for (int u = u0; u < t; ++u) v -= hs[u] * Zb[(int64_t)u * ZS + r];
           zt[r] = v;
         }
         __syncthreads();
@@ -1001,9 +1025,11 @@ __device__ __forceinline__ void orth_blocked(double* __restrict__ Z, int J, int 
       for (int r = tid; r < J; r += kEigThreads) zt[r] *= rn;
       __syncthreads();
     }
-    for (int x = tid; x < nb * Jp; x += kEigThreads) {
-      const int t = x / Jp, r = x - t * Jp;
-      if (r < J) Z[(int64_t)(i0 + t) * J + r] = Zb[x];
+    if (!GLB) {
+      for (int x = tid; x < nb * Jp; x += kEigThreads) {
+        const int t = x / Jp, r = x - t * Jp;
+        if (r < J) Z[(int64_t)(i0 + t) * J + r] = Zb[x];
+      }
     }
     __syncthreads();
   }
@@ -1016,20 +1042,22 @@ __host__ __device__ inline int orth_cap_batched(int64_t Jmax) {
   return (int)(Jmax * Jmax < kOrthCapBatched ? Jmax * Jmax : kOrthCapBatched);
 }
 inline bool orth_blocked_fits(int64_t J) { return orth_blocked_doubles(J) <= kEigLdsMax; }
+// the blocked form of a single matrix: 1 with the block in LDS, 2 in place
+inline int orth_blocked_mode(int64_t J) { return orth_blocked_fits(J) ? 1 : 2; }
 inline size_t orth_lds_bytes(int64_t J) {
   const int64_t copy = J + 16 + std::min<int64_t>(J * J, kOrthCap);
-  return sizeof(double) * (size_t)std::max<int64_t>(copy, orth_blocked_fits(J) ? orth_blocked_doubles(J) : 0);
+  return sizeof(double) * (size_t)std::max<int64_t>(copy, orth_blocked_doubles(J, orth_blocked_mode(J) == 2));
 }
 
 // The vectors are copied to LDS when R * J fits in `cap` doubles (the rounds
 // then cost LDS latency instead of global-memory round trips), and only the
 // vectors from the first one that changes onward are written back; otherwise
-// the blocked form runs (`blocked`, which needs orth_lds_bytes of LDS) or the
-// vector-by-vector loop on global memory (the batched form, whose workgroups
-// keep their LDS small).
+// the blocked form runs (`blocked` 1 or 2, which needs orth_lds_bytes of LDS)
+// or the vector-by-vector loop on global memory (the batched form, whose
+// workgroups keep their LDS small).
 __device__ __forceinline__ void orth_body(double* __restrict__ Zt, int J, const double* __restrict__ lam,
                                           const int64_t* __restrict__ Rp, const double* __restrict__ scal,
-                                          double* sh, int cap, bool blocked) {
+                                          double* sh, int cap, int blocked) {
   double* hs = sh;        // J
   double* sred = sh + J;  // 16
   const int R = (int)*Rp;
@@ -1038,7 +1066,8 @@ __device__ __forceinline__ void orth_body(double* __restrict__ Zt, int J, const 
   while (first < R && lam[first - 1] - lam[first] >= otol) ++first;
   if (first >= R) return;  // uniform: nothing to do
   if ((int64_t)R * J > cap) {
-    if (blocked) orth_blocked(Zt, J, R, first, lam, otol, sh);
+    if (blocked == 1) orth_blocked<false>(Zt, J, R, first, lam, otol, sh);
+    else if (blocked == 2) orth_blocked<true>(Zt, J, R, first, lam, otol, sh);
     else orth_loop(Zt, J, R, lam, otol, hs, sred);
     return;
   }
@@ -1054,7 +1083,7 @@ __global__ __launch_bounds__(kEigThreads) void eig_orth_kernel(double* __restric
                                                                const int64_t* __restrict__ Rp,
                                                                const double* __restrict__ scal, int blocked) {
   extern __shared__ double sh[];
-  orth_body(Zt, J, lam, Rp, scal, sh, (int)std::min<int64_t>((int64_t)J * J, kOrthCap), blocked != 0);
+  orth_body(Zt, J, lam, Rp, scal, sh, (int)std::min<int64_t>((int64_t)J * J, kOrthCap), blocked);
 }
 
 // ---------------------------------------------------------------- 6. back-transformation + signs
@@ -1444,7 +1473,19 @@ __global__ __launch_bounds__(kEigThreads) void eig_orth_batched(EigBatch b) {
   int m, J;
   if (!batch_matrix(b, m, J)) return;
   const int64_t o2 = (int64_t)m * b.Jmax * b.Jmax, o1 = (int64_t)m * b.Jmax;
-  orth_body(b.Zt + o2, J, b.lam + o1, b.R + m, b.scal + 8 * (int64_t)m, sh, orth_cap_batched(b.Jmax), false);
+  orth_body(b.Zt + o2, J, b.lam + o1, b.R + m, b.scal + 8 * (int64_t)m, sh, orth_cap_batched(b.Jmax), 0);
+}
+
+// Single matrices above 1024 rows: the register-staged LDS chunks of
+// eig_back_kernel no longer fit beside a vector of Q > 16 values per lane, so
+// the reflectors are read straight from global memory as in the batched form
+// (each row k of H is read by all R vectors, from L2).
+template <int Q>
+__global__ __launch_bounds__(256) void eig_back_direct_kernel(const double* __restrict__ H,
+                                                              const double* __restrict__ tau, int J,
+                                                              const double* __restrict__ Zt,
+                                                              const int64_t* __restrict__ Rp, double* __restrict__ U) {
+  back_body_direct<Q>(H, tau, J, Zt, Rp, U, blockIdx.x);
 }
 
 template <int Q>
@@ -1531,7 +1572,7 @@ hipError_t launch_eig_vectors(int J, const EigWork& w, const double* lam, const 
     LAUNCH_OK();
   }
   hipLaunchKernelGGL(eig_orth_kernel, dim3(1), dim3(kEigThreads), orth_lds_bytes(J), stream, w.Zt, J, lam, R,
-                     w.scal, orth_blocked_fits(J) ? 1 : 0);
+                     w.scal, orth_blocked_mode(J));
   LAUNCH_OK();
   const int q = (int)ceil_div(J, 64);
   if (q <= 1) launch_back<1>(w, J, R, U, stream);
@@ -1539,7 +1580,14 @@ hipError_t launch_eig_vectors(int J, const EigWork& w, const double* lam, const 
   else if (q <= 4) launch_back<4>(w, J, R, U, stream);
   else if (q <= 8) launch_back<8>(w, J, R, U, stream);
   else if (q <= 11) launch_back<11>(w, J, R, U, stream);
-  else launch_back<16>(w, J, R, U, stream);
+  else if (q <= 16) launch_back<16>(w, J, R, U, stream);
+  else if (q <= 24)
+    hipLaunchKernelGGL((eig_back_direct_kernel<24>), dim3(ceil_div(J, 4)), dim3(256), 0, stream, w.A, w.tau, J,
+                       w.Zt, R, U);
+  else if (q <= kEigMaxJ / 64)
+    hipLaunchKernelGGL((eig_back_direct_kernel<kEigMaxJ / 64>), dim3(ceil_div(J, 4)), dim3(256), 0, stream, w.A,
+                       w.tau, J, w.Zt, R, U);
+  else return hipErrorInvalidValue;
   return hipGetLastError();
 }
 

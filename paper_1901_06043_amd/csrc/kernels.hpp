@@ -105,6 +105,11 @@ hipError_t launch_ttm(const TI* Y, int J, uint64_t L, uint64_t cols, const doubl
                       int K, TO* Z, bool fp32_products, hipStream_t stream);
 
 // ---------------------------------------------------------------- eigensolver
+// Largest matrix of the single-matrix eigensolver: the back-transformation
+// holds a vector as J / 64 doubles per lane next to two reflectors (3 x 36
+// doubles at 2304), and inverse iteration keeps seven arrays of J doubles of
+// one vector in the 160 KB of LDS of a workgroup.
+constexpr int kEigMaxJ = 2304;
 struct EigWork {
   double* A;      // J*J   (copy of S, then Householder vectors in its rows)
   double* d;      // J
