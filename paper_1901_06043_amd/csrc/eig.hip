@@ -403,15 +403,14 @@ __global__ __launch_bounds__(1024) void eig_tridiag_tail_kernel(const double* S,
 
 // ---------------------------------------------------------------- 1b. tridiagonalisation steps, J > 208
 // While the trailing matrix is larger than the register-resident form holds,
-// each Householder step is two launches over blocks of kBigRows matrix rows
-// (A: J x J in global memory, global indices):
-//   eig_tri_big_p: every workgroup forms v_k from row k (the same fixed-order
-//     sums in each, hence the same v) and computes p_i = tau (A v)_i for its
-//     rows; workgroup 0 also saves v and the scalars;
-//   eig_tri_big_update: every workgroup forms w = p - (tau/2)(p.v) v (fixed
-//     order, the same in each) and applies A <- A - v w^T - w v^T to its rows;
-//     workgroup 0 writes d_k, e_k, tau_k and stores v_k in row k (the form the
-//     back-transformation reads).
+// each Householder step is a launch over blocks of kBigRows matrix rows
+// (A: J x J in global memory, global indices).  A step needs two passes that
+// depend on every row: p = tau A v (which needs v from the updated row k) and
+// the rank-2 update A <- A - v w^T - w v^T with w = p - (tau/2)(p.v) v (which
+// needs all of p).  eig_tri_big_step runs the update of step k - 1 and the
+// product of step k in one pass; eig_tri_big_update applies the last step's
+// update (every workgroup forms w in the same fixed order) and stores v_k in
+// row k, the form the back-transformation reads.
 constexpr int kBigRows = 16;
 constexpr int kBigThreads = 256;
 
@@ -424,50 +423,6 @@ __device__ __forceinline__ double block_sum_256(double v, double* sred) {
   const double s = (sred[0] + sred[1]) + (sred[2] + sred[3]);
   __syncthreads();
   return s;
-}
-
-// V, P: J doubles each; sc: beta, tau of the step.
-__global__ __launch_bounds__(kBigThreads) void eig_tri_big_p(const double* __restrict__ A, int J, int k,
-                                                             double* __restrict__ V, double* __restrict__ P,
-                                                             double* __restrict__ sc) {
-  extern __shared__ double sv[];  // J
-  __shared__ double sred[4];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const double* rk = A + (int64_t)k * J;
-  double part = 0.0;
-  for (int j = k + 2 + tid; j < J; j += kBigThreads) part += rk[j] * rk[j];
-  double sigma = block_sum_256(part, sred);
-  double alpha = rk[k + 1];
-  const bool tiny = row_is_tiny(alpha, sigma);  // uniform
-  if (tiny) {
-    part = 0.0;
-    for (int j = k + 2 + tid; j < J; j += kBigThreads) {
-      const double y = rk[j] * kRowScale;
-      part += y * y;
-    }
-    sigma = block_sum_256(part, sred);
-    alpha *= kRowScale;
-  }
-  double beta, tk, scale;
-  reflector(alpha, sigma, tiny, beta, tk, scale);
-  for (int j = k + 1 + tid; j < J; j += kBigThreads) {
-    const double v = (j == k + 1) ? 1.0 : rk[j] * scale;
-    sv[j] = v;
-    if (blockIdx.x == 0) V[j] = v;
-  }
-  if (blockIdx.x == 0 && tid == 0) {
-    sc[0] = beta;
-    sc[1] = tk;
-  }
-  __syncthreads();
-  const int r0 = k + 1 + (int)blockIdx.x * kBigRows, r1 = min(r0 + kBigRows, J);
-  for (int i = r0 + wave; i < r1; i += kBigThreads / 64) {  // one wave per row
-    const double* row = A + (int64_t)i * J;
-    double t = 0.0;
-    for (int j = k + 1 + lane; j < J; j += 64) t += row[j] * sv[j];
-    t = wave_sum_fast(t);
-    if (lane == 0) P[i] = tk * t;
-  }
 }
 
 __global__ __launch_bounds__(kBigThreads) void eig_tri_big_update(double* __restrict__ A, int J, int k,
@@ -499,12 +454,137 @@ __global__ __launch_bounds__(kBigThreads) void eig_tri_big_update(double* __rest
     for (int j = k + 1 + lane; j < J; j += 64) row[j] -= vi * sw[j] + wi * sv[j];
   }
   if (blockIdx.x == 0) {
-    if (tid == 0) {
+    if (tid == 0 && d != nullptr) {  // null after eig_tri_big_step, which wrote them
       d[k] = A[(int64_t)k * J + k];
       e[k] = sc[0];
       tau[k] = tk;
     }
     for (int j = k + 2 + tid; j < J; j += kBigThreads) A[(int64_t)k * J + j] = sv[j];
+  }
+}
+
+// The same steps with one launch each: launch k first applies the rank-2
+// update of step k - 1 (v, p and tau of that step, from the previous launch)
+// to the rows it owns, and forms row k as updated by every workgroup for
+// itself (a fixed-order computation, the same in each), so that the update
+// and the next reflector's matrix-vector product share one pass over the
+// rows.  Row k is read in launch k and written by no one then; workgroup 0
+// stores v_{k-1} into row k - 1 (which no launch reads again) and writes
+// d_k, e_k and tau_k.  V, P and the scalars alternate between two buffers.
+// After the last step, eig_tri_big_update (without d) applies its update.
+// Fixed-order sum over a workgroup of NW waves; every thread gets it.
+template <int NW>
+__device__ __forceinline__ double block_sum_nw(double v, double* sred) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  v = wave_sum_fast(v);
+  if (lane == 0) sred[wave] = v;
+  __syncthreads();
+  double s = 0.0;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) s += sred[w];
+  __syncthreads();
+  return s;
+}
+
+// NW waves, one matrix row each; RR = row entries per lane (J <= 64 RR), all
+// loaded before the step's reductions so that their latency overlaps them.
+template <int RR, int NW>
+__global__ __launch_bounds__(64 * NW) void eig_tri_big_step(double* __restrict__ A, int J, int k,
+                                                            const double* __restrict__ Vp,
+                                                            const double* __restrict__ Pp,
+                                                            const double* __restrict__ scp,
+                                                            double* __restrict__ Vc, double* __restrict__ Pc,
+                                                            double* __restrict__ scc, double* __restrict__ d,
+                                                            double* __restrict__ e, double* __restrict__ tau) {
+  constexpr int kStepThreads = 64 * NW;
+  extern __shared__ double sh[];
+  double* sv = sh;          // v of step k - 1 (indices >= k)
+  double* sw = sh + J;      // w of step k - 1
+  double* su = sh + 2 * J;  // row k after that update, then v of step k (indices >= k + 1)
+  __shared__ double sred[NW];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const bool upd = k > 0;  // uniform
+  const double* rk = A + (int64_t)k * J;
+  // this wave's row, loaded first (in bounds; used only if i < J)
+  const int i = k + 1 + (int)blockIdx.x * NW + wave;
+  double* row = A + (int64_t)min(i, J - 1) * J;
+  constexpr int kRowRegs = RR;
+  double a[kRowRegs];
+#pragma unroll
+  for (int u = 0; u < kRowRegs; ++u) {
+    const int j = k + 1 + lane + 64 * u;
+    a[u] = (j < J) ? row[j] : 0.0;
+  }
+  if (upd) {
+    const double tp = scp[1];
+    double part = 0.0;
+    for (int j = k + tid; j < J; j += kStepThreads) {
+      const double v = Vp[j], pj = Pp[j];
+      sv[j] = v;
+      sw[j] = pj;
+      part += pj * v;
+    }
+    const double c2 = 0.5 * tp * block_sum_nw<NW>(part, sred);  // (the sum's barriers publish sv, sw)
+    for (int j = k + tid; j < J; j += kStepThreads) sw[j] -= c2 * sv[j];
+    __syncthreads();
+  }
+  const double vk = upd ? sv[k] : 0.0, wk = upd ? sw[k] : 0.0;
+  double part = 0.0;
+  for (int j = k + 1 + tid; j < J; j += kStepThreads) {
+    const double x = upd ? rk[j] - (vk * sw[j] + wk * sv[j]) : rk[j];
+    su[j] = x;
+    if (j >= k + 2) part += x * x;
+  }
+  double sigma = block_sum_nw<NW>(part, sred);
+  // alpha from the same expression as su[k + 1] (bit-identical), not from
+  // su, whose entry k + 1 its owner rewrites below
+  double alpha = upd ? rk[k + 1] - (vk * sw[k + 1] + wk * sv[k + 1]) : rk[k + 1];
+  const bool tiny = row_is_tiny(alpha, sigma);  // uniform
+  if (tiny) {
+    part = 0.0;
+    for (int j = k + 2 + tid; j < J; j += kStepThreads) {
+      const double y = su[j] * kRowScale;
+      part += y * y;
+    }
+    sigma = block_sum_nw<NW>(part, sred);
+    alpha *= kRowScale;
+  }
+  double beta, tk, scale;
+  reflector(alpha, sigma, tiny, beta, tk, scale);
+  for (int j = k + 1 + tid; j < J; j += kStepThreads) {
+    const double v = (j == k + 1) ? 1.0 : su[j] * scale;
+    su[j] = v;  // each thread rewrites only its own entries
+    if (blockIdx.x == 0) Vc[j] = v;
+  }
+  if (blockIdx.x == 0) {
+    if (tid == 0) {
+      scc[0] = beta;
+      scc[1] = tk;
+      d[k] = upd ? rk[k] - 2.0 * vk * wk : rk[k];
+      e[k] = beta;
+      tau[k] = tk;
+    }
+    if (upd)
+      for (int j = k + 1 + tid; j < J; j += kStepThreads) A[(int64_t)(k - 1) * J + j] = sv[j];
+  }
+  __syncthreads();
+  if (i < J) {  // uniform per wave
+    const double vi = upd ? sv[i] : 0.0, wi = upd ? sw[i] : 0.0;
+    double t = 0.0;
+#pragma unroll
+    for (int u = 0; u < kRowRegs; ++u) {
+      const int j = k + 1 + lane + 64 * u;
+      if (j < J) {
+        double x = a[u];
+        if (upd) {
+          x -= vi * sw[j] + wi * sv[j];
+          row[j] = x;
+        }
+        t += x * su[j];
+      }
+    }
+    t = wave_sum_fast(t);
+    if (lane == 0) Pc[i] = tk * t;
   }
 }
 
@@ -1044,17 +1124,21 @@ __host__ __device__ inline int orth_cap_batched(int64_t Jmax) {
 inline bool orth_blocked_fits(int64_t J) { return orth_blocked_doubles(J) <= kEigLdsMax; }
 // the blocked form of a single matrix: 1 with the block in LDS, 2 in place
 inline int orth_blocked_mode(int64_t J) { return orth_blocked_fits(J) ? 1 : 2; }
-inline size_t orth_lds_bytes(int64_t J) {
+// LDS of eig_orth_kernel: the copy form, and the blocked form unless the
+// right-looking launches (rl) take the matrices beyond the copy
+inline size_t orth_lds_bytes(int64_t J, bool rl = false) {
   const int64_t copy = J + 16 + std::min<int64_t>(J * J, kOrthCap);
-  return sizeof(double) * (size_t)std::max<int64_t>(copy, orth_blocked_doubles(J, orth_blocked_mode(J) == 2));
+  return sizeof(double) *
+         (size_t)std::max<int64_t>(copy, rl ? 0 : orth_blocked_doubles(J, orth_blocked_mode(J) == 2));
 }
 
 // The vectors are copied to LDS when R * J fits in `cap` doubles (the rounds
 // then cost LDS latency instead of global-memory round trips), and only the
 // vectors from the first one that changes onward are written back; otherwise
-// the blocked form runs (`blocked` 1 or 2, which needs orth_lds_bytes of LDS)
-// or the vector-by-vector loop on global memory (the batched form, whose
-// workgroups keep their LDS small).
+// the blocked form runs (`blocked` 1 or 2, which needs orth_lds_bytes of LDS),
+// the right-looking launches that follow do the work (`blocked` 3), or the
+// vector-by-vector loop on global memory (the batched form, whose workgroups
+// keep their LDS small).
 __device__ __forceinline__ void orth_body(double* __restrict__ Zt, int J, const double* __restrict__ lam,
                                           const int64_t* __restrict__ Rp, const double* __restrict__ scal,
                                           double* sh, int cap, int blocked) {
@@ -1068,6 +1152,7 @@ __device__ __forceinline__ void orth_body(double* __restrict__ Zt, int J, const 
   if ((int64_t)R * J > cap) {
     if (blocked == 1) orth_blocked<false>(Zt, J, R, first, lam, otol, sh);
     else if (blocked == 2) orth_blocked<true>(Zt, J, R, first, lam, otol, sh);
+    else if (blocked == 3) return;
     else orth_loop(Zt, J, R, lam, otol, hs, sred);
     return;
   }
@@ -1084,6 +1169,297 @@ __global__ __launch_bounds__(kEigThreads) void eig_orth_kernel(double* __restric
                                                                const double* __restrict__ scal, int blocked) {
   extern __shared__ double sh[];
   orth_body(Zt, J, lam, Rp, scal, sh, (int)std::min<int64_t>((int64_t)J * J, kOrthCap), blocked);
+}
+
+// Right-looking form for single matrices of kRlMinJ <= J <= kRlMaxJ: two
+// sweeps of block modified Gram-Schmidt, each one launch per block
+// b = -1, 0, 1, ...: once block b is final, every later block c that holds
+// vectors whose window reaches into b is projected against b by a workgroup
+// of its own (coefficients C = Z_b Z_c^T masked to the windows, then
+// Z_c -= C^T Z_b, FP64 MFMA products, Z_c in LDS, Z_b read from global
+// memory), and the workgroup of block b + 1 then completes that block within
+// itself.  The projections of all later blocks run side by side on many CUs
+// instead of one after another on one.  One sweep leaves a loss of
+// orthogonality of the order of u times the condition of the iterates
+// (rounding in a later block's projection is not removed by an earlier one);
+// the second sweep, over nearly orthonormal vectors, brings it to rounding,
+// as the second pass of classical Gram-Schmidt does.  Within the block, the vectors
+// from the first one whose window reaches a block vector onward are
+// orthonormalised by two passes of Cholesky QR (G = Z Z^T = L L^T,
+// Z <- L^{-1} Z), which gives the Gram-Schmidt result in that order; if a
+// pivot shows a nearly dependent vector (L_tt^2 < 1e-8 G_tt) the block takes
+// the vector-by-vector classical Gram-Schmidt instead.  Block vectors outside
+// each other's window are already orthogonal to rounding (their eigenvalues
+// differ by more than 1e-2 ||T||), so treating them together changes them at
+// that level only.  Launches for blocks beyond R, and every launch when R * J
+// fits the LDS copy of eig_orth_kernel, return at once.
+constexpr int kRlWaves = 8;
+constexpr int kRlThreads = 64 * kRlWaves;
+constexpr int kRlMinJ = 384;
+constexpr int kRlMaxJ = 1024;
+__host__ __device__ constexpr int64_t orth_rl_doubles(int64_t J) {
+  return (int64_t)kOB * ((J + 15) & ~int64_t(15)) + kRlWaves * 256 + 2 * 256 + 16 + 16 + 16;
+}
+
+// Fixed-order sum over a workgroup of kRlThreads threads; all threads get it.
+__device__ __forceinline__ double block_sum_rl(double v, double* sred) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  v = wave_sum_fast(v);
+  if (lane == 0) sred[wave] = v;
+  __syncthreads();
+  double s = 0.0;
+#pragma unroll
+  for (int w = 0; w < kRlWaves; ++w) s += sred[w];
+  __syncthreads();
+  return s;
+}
+
+__global__ __launch_bounds__(kRlThreads) void eig_orth_rl_kernel(double* __restrict__ Z, int J,
+                                                                 const double* __restrict__ lam,
+                                                                 const int64_t* __restrict__ Rp,
+                                                                 const double* __restrict__ scal, int b, int cap) {
+  extern __shared__ double sh[];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int il = lane & 15, q = lane >> 4;
+  const int R = (int)*Rp;
+  if ((int64_t)R * J <= cap) return;  // eig_orth_kernel's LDS copy form did it
+  const int c = b + 1 + (int)blockIdx.x;
+  const int c0 = kOB * c;
+  if (c0 >= R) return;
+  const int nb = min(kOB, R - c0);
+  const int Jp = (J + 15) & ~15;
+  double* Zc = sh;                                       // [kOB][Jp], zero-padded
+  double* sP = Zc + kOB * Jp;                            // [kRlWaves][16][16] per-wave partial products
+  double* sC = sP + kRlWaves * 256;                      // [16][16] coefficients
+  double* sL = sC + 256;                                 // [16][16] Cholesky factor, row t = L_t*
+  double* sRd = sL + 256;                                // [16] 1 / L_tt
+  double* shs = sRd + 16;                                // [16] Gram-Schmidt coefficients
+  int* sjlo = reinterpret_cast<int*>(shs + 16);          // [16] window starts
+  int* sflag = sjlo + 16;                                // [1]
+  const double otol = 1e-2 * scal[0];
+  if (tid < kOB) {
+    // window start: smallest j <= i with lam_j - lam_i < otol (lam descending)
+    const int i = c0 + tid;
+    int lo = i < R ? 0 : i, hi = i;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (lam[mid] - lam[i] < otol) hi = mid;
+      else lo = mid + 1;
+    }
+    sjlo[tid] = lo;
+  }
+  __syncthreads();
+  int wmin = c0 + kOB, t0 = kOB;
+  for (int t = 0; t < nb; ++t) {
+    const int st = sjlo[t];
+    wmin = min(wmin, st);
+    if (st < c0 + t) t0 = min(t0, max(st, c0) - c0);
+  }
+  const int b0 = kOB * b;
+  const bool proj = b >= 0 && wmin < b0 + kOB;
+  const bool fin = (c == b + 1) && t0 < nb;
+  if (!proj && !fin) return;  // uniform
+  // Z_c into LDS, eight loads in flight per thread
+  for (int x0 = tid; x0 < kOB * Jp; x0 += 8 * kRlThreads) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int x = x0 + u * kRlThreads;
+      const int t = x / Jp, r = x - t * Jp;
+      v[u] = (x < kOB * Jp && t < nb && r < J) ? Z[(int64_t)(c0 + t) * J + r] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int x = x0 + u * kRlThreads;
+      if (x < kOB * Jp) Zc[x] = v[u];
+    }
+  }
+  __syncthreads();
+  const int nst = Jp / 4;  // reduction steps of 4
+  const int s0 = nst * wave / kRlWaves, s1 = nst * (wave + 1) / kRlWaves;
+  if (proj) {
+    {
+      // C[i][j] = sum_r Z_b[i][r] Z_c[j][r] over this wave's steps, 16 loads of
+      // Z_b in flight (Z_c is zero past J, so the clamped loads need no mask)
+      const double* zb = Z + (int64_t)(b0 + il) * J;
+      d4 acc = {0.0, 0.0, 0.0, 0.0};
+      for (int g0 = s0; g0 < s1; g0 += 16) {
+        double x[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) x[u] = zb[min(4 * (g0 + u) + q, J - 1)];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+          const int st = g0 + u;
+          const double av = (st < s1) ? x[u] : 0.0;
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, Zc[il * Jp + min(4 * st + q, Jp - 1)], acc, 0, 0, 0);
+        }
+      }
+      // D[(l >> 4) + 4v][l & 15] = C[i][j], i = q + 4 v, j = il
+#pragma unroll
+      for (int v = 0; v < 4; ++v) sP[wave * 256 + (q + 4 * v) * 16 + il] = acc[v];
+    }
+    __syncthreads();
+    if (tid < 256) {
+      const int i = tid >> 4, j = tid & 15;
+      double cv = 0.0;
+#pragma unroll
+      for (int w = 0; w < kRlWaves; ++w) cv += sP[w * 256 + tid];
+      sC[tid] = (j < nb && b0 + i >= sjlo[j]) ? cv : 0.0;
+    }
+    __syncthreads();
+    // Z_c[j][r] -= sum_i C[i][j] Z_b[i][r]: wave -> 16-column tiles T, all of
+    // its tiles' Z_b values loaded first (at most 8 tiles for J <= 1024)
+    {
+      constexpr int kTiles = kRlMaxJ / 16 / kRlWaves;
+      double x[kTiles][4];
+#pragma unroll
+      for (int tt = 0; tt < kTiles; ++tt) {
+        const int r = 16 * (wave + kRlWaves * tt) + il;
+#pragma unroll
+        for (int st = 0; st < 4; ++st) x[tt][st] = Z[(int64_t)(b0 + 4 * st + q) * J + min(r, J - 1)];  // in bounds
+      }
+      double cq[4];
+#pragma unroll
+      for (int st = 0; st < 4; ++st) cq[st] = -sC[(4 * st + q) * 16 + il];
+#pragma unroll
+      for (int tt = 0; tt < kTiles; ++tt) {
+        const int T = wave + kRlWaves * tt;
+        if (T < Jp / 16) {  // uniform per wave
+          const int r = 16 * T + il;
+          d4 acc;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) acc[v] = Zc[(q + 4 * v) * Jp + r];
+#pragma unroll
+          for (int st = 0; st < 4; ++st) {
+            const double bv = (r < J) ? x[tt][st] : 0.0;
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(cq[st], bv, acc, 0, 0, 0);
+          }
+#pragma unroll
+          for (int v = 0; v < 4; ++v) Zc[(q + 4 * v) * Jp + r] = acc[v];
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (fin) {
+    bool done = false;
+    for (int pass = 0; pass < 2; ++pass) {
+      {
+        // G = Z_c Z_c^T: lane (il, q) supplies Z_c[il][4 st + q] as both operands
+        d4 acc = {0.0, 0.0, 0.0, 0.0};
+        for (int st = s0; st < s1; ++st) {
+          const double v = Zc[il * Jp + 4 * st + q];
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(v, v, acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) sP[wave * 256 + (q + 4 * v) * 16 + il] = acc[v];
+      }
+      __syncthreads();
+      if (wave == 0) {
+        // Cholesky of the rows t0..nb-1 (the others: identity), lane t & 15
+        // holding row t; right-looking, column k by column k
+        const int t = lane & 15;
+        const bool act = t >= t0 && t < nb;
+        double a[16];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+          const int x = t * 16 + j;
+          double g = 0.0;
+#pragma unroll
+          for (int w = 0; w < kRlWaves; ++w) g += sP[w * 256 + x];
+          const bool jact = j >= t0 && j < nb;
+          a[j] = act ? (jact ? g : 0.0) : (j == t ? 1.0 : 0.0);
+        }
+        double gtt = 1.0;
+#pragma unroll
+        for (int j = 0; j < 16; ++j)
+          if (j == t) gtt = a[j];
+        double ratio = 1.0;
+        bool okp = true;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+          const double dk = __shfl(a[k], k, 64);  // lane k's updated diagonal
+          okp = okp && dk > 0.0;
+          const double lkk = dk > 0.0 ? sqrt(dk) : 1.0;
+          if (t == k) ratio = dk / gtt;
+          const double lik = (t == k) ? lkk : ((t > k) ? a[k] / lkk : 0.0);
+          a[k] = lik;
+#pragma unroll
+          for (int j = k + 1; j < 16; ++j) {
+            const double ljk = __shfl(lik, j, 64);
+            if (t >= j) a[j] -= lik * ljk;
+          }
+        }
+        const double rmin = act ? ratio : 1.0;
+        double m = rmin;
+#pragma unroll
+        for (int off = 8; off > 0; off >>= 1) m = fmin(m, __shfl_xor(m, off, 16));
+        if (lane < 16) {
+          double ltt = 1.0;
+#pragma unroll
+          for (int j = 0; j < 16; ++j) {
+            sL[t * 16 + j] = (j < t) ? a[j] : 0.0;
+            if (j == t) ltt = a[j];
+          }
+          sRd[t] = 1.0 / ltt;
+        }
+        if (lane == 0) sflag[0] = (okp && m >= 1e-8) ? 1 : 0;
+      }
+      __syncthreads();
+      if (!sflag[0]) break;  // uniform
+      // Z_c <- L^{-1} Z_c, column by column
+      for (int r = tid; r < J; r += kRlThreads) {
+        double z[16];
+#pragma unroll
+        for (int t = 0; t < 16; ++t) z[t] = Zc[t * Jp + r];
+#pragma unroll
+        for (int t = 0; t < 16; ++t) {
+          double v = z[t];
+#pragma unroll
+          for (int u = 0; u < t; ++u) v -= sL[t * 16 + u] * z[u];
+          z[t] = v * sRd[t];
+        }
+#pragma unroll
+        for (int t = 0; t < 16; ++t) Zc[t * Jp + r] = z[t];
+      }
+      __syncthreads();
+      done = pass == 1;
+    }
+    if (!done) {
+      // classical Gram-Schmidt, twice, vector by vector within the windows
+      for (int t = t0; t < nb; ++t) {
+        const int i = c0 + t;
+        if (sjlo[t] >= i) continue;  // uniform: no neighbour within otol
+        double* zt = Zc + t * Jp;
+        const int u0 = max(sjlo[t], c0) - c0;
+        for (int pass = 0; pass < 2 && u0 < t; ++pass) {
+          for (int u = u0 + wave; u < t; u += kRlWaves) {
+            double h = 0.0;
+            for (int r = lane; r < J; r += 64) h += Zc[u * Jp + r] * zt[r];
+            h = wave_sum_fast(h);
+            if (lane == 0) shs[u] = h;
+          }
+          __syncthreads();
+          for (int r = tid; r < J; r += kRlThreads) {
+            double v = zt[r];
+            for (int u = u0; u < t; ++u) v -= shs[u] * Zc[u * Jp + r];
+            zt[r] = v;
+          }
+          __syncthreads();
+        }
+        double nn = 0.0;
+        for (int r = tid; r < J; r += kRlThreads) nn += zt[r] * zt[r];
+        nn = block_sum_rl(nn, sP);
+        const double rn = 1.0 / sqrt(nn);
+        for (int r = tid; r < J; r += kRlThreads) zt[r] *= rn;
+        __syncthreads();
+      }
+    }
+  }
+  for (int x = tid; x < nb * Jp; x += kRlThreads) {
+    const int t = x / Jp, r = x - t * Jp;
+    if (r < J) Z[(int64_t)(c0 + t) * J + r] = Zc[x];
+  }
 }
 
 // ---------------------------------------------------------------- 6. back-transformation + signs
@@ -1518,16 +1894,29 @@ hipError_t launch_eig_values(const double* S, int J, double thr, const double* n
       // steps over the whole device until the trailing block fits the registers
       hipError_t err = hipMemcpyAsync(w.A, S, sizeof(double) * (size_t)J * J, hipMemcpyDeviceToDevice, stream);
       if (err != hipSuccess) return err;
-      double* V = w.Zt;  // the eigenvector buffer is free until inverse iteration
-      double* P = w.Zt + J;
-      double* sc = w.Zt + 2 * (size_t)J;
+      // the eigenvector buffer is free until inverse iteration: V, P and the
+      // step scalars, twice
+      double* V[2] = {w.Zt, w.Zt + 3 * (size_t)J};
+      double* P[2] = {w.Zt + J, w.Zt + 4 * (size_t)J};
+      double* sc[2] = {w.Zt + 2 * (size_t)J, w.Zt + 5 * (size_t)J};
       const int nbig = J - kRegMaxJ;
       for (int k = 0; k < nbig; ++k) {
-        const int grid = (int)ceil_div(J - k - 1, kBigRows);
-        hipLaunchKernelGGL(eig_tri_big_p, dim3(grid), dim3(kBigThreads), sizeof(double) * (size_t)J, stream, w.A, J,
-                           k, V, P, sc);
-        hipLaunchKernelGGL(eig_tri_big_update, dim3(grid), dim3(kBigThreads), sizeof(double) * 2 * (size_t)J, stream,
-                           w.A, J, k, V, P, sc, w.d, w.e, w.tau);
+        const int c = k & 1, pv = c ^ 1;
+        const size_t shs = sizeof(double) * 3 * (size_t)J;
+#define STEP_LAUNCH(RR, NW)                                                                                   \
+  hipLaunchKernelGGL((eig_tri_big_step<RR, NW>), dim3((int)ceil_div(J - k - 1, NW)), dim3(64 * NW), shs, stream, \
+                     w.A, J, k, V[pv], P[pv], sc[pv], V[c], P[c], sc[c], w.d, w.e, w.tau)
+        if (J <= 768) STEP_LAUNCH(12, 16);
+        else if (J <= 1536) STEP_LAUNCH(24, 8);
+        else STEP_LAUNCH(kEigMaxJ / 64, 8);
+#undef STEP_LAUNCH
+        LAUNCH_OK();
+      }
+      {
+        const int k = nbig - 1, c = k & 1;
+        hipLaunchKernelGGL(eig_tri_big_update, dim3((int)ceil_div(J - k - 1, kBigRows)), dim3(kBigThreads),
+                           sizeof(double) * 2 * (size_t)J, stream, w.A, J, k, V[c], P[c], sc[c], nullptr, w.e,
+                           w.tau);
         LAUNCH_OK();
       }
       src = w.A;
@@ -1571,9 +1960,21 @@ hipError_t launch_eig_vectors(int J, const EigWork& w, const double* lam, const 
                        w.scal, w.Zt, nvw);
     LAUNCH_OK();
   }
-  hipLaunchKernelGGL(eig_orth_kernel, dim3(1), dim3(kEigThreads), orth_lds_bytes(J), stream, w.Zt, J, lam, R,
-                     w.scal, orth_blocked_mode(J));
+  const bool rl = J >= kRlMinJ && J <= kRlMaxJ;
+  hipLaunchKernelGGL(eig_orth_kernel, dim3(1), dim3(kEigThreads), orth_lds_bytes(J, rl), stream, w.Zt, J, lam, R,
+                     w.scal, rl ? 3 : orth_blocked_mode(J));
   LAUNCH_OK();
+  if (rl) {
+    const int cap = (int)std::min<int64_t>((int64_t)J * J, kOrthCap);
+    const int nblk = (int)ceil_div(J, kOB);
+    const size_t shr = sizeof(double) * (size_t)orth_rl_doubles(J);
+    for (int sweep = 0; sweep < 2; ++sweep)
+      for (int b = -1; b + 1 < nblk; ++b) {
+        hipLaunchKernelGGL(eig_orth_rl_kernel, dim3(b < 0 ? 1 : nblk - b - 1), dim3(kRlThreads), shr, stream,
+                           w.Zt, J, lam, R, w.scal, b, cap);
+        LAUNCH_OK();
+      }
+  }
   const int q = (int)ceil_div(J, 64);
   if (q <= 1) launch_back<1>(w, J, R, U, stream);
   else if (q <= 2) launch_back<2>(w, J, R, U, stream);

@@ -10,6 +10,13 @@
 //     16-column group and feeds column 4q + s to step s;
 //   BF16 forms (16x16x32): lane (i, q) reads columns 8q .. 8q+7 of a
 //     32-column group, split in registers into bf16 pieces.
+// In FP64 arithmetic, a J whose last row block holds only REM (1 or 2) rows
+// (J = 33, 50, ...) computes the products with those rows on the VALU: the
+// MFMA blocks would be mostly padding (for J = 33, three of six 16 x 16
+// blocks for one row), and the kernel then runs at the MFMA rate rather than
+// at the rate it reads Y.  Each lane fetches the REM rows' values of its
+// columns from the lanes that loaded them (same lane group, lane m) and
+// accumulates the dot products of its rows with them.
 // Each wave walks column groups g = wave id, wave id + total waves, ..., so
 // that all waves stream neighbouring addresses; vector loads are used when the
 // lane's columns cannot cross a block of the unfolding (L a multiple of the
@@ -52,11 +59,15 @@ __device__ __forceinline__ void split_bf16(float x, __bf16& b0, __bf16& b1, __bf
 
 // PREC: 0 FP64, 1 FP32, 2 BF16X3, 3 BF16X6.  NB: row blocks (J <= 16 NB).
 // VEC: 0 scalar loads, 1 contiguous columns (L % G == 0), 2 L = 1.
-template <typename T, int PREC, int NB, int VEC>
+// REM: 0, or (FP64 only) the rows of the last block, whose products run on
+// the VALU.
+template <typename T, int PREC, int NB, int VEC, int REM>
 __global__ __launch_bounds__(kSNT) void gram_stream_kernel(StreamParams g) {
+  static_assert(REM == 0 || (PREC == 0 && NB >= 2), "VALU rows: FP64 with a full block above");
   constexpr int G = (PREC >= 2) ? 32 : 16;  // columns per group
   constexpr int CPL = G / 4;                // columns per lane (4 or 8)
   constexpr int NBLK = NB * (NB + 1) / 2;
+  constexpr int NBM = (REM > 0) ? NB - 1 : NB;  // row blocks of the MFMA products
   __shared__ double sred[NBLK * 256];
   __shared__ double ssq[kSW];
 
@@ -77,6 +88,13 @@ __global__ __launch_bounds__(kSNT) void gram_stream_kernel(StreamParams g) {
     acc64[b] = d4{0.0, 0.0, 0.0, 0.0};
     acc32[b] = f4{0.f, 0.f, 0.f, 0.f};
   }
+  // VALU rows: racc[rb][m] = sum over this lane's columns of
+  // Y[16 rb + i][c] * Y[16 (NB - 1) + m][c]
+  double racc[NB][REM > 0 ? REM : 1];
+#pragma unroll
+  for (int rb = 0; rb < NB; ++rb)
+#pragma unroll
+    for (int m = 0; m < (REM > 0 ? REM : 1); ++m) racc[rb][m] = 0.0;
   double sq = 0.0;
   int since_promote = 0;
 
@@ -149,7 +167,17 @@ __global__ __launch_bounds__(kSNT) void gram_stream_kernel(StreamParams g) {
         for (int bi = 0; bi < NB; ++bi)
 #pragma unroll
           for (int bj = bi; bj < NB; ++bj, ++b)
-            acc64[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(v[bi][s], v[bj][s], acc64[b], 0, 0, 0);
+            if (bj < NBM) acc64[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(v[bi][s], v[bj][s], acc64[b], 0, 0, 0);
+      }
+      if constexpr (REM > 0) {
+#pragma unroll
+        for (int m = 0; m < REM; ++m)
+#pragma unroll
+          for (int j = 0; j < CPL; ++j) {
+            const double xm = __shfl(v[NB - 1][j], (lane & ~15) | m, 64);
+#pragma unroll
+            for (int rb = 0; rb < NB; ++rb) racc[rb][m] = fma(v[rb][j], xm, racc[rb][m]);
+          }
       }
     } else if constexpr (PREC == 1) {
 #pragma unroll
@@ -218,15 +246,38 @@ __global__ __launch_bounds__(kSNT) void gram_stream_kernel(StreamParams g) {
   // D[(l>>4)+4r][l&15]; f32 MFMA result: lane l, register r -> D[4(l>>4)+r][l&15].
   const double wsq = wave_sum(sq);
   if (lane == 0) ssq[wave] = wsq;
+  if constexpr (REM > 0) {
+    // the four lane groups' sums of the VALU rows, in a fixed order
+#pragma unroll
+    for (int rb = 0; rb < NB; ++rb)
+#pragma unroll
+      for (int m = 0; m < REM; ++m) {
+        const double x = racc[rb][m] + __shfl_xor(racc[rb][m], 16, 64);
+        racc[rb][m] = x + __shfl_xor(x, 32, 64);
+      }
+  }
   for (int w = 0; w < kSW; ++w) {
     if (wave == w) {
+      int b = 0;
 #pragma unroll
-      for (int b = 0; b < NBLK; ++b)
+      for (int bi = 0; bi < NB; ++bi)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int row = (PREC == 0) ? (q + 4 * r) : (4 * q + r);
-          double* d = &sred[b * 256 + row * 16 + i];
-          *d = (w == 0) ? acc64[b][r] : *d + acc64[b][r];
+        for (int bj = bi; bj < NB; ++bj, ++b) {
+          if (bj < NBM) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int row = (PREC == 0) ? (q + 4 * r) : (4 * q + r);
+              double* d = &sred[b * 256 + row * 16 + i];
+              *d = (w == 0) ? acc64[b][r] : *d + acc64[b][r];
+            }
+          } else if (lane < 16) {
+            // block (bi, NB - 1): row i, columns m < REM (the rest is never read)
+#pragma unroll
+            for (int m = 0; m < (REM > 0 ? REM : 1); ++m) {
+              double* d = &sred[b * 256 + i * 16 + m];
+              *d = (w == 0) ? racc[bi][m] : *d + racc[bi][m];
+            }
+          }
         }
     }
     __syncthreads();
@@ -263,11 +314,11 @@ __global__ __launch_bounds__(256) void gram_stream_reduce_kernel(const double* _
   S[(int64_t)b * J + a] = s;
 }
 
-template <typename T, int PREC, int NB>
+template <typename T, int PREC, int NB, int REM = 0>
 void launch_stream(const StreamParams& g, int vec, int64_t nwg, hipStream_t s) {
-  if (vec == 1) hipLaunchKernelGGL((gram_stream_kernel<T, PREC, NB, 1>), dim3(nwg), dim3(kSNT), 0, s, g);
-  else if (vec == 2) hipLaunchKernelGGL((gram_stream_kernel<T, PREC, NB, 2>), dim3(nwg), dim3(kSNT), 0, s, g);
-  else hipLaunchKernelGGL((gram_stream_kernel<T, PREC, NB, 0>), dim3(nwg), dim3(kSNT), 0, s, g);
+  if (vec == 1) hipLaunchKernelGGL((gram_stream_kernel<T, PREC, NB, 1, REM>), dim3(nwg), dim3(kSNT), 0, s, g);
+  else if (vec == 2) hipLaunchKernelGGL((gram_stream_kernel<T, PREC, NB, 2, REM>), dim3(nwg), dim3(kSNT), 0, s, g);
+  else hipLaunchKernelGGL((gram_stream_kernel<T, PREC, NB, 0, REM>), dim3(nwg), dim3(kSNT), 0, s, g);
 }
 
 template <typename T, int PREC>
@@ -277,6 +328,20 @@ void launch_stream_nb(const StreamParams& g, int nb, int vec, int64_t nwg, hipSt
     case 2: launch_stream<T, PREC, 2>(g, vec, nwg, s); break;
     case 3: launch_stream<T, PREC, 3>(g, vec, nwg, s); break;
     default: launch_stream<T, PREC, 4>(g, vec, nwg, s); break;
+  }
+}
+
+// FP64 with 1 or 2 rows in the last block (J = 17, 18, 33, 34, 49, 50)
+template <typename T>
+void launch_stream_rem(const StreamParams& g, int nb, int rem, int vec, int64_t nwg, hipStream_t s) {
+  if (rem == 1) {
+    if (nb == 2) launch_stream<T, 0, 2, 1>(g, vec, nwg, s);
+    else if (nb == 3) launch_stream<T, 0, 3, 1>(g, vec, nwg, s);
+    else launch_stream<T, 0, 4, 1>(g, vec, nwg, s);
+  } else {
+    if (nb == 2) launch_stream<T, 0, 2, 2>(g, vec, nwg, s);
+    else if (nb == 3) launch_stream<T, 0, 3, 2>(g, vec, nwg, s);
+    else launch_stream<T, 0, 4, 2>(g, vec, nwg, s);
   }
 }
 
@@ -315,12 +380,18 @@ hipError_t launch_gram_stream(const T* Y, int J, uint64_t L, uint64_t K, int pre
   const bool aligned = (reinterpret_cast<uintptr_t>(Y) % 16) == 0;
   const int vec = (L == 1) ? 2 : ((L % (uint64_t)(G / 4) == 0 && aligned) ? 1 : 0);
   const int nb = p.ntiles;
+  const int rem = J % 16;
+  const bool valu_rows = prec == 0 && J > 16 && (rem == 1 || rem == 2);
   if constexpr (std::is_same<T, double>::value) {
     if (prec != 0) return hipErrorInvalidValue;
-    launch_stream_nb<T, 0>(g, nb, vec, p.nsplit, stream);
+    if (valu_rows) launch_stream_rem<T>(g, nb, rem, vec, p.nsplit, stream);
+    else launch_stream_nb<T, 0>(g, nb, vec, p.nsplit, stream);
   } else {
     switch (prec) {
-      case 0: launch_stream_nb<T, 0>(g, nb, vec, p.nsplit, stream); break;
+      case 0:
+        if (valu_rows) launch_stream_rem<T>(g, nb, rem, vec, p.nsplit, stream);
+        else launch_stream_nb<T, 0>(g, nb, vec, p.nsplit, stream);
+        break;
       case 1: launch_stream_nb<T, 1>(g, nb, vec, p.nsplit, stream); break;
       case 2: launch_stream_nb<T, 2>(g, nb, vec, p.nsplit, stream); break;
       default: launch_stream_nb<T, 3>(g, nb, vec, p.nsplit, stream); break;

@@ -62,6 +62,13 @@ GRAM_SHAPES = [
     ([1000, 250], [1]),
     ([300, 7], [0]),
     ([80, 384], [1]),
+    # streaming Gram with the last row block's 1 or 2 rows on the VALU:
+    # J = 17, 18, 34, 49 with unit stride, contiguous columns (L = 8) and
+    # scalar loads (L = 3)
+    ([17, 40, 9], [0]),
+    ([8, 18, 30], [1]),
+    ([3, 34, 20], [1]),
+    ([49, 36], [0, 1]),
 ]
 
 
