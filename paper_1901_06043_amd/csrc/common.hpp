@@ -89,4 +89,20 @@ __device__ __forceinline__ float wave_sum(float v) {
   return v;
 }
 
+// Sum of p[0], p[stride], ..., p[(n - 1) stride] in a fixed order: eight
+// running sums (term s goes to sum s % 8), combined pairwise, so that eight
+// loads are in flight instead of one.
+__device__ __forceinline__ double sum_strided8(const double* __restrict__ p, int64_t n, int64_t stride) {
+  double s[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  int64_t i = 0;
+  for (; i + 8 <= n; i += 8) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s[u] += p[(i + u) * stride];
+  }
+#pragma unroll
+  for (int u = 0; u < 8; ++u)
+    if (i + u < n) s[u] += p[(i + u) * stride];
+  return ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
+}
+
 }  // namespace tk

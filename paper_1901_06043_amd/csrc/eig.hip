@@ -1237,16 +1237,43 @@ __global__ __launch_bounds__(kRlThreads) void eig_orth_rl_kernel(double* __restr
   int* sjlo = reinterpret_cast<int*>(shs + 16);          // [16] window starts
   int* sflag = sjlo + 16;                                // [1]
   const double otol = 1e-2 * scal[0];
-  if (tid < kOB) {
-    // window start: smallest j <= i with lam_j - lam_i < otol (lam descending)
-    const int i = c0 + tid;
-    int lo = i < R ? 0 : i, hi = i;
-    while (lo < hi) {
-      const int mid = (lo + hi) >> 1;
-      if (lam[mid] - lam[i] < otol) hi = mid;
-      else lo = mid + 1;
+  // Z_c (zero-padded to Jp columns) and the window data are loaded together
+  constexpr int kZcRegs = kOB * kRlMaxJ / kRlThreads;
+  double zr[kZcRegs];
+#pragma unroll
+  for (int u = 0; u < kZcRegs; ++u) {
+    const int x = tid + u * kRlThreads;
+    const int t = x / Jp, r = x - t * Jp;
+    zr[u] = (x < kOB * Jp && t < nb && r < J) ? Z[(int64_t)(c0 + t) * J + r] : 0.0;
+  }
+  // window start of vector i: smallest j <= i with lam_j - lam_i < otol.  lam
+  // is descending, so the j < i with lam_j - lam_i >= otol form a prefix and
+  // the start is their count; each thread tests two j (R <= J <= 1024).
+  double lj[2];
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int j = tid + u * kRlThreads;
+    lj[u] = (j < R) ? lam[j] : 0.0;
+  }
+  int* scnt = reinterpret_cast<int*>(sP);  // [kRlWaves][16]
+#pragma unroll
+  for (int t = 0; t < kOB; ++t) {
+    const int i = c0 + t;
+    const double li = lam[min(i, R - 1)];
+    int cnt = 0;
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int j = tid + u * kRlThreads;
+      cnt += __popcll(__ballot(j < i && lj[u] - li >= otol));
     }
-    sjlo[tid] = lo;
+    if (lane == 0) scnt[wave * kOB + t] = cnt;
+  }
+  __syncthreads();
+  if (tid < kOB) {
+    int cnt = 0;
+#pragma unroll
+    for (int w = 0; w < kRlWaves; ++w) cnt += scnt[w * kOB + tid];
+    sjlo[tid] = (c0 + tid < R) ? cnt : c0 + tid;
   }
   __syncthreads();
   int wmin = c0 + kOB, t0 = kOB;
@@ -1259,20 +1286,10 @@ __global__ __launch_bounds__(kRlThreads) void eig_orth_rl_kernel(double* __restr
   const bool proj = b >= 0 && wmin < b0 + kOB;
   const bool fin = (c == b + 1) && t0 < nb;
   if (!proj && !fin) return;  // uniform
-  // Z_c into LDS, eight loads in flight per thread
-  for (int x0 = tid; x0 < kOB * Jp; x0 += 8 * kRlThreads) {
-    double v[8];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int x = x0 + u * kRlThreads;
-      const int t = x / Jp, r = x - t * Jp;
-      v[u] = (x < kOB * Jp && t < nb && r < J) ? Z[(int64_t)(c0 + t) * J + r] : 0.0;
-    }
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int x = x0 + u * kRlThreads;
-      if (x < kOB * Jp) Zc[x] = v[u];
-    }
+  for (int u = 0; u < kZcRegs; ++u) {
+    const int x = tid + u * kRlThreads;
+    if (x < kOB * Jp) Zc[x] = zr[u];
   }
   __syncthreads();
   const int nst = Jp / 4;  // reduction steps of 4

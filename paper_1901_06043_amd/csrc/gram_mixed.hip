@@ -535,8 +535,7 @@ __global__ __launch_bounds__(256) void gram_mp_reduce_kernel(const double* __res
   const int a = ra + 16 * bi + r;
   const int b = diag ? ra + 16 * bj + c : rb + 16 * (bj - 8) + c;
   if (a >= J || b >= J || (diag && bi == bj && r > c)) return;
-  double s = 0.0;
-  for (int64_t sp = 0; sp < nsplit; ++sp) s += part[((sp * npairs + pair) * nblk + qb) * 256 + rem];
+  const double s = sum_strided8(part + ((int64_t)pair * nblk + qb) * 256 + rem, nsplit, (int64_t)npairs * nblk * 256);
   S[(int64_t)a * J + b] = s;
   S[(int64_t)b * J + a] = s;
 }

@@ -308,8 +308,7 @@ __global__ __launch_bounds__(256) void gram_stream_reduce_kernel(const double* _
   const int r = rem >> 4, c = rem & 15;
   const int a = 16 * bi + r, b = 16 * bj + c;
   if (a >= J || b >= J || (bi == bj && r > c)) return;
-  double s = 0.0;
-  for (int64_t w = 0; w < nwg; ++w) s += part[(w * nblk + qb) * 256 + rem];
+  const double s = sum_strided8(part + (int64_t)qb * 256 + rem, nwg, (int64_t)nblk * 256);
   S[(int64_t)a * J + b] = s;
   S[(int64_t)b * J + a] = s;
 }
