@@ -817,11 +817,44 @@ tucker_status sthosvd_impl(const void* data, tucker_dtype dtype, const int64_t* 
     // Y <- Y x_n U_n^T: M(k, j) = U[j + k*J]
     int64_t total = 1;
     for (int k = 0; k < N; ++k) total *= cur[k];
-    const int64_t next_elems = total / J * Rw;
+    int64_t next_elems = total / J * Rw;
+    // the last product writes the compact core itself when one earlier mode
+    // p < n carries a zero slice and the direct-load kernel takes the product
+    int pad = -1, npad = 0;
+    if (padded && step == N - 1)
+      for (int k = 0; k < N; ++k)
+        if (k != n && cur[k] != t->ranks[k]) {
+          pad = k;
+          ++npad;
+        }
+    tk::TtmOutRemap rm;
+    bool fused = false;
+    if (npad == 1 && pad < n && Rw == R && ydt == TUCKER_F64 && wdt == TUCKER_F64) {
+      int64_t L, Rt;
+      left_right(cur, N, n, L, Rt);
+      if (L > 1 && L * Rt < (int64_t(1) << 32) &&
+          tk::ttm_dma_eligible((int)J, (uint64_t)L, (uint64_t)(L * Rt), (int)Rw, J, 1, 8, 8, Y, t->U[n])) {
+        rm.Lp = 1;
+        for (int k = 0; k < pad; ++k) rm.Lp *= cur[k];
+        rm.Pp = cur[pad];
+        rm.Rp = t->ranks[pad];
+        fused = true;
+        next_elems = next_elems / rm.Pp * rm.Rp;
+      }
+    }
     if (!async && (st = fits(round_bytes(dtype_size(wdt) * next_elems), "the next working tensor"))) return st;
     TmpBuf nbuf;
     HIP_TRY(nbuf.alloc(dtype_size(wdt) * next_elems, stream));
-    if ((st = run_ttm(Y, ydt, cur, N, n, t->U[n], Rw, J, 1, nbuf.p, wdt, reduced, stream))) return st;
+    if (fused) {
+      int64_t L, Rt;
+      left_right(cur, N, n, L, Rt);
+      HIP_TRY(tk::launch_ttm_dma(static_cast<const double*>(Y), (int)J, (uint64_t)L, (uint64_t)(L * Rt), t->U[n], J,
+                                 1, (int)Rw, static_cast<double*>(nbuf.p), stream, rm));
+      cur[pad] = t->ranks[pad];
+      padded = false;
+    } else if ((st = run_ttm(Y, ydt, cur, N, n, t->U[n], Rw, J, 1, nbuf.p, wdt, reduced, stream))) {
+      return st;
+    }
     HIP_TRY(hipEventRecord(ev[3], stream));
     ybuf.release();  // stream-ordered: after the TTM that read it
     ybuf.p = nbuf.p;

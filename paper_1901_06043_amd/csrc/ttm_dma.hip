@@ -42,6 +42,8 @@ struct TtmDmaParams {
   int64_t L, cols;
   int64_t msk, msj;   // M(k, j) at M + k msk + j msj (doubles)
   int64_t nkt, total;
+  int64_t Lo;          // L of the output (L unless remapped)
+  int64_t Lp, Pp, Rp;  // output remap (TtmOutRemap); Pp == Rp: none
 };
 
 // ORI 0 (L > 1): A = M (row form MF = 0, column form MF = 1), B = Y (column
@@ -251,15 +253,19 @@ struct Opnd<1, T> {  // column form
 };
 
 // One chunk of MFMAs (four steps of four j).  MK: compile-time block mask.
+// `half`: the chunk holds at most 8 valid j (the last chunk of a ragged J),
+// which steps 0 and 1 cover (j(s, q) = 2 q + (s & 1) + 8 (s >> 1)), so steps
+// 2 and 3 would only multiply zeros.
 template <unsigned MK, int FA, typename TA, int FB, typename TB>
 __device__ __forceinline__ void compute_chunk(const char* abuf, const char* bbuf, const int (&oa)[4], int da,
-                                              const int (&ob)[4], int db, d4 (&acc)[4][4]) {
+                                              const int (&ob)[4], int db, d4 (&acc)[4][4], bool half = false) {
   Opnd<FA, TA> a[2];
   Opnd<FB, TB> b[2];
   a[0].fetch(abuf, oa, da, 0);
   b[0].fetch(bbuf, ob, db, 0);
 #pragma unroll
   for (int s = 0; s < kJC / 4; ++s) {
+    if (s >= 2 && half) break;  // uniform
     // the row form's unit of step s (odd) is the one fetched for step s - 1
     const int cur = (FA == 0) ? (s >> 1) & 1 : s & 1;
     const int curb = (FB == 0) ? (s >> 1) & 1 : s & 1;
@@ -289,19 +295,20 @@ __device__ __forceinline__ void chunk_loop(const Loader<TY, ORI, MF, WY>& ld, co
   using TB = typename std::conditional<ORI == 0, TY, double>::type;
   constexpr int AOFF = (ORI == 0) ? 0 : C::MB, BOFF = (ORI == 0) ? C::MB : 0;
   const int nch = (g.J + kJC - 1) / kJC;
+  const bool last_half = g.J - kJC * (nch - 1) <= kJC / 2;
   issue_chunk(ld, g, 0, buf0, wave, lane);
   __builtin_amdgcn_s_waitcnt(0);
   fill_chunk(ld, g, 0, buf0, wave, lane);
   __syncthreads();
   for (int t = 0;; t += 2) {
     if (t + 1 < nch) issue_chunk(ld, g, t + 1, buf1, wave, lane);
-    compute_chunk<MK, FA, TA, FB, TB>(buf0 + AOFF, buf0 + BOFF, oa, da, ob, db, acc);
+    compute_chunk<MK, FA, TA, FB, TB>(buf0 + AOFF, buf0 + BOFF, oa, da, ob, db, acc, last_half && t + 1 == nch);
     if (t + 1 >= nch) break;
     __builtin_amdgcn_s_waitcnt(0);
     fill_chunk(ld, g, t + 1, buf1, wave, lane);
     __syncthreads();
     if (t + 2 < nch) issue_chunk(ld, g, t + 2, buf0, wave, lane);
-    compute_chunk<MK, FA, TA, FB, TB>(buf1 + AOFF, buf1 + BOFF, oa, da, ob, db, acc);
+    compute_chunk<MK, FA, TA, FB, TB>(buf1 + AOFF, buf1 + BOFF, oa, da, ob, db, acc, last_half && t + 2 == nch);
     if (t + 2 >= nch) break;
     __builtin_amdgcn_s_waitcnt(0);
     fill_chunk(ld, g, t + 2, buf0, wave, lane);
@@ -322,14 +329,21 @@ __device__ __forceinline__ void store_tile(const TtmDmaParams& g, const d4 (&acc
       const int64_t c = c0l + 16 * (b0 + y) + i;
       if (c >= g.cols) continue;
       const int64_t m = c / g.L, l = c - m * g.L;
-      TZ* zc = Z + l + g.L * (int64_t)g.K * m;
+      int64_t lo = l;
+      if (g.Pp != g.Rp) {  // uniform
+        const int64_t t = l / g.Lp, a = l - t * g.Lp;
+        const int64_t h = t / g.Pp, ip = t - h * g.Pp;
+        if (ip >= g.Rp) continue;  // a zero slice of the padded mode
+        lo = a + g.Lp * (ip + g.Rp * h);
+      }
+      TZ* zc = Z + lo + g.Lo * (int64_t)g.K * m;
 #pragma unroll
       for (int x = 0; x < 4; ++x) {
         if (!((MK >> (4 * x + y)) & 1u)) continue;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int k = k0 + 16 * (a0 + x) + q + 4 * v;
-          if (k < g.K) zc[g.L * (int64_t)k] = static_cast<TZ>(acc[x][y][v]);
+          if (k < g.K) zc[g.Lo * (int64_t)k] = static_cast<TZ>(acc[x][y][v]);
         }
       }
     }
@@ -452,8 +466,11 @@ bool ttm_dma_eligible(int J, uint64_t L, uint64_t cols, int K, int64_t msk, int6
 
 template <typename TY, typename TZ>
 hipError_t launch_ttm_dma(const TY* Y, int J, uint64_t L, uint64_t cols, const double* M, int64_t msk, int64_t msj,
-                          int K, TZ* Z, hipStream_t stream) {
+                          int K, TZ* Z, hipStream_t stream, const TtmOutRemap& rm) {
   if (!ttm_dma_eligible(J, L, cols, K, msk, msj, (int)sizeof(TY), (int)sizeof(TZ), Y, M))
+    return hipErrorInvalidValue;
+  const bool remap = rm.Pp != rm.Rp;
+  if (remap && (L == 1 || rm.Lp < 1 || rm.Rp < 1 || rm.Rp > rm.Pp || (int64_t)L % (rm.Lp * rm.Pp) != 0))
     return hipErrorInvalidValue;
   TtmDmaParams g{};
   g.Y = reinterpret_cast<const char*>(Y);
@@ -467,6 +484,10 @@ hipError_t launch_ttm_dma(const TY* Y, int J, uint64_t L, uint64_t cols, const d
   g.msj = msj;
   g.nkt = ceil_div(K, 128);
   g.total = g.nkt * ceil_div((int64_t)cols, 128);
+  g.Lp = remap ? rm.Lp : 1;
+  g.Pp = remap ? rm.Pp : 1;
+  g.Rp = remap ? rm.Rp : 1;
+  g.Lo = remap ? (int64_t)L / rm.Pp * rm.Rp : (int64_t)L;
   const int64_t grid = ceil_div(g.total, kXcds) * kXcds;
   const bool mrow = (msj == 1 && msk % 2 == 0);
   const bool y16 = ttm_dma_y16(J, L, (int)sizeof(TY), Y);
@@ -495,12 +516,12 @@ hipError_t launch_ttm_dma(const TY* Y, int J, uint64_t L, uint64_t cols, const d
 }
 
 template hipError_t launch_ttm_dma<double, double>(const double*, int, uint64_t, uint64_t, const double*, int64_t,
-                                                   int64_t, int, double*, hipStream_t);
+                                                   int64_t, int, double*, hipStream_t, const TtmOutRemap&);
 template hipError_t launch_ttm_dma<float, double>(const float*, int, uint64_t, uint64_t, const double*, int64_t,
-                                                  int64_t, int, double*, hipStream_t);
+                                                  int64_t, int, double*, hipStream_t, const TtmOutRemap&);
 template hipError_t launch_ttm_dma<double, float>(const double*, int, uint64_t, uint64_t, const double*, int64_t,
-                                                  int64_t, int, float*, hipStream_t);
+                                                  int64_t, int, float*, hipStream_t, const TtmOutRemap&);
 template hipError_t launch_ttm_dma<float, float>(const float*, int, uint64_t, uint64_t, const double*, int64_t,
-                                                 int64_t, int, float*, hipStream_t);
+                                                 int64_t, int, float*, hipStream_t, const TtmOutRemap&);
 
 }  // namespace tk

@@ -294,6 +294,38 @@ def test_padded_working_extent(tk, orc, order, given_ranks):
     assert abs(e - orc.relerr(X, ref)) <= 1e-10
 
 
+@pytest.mark.parametrize("order", [[0, 1, 2], [1, 0, 2]])
+@pytest.mark.parametrize("given_ranks", [False, True])
+def test_padded_extent_compact_last_product(tk, orc, order, given_ranks):
+    """The last mode has more than 64 rows of output, so its direct-load
+    product writes the compact core itself, dropping the zero slice of the
+    padded mode: mode 0 (order 0,1,2: the fastest mode) or mode 1 (order
+    1,0,2: the zero slice sits between mode-0 rows).  Core and factors equal
+    the oracle's up to column signs."""
+    dims, ranks = [41, 30, 160], [9, 9, 70]
+    X, dims = synthetic.random_tucker(dims, ranks, 1e-6, seed=23)
+    print(f"compact last product order={order} given_ranks={given_ranks}", flush=True)
+    x = to_dev(X, dims)
+    if given_ranks:
+        t = tk.sthosvd_ranks(x, ranks, mode_order=order, dims=dims)
+        ref = orc.sthosvd(X, dims, 0.0, order, ranks=ranks)
+    else:
+        t = tk.sthosvd(x, 1e-4, mode_order=order, dims=dims)
+        ref = orc.sthosvd(X, dims, 1e-4, order)
+    assert t.ranks == ref.ranks == ranks
+    G = t.core.cpu().numpy().reshape(-1)
+    assert G.size == int(np.prod(ranks))
+    assert np.abs(np.abs(G) - np.abs(ref.core)).max() <= 1e-10 * np.abs(ref.core).max()
+    for n in range(3):
+        U = t.factor(n).cpu().numpy()
+        Ur = ref.factors[n]
+        sgn = np.sign(np.sum(U * Ur, axis=0))
+        assert np.abs(U - Ur * sgn).max() <= 1e-9
+    xh = t.reconstruct()
+    e = float(torch.linalg.vector_norm((x - xh).reshape(-1)) / torch.linalg.vector_norm(x.reshape(-1)))
+    assert abs(e - orc.relerr(X, ref)) <= 1e-10
+
+
 def _check_sthosvd(tk, orc, X, dims, eps, order, dtype=torch.float64):
     print(f"sthosvd dims={dims} eps={eps} order={order}", flush=True)
     t = tk.sthosvd(to_dev(X, dims, dtype), eps, mode_order=order, dims=dims)
