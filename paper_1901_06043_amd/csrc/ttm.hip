@@ -335,8 +335,12 @@ constexpr int kResWaves = 8;
 // in flight per lane; the block loop is unrolled by kDepth so that each
 // buffer keeps its registers (no moves that would wait for a load).
 constexpr int kDepth = 3;
+// ROW1: K = 16 (RB - 1) + 1, so the last row block holds a single output row;
+// its products run on the VALU (each lane's four reduction rows of a block
+// times that factor row, summed over the four lane groups at the end)
+// instead of a 16 x 16 MFMA block that is one sixteenth used.
 
-template <typename TI, typename TO, typename CT, bool UNIT_L, int RB, int VW>
+template <typename TI, typename TO, typename CT, bool UNIT_L, int RB, int VW, bool ROW1 = false>
 __global__ __launch_bounds__(64 * kResWaves) void ttm_resident_kernel(const TI* __restrict__ Y, int J, uint32_t L,
                                                                       uint32_t cols, const double* __restrict__ M,
                                                                       int64_t msk, int64_t msj, int K,
@@ -368,18 +372,26 @@ __global__ __launch_bounds__(64 * kResWaves) void ttm_resident_kernel(const TI* 
       const uint32_t r = cc / L, l = cc - r * L;
       cbase = (int64_t)l + JL * r;
     }
+    constexpr int RBM = ROW1 ? RB - 1 : RB;  // row blocks on the MFMA
     typename A::type acc[RB];
 #pragma unroll
     for (int b = 0; b < RB; ++b) acc[b] = typename A::type{0, 0, 0, 0};
+    CT racc = (CT)0;  // ROW1: this lane's part of Z[16 (RB - 1)][c]
     // reduction row of (block jb, step s) for this lane: 16 jb + 4 q + s
     Raw4<TI> raw[kDepth];
     auto mma = [&](int jb, const CT (&y)[4]) {
 #pragma unroll
-      for (int b = 0; b < RB; ++b) {
+      for (int b = 0; b < RBM; ++b) {
         CT a4[4];
         ML::read4(&sM[(16 * b + i) * ldm + 16 * jb + 4 * q], a4);
 #pragma unroll
         for (int s2 = 0; s2 < 4; ++s2) acc[b] = A::mfma(a4[s2], y[s2], acc[b]);
+      }
+      if constexpr (ROW1) {
+        CT a4[4];
+        ML::read4(&sM[(16 * (RB - 1)) * ldm + 16 * jb + 4 * q], a4);
+#pragma unroll
+        for (int s2 = 0; s2 < 4; ++s2) racc = fma(a4[s2], y[s2], racc);
       }
     };
     if (nj < kDepth) {
@@ -429,6 +441,11 @@ __global__ __launch_bounds__(64 * kResWaves) void ttm_resident_kernel(const TI* 
         }
       }
     }
+    if constexpr (ROW1) {
+      // the four lane groups of column i, in a fixed order
+      const CT x = racc + __shfl_xor(racc, 16, 64);
+      racc = x + __shfl_xor(x, 32, 64);
+    }
     if (cok) {
       int64_t zb, kstride;
       if constexpr (UNIT_L) {
@@ -441,12 +458,14 @@ __global__ __launch_bounds__(64 * kResWaves) void ttm_resident_kernel(const TI* 
         kstride = L;
       }
 #pragma unroll
-      for (int b = 0; b < RB; ++b)
+      for (int b = 0; b < RBM; ++b)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int k = 16 * b + A::row(q, v);
           if (k < K) store_as(&Z[zb + kstride * k], (double)acc[b][v]);
         }
+      if constexpr (ROW1)
+        if (q == 0) store_as(&Z[zb + kstride * (16 * (RB - 1))], (double)racc);
     }
   }
 }
@@ -462,7 +481,33 @@ hipError_t launch_ttm_ct(const TI* Y, int J, uint64_t L, uint64_t cols, const do
 #define TR_LAUNCH(U, RBV, V)                                                                                   \
   hipLaunchKernelGGL((ttm_resident_kernel<TI, TO, CT, U, RBV, V>), dim3(grid), dim3(64 * kResWaves), lds,       \
                      stream, Y, J, (uint32_t)L, (uint32_t)cols, M, msk, msj, K, Z, nct)
+#define TR_LAUNCH1(U, RBV, V)                                                                                  \
+  hipLaunchKernelGGL((ttm_resident_kernel<TI, TO, CT, U, RBV, V, true>), dim3(grid), dim3(64 * kResWaves),     \
+                     lds, stream, Y, J, (uint32_t)L, (uint32_t)cols, M, msk, msj, K, Z, nct)
     const int vw = y_vector_width(Y, J, L);
+    if constexpr (std::is_same<CT, double>::value) {
+      if (K % 16 == 1 && K > 16) {
+      // FP64 with a single row in the last row block (K = 17, 33, 49)
+      if (vw == 4) {
+        if (rbr == 2) TR_LAUNCH1(true, 2, 4);
+        else if (rbr == 3) TR_LAUNCH1(true, 3, 4);
+        else TR_LAUNCH1(true, 4, 4);
+      } else if (vw == 2) {
+        if (rbr == 2) TR_LAUNCH1(true, 2, 2);
+        else if (rbr == 3) TR_LAUNCH1(true, 3, 2);
+        else TR_LAUNCH1(true, 4, 2);
+      } else if (L == 1) {
+        if (rbr == 2) TR_LAUNCH1(true, 2, 1);
+        else if (rbr == 3) TR_LAUNCH1(true, 3, 1);
+        else TR_LAUNCH1(true, 4, 1);
+      } else {
+        if (rbr == 2) TR_LAUNCH1(false, 2, 1);
+        else if (rbr == 3) TR_LAUNCH1(false, 3, 1);
+        else TR_LAUNCH1(false, 4, 1);
+      }
+      return hipGetLastError();
+      }
+    }
     if (vw == 4) {
       if (rbr == 1) TR_LAUNCH(true, 1, 4);
       else if (rbr == 2) TR_LAUNCH(true, 2, 4);
@@ -484,6 +529,7 @@ hipError_t launch_ttm_ct(const TI* Y, int J, uint64_t L, uint64_t cols, const do
       else if (rbr == 3) TR_LAUNCH(false, 3, 1);
       else TR_LAUNCH(false, 4, 1);
     }
+#undef TR_LAUNCH1
 #undef TR_LAUNCH
     return hipGetLastError();
   }

@@ -210,6 +210,13 @@ TTM_CASES = [
     # odd L or J with double input: 4-byte loads of Y
     ([9, 45, 33], 1, 150),
     ([99, 260], 0, 129),
+    # FP64 resident products whose last row block holds one row (K = 17, 33,
+    # 49; that row on the VALU): L = 1 with single, paired and 4-row loads,
+    # and L > 1
+    ([33, 40, 20], 0, 33),
+    ([50, 30], 0, 49),
+    ([64, 30], 0, 17),
+    ([40, 33, 20], 1, 33),
 ]
 
 
