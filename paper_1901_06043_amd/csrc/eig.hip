@@ -1171,15 +1171,16 @@ __global__ __launch_bounds__(kEigThreads) void eig_orth_kernel(double* __restric
   orth_body(Zt, J, lam, Rp, scal, sh, (int)std::min<int64_t>((int64_t)J * J, kOrthCap), blocked);
 }
 
-// Right-looking form for single matrices of kRlMinJ <= J <= kRlMaxJ: two
-// sweeps of block modified Gram-Schmidt, each one launch per block
-// b = -1, 0, 1, ...: once block b is final, every later block c that holds
+// Right-looking form for single matrices of kRlMinJ <= J <= kRlMaxJ: a sweep
+// of block modified Gram-Schmidt, one launch per block b = -1, 0, 1, ...,
+// then a second sweep in one launch (eig_orth_rl2_kernel).  In the first,
+// once block b is final, every later block c that holds
 // vectors whose window reaches into b is projected against b by a workgroup
 // of its own (coefficients C = Z_b Z_c^T masked to the windows, then
 // Z_c -= C^T Z_b, FP64 MFMA products, Z_c in LDS, Z_b read from global
 // memory), and the workgroup of block b + 1 then completes that block within
 // itself.  The projections of all later blocks run side by side on many CUs
-// instead of one after another on one.  One sweep leaves a loss of
+// instead of one after another on one.  This sweep leaves a loss of
 // orthogonality of the order of u times the condition of the iterates
 // (rounding in a later block's projection is not removed by an earlier one);
 // the second sweep, over nearly orthonormal vectors, brings it to rounding,
@@ -1200,6 +1201,8 @@ constexpr int kRlMaxJ = 1024;
 __host__ __device__ constexpr int64_t orth_rl_doubles(int64_t J) {
   return (int64_t)kOB * ((J + 15) & ~int64_t(15)) + kRlWaves * 256 + 2 * 256 + 16 + 16 + 16;
 }
+// the single-launch second sweep: a 64 x 16 coefficient block instead of 16 x 16
+__host__ __device__ constexpr int64_t orth_rl2_doubles(int64_t J) { return orth_rl_doubles(J) + 1024 - 256; }
 
 // Fixed-order sum over a workgroup of kRlThreads threads; all threads get it.
 __device__ __forceinline__ double block_sum_rl(double v, double* sred) {
@@ -1212,6 +1215,174 @@ __device__ __forceinline__ double block_sum_rl(double v, double* sred) {
   for (int w = 0; w < kRlWaves; ++w) s += sred[w];
   __syncthreads();
   return s;
+}
+
+// Window starts of block c's vectors (window of vector i: the j <= i with
+// lam_j - lam_i < otol; lam is descending, so the j < i outside the window
+// form a prefix and the start is their count; each thread tests two j, as
+// R <= J <= 1024), the smallest start (wmin) and the first block row whose
+// window reaches a block vector (t0; kOB if none).
+__device__ __forceinline__ void rl_block_windows(const double* __restrict__ lam, int R, int c0, int nb, double otol,
+                                                 int* sjlo, int* scnt, int& wmin, int& t0) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  double lj[2];
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int j = tid + u * kRlThreads;
+    lj[u] = (j < R) ? lam[j] : 0.0;
+  }
+#pragma unroll
+  for (int t = 0; t < kOB; ++t) {
+    const int i = c0 + t;
+    const double li = lam[min(i, R - 1)];
+    int cnt = 0;
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int j = tid + u * kRlThreads;
+      cnt += __popcll(__ballot(j < i && lj[u] - li >= otol));
+    }
+    if (lane == 0) scnt[wave * kOB + t] = cnt;
+  }
+  __syncthreads();
+  if (tid < kOB) {
+    int cnt = 0;
+#pragma unroll
+    for (int w = 0; w < kRlWaves; ++w) cnt += scnt[w * kOB + tid];
+    sjlo[tid] = (c0 + tid < R) ? cnt : c0 + tid;
+  }
+  __syncthreads();
+  wmin = c0 + kOB;
+  t0 = kOB;
+  for (int t = 0; t < nb; ++t) {
+    const int st = sjlo[t];
+    wmin = min(wmin, st);
+    if (st < c0 + t) t0 = min(t0, max(st, c0) - c0);
+  }
+}
+
+// Orthonormalisation of a block of kOB vectors within itself, held in LDS
+// (Zc, rows of Jp), from its row t0 on (shifted Cholesky QR3, or the
+// vector-by-vector classical Gram-Schmidt within the windows if a pivot
+// fails).  All kRlThreads threads call it.
+__device__ __forceinline__ void rl_block_finish(double* Zc, int Jp, int J, int c0, int nb, int t0, const int* sjlo,
+                                                double* sP, double* sL, double* sRd, double* shs, int* sflag) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int il = lane & 15, q = lane >> 4;
+  const int nst = Jp / 4;
+  const int s0 = nst * wave / kRlWaves, s1 = nst * (wave + 1) / kRlWaves;
+  bool done = false;
+  for (int pass = 0; pass < 2; ++pass) {
+    {
+      // G = Z_c Z_c^T: lane (il, q) supplies Z_c[il][4 st + q] as both operands
+      d4 acc = {0.0, 0.0, 0.0, 0.0};
+      for (int st = s0; st < s1; ++st) {
+        const double v = Zc[il * Jp + 4 * st + q];
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(v, v, acc, 0, 0, 0);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) sP[wave * 256 + (q + 4 * v) * 16 + il] = acc[v];
+    }
+    __syncthreads();
+    if (wave == 0) {
+      // Cholesky of the rows t0..nb-1 (the others: identity), lane t & 15
+      // holding row t; right-looking, column k by column k
+      const int t = lane & 15;
+      const bool act = t >= t0 && t < nb;
+      double a[16];
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        const int x = t * 16 + j;
+        double g = 0.0;
+#pragma unroll
+        for (int w = 0; w < kRlWaves; ++w) g += sP[w * 256 + x];
+        const bool jact = j >= t0 && j < nb;
+        a[j] = act ? (jact ? g : 0.0) : (j == t ? 1.0 : 0.0);
+      }
+      double gtt = 1.0;
+#pragma unroll
+      for (int j = 0; j < 16; ++j)
+        if (j == t) gtt = a[j];
+      double ratio = 1.0;
+      bool okp = true;
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        const double dk = __shfl(a[k], k, 64);  // lane k's updated diagonal
+        okp = okp && dk > 0.0;
+        const double lkk = dk > 0.0 ? sqrt(dk) : 1.0;
+        if (t == k) ratio = dk / gtt;
+        const double lik = (t == k) ? lkk : ((t > k) ? a[k] / lkk : 0.0);
+        a[k] = lik;
+#pragma unroll
+        for (int j = k + 1; j < 16; ++j) {
+          const double ljk = __shfl(lik, j, 64);
+          if (t >= j) a[j] -= lik * ljk;
+        }
+      }
+      const double rmin = act ? ratio : 1.0;
+      double m = rmin;
+#pragma unroll
+      for (int off = 8; off > 0; off >>= 1) m = fmin(m, __shfl_xor(m, off, 16));
+      if (lane < 16) {
+        double ltt = 1.0;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+          sL[t * 16 + j] = (j < t) ? a[j] : 0.0;
+          if (j == t) ltt = a[j];
+        }
+        sRd[t] = 1.0 / ltt;
+      }
+      if (lane == 0) sflag[0] = (okp && m >= 1e-8) ? 1 : 0;
+    }
+    __syncthreads();
+    if (!sflag[0]) break;  // uniform
+    // Z_c <- L^{-1} Z_c, column by column
+    for (int r = tid; r < J; r += kRlThreads) {
+      double z[16];
+#pragma unroll
+      for (int t = 0; t < 16; ++t) z[t] = Zc[t * Jp + r];
+#pragma unroll
+      for (int t = 0; t < 16; ++t) {
+        double v = z[t];
+#pragma unroll
+        for (int u = 0; u < t; ++u) v -= sL[t * 16 + u] * z[u];
+        z[t] = v * sRd[t];
+      }
+#pragma unroll
+      for (int t = 0; t < 16; ++t) Zc[t * Jp + r] = z[t];
+    }
+    __syncthreads();
+    done = pass == 1;
+  }
+  if (!done) {
+    // classical Gram-Schmidt, twice, vector by vector within the windows
+    for (int t = t0; t < nb; ++t) {
+      const int i = c0 + t;
+      if (sjlo[t] >= i) continue;  // uniform: no neighbour within otol
+      double* zt = Zc + t * Jp;
+      const int u0 = max(sjlo[t], c0) - c0;
+      for (int pass = 0; pass < 2 && u0 < t; ++pass) {
+        for (int u = u0 + wave; u < t; u += kRlWaves) {
+          double h = 0.0;
+          for (int r = lane; r < J; r += 64) h += Zc[u * Jp + r] * zt[r];
+          h = wave_sum_fast(h);
+          if (lane == 0) shs[u] = h;
+        }
+        __syncthreads();
+        for (int r = tid; r < J; r += kRlThreads) {
+          double v = zt[r];
+          for (int u = u0; u < t; ++u) v -= shs[u] * Zc[u * Jp + r];
+          zt[r] = v;
+        }
+        __syncthreads();
+      }
+      double nn = 0.0;
+      for (int r = tid; r < J; r += kRlThreads) nn += zt[r] * zt[r];
+      nn = block_sum_rl(nn, sP);
+      const double rn = 1.0 / sqrt(nn);
+      for (int r = tid; r < J; r += kRlThreads) zt[r] *= rn;
+      __syncthreads();
+    }
+  }
 }
 
 __global__ __launch_bounds__(kRlThreads) void eig_orth_rl_kernel(double* __restrict__ Z, int J,
@@ -1246,42 +1417,8 @@ __global__ __launch_bounds__(kRlThreads) void eig_orth_rl_kernel(double* __restr
     const int t = x / Jp, r = x - t * Jp;
     zr[u] = (x < kOB * Jp && t < nb && r < J) ? Z[(int64_t)(c0 + t) * J + r] : 0.0;
   }
-  // window start of vector i: smallest j <= i with lam_j - lam_i < otol.  lam
-  // is descending, so the j < i with lam_j - lam_i >= otol form a prefix and
-  // the start is their count; each thread tests two j (R <= J <= 1024).
-  double lj[2];
-#pragma unroll
-  for (int u = 0; u < 2; ++u) {
-    const int j = tid + u * kRlThreads;
-    lj[u] = (j < R) ? lam[j] : 0.0;
-  }
-  int* scnt = reinterpret_cast<int*>(sP);  // [kRlWaves][16]
-#pragma unroll
-  for (int t = 0; t < kOB; ++t) {
-    const int i = c0 + t;
-    const double li = lam[min(i, R - 1)];
-    int cnt = 0;
-#pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      const int j = tid + u * kRlThreads;
-      cnt += __popcll(__ballot(j < i && lj[u] - li >= otol));
-    }
-    if (lane == 0) scnt[wave * kOB + t] = cnt;
-  }
-  __syncthreads();
-  if (tid < kOB) {
-    int cnt = 0;
-#pragma unroll
-    for (int w = 0; w < kRlWaves; ++w) cnt += scnt[w * kOB + tid];
-    sjlo[tid] = (c0 + tid < R) ? cnt : c0 + tid;
-  }
-  __syncthreads();
-  int wmin = c0 + kOB, t0 = kOB;
-  for (int t = 0; t < nb; ++t) {
-    const int st = sjlo[t];
-    wmin = min(wmin, st);
-    if (st < c0 + t) t0 = min(t0, max(st, c0) - c0);
-  }
+  int wmin, t0;
+  rl_block_windows(lam, R, c0, nb, otol, sjlo, reinterpret_cast<int*>(sP), wmin, t0);
   const int b0 = kOB * b;
   const bool proj = b >= 0 && wmin < b0 + kOB;
   const bool fin = (c == b + 1) && t0 < nb;
@@ -1358,124 +1495,137 @@ __global__ __launch_bounds__(kRlThreads) void eig_orth_rl_kernel(double* __restr
     }
     __syncthreads();
   }
-  if (fin) {
-    bool done = false;
-    for (int pass = 0; pass < 2; ++pass) {
-      {
-        // G = Z_c Z_c^T: lane (il, q) supplies Z_c[il][4 st + q] as both operands
-        d4 acc = {0.0, 0.0, 0.0, 0.0};
-        for (int st = s0; st < s1; ++st) {
-          const double v = Zc[il * Jp + 4 * st + q];
-          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(v, v, acc, 0, 0, 0);
-        }
-#pragma unroll
-        for (int v = 0; v < 4; ++v) sP[wave * 256 + (q + 4 * v) * 16 + il] = acc[v];
-      }
-      __syncthreads();
-      if (wave == 0) {
-        // Cholesky of the rows t0..nb-1 (the others: identity), lane t & 15
-        // holding row t; right-looking, column k by column k
-        const int t = lane & 15;
-        const bool act = t >= t0 && t < nb;
-        double a[16];
-#pragma unroll
-        for (int j = 0; j < 16; ++j) {
-          const int x = t * 16 + j;
-          double g = 0.0;
-#pragma unroll
-          for (int w = 0; w < kRlWaves; ++w) g += sP[w * 256 + x];
-          const bool jact = j >= t0 && j < nb;
-          a[j] = act ? (jact ? g : 0.0) : (j == t ? 1.0 : 0.0);
-        }
-        double gtt = 1.0;
-#pragma unroll
-        for (int j = 0; j < 16; ++j)
-          if (j == t) gtt = a[j];
-        double ratio = 1.0;
-        bool okp = true;
-#pragma unroll
-        for (int k = 0; k < 16; ++k) {
-          const double dk = __shfl(a[k], k, 64);  // lane k's updated diagonal
-          okp = okp && dk > 0.0;
-          const double lkk = dk > 0.0 ? sqrt(dk) : 1.0;
-          if (t == k) ratio = dk / gtt;
-          const double lik = (t == k) ? lkk : ((t > k) ? a[k] / lkk : 0.0);
-          a[k] = lik;
-#pragma unroll
-          for (int j = k + 1; j < 16; ++j) {
-            const double ljk = __shfl(lik, j, 64);
-            if (t >= j) a[j] -= lik * ljk;
-          }
-        }
-        const double rmin = act ? ratio : 1.0;
-        double m = rmin;
-#pragma unroll
-        for (int off = 8; off > 0; off >>= 1) m = fmin(m, __shfl_xor(m, off, 16));
-        if (lane < 16) {
-          double ltt = 1.0;
-#pragma unroll
-          for (int j = 0; j < 16; ++j) {
-            sL[t * 16 + j] = (j < t) ? a[j] : 0.0;
-            if (j == t) ltt = a[j];
-          }
-          sRd[t] = 1.0 / ltt;
-        }
-        if (lane == 0) sflag[0] = (okp && m >= 1e-8) ? 1 : 0;
-      }
-      __syncthreads();
-      if (!sflag[0]) break;  // uniform
-      // Z_c <- L^{-1} Z_c, column by column
-      for (int r = tid; r < J; r += kRlThreads) {
-        double z[16];
-#pragma unroll
-        for (int t = 0; t < 16; ++t) z[t] = Zc[t * Jp + r];
-#pragma unroll
-        for (int t = 0; t < 16; ++t) {
-          double v = z[t];
-#pragma unroll
-          for (int u = 0; u < t; ++u) v -= sL[t * 16 + u] * z[u];
-          z[t] = v * sRd[t];
-        }
-#pragma unroll
-        for (int t = 0; t < 16; ++t) Zc[t * Jp + r] = z[t];
-      }
-      __syncthreads();
-      done = pass == 1;
-    }
-    if (!done) {
-      // classical Gram-Schmidt, twice, vector by vector within the windows
-      for (int t = t0; t < nb; ++t) {
-        const int i = c0 + t;
-        if (sjlo[t] >= i) continue;  // uniform: no neighbour within otol
-        double* zt = Zc + t * Jp;
-        const int u0 = max(sjlo[t], c0) - c0;
-        for (int pass = 0; pass < 2 && u0 < t; ++pass) {
-          for (int u = u0 + wave; u < t; u += kRlWaves) {
-            double h = 0.0;
-            for (int r = lane; r < J; r += 64) h += Zc[u * Jp + r] * zt[r];
-            h = wave_sum_fast(h);
-            if (lane == 0) shs[u] = h;
-          }
-          __syncthreads();
-          for (int r = tid; r < J; r += kRlThreads) {
-            double v = zt[r];
-            for (int u = u0; u < t; ++u) v -= shs[u] * Zc[u * Jp + r];
-            zt[r] = v;
-          }
-          __syncthreads();
-        }
-        double nn = 0.0;
-        for (int r = tid; r < J; r += kRlThreads) nn += zt[r] * zt[r];
-        nn = block_sum_rl(nn, sP);
-        const double rn = 1.0 / sqrt(nn);
-        for (int r = tid; r < J; r += kRlThreads) zt[r] *= rn;
-        __syncthreads();
-      }
-    }
-  }
+  if (fin) rl_block_finish(Zc, Jp, J, c0, nb, t0, sjlo, sP, sL, sRd, shs, sflag);
   for (int x = tid; x < nb * Jp; x += kRlThreads) {
     const int t = x / Jp, r = x - t * Jp;
     if (r < J) Z[(int64_t)(c0 + t) * J + r] = Zc[x];
+  }
+}
+
+// The second sweep in one launch: after the first sweep the vectors are
+// orthonormal up to a small error e, so each block can be projected against
+// all preceding vectors of its windows at once, reading them as the first
+// sweep left them (Zs) and writing its result elsewhere (Zd): the error left
+// is of order e^2 + u.  Workgroup c takes block c: projections against the
+// preceding vectors in chunks of 64 (coefficients C = Z_chunk Z_c^T over two
+// halves of the rows, masked to the windows, then Z_c -= C^T Z_chunk, FP64
+// MFMA), then the block finish.  Every block is written to Zd (unchanged
+// ones too), so that Zd holds all R vectors; when R * J fits the LDS copy
+// form of eig_orth_kernel, which left its result in Zs, the blocks are only
+// copied.
+__global__ __launch_bounds__(kRlThreads) void eig_orth_rl2_kernel(const double* __restrict__ Zs,
+                                                                  double* __restrict__ Zd, int J,
+                                                                  const double* __restrict__ lam,
+                                                                  const int64_t* __restrict__ Rp,
+                                                                  const double* __restrict__ scal, int cap) {
+  extern __shared__ double sh[];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int il = lane & 15, q = lane >> 4;
+  const int R = (int)*Rp;
+  const int c0 = kOB * (int)blockIdx.x;
+  if (c0 >= R) return;
+  const int nb = min(kOB, R - c0);
+  const int Jp = (J + 15) & ~15;
+  double* Zc = sh;                                       // [kOB][Jp], zero-padded
+  double* sP = Zc + kOB * Jp;                            // [2][64][16] partial coefficients (also the finish's)
+  double* sC = sP + kRlWaves * 256;                      // [64][16] coefficients of a chunk
+  double* sL = sC + 1024;                                // [16][16]
+  double* sRd = sL + 256;                                // [16]
+  double* shs = sRd + 16;                                // [16]
+  int* sjlo = reinterpret_cast<int*>(shs + 16);          // [16]
+  int* sflag = sjlo + 16;                                // [1]
+  constexpr int kZcRegs = kOB * kRlMaxJ / kRlThreads;
+  double zr[kZcRegs];
+#pragma unroll
+  for (int u = 0; u < kZcRegs; ++u) {
+    const int x = tid + u * kRlThreads;
+    const int t = x / Jp, r = x - t * Jp;
+    zr[u] = (x < kOB * Jp && t < nb && r < J) ? Zs[(int64_t)(c0 + t) * J + r] : 0.0;
+  }
+  auto store_regs = [&]() {
+#pragma unroll
+    for (int u = 0; u < kZcRegs; ++u) {
+      const int x = tid + u * kRlThreads;
+      const int t = x / Jp, r = x - t * Jp;
+      if (x < kOB * Jp && t < nb && r < J) Zd[(int64_t)(c0 + t) * J + r] = zr[u];
+    }
+  };
+  if ((int64_t)R * J <= cap) {  // uniform: the copy form's result, as it is
+    store_regs();
+    return;
+  }
+  const double otol = 1e-2 * scal[0];
+  int wmin, t0;
+  rl_block_windows(lam, R, c0, nb, otol, sjlo, reinterpret_cast<int*>(sP), wmin, t0);
+  if (wmin >= c0 + kOB) {  // uniform: no vector of the block has a window
+    store_regs();
+    return;
+  }
+#pragma unroll
+  for (int u = 0; u < kZcRegs; ++u) {
+    const int x = tid + u * kRlThreads;
+    if (x < kOB * Jp) Zc[x] = zr[u];
+  }
+  __syncthreads();
+  const int nst = Jp / 4;
+  for (int jc = wmin; jc < c0; jc += 64) {
+    const int nc = min(64, c0 - jc);
+    {
+      // C[jj][t] = sum_r Z[jc + jj][r] Z_c[t][r]: wave -> (16-row tile a of
+      // the chunk, half ks of the reduction steps)
+      const int a = wave & 3, ks = wave >> 2;
+      const int s0 = nst * ks / 2, s1 = nst * (ks + 1) / 2;
+      const int jj = 16 * a + il;
+      const double* zr0 = Zs + (int64_t)(jc + min(jj, nc - 1)) * J;
+      const bool rowok = jj < nc;
+      d4 acc = {0.0, 0.0, 0.0, 0.0};
+      for (int g0 = s0; g0 < s1; g0 += 16) {
+        double x[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) x[u] = zr0[min(4 * (g0 + u) + q, J - 1)];  // in bounds; masked below
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+          const int st = g0 + u;
+          const double av = (rowok && st < s1) ? x[u] : 0.0;
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, Zc[il * Jp + min(4 * st + q, Jp - 1)], acc, 0, 0, 0);
+        }
+      }
+      // D[(l >> 4) + 4v][l & 15]: chunk row 16 a + q + 4 v, block vector il
+#pragma unroll
+      for (int v = 0; v < 4; ++v) sP[(ks * 64 + 16 * a + q + 4 * v) * 16 + il] = acc[v];
+    }
+    __syncthreads();
+    for (int e = tid; e < 1024; e += kRlThreads) {
+      const int jj = e >> 4, t = e & 15;
+      const double cv = sP[e] + sP[1024 + e];
+      sC[e] = (jj < nc && t < nb && jc + jj >= sjlo[t]) ? cv : 0.0;
+    }
+    __syncthreads();
+    // Z_c[t][r] -= sum_jj C[jj][t] Z[jc + jj][r]: wave -> 16-column tiles,
+    // 16 steps of 4 chunk rows each
+    for (int T = wave; T < Jp / 16; T += kRlWaves) {
+      const int r = 16 * T + il;
+      d4 acc;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[v] = Zc[(q + 4 * v) * Jp + r];
+      double x[16];
+#pragma unroll
+      for (int st = 0; st < 16; ++st) x[st] = Zs[(int64_t)(jc + min(4 * st + q, nc - 1)) * J + min(r, J - 1)];
+#pragma unroll
+      for (int st = 0; st < 16; ++st) {
+        const int jj = 4 * st + q;
+        const double bv = (jj < nc && r < J) ? x[st] : 0.0;
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(-sC[jj * 16 + il], bv, acc, 0, 0, 0);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) Zc[(q + 4 * v) * Jp + r] = acc[v];
+    }
+    __syncthreads();
+  }
+  if (t0 < nb) rl_block_finish(Zc, Jp, J, c0, nb, t0, sjlo, sP, sL, sRd, shs, sflag);
+  for (int x = tid; x < nb * Jp; x += kRlThreads) {
+    const int t = x / Jp, r = x - t * Jp;
+    if (r < J) Zd[(int64_t)(c0 + t) * J + r] = Zc[x];
   }
 }
 
@@ -1497,10 +1647,12 @@ __host__ __device__ constexpr size_t back_lds_bytes(int Q, int cap) {
   return sizeof(double) * (2 * (size_t)(cap + 64) + 2 * (size_t)back_rows_max(Q));
 }
 
+// Zt and U may be the same buffer: each wave reads its vector before it
+// writes it, and no other wave touches it.
 template <int Q>
 __device__ __forceinline__ void back_body(const double* __restrict__ H, const double* __restrict__ tau, int J,
-                                          const double* __restrict__ Zt, const int64_t* __restrict__ Rp,
-                                          double* __restrict__ U, int bx, double* sh, int cap) {
+                                          const double* Zt, const int64_t* __restrict__ Rp, double* U, int bx,
+                                          double* sh, int cap) {
   constexpr int UQ = (Q + 3) / 4;          // row entries per thread (256 threads)
   constexpr int KCM = back_rows_max(Q);    // rows per chunk, bounded by the register staging
   const int kStride = cap + 64;  // buffer stride (reads of the last row may run 63 past kc * J)
@@ -1625,16 +1777,18 @@ __device__ __forceinline__ void back_body(const double* __restrict__ H, const do
 
 template <int Q>
 __global__ __launch_bounds__(256) void eig_back_kernel(const double* __restrict__ H, const double* __restrict__ tau,
-                                                       int J, const double* __restrict__ Zt,
-                                                       const int64_t* __restrict__ Rp, double* __restrict__ U) {
+                                                       int J, const double* Zt, const int64_t* __restrict__ Rp,
+                                                       double* U) {
   extern __shared__ double sh[];
   back_body<Q>(H, tau, J, Zt, Rp, U, blockIdx.x, sh, kBackCap);
 }
 
+// Z: the tridiagonal eigenvectors (w.Zt, or U itself after the single-launch
+// second re-orthogonalisation sweep)
 template <int Q>
-void launch_back(const EigWork& w, int J, const int64_t* R, double* U, hipStream_t s) {
+void launch_back(const EigWork& w, int J, const double* Z, const int64_t* R, double* U, hipStream_t s) {
   hipLaunchKernelGGL((eig_back_kernel<Q>), dim3(ceil_div(J, 4)), dim3(256), back_lds_bytes(Q, kBackCap), s, w.A,
-                     w.tau, J, w.Zt, R, U);
+                     w.tau, J, Z, R, U);
 }
 
 // Batched form (throughput over many small matrices, where LDS per vector
@@ -1985,20 +2139,24 @@ hipError_t launch_eig_vectors(int J, const EigWork& w, const double* lam, const 
     const int cap = (int)std::min<int64_t>((int64_t)J * J, kOrthCap);
     const int nblk = (int)ceil_div(J, kOB);
     const size_t shr = sizeof(double) * (size_t)orth_rl_doubles(J);
-    for (int sweep = 0; sweep < 2; ++sweep)
-      for (int b = -1; b + 1 < nblk; ++b) {
-        hipLaunchKernelGGL(eig_orth_rl_kernel, dim3(b < 0 ? 1 : nblk - b - 1), dim3(kRlThreads), shr, stream,
-                           w.Zt, J, lam, R, w.scal, b, cap);
-        LAUNCH_OK();
-      }
+    for (int b = -1; b + 1 < nblk; ++b) {
+      hipLaunchKernelGGL(eig_orth_rl_kernel, dim3(b < 0 ? 1 : nblk - b - 1), dim3(kRlThreads), shr, stream, w.Zt,
+                         J, lam, R, w.scal, b, cap);
+      LAUNCH_OK();
+    }
+    // second sweep into U, which the back-transformation then updates in place
+    hipLaunchKernelGGL(eig_orth_rl2_kernel, dim3(nblk), dim3(kRlThreads), sizeof(double) * (size_t)orth_rl2_doubles(J),
+                       stream, w.Zt, U, J, lam, R, w.scal, cap);
+    LAUNCH_OK();
   }
+  const double* Zv = rl ? U : w.Zt;
   const int q = (int)ceil_div(J, 64);
-  if (q <= 1) launch_back<1>(w, J, R, U, stream);
-  else if (q <= 2) launch_back<2>(w, J, R, U, stream);
-  else if (q <= 4) launch_back<4>(w, J, R, U, stream);
-  else if (q <= 8) launch_back<8>(w, J, R, U, stream);
-  else if (q <= 11) launch_back<11>(w, J, R, U, stream);
-  else if (q <= 16) launch_back<16>(w, J, R, U, stream);
+  if (q <= 1) launch_back<1>(w, J, Zv, R, U, stream);
+  else if (q <= 2) launch_back<2>(w, J, Zv, R, U, stream);
+  else if (q <= 4) launch_back<4>(w, J, Zv, R, U, stream);
+  else if (q <= 8) launch_back<8>(w, J, Zv, R, U, stream);
+  else if (q <= 11) launch_back<11>(w, J, Zv, R, U, stream);
+  else if (q <= 16) launch_back<16>(w, J, Zv, R, U, stream);
   else if (q <= 24)
     hipLaunchKernelGGL((eig_back_direct_kernel<24>), dim3(ceil_div(J, 4)), dim3(256), 0, stream, w.A, w.tau, J,
                        w.Zt, R, U);
