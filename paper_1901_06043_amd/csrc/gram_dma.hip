@@ -345,11 +345,12 @@ __global__ __launch_bounds__(kDNT, PREC == 0 ? 2 : 1) void gram_dma_kernel(DmaPa
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int i = lane & 15, q = lane >> 4;
-  int a0, b0;
+  int a0, b0, bs;
   unsigned mask;
-  dma::wave_task(wave, diag, r0a, r0b, g.J, a0, b0, mask);
+  dma::wave_task(wave, diag, r0a, r0b, g.J, a0, b0, bs, mask);
   a0 = __builtin_amdgcn_readfirstlane(a0);
   b0 = __builtin_amdgcn_readfirstlane(b0);
+  bs = __builtin_amdgcn_readfirstlane(bs);
   mask = __builtin_amdgcn_readfirstlane(mask);
   const int pb = diag ? 0 : I::TB;  // B operand's tile image
 
@@ -358,7 +359,7 @@ __global__ __launch_bounds__(kDNT, PREC == 0 ? 2 : 1) void gram_dma_kernel(DmaPa
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
     oa[t] = I::at(16 * (a0 + t) + i, I::col(0, q));
-    ob[t] = pb + I::at(16 * (b0 + t) + i, I::col(0, q));
+    ob[t] = pb + I::at(16 * (b0 + bs * t) + i, I::col(0, q));
   }
   if constexpr (LAY == 1) d = I::at(i, I::col(I::E, q)) - I::at(i, I::col(0, q));
 
@@ -377,6 +378,7 @@ __global__ __launch_bounds__(kDNT, PREC == 0 ? 2 : 1) void gram_dma_kernel(DmaPa
   if (mask == dma::kMaskFull) DMA_LOOP(dma::kMaskFull);
   else if (mask == dma::kMaskUpper) DMA_LOOP(dma::kMaskUpper);
   else if (mask == dma::kMaskHalf) DMA_LOOP(dma::kMaskHalf);
+  else if (mask == dma::kMaskCol1) DMA_LOOP(dma::kMaskCol1);
   else if (mask == 0u) DMA_LOOP(0u);
   else DMA_LOOP(kGeneric);
 #undef DMA_LOOP
@@ -398,7 +400,7 @@ __global__ __launch_bounds__(kDNT, PREC == 0 ? 2 : 1) void gram_dma_kernel(DmaPa
 #pragma unroll
     for (int y = 0; y < 4; ++y) {
       if ((mask >> (4 * x + y)) & 1u) {
-        const int bi = a0 + x, bj = b0 + y;
+        const int bi = a0 + x, bj = b0 + bs * y;
         const int qb = diag ? dma::tri_index(bi, bj) : bi * 8 + bj;
 #pragma unroll
         for (int v = 0; v < 4; ++v) P[(int64_t)qb * 256 + (PREC == 0 ? q + 4 * v : 4 * q + v) * 16 + i] = acc[x][y][v];

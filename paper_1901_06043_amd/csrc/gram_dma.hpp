@@ -81,31 +81,37 @@ __host__ __device__ inline int tri_index(int bi, int bj) { return bi * 8 - bi * 
 constexpr unsigned kMaskFull = 0xFFFFu;
 constexpr unsigned kMaskUpper = 0x8CEFu;  // x <= y
 constexpr unsigned kMaskHalf = 0x3333u;   // y < 2
+constexpr unsigned kMaskCol1 = 0x1111u;   // y = 0
 
 // The part of a tile pair's 8 x 8 blocks of 16 x 16 that wave w (of 4)
-// computes: blocks (a0 + x, b0 + y) of the pair's A and B tiles for the bits
-// 4 x + y set in mask.  Off-diagonal pairs: wave w takes the 4 x 4 blocks at
-// (4 (w >> 1), 4 (w & 1)).  Diagonal pairs need the upper triangle (36
-// blocks): waves 0 and 2 take the upper 10 blocks of the diagonal 4 x 4
-// grids, waves 1 and 3 the two 4 x 2 halves of the off-diagonal one.  Blocks
-// whose rows lie at or beyond J are dropped.
-__host__ __device__ inline void wave_task(int w, bool diag, int ra, int rb, int J, int& a0, int& b0,
+// computes: blocks (a0 + x, b0 + bs y) of the pair's A and B tiles for the
+// bits 4 x + y set in mask.  Off-diagonal pairs: wave w takes the A blocks
+// 4 (w >> 1) .. + 3 and every other B block from w & 1 (bs = 2), so that a
+// ragged last B tile (J = 672: two blocks) gives each wave the same share
+// instead of leaving two waves idle.  Diagonal pairs need the upper triangle
+// (36 blocks, bs = 1): waves 0 and 2 take the upper 10 blocks of the diagonal
+// 4 x 4 grids, waves 1 and 3 the two 4 x 2 halves of the off-diagonal one.
+// Blocks whose rows lie at or beyond J are dropped.
+__host__ __device__ inline void wave_task(int w, bool diag, int ra, int rb, int J, int& a0, int& b0, int& bs,
                                           unsigned& mask) {
   if (!diag) {
     a0 = 4 * (w >> 1);
-    b0 = 4 * (w & 1);
+    b0 = w & 1;
+    bs = 2;
     mask = kMaskFull;
   } else if (w == 0 || w == 2) {
     a0 = b0 = 2 * w;
+    bs = 1;
     mask = kMaskUpper;
   } else {
     a0 = 0;
     b0 = (w == 1) ? 4 : 6;
+    bs = 1;
     mask = kMaskHalf;
   }
   for (int x = 0; x < 4; ++x)
     for (int y = 0; y < 4; ++y)
-      if (ra + 16 * (a0 + x) >= J || rb + 16 * (b0 + y) >= J) mask &= ~(1u << (4 * x + y));
+      if (ra + 16 * (a0 + x) >= J || rb + 16 * (b0 + bs * y) >= J) mask &= ~(1u << (4 * x + y));
 }
 
 }  // namespace dma

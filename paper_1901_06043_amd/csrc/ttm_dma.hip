@@ -323,7 +323,7 @@ __device__ __forceinline__ void store_tile(const TtmDmaParams& g, const d4 (&acc
                                            int a0, int b0, int i, int q) {
   TZ* __restrict__ Z = reinterpret_cast<TZ*>(g.Z);
   if constexpr (ORI == 0) {
-    // D rows k = k0 + 16 (a0 + x) + q + 4 v, columns c = c0 + 16 (b0 + y) + i
+    // D rows k = k0 + 16 (a0 + 2 x) + q + 4 v, columns c = c0 + 16 (b0 + y) + i
 #pragma unroll
     for (int y = 0; y < 4; ++y) {
       const int64_t c = c0l + 16 * (b0 + y) + i;
@@ -342,13 +342,13 @@ __device__ __forceinline__ void store_tile(const TtmDmaParams& g, const d4 (&acc
         if (!((MK >> (4 * x + y)) & 1u)) continue;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const int k = k0 + 16 * (a0 + x) + q + 4 * v;
+          const int k = k0 + 16 * (a0 + 2 * x) + q + 4 * v;
           if (k < g.K) zc[g.Lo * (int64_t)k] = static_cast<TZ>(acc[x][y][v]);
         }
       }
     }
   } else {
-    // D rows c = c0 + 16 (a0 + x) + q + 4 v, columns k = k0 + 16 (b0 + y) + i
+    // D rows c = c0 + 16 (a0 + x) + q + 4 v, columns k = k0 + 16 (b0 + 2 y) + i
 #pragma unroll
     for (int x = 0; x < 4; ++x) {
 #pragma unroll
@@ -358,7 +358,7 @@ __device__ __forceinline__ void store_tile(const TtmDmaParams& g, const d4 (&acc
 #pragma unroll
         for (int y = 0; y < 4; ++y) {
           if (!((MK >> (4 * x + y)) & 1u)) continue;
-          const int k = k0 + 16 * (b0 + y) + i;
+          const int k = k0 + 16 * (b0 + 2 * y) + i;
           if (k < g.K) Z[k + (int64_t)g.K * c] = static_cast<TZ>(acc[x][y][v]);
         }
       }
@@ -399,11 +399,20 @@ __global__ __launch_bounds__(kTDNT, 2) void ttm_dma_kernel(TtmDmaParams g) {
   Loader<TY, ORI, MF, WY> ld;
   loader_init(ld, g, k0, c0l, wave, lane);
 
-  // the wave's 64 x 64 part: A blocks a0 + x, B blocks b0 + y (16 rows each)
-  const int a0 = 4 * (wave >> 1), b0 = 4 * (wave & 1);
-  // output rows k beyond K: ORI 0 drops A block rows, ORI 1 B block columns
-  const int kb0 = (ORI == 0) ? k0 + 16 * a0 : k0 + 16 * b0;
-  const int nv = max(0, min(4, (g.K - kb0 + 15) / 16));
+  // the wave's 64 x 64 part of the tile's 8 x 8 blocks of 16 x 16: along the
+  // output rows k the waves take every other block (blocks kw, kw + 2,
+  // kw + 4, kw + 6), along the columns four consecutive ones, so that a
+  // ragged last row tile (K = 469: six blocks; 448: four) splits evenly
+  // between the two waves of a column half instead of leaving one idle.
+  // ORI 0: A blocks a0 + 2 x (k), B blocks b0 + y (c); ORI 1: A blocks
+  // a0 + x (c), B blocks b0 + 2 y (k).
+  const int a0 = (ORI == 0) ? (wave >> 1) : 4 * (wave >> 1);
+  const int b0 = (ORI == 0) ? 4 * (wave & 1) : (wave & 1);
+  // output rows k beyond K drop this wave's last k blocks: ORI 0 A block
+  // rows, ORI 1 B block columns
+  const int kw = (ORI == 0) ? a0 : b0;
+  const int nbk = min(8, (g.K - k0 + 15) / 16);
+  const int nv = max(0, min(4, (nbk - kw + 1) / 2));
   const unsigned mask = (ORI == 0) ? tdma::rows_mask(nv) : tdma::cols_mask(nv);
   // operand offsets of the lane's blocks at step 0 (row form: and the byte
   // distance d to its second unit, whose sign depends on the row's swizzle)
@@ -413,8 +422,8 @@ __global__ __launch_bounds__(kTDNT, 2) void ttm_dma_kernel(TtmDmaParams g) {
     using IB = typename std::conditional<ORI == 0, typename C::IY, typename C::IM>::type;
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-      oa[t] = IA::at(16 * (a0 + t) + i, IA::jstep(0, q));
-      ob[t] = IB::at(16 * (b0 + t) + i, IB::jstep(0, q));
+      oa[t] = IA::at(16 * (a0 + (ORI == 0 ? 2 : 1) * t) + i, IA::jstep(0, q));
+      ob[t] = IB::at(16 * (b0 + (ORI == 0 ? 1 : 2) * t) + i, IB::jstep(0, q));
     }
     da = IA::at(i, IA::jstep(2, q)) - IA::at(i, IA::jstep(0, q));
     db = IB::at(i, IB::jstep(2, q)) - IB::at(i, IB::jstep(0, q));
