@@ -1887,9 +1887,9 @@ __device__ __forceinline__ void invit_body_lean(const double* __restrict__ d, co
 #undef W
 }
 
-// Batched form: one wave per vector reading the reflectors straight from
-// global memory (the next one prefetched); many workgroups per CU hide the
-// latency, and no LDS is used.
+// One wave per vector reading the reflectors straight from global memory
+// (the next one prefetched); many workgroups per CU hide the latency, and no
+// LDS is used.
 template <int Q>
 __device__ __forceinline__ void back_body_direct(const double* __restrict__ H, const double* __restrict__ tau, int J,
                                           const double* __restrict__ Zt, const int64_t* __restrict__ Rp,
@@ -2025,7 +2025,7 @@ __global__ __launch_bounds__(kEigThreads) void eig_orth_batched(EigBatch b) {
 
 // Single matrices above 1024 rows: the register-staged LDS chunks of
 // eig_back_kernel no longer fit beside a vector of Q > 16 values per lane, so
-// the reflectors are read straight from global memory as in the batched form
+// the reflectors are read straight from global memory
 // (each row k of H is read by all R vectors, from L2).
 template <int Q>
 __global__ __launch_bounds__(256) void eig_back_direct_kernel(const double* __restrict__ H,
@@ -2035,12 +2035,78 @@ __global__ __launch_bounds__(256) void eig_back_direct_kernel(const double* __re
   back_body_direct<Q>(H, tau, J, Zt, Rp, U, blockIdx.x);
 }
 
-template <int Q>
-__global__ __launch_bounds__(256) void eig_back_batched(EigBatch b) {
+// Batched back-transformation with one workgroup per matrix: its reflectors
+// (J <= 128: at most 128 KB) are read once into LDS, then each of the 16
+// waves applies them to every 16th vector from LDS.  Reading each reflector
+// from global memory once per vector made every step of the sequence wait
+// for a global load.
+__global__ __launch_bounds__(1024) void eig_back_batched_lds(EigBatch b) {
+  extern __shared__ double sh[];
   int m, J;
   if (!batch_matrix(b, m, J)) return;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int R = (int)b.R[m];
   const int64_t o2 = (int64_t)m * b.Jmax * b.Jmax, o1 = (int64_t)m * b.Jmax;
-  back_body_direct<Q>(b.A + o2, b.tau + o1, J, b.Zt + o2, b.R + m, b.U + o2, blockIdx.x);
+  double* sH = sh;                        // [J][J]: row k holds v_k at k + 2 .. J - 1
+  double* stau = sh + (int64_t)J * J;     // [J]
+  const double* H = b.A + o2;
+  for (int x = tid; x < J * J; x += 1024) sH[x] = H[x];
+  for (int x = tid; x < J; x += 1024) stau[x] = b.tau[o1 + x];
+  __syncthreads();
+  const double* Zt = b.Zt + o2;
+  double* U = b.U + o2;
+  for (int vec = wave; vec < R; vec += 16) {  // uniform per wave
+    double z[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int r = lane + 64 * u;
+      z[u] = (r < J) ? Zt[(int64_t)vec * J + r] : 0.0;
+    }
+    for (int k = J - 3; k >= 0; --k) {
+      const double tk = stau[k];
+      if (tk == 0.0) continue;  // uniform
+      double v[2];
+      double s = 0.0;
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int r = lane + 64 * u;
+        v[u] = (r == k + 1) ? 1.0 : ((r > k + 1 && r < J) ? sH[k * J + r] : 0.0);
+        s = fma(v[u], z[u], s);
+      }
+      s = wave_sum_fast(s) * tk;
+#pragma unroll
+      for (int u = 0; u < 2; ++u) z[u] = fma(-s, v[u], z[u]);
+    }
+    // sign convention: entry of largest magnitude (lowest index on ties) positive
+    double ba = -1.0, bv = 0.0;
+    int bi = J;
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int r = lane + 64 * u;
+      if (r < J && fabs(z[u]) > ba) {
+        ba = fabs(z[u]);
+        bv = z[u];
+        bi = r;
+      }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const double oa = __shfl_xor(ba, off, 64);
+      const double ov = __shfl_xor(bv, off, 64);
+      const int oi = __shfl_xor(bi, off, 64);
+      if (oa > ba || (oa == ba && oi < bi)) {
+        ba = oa;
+        bv = ov;
+        bi = oi;
+      }
+    }
+    const double sgn = (bv < 0.0) ? -1.0 : 1.0;
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int r = lane + 64 * u;
+      if (r < J) U[(int64_t)vec * J + r] = sgn * z[u];
+    }
+  }
 }
 
 }  // namespace
@@ -2190,10 +2256,7 @@ hipError_t launch_eig_truncate_batched(const EigBatch& b, double thr_mul, hipStr
                      stream, b, nvw);
   hipLaunchKernelGGL(eig_orth_batched, dim3(1, nb), dim3(kEigThreads),
                      sizeof(double) * ((size_t)J + 16 + (size_t)orth_cap_batched(J)), stream, b);
-  if (J <= 64)
-    hipLaunchKernelGGL((eig_back_batched<1>), dim3(ceil_div(J, 4), nb), dim3(256), 0, stream, b);
-  else
-    hipLaunchKernelGGL((eig_back_batched<2>), dim3(ceil_div(J, 4), nb), dim3(256), 0, stream, b);
+  hipLaunchKernelGGL(eig_back_batched_lds, dim3(1, nb), dim3(1024), sizeof(double) * ((size_t)J * J + J), stream, b);
   return hipGetLastError();
 }
 
