@@ -388,7 +388,7 @@ tucker_status tucker_set_postprocess(tucker_t* t, int n, const double* shift, co
  * ------------------------------------------------------------------------ */
 typedef struct tucker_batch tucker_batch;
 
-/*   count      number of tensors, >= 1.
+/*   count      number of tensors, 1 .. 4194304 (2^22).
  *   data       host array of `count` device pointers (natural descending, `dtype`).
  *   dims       host, count x N sizes (tensor t's sizes at dims + t*N), each 1..128.
  *   eps, mode_order, prec: as for tucker_sthosvd (the order is shared; AUTO

@@ -1815,6 +1815,9 @@ tucker_status tucker_batch_create(int count, const void* const* data, tucker_dty
   if (!out) return fail(TUCKER_EINVAL, "out is NULL");
   *out = nullptr;
   if (count < 1) return fail(TUCKER_EINVAL, "count=%d < 1", count);
+  // one workgroup of up to 1024 threads per tensor in the batched eigensolver:
+  // the work-items of a launch stay below 2^32
+  if (count > (1 << 22)) return fail(TUCKER_EINVAL, "count=%d above %d", count, 1 << 22);
   if (!data || !dims) return fail(TUCKER_EINVAL, "NULL argument");
   if (dtype != TUCKER_F32 && dtype != TUCKER_F64) return fail(TUCKER_EINVAL, "bad dtype");
   if (prec < TUCKER_GRAM_FP64 || prec > TUCKER_GRAM_AUTO) return fail(TUCKER_EINVAL, "bad Gram precision");

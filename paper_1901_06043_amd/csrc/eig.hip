@@ -1791,16 +1791,17 @@ void launch_back(const EigWork& w, int J, const double* Z, const int64_t* R, dou
                      w.tau, J, Z, R, U);
 }
 
-// Batched form (throughput over many small matrices, where LDS per vector
-// limits the vectors in flight): four arrays per vector, and each step
-// factors again.  One thread per vector; a workgroup of 64 threads serves
-// `nvw` vectors and
-// keeps, per vector, the upper factor of the pivoted LU of (T - lambda I)/||T||
-// (reciprocal pivots, first and second superdiagonal) and the iterate in LDS,
-// interleaved by thread so that accesses are bank-conflict free.  Each
-// iteration factors and forward-substitutes in one pass (the multipliers and
-// interchanges are applied to the right-hand side as they are produced) and
-// back-substitutes in a second pass.
+// Batched form (throughput over many small matrices): one thread per vector;
+// a workgroup of 64 threads serves `nvw` vectors and keeps, per vector, the
+// upper factor of the pivoted LU of (T - lambda I)/||T|| (reciprocal pivots,
+// first and second superdiagonal) and the iterate in LDS, interleaved by
+// thread so that accesses are bank-conflict free.  Each iteration factors and
+// forward-substitutes in one pass (the multipliers and interchanges are
+// applied to the right-hand side as they are produced) and back-substitutes
+// in a second pass.  Only the kept vectors (typically a small fraction of
+// the rows) take part, so a group serves few of them: its LDS stays small and
+// many groups, each a latency-bound chain, are in flight per CU.
+constexpr int kInvitBatchedRows = 512;  // vectors per group times rows: 16 KB of LDS per group
 __device__ __forceinline__ void invit_body_lean(const double* __restrict__ d, const double* __restrict__ e, int J,
                                            const double* __restrict__ lam, const int64_t* __restrict__ Rp,
                                            const double* __restrict__ scal, double* __restrict__ Zt, int nvw,
@@ -1964,11 +1965,11 @@ __device__ __forceinline__ void back_body_direct(const double* __restrict__ H, c
 
 // ---------------------------------------------------------------- batched form
 // Many independent matrices of sizes J_m <= kBatchMaxJ in one launch per step:
-// blockIdx.y selects the matrix, J_m is read from the device (0 = no matrix),
+// blockIdx.x selects the matrix, J_m is read from the device (0 = no matrix),
 // and every per-matrix array sits at a fixed stride (Jmax^2 or Jmax) with the
 // matrix stored contiguously (leading dimension J_m) at its start.
 __device__ __forceinline__ bool batch_matrix(const EigBatch& b, int& m, int& J) {
-  m = blockIdx.y;
+  m = blockIdx.x;
   J = (m < b.count) ? b.J[m] : 0;
   return J > 0;
 }
@@ -1989,12 +1990,15 @@ __global__ __launch_bounds__(64 * NW) void eig_tridiag_reg_batched(EigBatch b, i
                                b.A + o2 + (int64_t)k0 * J + k0, J, b.d + o1 + k0, b.e + o1 + k0, b.tau + o1 + k0);
 }
 
-__global__ __launch_bounds__(256) void eig_bisect_batched(EigBatch b) {
+// One workgroup per (matrix, group of 256 / kBisLanesBatched eigenvalues),
+// the groups of a matrix consecutive: blockIdx.x = m * groups + g.
+__global__ __launch_bounds__(256) void eig_bisect_batched(EigBatch b, int groups) {
   extern __shared__ double sh[];
-  int m, J;
-  if (!batch_matrix(b, m, J) || (int)blockIdx.x * (256 / kBisLanesBatched) >= J) return;
+  const int m = (int)(blockIdx.x / (unsigned)groups), g = (int)(blockIdx.x % (unsigned)groups);
+  const int J = (m < b.count) ? b.J[m] : 0;
+  if (J <= 0 || g * (256 / kBisLanesBatched) >= J) return;
   const int64_t o1 = (int64_t)m * b.Jmax;
-  bisect_body<kBisLanesBatched>(b.d + o1, b.e + o1, J, b.lam + o1, b.scal + 8 * (int64_t)m, blockIdx.x);
+  bisect_body<kBisLanesBatched>(b.d + o1, b.e + o1, J, b.lam + o1, b.scal + 8 * (int64_t)m, g);
 }
 
 __global__ void eig_truncate_batched(EigBatch b, double thr_mul) {
@@ -2012,7 +2016,7 @@ __global__ __launch_bounds__(64) void eig_invit_batched(EigBatch b, int nvw) {
   if (!batch_matrix(b, m, J)) return;
   const int64_t o2 = (int64_t)m * b.Jmax * b.Jmax, o1 = (int64_t)m * b.Jmax;
   invit_body_lean(b.d + o1, b.e + o1, J, b.lam + o1, b.R + m, b.scal + 8 * (int64_t)m, b.Zt + o2, nvw, sh,
-                  blockIdx.x);
+                  blockIdx.y);
 }
 
 __global__ __launch_bounds__(kEigThreads) void eig_orth_batched(EigBatch b) {
@@ -2241,22 +2245,27 @@ hipError_t launch_eig_truncate(const double* S, int J, double thr, const double*
 
 hipError_t launch_eig_truncate_batched(const EigBatch& b, double thr_mul, hipStream_t stream) {
   if (b.Jmax > kBatchMaxJ || b.count <= 0) return hipErrorInvalidValue;
-  const int nb = b.count;
+  // The matrix index is blockIdx.x (up to 2^31 - 1 matrices): consecutive
+  // workgroups take different matrices, which the dispatcher deals round the
+  // XCDs, so the groups of a matrix that carry work (the first of a split
+  // launch) spread over the whole chip instead of gathering on a few XCDs.
+  const unsigned nb = (unsigned)b.count;
   // tridiagonalisation phases, largest first (as in the single-matrix path)
-  hipLaunchKernelGGL((eig_tridiag_reg_batched<16, 2, 8>), dim3(1, nb), dim3(64 * 16), 0, stream, b, 128, 96);
-  hipLaunchKernelGGL((eig_tridiag_reg_batched<16, 2, 6>), dim3(1, nb), dim3(64 * 16), 0, stream, b, 96, 64);
-  hipLaunchKernelGGL((eig_tridiag_reg_batched<16, 1, 4>), dim3(1, nb), dim3(64 * 16), 0, stream, b, 64, 32);
-  hipLaunchKernelGGL((eig_tridiag_reg_batched<8, 1, 2>), dim3(1, nb), dim3(64 * 8), 0, stream, b, 32, 0);
+  hipLaunchKernelGGL((eig_tridiag_reg_batched<16, 2, 8>), dim3(nb), dim3(64 * 16), 0, stream, b, 128, 96);
+  hipLaunchKernelGGL((eig_tridiag_reg_batched<16, 2, 6>), dim3(nb), dim3(64 * 16), 0, stream, b, 96, 64);
+  hipLaunchKernelGGL((eig_tridiag_reg_batched<16, 1, 4>), dim3(nb), dim3(64 * 16), 0, stream, b, 64, 32);
+  hipLaunchKernelGGL((eig_tridiag_reg_batched<8, 1, 2>), dim3(nb), dim3(64 * 8), 0, stream, b, 32, 0);
   const int J = b.Jmax;
   const size_t shb = sizeof(double) * (2 * (size_t)J + 4);
-  hipLaunchKernelGGL(eig_bisect_batched, dim3(ceil_div(J, 256 / kBisLanesBatched), nb), dim3(256), shb, stream, b);
-  hipLaunchKernelGGL(eig_truncate_batched, dim3(ceil_div(nb, 64)), dim3(64), 0, stream, b, thr_mul);
-  const int nvw = (int)std::max<int64_t>(1, std::min<int64_t>(64, (128 * 1024) / (32 * (int64_t)J)));
-  hipLaunchKernelGGL(eig_invit_batched, dim3(ceil_div(J, nvw), nb), dim3(64), sizeof(double) * 4 * (size_t)J * nvw,
+  const int groups = (int)ceil_div(J, 256 / kBisLanesBatched);
+  hipLaunchKernelGGL(eig_bisect_batched, dim3(nb * (unsigned)groups), dim3(256), shb, stream, b, groups);
+  hipLaunchKernelGGL(eig_truncate_batched, dim3(ceil_div((int)nb, 64)), dim3(64), 0, stream, b, thr_mul);
+  const int nvw = std::max(1, std::min(64, kInvitBatchedRows / J));
+  hipLaunchKernelGGL(eig_invit_batched, dim3(nb, ceil_div(J, nvw)), dim3(64), sizeof(double) * 4 * (size_t)J * nvw,
                      stream, b, nvw);
-  hipLaunchKernelGGL(eig_orth_batched, dim3(1, nb), dim3(kEigThreads),
+  hipLaunchKernelGGL(eig_orth_batched, dim3(nb), dim3(kEigThreads),
                      sizeof(double) * ((size_t)J + 16 + (size_t)orth_cap_batched(J)), stream, b);
-  hipLaunchKernelGGL(eig_back_batched_lds, dim3(1, nb), dim3(1024), sizeof(double) * ((size_t)J * J + J), stream, b);
+  hipLaunchKernelGGL(eig_back_batched_lds, dim3(nb), dim3(1024), sizeof(double) * ((size_t)J * J + J), stream, b);
   return hipGetLastError();
 }
 
