@@ -38,7 +38,9 @@ Also on the same JSON line:
   eps 1e-2..1e-5 with every Gram form;
 * batched_form: 1024 independent float32 3-way tensors (sizes U{16..128},
   ranks U{2..I/4}, noise 1e-4) at eps 1e-3, one batched run replayed from a
-  captured HIP graph against a loop of single-tensor calls, per Gram form.
+  captured HIP graph against a loop of single-tensor calls, per Gram form;
+  `hbm_floor_frac` = (input bytes read once at 8 TB/s) / replay time, the
+  replay's fraction of its HBM floor.
 
 `--sections none --no-cpu-baseline --steps 2 --warmup 1` is the short run
 used under rocprofv3.
@@ -57,6 +59,7 @@ if ROOT not in sys.path:
 
 METRIC = "ST-HOSVD input GB/s + Gram TFLOP/s, mixed/batched vs FP64 GPU at rel err≤1.05ε"
 PEAK_FP64_TFLOPS = 78.6
+HBM_PEAK_BPS = 8.0e12  # MI355X HBM3E, bytes per second
 PEAK_HBM_GBS = 8000.0
 FORMS = ["fp64", "fp32", "bf16x6", "bf16x3"]
 LARGE_DIMS = [672, 672, 33, 626]
@@ -301,7 +304,9 @@ def batched_section(tk, torch, synthetic, reps):
             t.free()
         rows.append({"gram": prec, "graph_ms": round(graph_ms, 3), "eager_run_ms": round(eager_ms, 3),
                      "loop_of_single_calls_ms": round(loop_ms, 2), "speedup_vs_loop": round(loop_ms / graph_ms, 2),
-                     "input_GBs": round(nbytes / graph_ms / 1e6, 2), "plan_create_s": round(create_s, 3),
+                     "input_GBs": round(nbytes / graph_ms / 1e6, 2),
+                     "hbm_floor_frac": round(nbytes / HBM_PEAK_BPS / (graph_ms / 1e3), 4),
+                     "plan_create_s": round(create_s, 3),
                      "tiles_gram_chunks_ttm_tiles": list(b.tiles()),
                      "ranks_match_single_calls": sum(r == q for r, q in zip(ranks, single_ranks)),
                      "worst_relerr_sampled": worst, "within_1.05eps": bool(worst <= 1.05 * eps)})

@@ -2250,11 +2250,14 @@ hipError_t launch_eig_truncate_batched(const EigBatch& b, double thr_mul, hipStr
   // XCDs, so the groups of a matrix that carry work (the first of a split
   // launch) spread over the whole chip instead of gathering on a few XCDs.
   const unsigned nb = (unsigned)b.count;
-  // tridiagonalisation phases, largest first (as in the single-matrix path)
+  // Tridiagonalisation phases, largest first (as in the single-matrix path).
+  // From 96 rows down each lane holds more rows (NG) in fewer waves, so that
+  // several matrices share a CU (the 96-row phase: 4 waves of 137 VGPRs,
+  // 3 workgroups per CU); the 128-row phase is fastest with 16 waves.
   hipLaunchKernelGGL((eig_tridiag_reg_batched<16, 2, 8>), dim3(nb), dim3(64 * 16), 0, stream, b, 128, 96);
-  hipLaunchKernelGGL((eig_tridiag_reg_batched<16, 2, 6>), dim3(nb), dim3(64 * 16), 0, stream, b, 96, 64);
-  hipLaunchKernelGGL((eig_tridiag_reg_batched<16, 1, 4>), dim3(nb), dim3(64 * 16), 0, stream, b, 64, 32);
-  hipLaunchKernelGGL((eig_tridiag_reg_batched<8, 1, 2>), dim3(nb), dim3(64 * 8), 0, stream, b, 32, 0);
+  hipLaunchKernelGGL((eig_tridiag_reg_batched<4, 6, 6>), dim3(nb), dim3(64 * 4), 0, stream, b, 96, 64);
+  hipLaunchKernelGGL((eig_tridiag_reg_batched<4, 4, 4>), dim3(nb), dim3(64 * 4), 0, stream, b, 64, 32);
+  hipLaunchKernelGGL((eig_tridiag_reg_batched<2, 4, 2>), dim3(nb), dim3(64 * 2), 0, stream, b, 32, 0);
   const int J = b.Jmax;
   const size_t shb = sizeof(double) * (2 * (size_t)J + 4);
   const int groups = (int)ceil_div(J, 256 / kBisLanesBatched);
