@@ -1230,12 +1230,40 @@ tucker_status reconstruct_impl(const tucker_t* t, const tucker_op* ops, const in
   const void* Y = t->core;
   tucker_dtype ydt = t->core_dtype;
   const bool f32p = (t->core_dtype == TUCKER_F32 && out_dtype == TUCKER_F32);
+  // A mode-0 product over an odd extent R_0 reads the columns of its
+  // unfolding (R_0 consecutive doubles, 8-byte aligned) in 4-byte pieces.
+  // When the FP64 product just before it takes the direct-load kernel, that
+  // product appends a zero slice to mode 0 (extent R_0 + 1, the output remap)
+  // and the mode-0 product multiplies by [W_0 0] with 16-byte loads.
+  int zpad_step = -1;
+  TmpBuf wpad;
+  for (int s = 1; s < N; ++s)
+    if (ord[s] == 0 && cur[0] % 2 == 1 && cur[0] > 1 && !f32p && t->core_dtype == TUCKER_F64 && msk[0] == 1) {
+      const int n = ord[s - 1];
+      int64_t pc[TUCKER_MAX_MODES];  // sizes before step s - 1
+      std::memcpy(pc, t->ranks, sizeof(int64_t) * N);
+      for (int q = 0; q < s - 1; ++q) pc[ord[q]] = K[ord[q]];
+      int64_t L, Rt;
+      left_right(pc, N, n, L, Rt);
+      // (the core and every intermediate are 16-byte aligned allocations)
+      if (L * Rt < (int64_t(1) << 32) && K[0] % 2 == 0 &&
+          tk::ttm_dma_eligible((int)pc[n], (uint64_t)L, (uint64_t)(L * Rt), (int)K[n], msk[n], msj[n], 8, 8, t->core,
+                               M[n])) {
+        zpad_step = s - 1;
+        const int64_t J0 = cur[0];
+        HIP_TRY(wpad.alloc(sizeof(double) * K[0] * (J0 + 1), stream));
+        HIP_TRY(hipMemcpy2DAsync(wpad.p, sizeof(double) * K[0], M[0], sizeof(double) * msj[0], sizeof(double) * K[0],
+                                 J0, hipMemcpyDeviceToDevice, stream));
+        HIP_TRY(tk::launch_fill(wpad.as<double>() + K[0] * J0, (uint64_t)K[0], 0.0, stream));
+      }
+    }
   TmpBuf a;
   for (int step = 0; step < N; ++step) {
     const int n = ord[step];
     int64_t total = 1;
     for (int k = 0; k < N; ++k) total *= cur[k];
-    const int64_t next = total / cur[n] * K[n];
+    int64_t next = total / cur[n] * K[n];
+    if (step == zpad_step) next = next / cur[0] * (cur[0] + 1);
     const bool last = (step == N - 1);
     void* Z = out;
     tucker_dtype zdt = out_dtype;
@@ -1245,7 +1273,21 @@ tucker_status reconstruct_impl(const tucker_t* t, const tucker_op* ops, const in
       HIP_TRY(nb.alloc(dtype_size(zdt) * next, stream));
       Z = nb.p;
     }
-    if ((st = run_ttm(Y, ydt, cur, N, n, M[n], K[n], msk[n], msj[n], Z, zdt, f32p, stream))) return st;
+    if (step == zpad_step) {
+      int64_t L, Rt;
+      left_right(cur, N, n, L, Rt);
+      tk::TtmOutRemap rm;
+      rm.Lp = 1;
+      rm.Pp = cur[0];
+      rm.Rp = cur[0] + 1;
+      HIP_TRY(tk::launch_ttm_dma(static_cast<const double*>(Y), (int)cur[n], (uint64_t)L, (uint64_t)(L * Rt), M[n],
+                                 msk[n], msj[n], (int)K[n], static_cast<double*>(Z), stream, rm));
+      cur[0] += 1;
+    } else if (n == 0 && zpad_step >= 0) {
+      if ((st = run_ttm(Y, ydt, cur, N, n, wpad.as<double>(), K[0], 1, K[0], Z, zdt, f32p, stream))) return st;
+    } else if ((st = run_ttm(Y, ydt, cur, N, n, M[n], K[n], msk[n], msj[n], Z, zdt, f32p, stream))) {
+      return st;
+    }
     a.release();
     if (!last) {
       a.p = nb.p;

@@ -97,11 +97,13 @@ __global__ void sum_fixed_kernel(const double* __restrict__ x, int64_t n, double
 // contiguous rows of M and double output.  launch_ttm uses it when eligible.
 bool ttm_dma_eligible(int J, uint64_t L, uint64_t cols, int K, int64_t msk, int64_t msj, int ysize, int zsize,
                       const void* Y, const void* M);
-// Output of a mode product (L > 1) whose L covers a mode p that was padded
-// from its rank Rp to Pp (zero slices i_p >= Rp, from zero columns of that
-// mode's factor): l = a + Lp (i_p + Pp h) on input is written to
-// a + Lp (i_p + Rp h), the zero slices dropped, so that the output is the
-// compact tensor.  Pp == Rp: no remap.
+// Output of a mode product (L > 1) whose L covers a mode p of extent Pp on
+// input and Rp on output: l = a + Lp (i_p + Pp h) on input is written to
+// a + Lp (i_p + Rp h).  Rp < Pp drops the zero slices i_p >= Rp of a padded
+// mode (from zero columns of that mode's factor), so that the output is the
+// compact tensor; Rp = Pp + 1 appends a zero slice i_p = Pp (written with the
+// slice before it), so that a later product over mode p meets an even
+// extent.  Pp == Rp: no remap.
 struct TtmOutRemap {
   int64_t Lp = 1, Pp = 1, Rp = 1;
 };

@@ -330,11 +330,13 @@ __device__ __forceinline__ void store_tile(const TtmDmaParams& g, const d4 (&acc
       if (c >= g.cols) continue;
       const int64_t m = c / g.L, l = c - m * g.L;
       int64_t lo = l;
+      bool zpad = false;  // also write the appended zero slice after this one
       if (g.Pp != g.Rp) {  // uniform
         const int64_t t = l / g.Lp, a = l - t * g.Lp;
         const int64_t h = t / g.Pp, ip = t - h * g.Pp;
         if (ip >= g.Rp) continue;  // a zero slice of the padded mode
         lo = a + g.Lp * (ip + g.Rp * h);
+        zpad = g.Rp > g.Pp && ip == g.Pp - 1;
       }
       TZ* zc = Z + lo + g.Lo * (int64_t)g.K * m;
 #pragma unroll
@@ -343,7 +345,10 @@ __device__ __forceinline__ void store_tile(const TtmDmaParams& g, const d4 (&acc
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int k = k0 + 16 * (a0 + 2 * x) + q + 4 * v;
-          if (k < g.K) zc[g.Lo * (int64_t)k] = static_cast<TZ>(acc[x][y][v]);
+          if (k < g.K) {
+            zc[g.Lo * (int64_t)k] = static_cast<TZ>(acc[x][y][v]);
+            if (zpad) zc[g.Lp + g.Lo * (int64_t)k] = static_cast<TZ>(0.0);
+          }
         }
       }
     }
@@ -479,7 +484,7 @@ hipError_t launch_ttm_dma(const TY* Y, int J, uint64_t L, uint64_t cols, const d
   if (!ttm_dma_eligible(J, L, cols, K, msk, msj, (int)sizeof(TY), (int)sizeof(TZ), Y, M))
     return hipErrorInvalidValue;
   const bool remap = rm.Pp != rm.Rp;
-  if (remap && (L == 1 || rm.Lp < 1 || rm.Rp < 1 || rm.Rp > rm.Pp || (int64_t)L % (rm.Lp * rm.Pp) != 0))
+  if (remap && (L == 1 || rm.Lp < 1 || rm.Rp < 1 || rm.Rp > rm.Pp + 1 || (int64_t)L % (rm.Lp * rm.Pp) != 0))
     return hipErrorInvalidValue;
   TtmDmaParams g{};
   g.Y = reinterpret_cast<const char*>(Y);

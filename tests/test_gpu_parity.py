@@ -419,6 +419,30 @@ def test_reconstruct_subrange_parity(tk, orc):
                                        atol=tol * np.abs(Zref).max())
 
 
+@pytest.mark.parametrize("order", [[2, 0, 1], [1, 2, 0], [0, 1, 2]])
+def test_reconstruct_odd_mode0_extent(tk, orc, order):
+    """R_0 = 65 (odd): when mode 0 is not reconstructed first, the product just
+    before it appends a zero slice to mode 0 (extent 66) and the mode-0
+    product multiplies by the factor with a zero column appended, on 16-byte
+    loads.  Full and sub-range reconstructions (an even and an odd number of
+    mode-0 rows, where the latter keeps the odd extent), FP64 and FP32
+    output, against the oracle's reconstruction."""
+    dims, ranks = [130, 40, 96], [65, 20, 70]
+    X, dims = synthetic.random_tucker(dims, ranks, 1e-6, seed=29)
+    print(f"reconstruct odd mode-0 extent order={order}", flush=True)
+    t = tk.sthosvd_ranks(to_dev(X, dims), ranks, dims=dims)
+    ref = orc.sthosvd(X, dims, 0.0, ranks=ranks)
+    assert t.ranks == ref.ranks == ranks
+    for begin, end in (([0, 0, 0], dims), ([3, 5, 0], [127, 40, 96]), ([3, 0, 7], [126, 40, 90])):
+        for odt in (torch.float64, torch.float32):
+            Z = t.reconstruct(begin, end, order=order, out_dtype=odt)
+            Zref, zd = orc.reconstruct(ref, begin, end)
+            assert list(Z.shape) == zd[::-1]
+            tol = 1e-9 if odt == torch.float64 else 1e-5
+            np.testing.assert_allclose(Z.cpu().numpy().reshape(-1).astype(np.float64), Zref,
+                                       atol=tol * np.abs(Zref).max())
+
+
 def test_reconstruct_bad_range(tk):
     t = tk.sthosvd(torch.rand((4, 5, 6), dtype=torch.float64, device="cuda"), 0.1)
     with pytest.raises(tk.TuckerError):
