@@ -388,13 +388,14 @@ tucker_status tucker_set_postprocess(tucker_t* t, int n, const double* shift, co
  * ------------------------------------------------------------------------ */
 typedef struct tucker_batch tucker_batch;
 
-/*   count      number of tensors, 1 .. 4194304 (2^22).
+/*   count      number of tensors, 1 .. 4194303 (2^22 - 1).
  *   data       host array of `count` device pointers (natural descending, `dtype`).
  *   dims       host, count x N sizes (tensor t's sizes at dims + t*N), each 1..128.
  *   eps, mode_order, prec: as for tucker_sthosvd (the order is shared; AUTO
  *              is resolved once for the batch).
  *   stream     used for the plan's uploads and its tuning runs; synchronised.
- * Errors: EINVAL (arguments), EUNSUPPORTED (a size above 128), ENOMEM, EHIP. */
+ * Errors: EINVAL (arguments), EUNSUPPORTED (a size above 128, or more than 2^23 Gram or
+ *         2^24 product work items in a step), ENOMEM, EHIP. */
 tucker_status tucker_batch_create(int count, const void* const* data, tucker_dtype dtype,
                                   const int64_t* dims, int N, double eps, const int* mode_order,
                                   tucker_gram_prec prec, hipStream_t stream, tucker_batch** out);

@@ -1820,6 +1820,11 @@ tucker_status batch_upload_plans(tucker_batch* b, const BatchTiles& tiles, int64
     int nsmall = 0;
     int64_t pe = 0;
     plan_step_items(b, s, tiles, gi, gf, nsmall, ti, pe);
+    // one workgroup per item (512 threads for the Gram, 256 for the product):
+    // the work-items of a launch stay below 2^32
+    if (gi.size() / 4 >= (size_t(1) << 23) || ti.size() / 3 >= (size_t(1) << 24))
+      return fail(TUCKER_EUNSUPPORTED, "step %d: %zu Gram and %zu product work items, above 2^23 and 2^24", s,
+                  gi.size() / 4, ti.size() / 3);
     HIP_TRY(b->upload(&b->gitems[s], gi));
     HIP_TRY(b->upload(&b->gfirst[s], gf));
     HIP_TRY(b->upload(&b->titems[s], ti));
@@ -1859,7 +1864,7 @@ tucker_status tucker_batch_create(int count, const void* const* data, tucker_dty
   if (count < 1) return fail(TUCKER_EINVAL, "count=%d < 1", count);
   // one workgroup of up to 1024 threads per tensor in the batched eigensolver:
   // the work-items of a launch stay below 2^32
-  if (count > (1 << 22)) return fail(TUCKER_EINVAL, "count=%d above %d", count, 1 << 22);
+  if (count >= (1 << 22)) return fail(TUCKER_EINVAL, "count=%d above %d", count, (1 << 22) - 1);
   if (!data || !dims) return fail(TUCKER_EINVAL, "NULL argument");
   if (dtype != TUCKER_F32 && dtype != TUCKER_F64) return fail(TUCKER_EINVAL, "bad dtype");
   if (prec < TUCKER_GRAM_FP64 || prec > TUCKER_GRAM_AUTO) return fail(TUCKER_EINVAL, "bad Gram precision");

@@ -571,12 +571,12 @@ __global__ __launch_bounds__(kNT) void gram_batch_kernel(GramBatch b, int item0)
 // Per tensor: sum its items' partial blocks (in item order) into S_t (J x J,
 // both triangles) and, when nx2 is set, its items' sums of squares.
 __global__ __launch_bounds__(256) void gram_batch_reduce_kernel(GramBatch b) {
-  const int t = blockIdx.y;
+  const int t = blockIdx.x;
   const int J = b.J[t];
   if (J <= 0) return;
   if (b.flag != nullptr && b.flag[t] == 0) return;
   const int nb = (J + 15) / 16, nblk = nb * (nb + 1) / 2;
-  const int idx = blockIdx.x * 256 + threadIdx.x;
+  const int idx = blockIdx.y * 256 + threadIdx.x;
   const int i0 = b.ifirst[2 * t], i1 = b.ifirst[2 * t + 1];
   if (idx == 0 && b.nx2 != nullptr) {
     double s = 0.0;
@@ -735,7 +735,7 @@ hipError_t launch_gram_batched(const GramBatch& b, int prec, bool unit_l, hipStr
       default: launch_batch<T, 3>(b, unit_l, stream); break;
     }
   }
-  hipLaunchKernelGGL(gram_batch_reduce_kernel, dim3(36, b.count), dim3(256), 0, stream, b);
+  hipLaunchKernelGGL(gram_batch_reduce_kernel, dim3(b.count, 36), dim3(256), 0, stream, b);
   return hipGetLastError();
 }
 

@@ -149,7 +149,7 @@ def test_batch_create_rejects_bad_arguments_without_gpu(tk):
     ptrs = (ctypes.c_void_p * 2)(16, 32)  # never dereferenced: validation precedes device work
     good = tk._i64([16, 20, 30, 40, 50, 60])
     assert L.tucker_batch_create(0, ptrs, 0, good, 3, 1e-3, None, 0, None, ctypes.byref(h)) == 1
-    assert L.tucker_batch_create((1 << 22) + 1, ptrs, 0, good, 3, 1e-3, None, 0, None, ctypes.byref(h)) == 1
+    assert L.tucker_batch_create(1 << 22, ptrs, 0, good, 3, 1e-3, None, 0, None, ctypes.byref(h)) == 1
     assert L.tucker_batch_create(2, None, 0, good, 3, 1e-3, None, 0, None, ctypes.byref(h)) == 1
     assert L.tucker_batch_create(2, ptrs, 0, tk._i64([16, 20, 0, 40, 50, 60]), 3, 1e-3, None, 0, None,
                                  ctypes.byref(h)) == 1
