@@ -90,20 +90,6 @@ __device__ __forceinline__ double block_max(double v, double* sred) {
 // positions k+2..J-1 (implicit 1 at k+1).
 constexpr int kRegMaxJ = 208;
 
-template <int NW, int NG, int NC>
-__device__ __forceinline__ void write_row(int k, int wave, int rs, int c, const double (&a)[NG][NC], double* sx) {
-  const int blk = k >> 2;
-  if (wave == blk % NW && rs == (k & 3)) {
-    const int gk = blk / NW;
-#pragma unroll
-    for (int g = 0; g < NG; ++g)
-      if (g == gk) {
-#pragma unroll
-        for (int cc = 0; cc < NC; ++cc) sx[c + 16 * cc] = a[g][cc];
-      }
-  }
-}
-
 // Householder scalars of a step from alpha = a_k,k+1 and sigma =
 // sum_{j >= k+2} a_kj^2: beta = -sign(alpha) sqrt(alpha^2 + sigma),
 // tau = (beta - alpha) / beta, scale = 1 / (alpha - beta); tau = scale = 0
