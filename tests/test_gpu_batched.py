@@ -180,3 +180,36 @@ def test_batched_graph_replay(tk, batch48):
             assert torch.equal(b.item(i).core, ref_cores[i]), (rep, i)
         del junk
     b.free()
+
+
+def test_batched_count_above_grid_y_limit(tk, orc):
+    """70000 tensors of 4 x 4 x 4 (Tucker ranks 2, 2, 2, noise 1e-6), more than
+    a grid's y dimension holds (65535): every batched launch keeps the tensor
+    index on x.  All ranks are 2, the norms equal numpy's, and sampled tensors
+    match the oracle (ranks, relative error) and the single-tensor call."""
+    count, eps = 70000, 1e-3
+    rng = np.random.default_rng(70000)
+    U = [np.linalg.qr(rng.standard_normal((count, 4, 2)))[0] for _ in range(3)]
+    G = rng.standard_normal((count, 2, 2, 2))
+    X = np.einsum("tabc,tia,tjb,tkc->tijk", G, U[0], U[1], U[2])
+    X = (X + 1e-6 * rng.standard_normal(X.shape)).astype(np.float32)
+    print(f"batched count={count}", flush=True)
+    flat = torch.from_numpy(X).to("cuda")  # one buffer; tensor t is the 256-byte slice t
+    xs = [flat[t] for t in range(count)]
+    b = tk.Batch(xs, eps, prec="fp64", dims=[[4, 4, 4]] * count)
+    b.run()
+    assert all(r == [2, 2, 2] for r in b.ranks())
+    nx2 = np.sum(X.astype(np.float64) ** 2, axis=(1, 2, 3))
+    np.testing.assert_allclose(np.array(b.norm2()), nx2, rtol=1e-12)
+    assert not any(b.status())
+    for t in (0, 1, 65534, 65535, 65536, count - 1):
+        Xt = X[t].astype(np.float64).reshape(-1)
+        ref = orc.sthosvd(Xt, [4, 4, 4], eps)
+        it = b.item(t)
+        assert list(it.ranks) == ref.ranks == [2, 2, 2]
+        assert abs(relerr(it, xs[t]) - orc.relerr(Xt, ref)) <= 1e-7
+        single = tk.sthosvd(xs[t], eps, dims=[4, 4, 4])
+        assert list(single.ranks) == [2, 2, 2]
+        it.free()
+        single.free()
+    b.free()
