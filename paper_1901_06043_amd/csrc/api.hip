@@ -478,7 +478,7 @@ struct HandleGuard {
 };
 
 struct Events {
-  hipEvent_t ev[5 * TUCKER_MAX_MODES] = {nullptr};
+  hipEvent_t ev[7 * TUCKER_MAX_MODES] = {nullptr};
   int n = 0;
   ~Events() {
     for (int i = 0; i < n; ++i) (void)hipEventDestroy(ev[i]);
@@ -702,7 +702,7 @@ tucker_status sthosvd_impl(const void* data, tucker_dtype dtype, const int64_t* 
   double* h_nx2 = reinterpret_cast<double*>(static_cast<char*>(hp) + 16);
 
   Events evs;
-  HIP_TRY(evs.create(5 * N));
+  HIP_TRY(evs.create(7 * N));  // 5 per step, then 2 per deferred product
   hipEvent_t rank_ready = nullptr;
   HIP_TRY(hipEventCreateWithFlags(&rank_ready, hipEventDisableTiming));
   struct EventGuard {
@@ -722,6 +722,7 @@ tucker_status sthosvd_impl(const void* data, tucker_dtype dtype, const int64_t* 
   HIP_TRY(ewbuf.alloc(sizeof(double) * tk::eig_work_doubles(maxJ), stream));
   const double thr_mul = fixed_ranks ? 0.0 : eps * eps / N;
   bool padded = false;  // some working extent exceeds its rank (working_rank)
+  int ndef = 0, defm[TUCKER_MAX_MODES];  // modes whose product is deferred to the end
 
   for (int step = 0; step < N; ++step) {
     const int n = order[step];
@@ -808,6 +809,16 @@ tucker_status sthosvd_impl(const void* data, tucker_dtype dtype, const int64_t* 
       t->norm2 = nx2;
     }
     t->ranks[n] = R;
+    // A mode kept at full rank (R = J) is an orthogonal change of basis, under
+    // which the Gram Y_(m) Y_(m)^T of every other mode m is invariant: its
+    // product commutes with the later ones and changes none of their Grams,
+    // so it is applied last, to the core-sized tensor (FP64 form; never the
+    // last step itself).
+    if (R == J && !reduced && step < N - 1) {
+      defm[ndef++] = n;
+      HIP_TRY(hipEventRecord(ev[3], stream));
+      continue;
+    }
     // working extent (R, or R + 1 with a zero column R of U_n)
     const int64_t Rw = working_rank(cur, N, order, step, R, reduced);
     if (Rw != R) {
@@ -882,6 +893,29 @@ tucker_status sthosvd_impl(const void* data, tucker_dtype dtype, const int64_t* 
     ybuf.s = stream;
     cbuf.p = nullptr;
   }
+  // the deferred full-rank products (Y <- Y x_m U_m^T), on the compact core
+  // (ybuf holds it, of sizes R_0 .. R_{N-1}: the last step always runs its
+  // product)
+  Y = ybuf.p;
+  ydt = TUCKER_F64;
+  std::memcpy(cur, t->ranks, sizeof(int64_t) * N);
+  for (int i = 0; i < ndef; ++i) {
+    const int m = defm[i];
+    int64_t total = 1;
+    for (int k = 0; k < N; ++k) total *= cur[k];
+    if (!async && (st = fits(round_bytes(sizeof(double) * total), "the core"))) return st;
+    TmpBuf nbuf;
+    HIP_TRY(nbuf.alloc(sizeof(double) * total, stream));
+    HIP_TRY(hipEventRecord(evs.ev[5 * N + 2 * i], stream));
+    if ((st = run_ttm(Y, ydt, cur, N, m, t->U[m], cur[m], cur[m], 1, nbuf.p, TUCKER_F64, false, stream))) return st;
+    HIP_TRY(hipEventRecord(evs.ev[5 * N + 2 * i + 1], stream));
+    ybuf.release();
+    ybuf.p = nbuf.p;
+    ybuf.s = stream;
+    nbuf.p = nullptr;
+    Y = ybuf.p;
+    ydt = TUCKER_F64;
+  }
   // the last Y is the core; hand ownership to the handle
   t->core = ybuf.p;
   t->owned.push_back(ybuf.p);
@@ -906,6 +940,11 @@ tucker_status sthosvd_impl(const void* data, tucker_dtype dtype, const int64_t* 
     t->ms[4 * n + 1] = b;
     t->ms[4 * n + 2] = c;
     t->ms[4 * n + 3] = k;
+  }
+  for (int i = 0; i < ndef; ++i) {
+    float c = 0;
+    HIP_TRY(hipEventElapsedTime(&c, evs.ev[5 * N + 2 * i], evs.ev[5 * N + 2 * i + 1]));
+    t->ms[4 * defm[i] + 2] = c;
   }
   *out = g.take();
   return TUCKER_OK;

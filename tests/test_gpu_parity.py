@@ -301,6 +301,50 @@ def test_padded_working_extent(tk, orc, order, given_ranks):
     assert abs(e - orc.relerr(X, ref)) <= 1e-10
 
 
+@pytest.mark.parametrize("order", [[0, 1, 2, 3], [1, 0, 3, 2], [2, 1, 0, 3], [3, 2, 1, 0]])
+@pytest.mark.parametrize("given_ranks", [False, True])
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_full_rank_mode_product_deferred(tk, orc, order, given_ranks, dtype):
+    """Mode 1 keeps its full rank (R_1 = J_1 = 6): its product is a change of
+    basis that leaves the later Grams unchanged, so it runs last, on the
+    compact core (after the zero slice of the odd rank R_0 = 5 is dropped).
+    Ranks, core and factors equal the oracle's up to column signs, and the
+    error identity holds, in four orders (mode 1 first, in the middle and
+    last), with eps and with given ranks, for float32 and float64 input."""
+    dims, ranks = [41, 6, 26, 30], [5, 6, 7, 9]
+    X, dims = synthetic.random_tucker(dims, ranks, 1e-6, seed=31)
+    if dtype == torch.float32:
+        X = X.astype(np.float32).astype(np.float64)
+    print(f"deferred full-rank product order={order} given_ranks={given_ranks} dtype={dtype}", flush=True)
+    x = to_dev(X, dims, dtype)
+    if given_ranks:
+        t = tk.sthosvd_ranks(x, ranks, mode_order=order, dims=dims)
+        ref = orc.sthosvd(X, dims, 0.0, order, ranks=ranks)
+    else:
+        t = tk.sthosvd(x, 1e-4, mode_order=order, dims=dims)
+        ref = orc.sthosvd(X, dims, 1e-4, order)
+    assert t.ranks == ref.ranks == ranks
+    G = t.core.cpu().numpy().reshape(-1)
+    assert G.size == int(np.prod(ranks))
+    Gs = G.reshape(ranks[::-1])
+    Gr = ref.core.reshape(ranks[::-1])
+    # the core up to the column signs of the factors
+    sg = []
+    for n in range(4):
+        U = t.factor(n).cpu().numpy()
+        Ur = ref.factors[n]
+        sgn = np.sign(np.sum(U * Ur, axis=0))
+        assert np.abs(U - Ur * sgn).max() <= 1e-9
+        sg.append(sgn)
+    S = np.einsum("a,b,c,d->dcba", sg[0], sg[1], sg[2], sg[3])
+    assert np.abs(Gs - Gr * S).max() <= 1e-10 * np.abs(Gr).max()
+    xh = t.reconstruct(out_dtype=torch.float64)
+    e = float(torch.linalg.vector_norm((x.to(torch.float64) - xh).reshape(-1))
+              / torch.linalg.vector_norm(x.to(torch.float64).reshape(-1)))
+    assert abs(e - orc.relerr(X, ref)) <= 1e-10
+    t.free()
+
+
 @pytest.mark.parametrize("order", [[0, 1, 2], [1, 0, 2]])
 @pytest.mark.parametrize("given_ranks", [False, True])
 def test_padded_extent_compact_last_product(tk, orc, order, given_ranks):
