@@ -98,10 +98,11 @@ __global__ __launch_bounds__(kSNT) void gram_stream_kernel(StreamParams g) {
   double sq = 0.0;
   int since_promote = 0;
 
-  for (int64_t grp = wid; grp < g.ngroups; grp += g.nwaves) {
+  // raw[rb][j]: row 16 rb + i, column c0 + j of a group, as loaded; the loads
+  // of group grp + nwaves are issued before the products of group grp
+  T raw[NB][CPL];
+  auto load = [&](int64_t grp) {
     const uint64_t c0 = (uint64_t)grp * G + (uint64_t)(CPL * q);  // this lane's first column
-    // v[rb][j]: row 16 rb + i, column c0 + j
-    double v[NB][CPL];
 #pragma unroll
     for (int rb = 0; rb < NB; ++rb) {
       const int row = 16 * rb + i;
@@ -109,56 +110,63 @@ __global__ __launch_bounds__(kSNT) void gram_stream_kernel(StreamParams g) {
       if constexpr (VEC == 1) {
         // CPL consecutive columns within one block of the unfolding
         const bool cok = rok && c0 < K;
-        int64_t base = 0;
-        if (cok) {
-          const uint64_t r = c0 / L, l = c0 - r * L;
-          base = (int64_t)l + JL * (int64_t)r + (int64_t)L * row;
-        }
         if (cok) {
           // 16-byte vector loads: base is a multiple of CPL and Y is 16-byte aligned
-          const T* src = Y + base;
+          const uint64_t r = c0 / L, l = c0 - r * L;
+          const T* src = Y + ((int64_t)l + JL * (int64_t)r + (int64_t)L * row);
           if constexpr (sizeof(T) == 4) {
 #pragma unroll
             for (int j = 0; j < CPL; j += 4) {
               const float4 f = *reinterpret_cast<const float4*>(src + j);
-              v[rb][j] = f.x;
-              v[rb][j + 1] = f.y;
-              v[rb][j + 2] = f.z;
-              v[rb][j + 3] = f.w;
+              raw[rb][j] = f.x;
+              raw[rb][j + 1] = f.y;
+              raw[rb][j + 2] = f.z;
+              raw[rb][j + 3] = f.w;
             }
           } else {
 #pragma unroll
             for (int j = 0; j < CPL; j += 2) {
               const double2 d = *reinterpret_cast<const double2*>(src + j);
-              v[rb][j] = d.x;
-              v[rb][j + 1] = d.y;
+              raw[rb][j] = d.x;
+              raw[rb][j + 1] = d.y;
             }
           }
         } else {
 #pragma unroll
-          for (int j = 0; j < CPL; ++j) v[rb][j] = 0.0;
+          for (int j = 0; j < CPL; ++j) raw[rb][j] = (T)0;
         }
       } else if constexpr (VEC == 2) {
 #pragma unroll
         for (int j = 0; j < CPL; ++j) {
           const uint64_t c = c0 + j;
-          v[rb][j] = (rok && c < K) ? (double)Y[(int64_t)row + (int64_t)J * (int64_t)c] : 0.0;
+          raw[rb][j] = (rok && c < K) ? Y[(int64_t)row + (int64_t)J * (int64_t)c] : (T)0;
         }
       } else {
 #pragma unroll
         for (int j = 0; j < CPL; ++j) {
           const uint64_t c = c0 + j;
-          double x = 0.0;
+          T x = (T)0;
           if (rok && c < K) {
             const uint64_t r = c / L, l = c - r * L;
-            x = (double)Y[(int64_t)l + JL * (int64_t)r + (int64_t)L * row];
+            x = Y[(int64_t)l + JL * (int64_t)r + (int64_t)L * row];
           }
-          v[rb][j] = x;
+          raw[rb][j] = x;
         }
       }
-#pragma unroll
-      for (int j = 0; j < CPL; ++j) sq += v[rb][j] * v[rb][j];
     }
+  };
+  if (wid < g.ngroups) load(wid);
+  for (int64_t grp = wid; grp < g.ngroups; grp += g.nwaves) {
+    // v[rb][j]: row 16 rb + i, column c0 + j
+    double v[NB][CPL];
+#pragma unroll
+    for (int rb = 0; rb < NB; ++rb)
+#pragma unroll
+      for (int j = 0; j < CPL; ++j) {
+        v[rb][j] = (double)raw[rb][j];
+        sq += v[rb][j] * v[rb][j];
+      }
+    if (grp + g.nwaves < g.ngroups) load(grp + g.nwaves);  // uniform
     if constexpr (PREC == 0) {
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
