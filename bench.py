@@ -360,8 +360,8 @@ def main():
     ap.add_argument("--form-reps", type=int, default=3, help="timed compressions per form in extra sections")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: every GPU box of this build has one GPU and the library has "
-              "no multi-GPU path; run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path (its sharding is a design, "
+              "not code); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
