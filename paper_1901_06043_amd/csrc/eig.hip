@@ -2026,10 +2026,15 @@ __global__ __launch_bounds__(256) void eig_back_direct_kernel(const double* __re
 }
 
 // Batched back-transformation with one workgroup per matrix: its reflectors
-// (J <= 128: at most 128 KB) are read once into LDS, then each of the 16
+// are read once into LDS, packed (v_k's entries k + 2 .. J - 1 only: at most
+// 63 KB at J = 128, so that two matrices share a CU), then each of the 16
 // waves applies them to every 16th vector from LDS.  Reading each reflector
 // from global memory once per vector made every step of the sequence wait
 // for a global load.
+__host__ __device__ constexpr int back_packed_offset(int J, int k) { return k * (J - 2) - k * (k - 1) / 2; }
+inline size_t back_batched_lds_bytes(int J) {
+  return sizeof(double) * ((size_t)back_packed_offset(J, J - 2 > 0 ? J - 2 : 0) + (size_t)J);
+}
 __global__ __launch_bounds__(1024) void eig_back_batched_lds(EigBatch b) {
   extern __shared__ double sh[];
   int m, J;
@@ -2037,10 +2042,14 @@ __global__ __launch_bounds__(1024) void eig_back_batched_lds(EigBatch b) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int R = (int)b.R[m];
   const int64_t o2 = (int64_t)m * b.Jmax * b.Jmax, o1 = (int64_t)m * b.Jmax;
-  double* sH = sh;                        // [J][J]: row k holds v_k at k + 2 .. J - 1
-  double* stau = sh + (int64_t)J * J;     // [J]
+  // sP[back_packed_offset(J, k) + r - k - 2] = v_k[r], r = k + 2 .. J - 1
+  double* sP = sh;
+  double* stau = sh + (J > 2 ? back_packed_offset(J, J - 2) : 0);  // [J]
   const double* H = b.A + o2;
-  for (int x = tid; x < J * J; x += 1024) sH[x] = H[x];
+  for (int k = wave; k + 2 < J; k += 16) {
+    const int ok = back_packed_offset(J, k) - k - 2;
+    for (int r = k + 2 + lane; r < J; r += 64) sP[ok + r] = H[(int64_t)k * J + r];
+  }
   for (int x = tid; x < J; x += 1024) stau[x] = b.tau[o1 + x];
   __syncthreads();
   const double* Zt = b.Zt + o2;
@@ -2060,7 +2069,7 @@ __global__ __launch_bounds__(1024) void eig_back_batched_lds(EigBatch b) {
 #pragma unroll
       for (int u = 0; u < 2; ++u) {
         const int r = lane + 64 * u;
-        v[u] = (r == k + 1) ? 1.0 : ((r > k + 1 && r < J) ? sH[k * J + r] : 0.0);
+        v[u] = (r == k + 1) ? 1.0 : ((r > k + 1 && r < J) ? sP[back_packed_offset(J, k) - k - 2 + r] : 0.0);
         s = fma(v[u], z[u], s);
       }
       s = wave_sum_fast(s) * tk;
@@ -2254,7 +2263,7 @@ hipError_t launch_eig_truncate_batched(const EigBatch& b, double thr_mul, hipStr
                      stream, b, nvw);
   hipLaunchKernelGGL(eig_orth_batched, dim3(nb), dim3(kEigThreads),
                      sizeof(double) * ((size_t)J + 16 + (size_t)orth_cap_batched(J)), stream, b);
-  hipLaunchKernelGGL(eig_back_batched_lds, dim3(nb), dim3(1024), sizeof(double) * ((size_t)J * J + J), stream, b);
+  hipLaunchKernelGGL(eig_back_batched_lds, dim3(nb), dim3(1024), back_batched_lds_bytes(J), stream, b);
   return hipGetLastError();
 }
 
