@@ -812,8 +812,10 @@ tucker_status sthosvd_impl(const void* data, tucker_dtype dtype, const int64_t* 
     // A mode kept at full rank (R = J) is an orthogonal change of basis, under
     // which the Gram Y_(m) Y_(m)^T of every other mode m is invariant: its
     // product commutes with the later ones and changes none of their Grams,
-    // so it is applied last, to the core-sized tensor (FP64 form; never the
-    // last step itself).
+    // so it is applied last, to the core-sized tensor (never the last step
+    // itself).  FP64 form only: the reduced forms keep Alg. 1's order, so that
+    // their rounding (and any rank it moves at a threshold tie) is that of
+    // the mode loop composed from the single-step calls.
     if (R == J && !reduced && step < N - 1) {
       defm[ndef++] = n;
       HIP_TRY(hipEventRecord(ev[3], stream));
@@ -894,27 +896,26 @@ tucker_status sthosvd_impl(const void* data, tucker_dtype dtype, const int64_t* 
     cbuf.p = nullptr;
   }
   // the deferred full-rank products (Y <- Y x_m U_m^T), on the compact core
-  // (ybuf holds it, of sizes R_0 .. R_{N-1}: the last step always runs its
-  // product)
+  // (ybuf holds it, of sizes R_0 .. R_{N-1} in the working type: the last
+  // step always runs its product)
   Y = ybuf.p;
-  ydt = TUCKER_F64;
+  ydt = wdt;
   std::memcpy(cur, t->ranks, sizeof(int64_t) * N);
   for (int i = 0; i < ndef; ++i) {
     const int m = defm[i];
     int64_t total = 1;
     for (int k = 0; k < N; ++k) total *= cur[k];
-    if (!async && (st = fits(round_bytes(sizeof(double) * total), "the core"))) return st;
+    if (!async && (st = fits(round_bytes(dtype_size(wdt) * total), "the core"))) return st;
     TmpBuf nbuf;
-    HIP_TRY(nbuf.alloc(sizeof(double) * total, stream));
+    HIP_TRY(nbuf.alloc(dtype_size(wdt) * total, stream));
     HIP_TRY(hipEventRecord(evs.ev[5 * N + 2 * i], stream));
-    if ((st = run_ttm(Y, ydt, cur, N, m, t->U[m], cur[m], cur[m], 1, nbuf.p, TUCKER_F64, false, stream))) return st;
+    if ((st = run_ttm(Y, ydt, cur, N, m, t->U[m], cur[m], cur[m], 1, nbuf.p, wdt, reduced, stream))) return st;
     HIP_TRY(hipEventRecord(evs.ev[5 * N + 2 * i + 1], stream));
     ybuf.release();
     ybuf.p = nbuf.p;
     ybuf.s = stream;
     nbuf.p = nullptr;
     Y = ybuf.p;
-    ydt = TUCKER_F64;
   }
   // the last Y is the core; hand ownership to the handle
   t->core = ybuf.p;
