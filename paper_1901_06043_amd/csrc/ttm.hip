@@ -187,13 +187,14 @@ __device__ __forceinline__ void use4(const Raw4<TI>& r, bool cok, int J, int jb,
 // NW: waves per workgroup.  One workgroup tile: output rows
 // [64 rt, 64 rt + 16 RB) and columns [16 NW CG ct, 16 NW CG (ct + 1)) (16 CG
 // per wave); 16-row blocks that lie wholly beyond K are skipped.
+// sM: kTK * MLds<CT>::S values of LDS for the M block (64 output rows x 64
+// reduction rows).
 template <typename TI, typename TO, typename CT, bool UNIT_L, int RB, int VW, int CG, int NW>
-__device__ __forceinline__ void ttm_tile(const TI* __restrict__ Y, int J, uint32_t L, uint32_t cols,
-                                         const double* __restrict__ M, int64_t msk, int64_t msj, int K,
-                                         TO* __restrict__ Z, int64_t ct, int rt) {
+__device__ __forceinline__ void ttm_tile_s(const TI* __restrict__ Y, int J, uint32_t L, uint32_t cols,
+                                           const double* __restrict__ M, int64_t msk, int64_t msj, int K,
+                                           TO* __restrict__ Z, int64_t ct, int rt, CT* sM) {
   using A = Acc<CT>;
   using ML = MLds<CT>;
-  __shared__ __align__(16) CT sM[kTK * ML::S];  // M block: 64 output rows x 64 reduction rows
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t c0 = (ct * NW + wave) * 16 * CG;  // this wave's first column
   const int k0 = rt * kTK;
@@ -284,6 +285,14 @@ __device__ __forceinline__ void ttm_tile(const TI* __restrict__ Y, int J, uint32
   }
 }
 
+template <typename TI, typename TO, typename CT, bool UNIT_L, int RB, int VW, int CG, int NW>
+__device__ __forceinline__ void ttm_tile(const TI* __restrict__ Y, int J, uint32_t L, uint32_t cols,
+                                         const double* __restrict__ M, int64_t msk, int64_t msj, int K,
+                                         TO* __restrict__ Z, int64_t ct, int rt) {
+  __shared__ __align__(16) CT sM[kTK * MLds<CT>::S];
+  ttm_tile_s<TI, TO, CT, UNIT_L, RB, VW, CG, NW>(Y, J, L, cols, M, msk, msj, K, Z, ct, rt, sM);
+}
+
 template <typename TI, typename TO, typename CT, bool UNIT_L, int RB, int VW>
 __global__ __launch_bounds__(64 * kTileWaves) void ttm_kernel(const TI* __restrict__ Y, int J, uint32_t L,
                                                               uint32_t cols, const double* __restrict__ M,
@@ -295,11 +304,104 @@ __global__ __launch_bounds__(64 * kTileWaves) void ttm_kernel(const TI* __restri
                                                                          item / nrt, (int)(item % nrt));
 }
 
+// Batched item with the factor resident in LDS (K <= 32, J <= kBatchMaxJ):
+// the workgroup stages M = U_t^T (32 rows, J padded to 16) once and walks
+// the item's column tiles [ct0, ct1) of 16 columns per wave; each lane issues
+// the loads of all 16-row blocks of its column before the products.  (The
+// generic tile stages a 64 x 64 block of M for every tile, as many values as
+// the tile's Y block when J <= 64.)
+constexpr int kResBatchRows = 32;
+template <typename CT>
+constexpr int res_batch_lds() {
+  return kResBatchRows * ((sizeof(CT) == 4) ? (((kBatchMaxJ + 63) & ~63) + 4) : (((kBatchMaxJ + 31) & ~31) + 2));
+}
+template <typename TI, typename TO, typename CT, bool UNIT_L>
+__device__ __forceinline__ void ttm_batch_resident(const TI* __restrict__ Y, int J, uint32_t L, uint32_t cols,
+                                                   const double* __restrict__ U, int K, TO* __restrict__ Z,
+                                                   int64_t ct0, int64_t ct1, CT* sM) {
+  using A = Acc<CT>;
+  using ML = MLds<CT>;
+  constexpr int RB = kResBatchRows / 16, NJ = kBatchMaxJ / 16;
+  const int nj = (J + 15) / 16;
+  const int jp = 16 * nj;
+  const int ldm = ML::ld(jp);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int e = tid; e < kResBatchRows * jp; e += 64 * kWaves) {
+    const int k = e / jp, j = e - k * jp;
+    sM[k * ldm + j] = (k < K && j < J) ? (CT)U[(int64_t)k * J + j] : (CT)0;
+  }
+  __syncthreads();
+  const int q = lane >> 4, i = lane & 15;
+  const int64_t JL = (int64_t)J * L;
+  for (int64_t ct = ct0; ct < ct1; ++ct) {
+    const int64_t c = (ct * kWaves + wave) * 16 + i;  // this lane's column
+    const bool cok = c < (int64_t)cols;
+    const int64_t ca = cok ? c : (int64_t)cols - 1;  // clamped, for addresses only
+    int64_t cbase;
+    if constexpr (UNIT_L) {
+      cbase = (int64_t)J * ca;
+    } else {
+      const uint32_t cc = (uint32_t)ca;
+      const uint32_t r = cc / L, l = cc - r * L;
+      cbase = (int64_t)l + JL * r;
+    }
+    typename A::type acc[RB];
+#pragma unroll
+    for (int b = 0; b < RB; ++b) acc[b] = typename A::type{0, 0, 0, 0};
+    // the blocks in two halves of NJ / 2, all loads of a half issued first
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      if (h * (NJ / 2) >= nj) break;  // uniform
+      Raw4<TI> raw[NJ / 2];
+#pragma unroll
+      for (int u = 0; u < NJ / 2; ++u)
+        if (h * (NJ / 2) + u < nj) issue4<TI, UNIT_L, 1>(Y, cbase, J, L, h * (NJ / 2) + u, q, raw[u]);  // uniform
+#pragma unroll
+      for (int u = 0; u < NJ / 2; ++u) {
+        const int jb = h * (NJ / 2) + u;
+        if (jb >= nj) break;  // uniform
+        CT y[4];
+        use4<TI, CT, UNIT_L>(raw[u], cok, J, jb, q, y);
+#pragma unroll
+        for (int b = 0; b < RB; ++b) {
+          if (16 * b >= K) break;  // uniform: a block of padding rows
+          CT a4[4];
+          ML::read4(&sM[(16 * b + i) * ldm + 16 * jb + 4 * q], a4);
+#pragma unroll
+          for (int s2 = 0; s2 < 4; ++s2) acc[b] = A::mfma(a4[s2], y[s2], acc[b]);
+        }
+      }
+    }
+    if (!cok) continue;
+    int64_t zb, kstride;
+    if constexpr (UNIT_L) {
+      zb = (int64_t)K * c;
+      kstride = 1;
+    } else {
+      const uint32_t cc = (uint32_t)c;
+      const uint32_t r = cc / L, l = cc - r * L;
+      zb = (int64_t)l + (int64_t)L * K * r;
+      kstride = L;
+    }
+#pragma unroll
+    for (int b = 0; b < RB; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int k = 16 * b + A::row(q, v);
+        if (k < K) store_as(&Z[zb + kstride * k], (double)acc[b][v]);
+      }
+  }
+}
+
 // Batched form: item i covers column tiles [ct0, ct1) of tensor t (planned
 // from upper bounds of the sizes); the current sizes and the rank R_t come
-// from the device, every row tile of R_t is computed, and M = U_t^T.
+// from the device, every row tile of R_t is computed, and M = U_t^T.  Ranks
+// up to 32 keep M resident (ttm_batch_resident); larger ones take the
+// generic tile, which stages M per tile.
 template <typename TI, typename TO, typename CT, bool UNIT_L>
 __global__ __launch_bounds__(256) void ttm_batch_kernel(TtmBatch b) {
+  constexpr int kLds = res_batch_lds<CT>() > kTK * MLds<CT>::S ? res_batch_lds<CT>() : kTK * MLds<CT>::S;
+  __shared__ __align__(16) CT sM[kLds];
   const int64_t* d = b.items + 3 * (int64_t)blockIdx.x;
   const int t = (int)d[0];
   const int J = b.J[t];
@@ -315,9 +417,13 @@ __global__ __launch_bounds__(256) void ttm_batch_kernel(TtmBatch b) {
   const TI* Y = static_cast<const TI*>(b.Y[t]);
   TO* Z = static_cast<TO*>(b.Z[t]);
   const double* U = b.U + (int64_t)t * b.Jmax * b.Jmax;
+  if (K <= kResBatchRows && J <= kBatchMaxJ) {
+    ttm_batch_resident<TI, TO, CT, UNIT_L>(Y, J, (uint32_t)L, (uint32_t)cols, U, K, Z, d[1], ct1, sM);
+    return;
+  }
   for (int64_t ct = d[1]; ct < ct1; ++ct)
     for (int rt = 0; rt * kTK < K; ++rt)
-      ttm_tile<TI, TO, CT, UNIT_L, 4, 1, 1, kWaves>(Y, J, (uint32_t)L, (uint32_t)cols, U, J, 1, K, Z, ct, rt);
+      ttm_tile_s<TI, TO, CT, UNIT_L, 4, 1, 1, kWaves>(Y, J, (uint32_t)L, (uint32_t)cols, U, J, 1, K, Z, ct, rt, sM);
 }
 
 // Resident-M variant for K <= 64 with M (K_pad x J) small enough for LDS:
