@@ -810,13 +810,11 @@ tucker_status sthosvd_impl(const void* data, tucker_dtype dtype, const int64_t* 
     }
     t->ranks[n] = R;
     // A mode kept at full rank (R = J) is an orthogonal change of basis, under
-    // which the Gram Y_(m) Y_(m)^T of every other mode m is invariant: its
-    // product commutes with the later ones and changes none of their Grams,
-    // so it is applied last, to the core-sized tensor (never the last step
-    // itself).  FP64 form only: the reduced forms keep Alg. 1's order, so that
-    // their rounding (and any rank it moves at a threshold tie) is that of
-    // the mode loop composed from the single-step calls.
-    if (R == J && !reduced && step < N - 1) {
+    // which the Gram Y_(m) Y_(m)^T of every other mode m is invariant (and so
+    // is ||Y||, which the range guards compare with): its product commutes
+    // with the later ones and changes none of their Grams, so it is applied
+    // last, to the core-sized tensor (never the last step itself).
+    if (R == J && step < N - 1) {
       defm[ndef++] = n;
       HIP_TRY(hipEventRecord(ev[3], stream));
       continue;
