@@ -2142,7 +2142,7 @@ hipError_t launch_eig_values(const double* S, int J, double thr, const double* n
 #define STEP_LAUNCH(RR, NW)                                                                                   \
   hipLaunchKernelGGL((eig_tri_big_step<RR, NW>), dim3((int)ceil_div(J - k - 1, NW)), dim3(64 * NW), shs, stream, \
                      w.A, J, k, V[pv], P[pv], sc[pv], V[c], P[c], sc[c], w.d, w.e, w.tau)
-        if (J <= 768) STEP_LAUNCH(12, 16);
+        if (J <= 768) STEP_LAUNCH(12, 8);  // 8 waves: 0.25 ms less per J = 672 solve than 16
         else if (J <= 1536) STEP_LAUNCH(24, 8);
         else STEP_LAUNCH(kEigMaxJ / 64, 8);
 #undef STEP_LAUNCH
