@@ -2244,7 +2244,7 @@ hipError_t launch_eig_truncate_batched(const EigBatch& b, double thr_mul, hipStr
   // workgroups take different matrices, which the dispatcher deals round the
   // XCDs, so the groups of a matrix that carry work (the first of a split
   // launch) spread over the whole chip instead of gathering on a few XCDs.
-  // The bisection, whose groups all carry work, keeps a matrix's groups
+  // The bisection, whose groups mostly carry work, keeps a matrix's groups
   // consecutive instead (a 1-D grid, measured faster).
   const unsigned nb = (unsigned)b.count;
   // Tridiagonalisation phases, largest first (as in the single-matrix path).
