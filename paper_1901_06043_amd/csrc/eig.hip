@@ -623,6 +623,40 @@ __device__ __forceinline__ int sturm_count(const double* sd, const double* se2, 
   return cnt;
 }
 
+// Starting intervals from geometric brackets: the Sturm counts at 0 and at
+// tnorm * 10^-k, k = 15 .. 0 (one per lane of the first wave), after which
+// eigenvalue a starts from the tightest bracket [x, y] with count(x) <= a <
+// count(y) inside the Gershgorin interval.  A Gram matrix's eigenvalues span
+// many decades and most are small, so each starts from an interval about its
+// own size instead of the whole spectrum: several multisection rounds fewer
+// for the small ones.
+constexpr int kGeoPts = 17;
+__device__ __forceinline__ void geo_brackets(const double* sd, const double* se2, int J, const TriBounds& b,
+                                             double* sx, int* scnt) {
+  const int tid = threadIdx.x;
+  if (tid < kGeoPts) {
+    double x = 0.0;
+    if (tid > 0) {
+      x = b.tnorm;  // tnorm * 10^-(kGeoPts - 1 - tid)
+      for (int k = tid; k < kGeoPts - 1; ++k) x *= 0.1;
+    }
+    sx[tid] = x;
+    scnt[tid] = sturm_count(sd, se2, J, x, b.pivmin);
+  }
+  __syncthreads();
+}
+__device__ __forceinline__ void geo_start(const double* sx, const int* scnt, int a, const TriBounds& b, double& lo,
+                                          double& hi) {
+  lo = b.glo;
+  hi = b.ghi;
+  for (int p = 0; p < kGeoPts; ++p) {
+    const double x = sx[p];
+    const int c = scnt[p];
+    if (c <= a && x > lo) lo = x;
+    if (c > a && x < hi) hi = x;
+  }
+}
+
 // 256 threads, LANES per eigenvalue (LANES interior points per round), used
 // by the batched form with 4 lanes: a batch holds thousands of eigenvalues,
 // so the total number of Sturm counts (LANES x rounds: 4 x ~23 against
@@ -637,7 +671,10 @@ __device__ __forceinline__ void bisect_body(const double* __restrict__ d, const 
   double* sd = sh;            // J
   double* se2 = sh + J;       // J
   double* sred = sh + 2 * J;  // 4
+  __shared__ double sgx[kGeoPts];
+  __shared__ int sgc[kGeoPts];
   const TriBounds b = tri_bounds(d, e, J, sd, se2, sred);
+  geo_brackets(sd, se2, J, b, sgx, sgc);
   const int tid = threadIdx.x, lane = tid & 63;
   const int q = lane & (LANES - 1), gbase = lane & ~(LANES - 1);
   const int a = bx * (256 / LANES) + tid / LANES;  // ascending index
@@ -646,7 +683,8 @@ __device__ __forceinline__ void bisect_body(const double* __restrict__ d, const 
     scal[1] = b.pivmin;
   }
   if (a >= J) return;
-  double lo = b.glo, hi = b.ghi;
+  double lo, hi;
+  geo_start(sgx, sgc, a, b, lo, hi);
   for (int it = 0; it < 64 && (hi - lo) > b.atol; ++it) {
     const double h = (hi - lo) / (LANES + 1);
     const double sig = lo + h * (q + 1);
@@ -675,14 +713,18 @@ __global__ __launch_bounds__(256) void eig_bisect_wide_kernel(const double* __re
   double* se2 = sh + J;       // J
   double* sred = sh + 2 * J;  // 4
   __shared__ uint64_t sbal[4];
+  __shared__ double sgx[kGeoPts];
+  __shared__ int sgc[kGeoPts];
   const TriBounds b = tri_bounds(d, e, J, sd, se2, sred);
+  geo_brackets(sd, se2, J, b, sgx, sgc);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int a = blockIdx.x;  // ascending index
   if (a == 0 && tid == 0) {
     scal[0] = b.tnorm;
     scal[1] = b.pivmin;
   }
-  double lo = b.glo, hi = b.ghi;
+  double lo, hi;
+  geo_start(sgx, sgc, a, b, lo, hi);
   for (int it = 0; it < 64 && (hi - lo) > b.atol; ++it) {
     const double h = (hi - lo) / 257.0;
     const double sig = lo + h * (tid + 1);
