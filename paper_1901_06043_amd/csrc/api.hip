@@ -310,6 +310,17 @@ void left_right(const int64_t* dims, int N, int n, int64_t& L, int64_t& Rt) {
 
 constexpr int64_t kMaxEigJ = tk::kEigMaxJ;
 
+// Products of the direct-load tile-pair Gram for an arithmetic form and the
+// stride L of the mode's rows (0 FP64, 1 FP32, 3 BF16X6), or -1 where the
+// register-staged tile pairs are used: the reduced forms on row segments and
+// BF16X3 (two pieces, FP32 sums over 8 chunks), which measured faster there.
+int dma_gram_prec(tucker_gram_prec prec, int64_t L) {
+  if (prec == TUCKER_GRAM_FP64) return 0;
+  if (prec == TUCKER_GRAM_FP32 && L == 1) return 1;
+  if (prec == TUCKER_GRAM_BF16X6 && L == 1) return 3;
+  return -1;
+}
+
 // Gram of mode n of a tensor in (ptr, dtype) -> S (J x J FP64), optional norm.
 tucker_status run_gram(const void* Y, tucker_dtype dt, const int64_t* dims, int N, int n, tucker_gram_prec prec,
                        double* S, double* norm2, hipStream_t s, hipEvent_t after_main = nullptr) {
@@ -348,10 +359,10 @@ tucker_status run_gram(const void* Y, tucker_dtype dt, const int64_t* dims, int 
     return TUCKER_OK;
   }
   const int es = (dt == TUCKER_F64) ? 8 : 4;
-  // FP32 products: the direct-load kernel runs one workgroup per CU (its
-  // FP32 chunk sums and FP64 accumulators need more than 256 registers); it
-  // beat the register-staged kernel on unit-stride modes only
-  const int dprec = (prec == TUCKER_GRAM_FP64) ? 0 : ((prec == TUCKER_GRAM_FP32 && L == 1) ? 1 : -1);
+  // reduced forms: the direct-load kernel runs one workgroup per CU (its
+  // FP32 chunk sums or bf16 pieces and FP64 accumulators need more than 256
+  // registers)
+  const int dprec = dma_gram_prec(prec, L);
   if (dprec >= 0 && tk::gram_dma_eligible((int)J, (uint64_t)L, es, Y)) {
     // larger modes, FP64 or FP32 products: tile pairs staged by direct
     // global-to-LDS loads
@@ -545,12 +556,12 @@ int64_t gram_scratch_doubles(const int64_t* dims, int N, int n, tucker_gram_prec
   else if (prec == TUCKER_GRAM_FP64 && J <= tk::kTriMaxJ) p = tk::plan_gram_f64((int)J, (uint64_t)L, (uint64_t)K);
   else p = tk::plan_gram_mp((int)J, (uint64_t)K, (int)prec);
   int64_t need = p.part_elems + p.sq_elems;
-  if ((prec == TUCKER_GRAM_FP64 && J > tk::kTriMaxJ) || (prec == TUCKER_GRAM_FP32 && L == 1 && J > tk::kStreamMaxJ)) {
+  const int dprec = dma_gram_prec(prec, L);
+  if (dprec >= 0 && J > (dprec == 0 ? tk::kTriMaxJ : tk::kStreamMaxJ)) {
     // the tile-pair kernel with direct LDS loads (FP64: either input type;
-    // FP32 products: float input)
-    const int dprec = (prec == TUCKER_GRAM_FP64) ? 0 : 1;
+    // reduced forms: float input)
     for (int es : {4, 8}) {
-      if (dprec == 1 && es == 8) continue;
+      if (dprec >= 1 && es == 8) continue;
       if (tk::gram_dma_eligible((int)J, (uint64_t)L, es, nullptr)) {
         const tk::GramPlan d = tk::plan_gram_dma((int)J, (uint64_t)L, (uint64_t)K, es, dprec);
         need = std::max(need, d.part_elems + d.sq_elems);

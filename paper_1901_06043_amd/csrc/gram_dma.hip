@@ -1,7 +1,10 @@
 // Gram matrix S = Y_(n) Y_(n)^T (Alg. 2; flop count Sec. 7) for mode sizes
 // above the whole-triangle kernel's range: FP64 products of float or double
-// input, or (the FP32 form) FP32 MFMA products of float input summed in FP32
-// over each 32-column chunk and in FP64 across chunks.
+// input, or, for float input, FP32 MFMA products (the FP32 form) or the
+// three-piece bf16 split products of the BF16X6 form (b0 = bf16(x),
+// b1 = bf16(x - b0), b2 = bf16(x - b0 - b1); b2 c0 + b0 c2 + b1 c1 +
+// b1 c0 + b0 c1 + b0 c0 with v_mfma_f32_16x16x32_bf16), each summed in FP32
+// over a 32-column chunk and in FP64 across chunks.
 //
 // Work items: a pair of 128-row tiles (ta <= tb) and a contiguous range of
 // column chunks.  Four waves per workgroup; each holds a 64 x 64 part of the
@@ -209,12 +212,91 @@ struct Ops<T, 1> {
 // known only at run time (ragged last tiles), tested block by block.
 constexpr unsigned kGeneric = 0x10000u;
 
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+
+// The bf16 pieces of eight FP32 values: b0 = bf16(x), b1 = bf16(x - b0)
+// (x - b0 is exact in FP32) and b2 = bf16(x - b0 - b1).
+__device__ __forceinline__ void split8(const float (&v)[8], bf8 (&p)[3]) {
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const float x = v[e];
+    const __bf16 b0 = (__bf16)x;
+    const float r1 = x - (float)b0;
+    const __bf16 b1 = (__bf16)r1;
+    p[0][e] = b0;
+    p[1][e] = b1;
+    p[2][e] = (__bf16)(r1 - (float)b1);
+  }
+}
+
+// The eight FP32 values of one operand block that lane (i, q) supplies to a
+// bf16 MFMA (K = 32, 8 per lane group): slot e holds the column that the FP32
+// form reads at its step e (Img::col(e, q)); off is the block's group-0 byte
+// offset, d (layout 1) the distance to the lane's second unit.
+template <int LAY>
+__device__ __forceinline__ void read8(const char* buf, int off, int d, float (&v)[8]) {
+  if constexpr (LAY == 0) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) v[e] = *reinterpret_cast<const float*>(buf + off + e * 4 * Img<4, 0>::CB);
+  } else {
+    const float4 u0 = *reinterpret_cast<const float4*>(buf + off);
+    const float4 u1 = *reinterpret_cast<const float4*>(buf + off + d);
+    v[0] = u0.x; v[1] = u0.y; v[2] = u0.z; v[3] = u0.w;
+    v[4] = u1.x; v[5] = u1.y; v[6] = u1.z; v[7] = u1.w;
+  }
+}
+
+// BF16X6 products of one chunk (PREC 3).  The slot map of read8 is the same
+// for both operands, so slot e of lane group q is the same column in A and B.
+// The A blocks are split once per chunk, the B blocks one at a time; each
+// block's FP32 chunk sum, smallest terms first, is then added to its FP64
+// accumulator.
+template <unsigned MK, int LAY>
+__device__ __forceinline__ void compute_chunk_bf(const char* buf, const int (&oa)[4], const int (&ob)[4], int d,
+                                                 d4 (&acc)[4][4], unsigned mask) {
+  auto on = [&](int x, int y) {
+    return (MK == kGeneric) ? ((mask >> (4 * x + y)) & 1u) : ((MK >> (4 * x + y)) & 1u);
+  };
+  bf8 ap[4][3];
+#pragma unroll
+  for (int x = 0; x < 4; ++x) {
+    float v[8];
+    read8<LAY>(buf, oa[x], d, v);
+    split8(v, ap[x]);
+  }
+#pragma unroll
+  for (int y = 0; y < 4; ++y) {
+    float v[8];
+    read8<LAY>(buf, ob[y], d, v);
+    bf8 bp[3];
+    split8(v, bp);
+#pragma unroll
+    for (int x = 0; x < 4; ++x) {
+      if (on(x, y)) {
+        f4 c = f4{0.f, 0.f, 0.f, 0.f};
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ap[x][2], bp[0], c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ap[x][0], bp[2], c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ap[x][1], bp[1], c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ap[x][1], bp[0], c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ap[x][0], bp[1], c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ap[x][0], bp[0], c, 0, 0, 0);
+#pragma unroll
+        for (int v2 = 0; v2 < 4; ++v2) acc[x][y][v2] += (double)c[v2];
+      }
+    }
+  }
+}
+
 // PREC 0: FP64 products and accumulation.  PREC 1 (float input): FP32 MFMA
 // products accumulated in FP32 over the chunk's 32 columns, then added to
 // the FP64 accumulators.
 template <unsigned MK, typename T, int LAY, int PREC>
 __device__ __forceinline__ void compute_chunk(const char* buf, const int (&oa)[4], const int (&ob)[4], int d,
                                               d4 (&acc)[4][4], unsigned mask) {
+  if constexpr (PREC == 3) {
+    compute_chunk_bf<MK, LAY>(buf, oa, ob, d, acc, mask);
+    return;
+  }
   using O = Ops<T, LAY>;
   O cur, nxt;
   cur.d = nxt.d = d;
@@ -293,8 +375,8 @@ template <unsigned MK, typename T, int LAY, int PREC>
 __device__ __forceinline__ void chunk_loop(const DmaParams& g, int64_t split, int64_t ns, int64_t niter, char* buf0, char* buf1,
                                            int nslots, int r0a, int r0b, int wave, int lane, const int (&oa)[4],
                                            const int (&ob)[4], int d, d4 (&acc)[4][4], unsigned mask, double& sq) {
-  // PREC 1: diagonal items also sum the squares of their tile's rows
-  const bool dsq = (PREC == 1) && nslots == 1;
+  // reduced forms: diagonal items also sum the squares of their tile's rows
+  const bool dsq = (PREC >= 1) && nslots == 1;
   const int tid = 64 * wave + lane;
   if (niter <= 0) return;
   issue_chunk<T, LAY>(g, split, buf0, nslots, r0a, r0b, wave, lane);
@@ -303,7 +385,7 @@ __device__ __forceinline__ void chunk_loop(const DmaParams& g, int64_t split, in
   __syncthreads();
   for (int64_t t = 0;; t += 2) {
     if (t + 1 < niter) issue_chunk<T, LAY>(g, split + (t + 1) * ns, buf1, nslots, r0a, r0b, wave, lane);
-    if constexpr (PREC == 1)
+    if constexpr (PREC >= 1)
       if (dsq) sq += chunk_sq<LAY>(buf0, r0a, g.J, tid);
     compute_chunk<MK, T, LAY, PREC>(buf0, oa, ob, d, acc, mask);
     if (t + 1 >= niter) break;
@@ -311,7 +393,7 @@ __device__ __forceinline__ void chunk_loop(const DmaParams& g, int64_t split, in
     fill_chunk<T, LAY>(g, split + (t + 1) * ns, buf1, nslots, wave, lane);
     __syncthreads();
     if (t + 2 < niter) issue_chunk<T, LAY>(g, split + (t + 2) * ns, buf0, nslots, r0a, r0b, wave, lane);
-    if constexpr (PREC == 1)
+    if constexpr (PREC >= 1)
       if (dsq) sq += chunk_sq<LAY>(buf1, r0a, g.J, tid);
     compute_chunk<MK, T, LAY, PREC>(buf1, oa, ob, d, acc, mask);
     if (t + 2 >= niter) break;
@@ -322,11 +404,12 @@ __device__ __forceinline__ void chunk_loop(const DmaParams& g, int64_t split, in
 }
 
 // FP64 products: two workgroups per CU (at most 256 registers per lane).
-// FP32 products keep FP32 chunk sums beside the FP64 accumulators, which does
-// not fit 256 registers: one workgroup (one wave per SIMD) per CU.
+// The reduced forms keep FP32 chunk sums or bf16 pieces beside the FP64
+// accumulators, which does not fit 256 registers: one workgroup (one wave per
+// SIMD) per CU.
 template <typename T, int LAY, int PREC>
 __global__ __launch_bounds__(kDNT, PREC == 0 ? 2 : 1) void gram_dma_kernel(DmaParams g) {
-  static_assert(PREC == 0 || sizeof(T) == 4, "FP32 products read float input");
+  static_assert(PREC == 0 || sizeof(T) == 4, "the reduced forms read float input");
   using I = Img<sizeof(T), LAY>;
   __shared__ __attribute__((aligned(16))) char buf0[2 * I::TB];
   __shared__ __attribute__((aligned(16))) char buf1[2 * I::TB];
@@ -383,7 +466,7 @@ __global__ __launch_bounds__(kDNT, PREC == 0 ? 2 : 1) void gram_dma_kernel(DmaPa
   else DMA_LOOP(kGeneric);
 #undef DMA_LOOP
 
-  if constexpr (PREC == 1) {
+  if constexpr (PREC >= 1) {
     // the item's sum of squares (zero unless diagonal), in wave order
     __shared__ double sred[kDW];
     const double sw = wave_sum(sq);
@@ -451,7 +534,7 @@ GramPlan plan_gram_dma(int J, uint64_t L, uint64_t K, int elem_size, int prec) {
   p.cps = ceil_div(p.nchunks, nsplit);
   p.nsplit = ceil_div(p.nchunks, p.cps);
   p.part_elems = p.nsplit * p.npairs * 64 * 256;
-  p.sq_elems = (prec == 1) ? p.nsplit * p.npairs : 0;
+  p.sq_elems = (prec >= 1) ? p.nsplit * p.npairs : 0;
   return p;
 }
 
@@ -459,7 +542,7 @@ template <typename T>
 hipError_t launch_gram_dma(const T* Y, int J, uint64_t L, uint64_t K, int prec, const GramPlan& p, double* part,
                            double* sq, double* S, double* norm2, hipStream_t stream, hipEvent_t after_main) {
   if (!gram_dma_eligible(J, L, (int)sizeof(T), Y)) return hipErrorInvalidValue;
-  if (prec != 0 && (prec != 1 || sizeof(T) != 4 || sq == nullptr)) return hipErrorInvalidValue;
+  if (prec != 0 && ((prec != 1 && prec != 3) || sizeof(T) != 4 || sq == nullptr)) return hipErrorInvalidValue;
   DmaParams g{};
   g.Y = reinterpret_cast<const char*>(Y);
   g.J = J;
@@ -480,6 +563,10 @@ hipError_t launch_gram_dma(const T* Y, int J, uint64_t L, uint64_t K, int prec, 
     if (prec == 1) {
       if (L == 1) hipLaunchKernelGGL((gram_dma_kernel<T, 0, 1>), dim3(grid), dim3(kDNT), 0, stream, g);
       else hipLaunchKernelGGL((gram_dma_kernel<T, 1, 1>), dim3(grid), dim3(kDNT), 0, stream, g);
+    } else if (prec == 3 && L == 1) {
+      hipLaunchKernelGGL((gram_dma_kernel<T, 0, 3>), dim3(grid), dim3(kDNT), 0, stream, g);
+    } else if (prec == 3) {
+      return hipErrorInvalidValue;  // BF16X6 takes unit-stride modes only
     }
   }
   if (prec == 0) {
@@ -489,7 +576,7 @@ hipError_t launch_gram_dma(const T* Y, int J, uint64_t L, uint64_t K, int prec, 
   if (after_main) (void)hipEventRecord(after_main, stream);
   launch_gram_pair_reduce(part, p.ntiles, p.npairs, p.nsplit, J, S, stream);
   if (norm2) {
-    // FP64: the trace of S is the FP64 sum of squares; FP32 products: the
+    // FP64: the trace of S is the FP64 sum of squares; reduced forms: the
     // diagonal items' FP64 sums of squares, in item order
     if (prec == 0) hipLaunchKernelGGL(gram_trace_kernel, dim3(1), dim3(256), 0, stream, S, J, norm2);
     else hipLaunchKernelGGL(sum_fixed_kernel, dim3(1), dim3(256), 0, stream, sq, g.total, norm2);

@@ -75,11 +75,12 @@ def test_gram_reduced_parity(tk, orc, dims, modes, prec):
         assert float(nrm.item()) == pytest.approx(orc.norm2(X.astype(np.float64)), rel=1e-11)
 
 
-def test_bf16x3_bias_bf16x6_unbiased(tk, orc):
+@pytest.mark.parametrize("dims", [[48, 4000], [256, 600]])
+def test_bf16x3_bias_bf16x6_unbiased(tk, orc, dims):
     """The product dropped by BF16X3 is a Gram of bf16 rounding residuals, so
     its trace error is negative and about 2^-16/3 of the trace (uniform
-    residuals); BF16X6 removes it."""
-    dims = [48, 4000]
+    residuals); BF16X6 removes it.  A mode of 48 takes the streaming kernel,
+    one of 256 the tile pairs (BF16X6: with direct loads)."""
     rng = np.random.default_rng(11)
     X = rng.standard_normal(int(np.prod(dims))).astype(np.float32)
     Sref = orc.gram(X.astype(np.float64), dims, 0)
