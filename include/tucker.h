@@ -53,15 +53,17 @@ typedef enum { TUCKER_F32 = 0, TUCKER_F64 = 1 } tucker_dtype;
  * carry the working tensor in FP32, with FP32 MFMA products in its mode
  * products; they are not part of the paper (which is FP64 only) and each
  * result's error is reported against the FP64 path.
- *   FP32   : FP32 MFMA products, FP32 accumulation within groups of 256
+ *   FP32   : FP32 MFMA products, FP32 accumulation within groups of 32
  *            columns of the unfolding, group sums accumulated in FP64.
  *   BF16X3 : each FP32 value split as x = b0 + b1 + r in bfloat16
  *            (b0 = bf16(x), b1 = bf16(x - b0)); products b1*b0' + b0*b1' +
- *            b0*b0' on BF16 MFMA, FP32 accumulation per group, FP64 across
- *            groups (Henry, Tang & Heinecke, ARITH 2019).  The dropped b1*b1'
- *            term makes the Gram a slight under-estimate (relative ~1e-6).
+ *            b0*b0' on BF16 MFMA, FP32 accumulation within groups of 256
+ *            columns, FP64 across groups (Henry, Tang & Heinecke, ARITH
+ *            2019).  The dropped b1*b1' term makes the Gram a slight
+ *            under-estimate (relative ~1e-6).
  *   BF16X6 : three pieces b0, b1, b2 and the six products b2*b0' + b0*b2' +
- *            b1*b1' + b1*b0' + b0*b1' + b0*b0'.
+ *            b1*b1' + b1*b0' + b0*b1' + b0*b0', FP32 accumulation within
+ *            groups of 32 columns, FP64 across groups.
  *   AUTO   : the cheapest form whose predicted error of the truncation's tail
  *            sums, delta * ||X||^2, is at most 1% of the slack of a 1.05 eps
  *            target, (1.05^2 - 1) eps^2 ||X||^2 / N; delta = 2^-16/3 for
