@@ -35,14 +35,16 @@ struct GramPlan {
   int64_t sq_elems;    // doubles of sum-of-squares workspace
 };
 
-// FP64 Gram for J > 128 with direct global-to-LDS staging (gram_dma.hip):
-// float or double input, unit stride (L = 1) or row segments (L >= 64 or L a
+// Gram for J > 128 with direct global-to-LDS staging (gram_dma.hip): float
+// or double input, unit stride (L = 1) or row segments (L >= 64 or L a
 // multiple of the chunk width 128 / sizeof(T)), 16-byte aligned base and
 // column (L = 1) or row stride.  Partial blocks in the tile-pair layout of
-// launch_gram_pair_reduce; norm2 (may be null) receives trace(S).
+// launch_gram_pair_reduce; norm2 (may be null) receives the FP64 sum of
+// squares (trace(S) with FP64 products).
 bool gram_dma_eligible(int J, uint64_t L, int elem_size, const void* Y);
-// prec 0: FP64 products; prec 1: FP32 products of float input (sq: one
-// double per item, p.sq_elems).
+// prec 0: FP64 products; prec 1: FP32 products, prec 3: BF16X6 products, both
+// of float input with unit stride only (sq: one double per item,
+// p.sq_elems).  Other combinations return hipErrorInvalidValue.
 GramPlan plan_gram_dma(int J, uint64_t L, uint64_t K, int elem_size, int prec);
 template <typename T>
 hipError_t launch_gram_dma(const T* Y, int J, uint64_t L, uint64_t K, int prec, const GramPlan& p, double* part,
