@@ -560,14 +560,11 @@ hipError_t launch_gram_dma(const T* Y, int J, uint64_t L, uint64_t K, int prec, 
   g.sq = sq;
   const int64_t grid = ceil_div(g.total, kXcds) * kXcds;
   if constexpr (sizeof(T) == 4) {
-    if (prec == 1) {
-      if (L == 1) hipLaunchKernelGGL((gram_dma_kernel<T, 0, 1>), dim3(grid), dim3(kDNT), 0, stream, g);
-      else hipLaunchKernelGGL((gram_dma_kernel<T, 1, 1>), dim3(grid), dim3(kDNT), 0, stream, g);
-    } else if (prec == 3 && L == 1) {
-      hipLaunchKernelGGL((gram_dma_kernel<T, 0, 3>), dim3(grid), dim3(kDNT), 0, stream, g);
-    } else if (prec == 3) {
-      return hipErrorInvalidValue;  // BF16X6 takes unit-stride modes only
-    }
+    // the reduced forms take unit-stride modes only (on row segments the
+    // register-staged tile pairs measured faster)
+    if (prec != 0 && L != 1) return hipErrorInvalidValue;
+    if (prec == 1) hipLaunchKernelGGL((gram_dma_kernel<T, 0, 1>), dim3(grid), dim3(kDNT), 0, stream, g);
+    else if (prec == 3) hipLaunchKernelGGL((gram_dma_kernel<T, 0, 3>), dim3(grid), dim3(kDNT), 0, stream, g);
   }
   if (prec == 0) {
     if (L == 1) hipLaunchKernelGGL((gram_dma_kernel<T, 0, 0>), dim3(grid), dim3(kDNT), 0, stream, g);
